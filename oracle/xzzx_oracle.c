@@ -1,0 +1,949 @@
+/*
+ * xzzx_oracle.c -- plain CPU oracle for the simulated-annealing (SA) decoder of
+ * the XZZX surface code (arXiv:2509.17837, "Simulated-annealing decoder for the
+ * XZZX code with greedy-matching initialization").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library under paper_2509_17837_amd/) never links, loads or calls it,
+ * and this file shares no code, header, table or helper with that path.
+ *
+ * Style: slow, single-threaded, no blocking or fusion.  Every function follows
+ * one passage of the paper, cited in its comment.  Where the paper leaves a
+ * choice open (lattice layout, random-number stream, sweep order, rounding of
+ * the acceptance test, tie rules) the reading used is stated at the function.
+ *
+ * Pauli codes follow the paper's two-bit encoding (footnote to Eq. (10)):
+ * upper bit = X component, lower bit = Z component, so I=0, Z=1, X=2, Y=3.
+ * Multiplying two configurations is a bitwise XOR of the codes (footnote to
+ * Alg. 3).
+ *
+ * Pinning status: every function below is pinned by a CPU test (closed forms,
+ * brute force, invariants, published known-answer vectors), except the exact
+ * tie order of the randomized greedy matching, which the paper leaves free
+ * ("pick uniformly at random", Alg. 6) -- only its distributional properties
+ * and its matching weight are pinned; the byte-exact order is this oracle's
+ * definition (parity unpinned by the paper).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_ROTATED 0
+#define OR_PLANAR 1
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+#define OR_EINVARIANT (-7)
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 counter-based generator.                                     */
+/* Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"  */
+/* (SC'11), Sec. 5: ten rounds; each round multiplies words 0 and 2 by the    */
+/* two Philox multipliers, swaps/xors the high halves with the other words    */
+/* and the round key; the key is bumped by the two Weyl constants.            */
+/* ------------------------------------------------------------------------- */
+void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static uint32_t philox_word(uint64_t seed, uint32_t a, uint32_t b, uint32_t c, uint32_t d, int w)
+{
+    uint32_t ctr[4] = {a, b, c, d};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    or_philox4x32_10(ctr, key, out);
+    return out[w];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Lattice.                                                                   */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int nedge;          /* incident edges, ascending edge id */
+    int eid[8];         /* edge id = 2*qubit + (component is X ? 1 : 0) */
+    int other[8];       /* other node index, -1 for a boundary half-edge */
+    int64_t w[8];
+} or_node;
+
+typedef struct {
+    int layout, d, nq, nstab;
+    int *fq;            /* [nstab][4] qubit on slot, -1 if absent */
+    uint8_t *fm;        /* [nstab][4] generator's Pauli code on slot (X=2 / Z=1) */
+    int *fx, *fy;       /* face coordinates (cell for rotated, doubled for planar) */
+    int *fclass;        /* colour class 0..3 (qubit-disjoint within a class) */
+    int *fcolour;       /* decoding-graph colour 0/1 (white/gray) */
+    int *frank;         /* rank inside its colour class */
+    int ncls[4];
+    int *cls_face[4];   /* face id by (class, rank) */
+    uint8_t *lx, *lz;   /* logical representatives */
+    /* greedy tables, built for one pair of greedy weights */
+    int have_tables;
+    int32_t wg[2];      /* W~_x, W~_z */
+    int ncol[2];
+    int *col_face[2];   /* node -> face id (ascending face id) */
+    int *node_of_face;  /* face -> node index within its colour */
+    or_node *nodes[2];
+    int64_t *dint[2];   /* [n][n] shortest path over interior edges */
+    int64_t *db[2];     /* [n] distance to the boundary */
+} or_lat;
+
+static int in_rot(int d, int x, int y) { return x >= 0 && x < d && y >= 0 && y < d; }
+
+/* Rotated layout (d^2 qubits, d^2-1 generators).  The paper draws the code as
+ * a rotated square lattice (Sec. II); the configurations measured in this
+ * project use the d^2-qubit rotated form.  Qubit (x,y), q = y*d + x.  Cell
+ * (i,j) in [-1,d-1]^2 touches (i,j) [X], (i+1,j) [Z], (i,j+1) [Z], (i+1,j+1)
+ * [X]: the X-Z-Z-X pattern of Eq. (1).  Bulk cells are all generators; on the
+ * boundary only every other cell is (bottom: i odd, top: i even, left: j even,
+ * right: j odd), giving the two-body boundary generators. */
+static int rot_is_face(int d, int i, int j)
+{
+    if (i >= 0 && i <= d - 2 && j >= 0 && j <= d - 2) return 1;
+    if (j == -1 && i >= 0 && i <= d - 2) return (i & 1) == 1;
+    if (j == d - 1 && i >= 0 && i <= d - 2) return (i & 1) == 0;
+    if (i == -1 && j >= 0 && j <= d - 2) return (j & 1) == 0;
+    if (i == d - 1 && j >= 0 && j <= d - 2) return (j & 1) == 1;
+    return 0;
+}
+
+/* Planar layout, exactly the paper's: N_q = d^2+(d-1)^2, N_stab = 2d(d-1)
+ * (Sec. II).  Doubled coordinates: the white face (i,j), i=1..d, j=1..d-1 of
+ * Sec. IV.B.1 sits at (2i,2j); the gray face (i,j), i=1..d-1, j=1..d sits at
+ * (2i+1,2j-1).  Qubits sit at the (odd,even) points x in [3,2d-1],
+ * y in [2,2d-2] and the (even,odd) points x in [2,2d], y in [1,2d-1].  The
+ * generator at (x,y) is X(x-1,y) Z(x,y+1) Z(x,y-1) X(x+1,y), Eq. (1), restricted
+ * to the qubits that exist (three-body at the boundaries). */
+static int pl_qubit_index(int d, int x, int y)
+{
+    if ((x & 1) == 1 && (y & 1) == 0) {
+        if (x < 3 || x > 2 * d - 1 || y < 2 || y > 2 * d - 2) return -1;
+        return ((y - 2) / 2) * (d - 1) + (x - 3) / 2;
+    }
+    if ((x & 1) == 0 && (y & 1) == 1) {
+        if (x < 2 || x > 2 * d || y < 1 || y > 2 * d - 1) return -1;
+        return (d - 1) * (d - 1) + ((y - 1) / 2) * d + (x - 2) / 2;
+    }
+    return -1;
+}
+
+static int floordiv2(int a) { return (a >= 0) ? a / 2 : -((-a + 1) / 2); }
+static int mod2(int a) { return ((a % 2) + 2) % 2; }
+
+void or_lattice_free(or_lat *L);
+
+or_lat *or_lattice_new(int layout, int d)
+{
+    if (d < 3 || (d & 1) == 0 || d > 63) return NULL;
+    if (layout != OR_ROTATED && layout != OR_PLANAR) return NULL;
+    or_lat *L = (or_lat *)calloc(1, sizeof(or_lat));
+    if (!L) return NULL;
+    L->layout = layout;
+    L->d = d;
+    if (layout == OR_ROTATED) {
+        L->nq = d * d;
+        L->nstab = d * d - 1;
+    } else {
+        L->nq = d * d + (d - 1) * (d - 1);
+        L->nstab = 2 * d * (d - 1);
+    }
+    int ns = L->nstab;
+    L->fq = (int *)malloc(sizeof(int) * 4 * ns);
+    L->fm = (uint8_t *)calloc(4 * ns, 1);
+    L->fx = (int *)malloc(sizeof(int) * ns);
+    L->fy = (int *)malloc(sizeof(int) * ns);
+    L->fclass = (int *)malloc(sizeof(int) * ns);
+    L->fcolour = (int *)malloc(sizeof(int) * ns);
+    L->frank = (int *)malloc(sizeof(int) * ns);
+    L->lx = (uint8_t *)calloc(L->nq, 1);
+    L->lz = (uint8_t *)calloc(L->nq, 1);
+    L->node_of_face = (int *)malloc(sizeof(int) * ns);
+    if (!L->fq || !L->fm || !L->fx || !L->fy || !L->fclass || !L->fcolour || !L->frank ||
+        !L->lx || !L->lz || !L->node_of_face) {
+        or_lattice_free(L);
+        return NULL;
+    }
+    int f = 0;
+    if (layout == OR_ROTATED) {
+        /* faces in row-major order over (j, i) */
+        for (int j = -1; j <= d - 1; ++j)
+            for (int i = -1; i <= d - 1; ++i) {
+                if (!rot_is_face(d, i, j)) continue;
+                int sx[4] = {i, i + 1, i, i + 1};
+                int sy[4] = {j, j, j + 1, j + 1};
+                uint8_t sm[4] = {2, 1, 1, 2};
+                for (int s = 0; s < 4; ++s) {
+                    if (in_rot(d, sx[s], sy[s])) {
+                        L->fq[4 * f + s] = sy[s] * d + sx[s];
+                        L->fm[4 * f + s] = sm[s];
+                    } else {
+                        L->fq[4 * f + s] = -1;
+                        L->fm[4 * f + s] = 0;
+                    }
+                }
+                L->fx[f] = i;
+                L->fy[f] = j;
+                L->fclass[f] = ((i + 1) & 1) + 2 * ((j + 1) & 1);
+                L->fcolour[f] = (i + j + 2) & 1;
+                ++f;
+            }
+        /* logical representatives: L_Z runs left to right along row y=0,
+         * L_X runs top to bottom along column x=0 (Sec. II) */
+        for (int x = 0; x < d; ++x) L->lz[x] = (x & 1) ? 2 : 1;
+        for (int y = 0; y < d; ++y) L->lx[y * d] = (y & 1) ? 1 : 2;
+    } else {
+        /* faces in row-major order over (y, x) of doubled coordinates */
+        for (int y = 1; y <= 2 * d; ++y)
+            for (int x = 2; x <= 2 * d + 1; ++x) {
+                int white = ((x & 1) == 0 && (y & 1) == 0 && x >= 2 && x <= 2 * d && y >= 2 && y <= 2 * d - 2);
+                int gray = ((x & 1) == 1 && (y & 1) == 1 && x >= 3 && x <= 2 * d - 1 && y >= 1 && y <= 2 * d - 1);
+                if (!white && !gray) continue;
+                int sx[4] = {x - 1, x, x, x + 1};
+                int sy[4] = {y, y + 1, y - 1, y};
+                uint8_t sm[4] = {2, 1, 1, 2};
+                for (int s = 0; s < 4; ++s) {
+                    int q = pl_qubit_index(d, sx[s], sy[s]);
+                    L->fq[4 * f + s] = q;
+                    L->fm[4 * f + s] = (q >= 0) ? sm[s] : 0;
+                }
+                L->fx[f] = x;
+                L->fy[f] = y;
+                L->fclass[f] = mod2(floordiv2(x + y)) + 2 * mod2(floordiv2(x - y));
+                L->fcolour[f] = x & 1;
+                ++f;
+            }
+        for (int i = 1; i <= d; ++i) L->lz[pl_qubit_index(d, 2 * i, 1)] = 1;
+        for (int j = 1; j <= d; ++j) L->lx[pl_qubit_index(d, 2, 2 * j - 1)] = 2;
+    }
+    if (f != ns) {
+        or_lattice_free(L);
+        return NULL;
+    }
+    /* rank inside each colour class in face-id order */
+    for (int k = 0; k < 4; ++k) L->ncls[k] = 0;
+    for (int g = 0; g < ns; ++g) L->frank[g] = L->ncls[L->fclass[g]]++;
+    for (int k = 0; k < 4; ++k) {
+        L->cls_face[k] = (int *)malloc(sizeof(int) * (L->ncls[k] > 0 ? L->ncls[k] : 1));
+        if (!L->cls_face[k]) { or_lattice_free(L); return NULL; }
+    }
+    for (int g = 0; g < ns; ++g) L->cls_face[L->fclass[g]][L->frank[g]] = g;
+    return L;
+}
+
+void or_lattice_free(or_lat *L)
+{
+    if (!L) return;
+    free(L->fq); free(L->fm); free(L->fx); free(L->fy); free(L->fclass);
+    free(L->fcolour); free(L->frank); free(L->lx); free(L->lz); free(L->node_of_face);
+    for (int k = 0; k < 4; ++k) free(L->cls_face[k]);
+    for (int g = 0; g < 2; ++g) {
+        free(L->col_face[g]); free(L->nodes[g]); free(L->dint[g]); free(L->db[g]);
+    }
+    free(L);
+}
+
+int or_lattice_nq(const or_lat *L) { return L->nq; }
+int or_lattice_nstab(const or_lat *L) { return L->nstab; }
+int or_lattice_ncls(const or_lat *L, int k) { return L->ncls[k]; }
+
+/* Export the lattice tables (for tests). */
+void or_lattice_export(const or_lat *L, int32_t *fq, uint8_t *fm, int32_t *fxy, int32_t *fclass,
+                       int32_t *fcolour, int32_t *frank, uint8_t *lx, uint8_t *lz)
+{
+    for (int f = 0; f < L->nstab; ++f) {
+        for (int s = 0; s < 4; ++s) {
+            if (fq) fq[4 * f + s] = L->fq[4 * f + s];
+            if (fm) fm[4 * f + s] = L->fm[4 * f + s];
+        }
+        if (fxy) { fxy[2 * f] = L->fx[f]; fxy[2 * f + 1] = L->fy[f]; }
+        if (fclass) fclass[f] = L->fclass[f];
+        if (fcolour) fcolour[f] = L->fcolour[f];
+        if (frank) frank[f] = L->frank[f];
+    }
+    if (lx) memcpy(lx, L->lx, L->nq);
+    if (lz) memcpy(lz, L->lz, L->nq);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Noise, energy weights, Nishimori temperature.                              */
+/* ------------------------------------------------------------------------- */
+
+/* Eq. (5) with a Y bias.  convention 0: p_Y = p*eta/(eta+1),
+ * p_X = p_Z = p/(2(eta+1)).  convention 1 (the paper's Sec. V.A):
+ * p_x:p_y:p_z = 1:eta:1. */
+int or_noise(double p, double eta, int convention, double pxyz[3])
+{
+    if (!(p > 0.0 && p < 0.5) || !(eta > 0.0)) return OR_EINVAL;
+    if (convention == 0) {
+        pxyz[0] = p / (2.0 * (eta + 1.0));
+        pxyz[1] = p * eta / (eta + 1.0);
+        pxyz[2] = p / (2.0 * (eta + 1.0));
+    } else if (convention == 1) {
+        pxyz[0] = p / (eta + 2.0);
+        pxyz[1] = p * eta / (eta + 2.0);
+        pxyz[2] = p / (eta + 2.0);
+    } else {
+        return OR_EINVAL;
+    }
+    return OR_OK;
+}
+
+/* Energy weights by Pauli code (I, Z, X, Y).  Eqs. (8)-(12): the weight of a
+ * single X, Y or Z error in the Boltzmann factor pi(C) = exp(-beta_N H(C)) is
+ * beta_N * alpha_mu = -ln(p_mu/(1-p)) nats.  Quantised to integers at a scale of
+ * 2^16 per nat.  Greedy-matching weights (Eq. (27)): -ln(p~_mu/(1-p)) with
+ * p~_x = p_x+p_y, p~_z = p_z+p_y, same scale.  p is the total error rate. */
+int or_weights(double p, const double pxyz[3], int32_t w[4], int32_t wg[2])
+{
+    if (!(p > 0.0 && p < 0.5)) return OR_EINVAL;
+    for (int i = 0; i < 3; ++i)
+        if (!(pxyz[i] > 0.0 && pxyz[i] < 1.0 - p)) return OR_EINVAL;
+    double q = 1.0 - p;
+    w[0] = 0;
+    w[1] = (int32_t)llround(65536.0 * -log(pxyz[2] / q)); /* Z */
+    w[2] = (int32_t)llround(65536.0 * -log(pxyz[0] / q)); /* X */
+    w[3] = (int32_t)llround(65536.0 * -log(pxyz[1] / q)); /* Y */
+    wg[0] = (int32_t)llround(65536.0 * -log((pxyz[0] + pxyz[1]) / q)); /* X component */
+    wg[1] = (int32_t)llround(65536.0 * -log((pxyz[2] + pxyz[1]) / q)); /* Z component */
+    return OR_OK;
+}
+
+/* Eq. (10): H(C) = sum of per-qubit weights (in the quantised nat units). */
+int64_t or_energy(const or_lat *L, const int32_t w[4], const uint8_t *cfg)
+{
+    int64_t e = 0;
+    for (int q = 0; q < L->nq; ++q) e += w[cfg[q] & 3];
+    return e;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Inverse-temperature schedules (beta in nats; beta = 1 is the Nishimori    */
+/* point of Eq. (12)).                                                        */
+/* kind 0: linear b0..b1 inclusive; kind 1: geometric b0..b1 inclusive;       */
+/* kind 2: Eq. (23)-(24), beta_i = b0 (1 + gamma ln i), i = 1..n, with        */
+/*         gamma = (b1/b0 - 1)/ln n for n >= 2 and 0 otherwise.               */
+/* ------------------------------------------------------------------------- */
+int or_schedule(int kind, double b0, double b1, int n, double *beta)
+{
+    if (n < 0 || !(b0 >= 0.0) || !(b1 >= 0.0)) return OR_EINVAL;
+    for (int t = 0; t < n; ++t) {
+        if (kind == 0) {
+            beta[t] = (n == 1) ? b0 : b0 + (b1 - b0) * ((double)t / (double)(n - 1));
+        } else if (kind == 1) {
+            if (!(b0 > 0.0)) return OR_EINVAL;
+            beta[t] = (n == 1) ? b0 : b0 * pow(b1 / b0, (double)t / (double)(n - 1));
+        } else if (kind == 2) {
+            if (!(b0 > 0.0)) return OR_EINVAL;
+            double gamma = (n >= 2) ? (b1 / b0 - 1.0) / log((double)n) : 0.0;
+            beta[t] = b0 * (1.0 + gamma * log((double)(t + 1)));
+        } else {
+            return OR_EINVAL;
+        }
+    }
+    return OR_OK;
+}
+
+/* Acceptance threshold of Alg. 3 on a 32-bit draw u (r = u / 2^32):
+ * r < min{1, exp(-beta dE)}.  For dE <= 0 the move is always accepted; for
+ * dE > 0 (dE in units of 2^-16 nats) the integer rule is u < T with
+ * T = ceil(2^32 exp(-(beta*dE) 2^-16)), clamped to 2^32-1. */
+uint32_t or_threshold(double beta, int64_t dE)
+{
+    if (dE <= 0) return 0xFFFFFFFFu;
+    double x = exp(-(beta * (double)dE) * 0x1p-16);
+    double t = ceil(ldexp(x, 32));
+    if (t >= 4294967295.0) return 0xFFFFFFFFu;
+    return (uint32_t)t;
+}
+
+static int accept_move(double beta, int64_t dE, uint32_t u)
+{
+    if (dE <= 0) return 1;
+    return u < or_threshold(beta, dE);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Syndrome, Eqs. (2) and (A2): s_f = 1 iff C anticommutes with G_f.          */
+/* ------------------------------------------------------------------------- */
+static int anticommute(uint8_t a, uint8_t b)
+{
+    int ax = (a >> 1) & 1, az = a & 1, bx = (b >> 1) & 1, bz = b & 1;
+    return (ax & bz) ^ (az & bx);
+}
+
+void or_syndrome(const or_lat *L, const uint8_t *cfg, uint8_t *syn)
+{
+    for (int f = 0; f < L->nstab; ++f) {
+        int s = 0;
+        for (int k = 0; k < 4; ++k) {
+            int q = L->fq[4 * f + k];
+            if (q >= 0) s ^= anticommute(cfg[q], L->fm[4 * f + k]);
+        }
+        syn[f] = (uint8_t)s;
+    }
+}
+
+/* Symplectic product of two configurations (1 iff they anticommute). */
+int or_symp(const or_lat *L, const uint8_t *a, const uint8_t *b)
+{
+    int s = 0;
+    for (int q = 0; q < L->nq; ++q) s ^= anticommute(a[q], b[q]);
+    return s;
+}
+
+/* Logical class of a*b (Alg. 7, "via commutation with L_X and L_Z"):
+ * a*b must have a trivial syndrome.  Returns 0=I, 1=X, 2=Y, 3=Z, or -1 if the
+ * product is not syndrome-free.  [a*b] = [L_X] anticommutes with L_Z only,
+ * [L_Z] with L_X only, [L_Y] with both. */
+int or_class(const or_lat *L, const uint8_t *a, const uint8_t *b)
+{
+    uint8_t *e = (uint8_t *)malloc(L->nq);
+    uint8_t *s = (uint8_t *)malloc(L->nstab);
+    if (!e || !s) { free(e); free(s); return -2; }
+    for (int q = 0; q < L->nq; ++q) e[q] = (a[q] ^ b[q]) & 3;
+    or_syndrome(L, e, s);
+    int bad = 0;
+    for (int f = 0; f < L->nstab; ++f) bad |= s[f];
+    int ax = or_symp(L, e, L->lz);
+    int az = or_symp(L, e, L->lx);
+    free(e); free(s);
+    if (bad) return -1;
+    if (!ax && !az) return 0;
+    if (ax && !az) return 1;
+    if (ax && az) return 2;
+    return 3;
+}
+
+/* Pauli product of two class indices (I=0, X=1, Y=2, Z=3), phases ignored. */
+int or_class_mul(int a, int b)
+{
+    static const int xb[4] = {0, 1, 1, 0}, zb[4] = {0, 0, 1, 1};
+    int x = xb[a] ^ xb[b], z = zb[a] ^ zb[b];
+    if (!x && !z) return 0;
+    if (x && !z) return 1;
+    if (x && z) return 2;
+    return 3;
+}
+
+/* Representative of L_P (P = 0..3) written into out. */
+void or_logical(const or_lat *L, int P, uint8_t *out)
+{
+    for (int q = 0; q < L->nq; ++q) {
+        uint8_t v = 0;
+        if (P == 1 || P == 2) v ^= L->lx[q];
+        if (P == 3 || P == 2) v ^= L->lz[q];
+        out[q] = v;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Greedy matching, Algs. 5-6 with the weights of Eqs. (25)-(30).             */
+/*                                                                             */
+/* Decoding graph of colour g (Sec. III): nodes are the faces of colour g;    */
+/* the X (Z) component of a qubit flips one or two faces of one colour; with  */
+/* two it is an edge between them, with one it is a boundary half-edge.       */
+/* Edge weight: W~_x for an X component, W~_z for a Z component (Eq. (27)).   */
+/* Distances: the weighted Manhattan distances of Eqs. (26)-(30) are the      */
+/* shortest-path lengths in this graph; the oracle computes them by Dijkstra  */
+/* (valid for either layout).  w(u,v) = min(d_int(u,v), d_b(u)+d_b(v)),        */
+/* w(u,b) = d_b(u)  (Eqs. (25), (30)).                                         */
+/* ------------------------------------------------------------------------- */
+
+static void heap_push(int64_t *hk, int *hv, int *hn, int64_t k, int v)
+{
+    int i = (*hn)++;
+    hk[i] = k; hv[i] = v;
+    while (i > 0) {
+        int p = (i - 1) / 2;
+        if (hk[p] <= hk[i]) break;
+        int64_t tk = hk[p]; hk[p] = hk[i]; hk[i] = tk;
+        int tv = hv[p]; hv[p] = hv[i]; hv[i] = tv;
+        i = p;
+    }
+}
+
+static void heap_pop(int64_t *hk, int *hv, int *hn, int64_t *k, int *v)
+{
+    *k = hk[0]; *v = hv[0];
+    int n = --(*hn);
+    hk[0] = hk[n]; hv[0] = hv[n];
+    int i = 0;
+    for (;;) {
+        int l = 2 * i + 1, r = l + 1, m = i;
+        if (l < n && hk[l] < hk[m]) m = l;
+        if (r < n && hk[r] < hk[m]) m = r;
+        if (m == i) break;
+        int64_t tk = hk[m]; hk[m] = hk[i]; hk[i] = tk;
+        int tv = hv[m]; hv[m] = hv[i]; hv[i] = tv;
+        i = m;
+    }
+}
+
+static void free_tables(or_lat *L)
+{
+    for (int g = 0; g < 2; ++g) {
+        free(L->col_face[g]); L->col_face[g] = NULL;
+        free(L->nodes[g]); L->nodes[g] = NULL;
+        free(L->dint[g]); L->dint[g] = NULL;
+        free(L->db[g]); L->db[g] = NULL;
+    }
+    L->have_tables = 0;
+}
+
+int or_build_tables(or_lat *L, const int32_t wg[2])
+{
+    if (L->have_tables && L->wg[0] == wg[0] && L->wg[1] == wg[1]) return OR_OK;
+    free_tables(L);
+    if (wg[0] <= 0 || wg[1] <= 0) return OR_EINVAL;
+    L->wg[0] = wg[0];
+    L->wg[1] = wg[1];
+    for (int g = 0; g < 2; ++g) {
+        int n = 0;
+        for (int f = 0; f < L->nstab; ++f) if (L->fcolour[f] == g) ++n;
+        L->ncol[g] = n;
+        L->col_face[g] = (int *)malloc(sizeof(int) * n);
+        L->nodes[g] = (or_node *)calloc(n, sizeof(or_node));
+        L->dint[g] = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * n);
+        L->db[g] = (int64_t *)malloc(sizeof(int64_t) * n);
+        if (!L->col_face[g] || !L->nodes[g] || !L->dint[g] || !L->db[g]) { free_tables(L); return OR_ENOMEM; }
+        n = 0;
+        for (int f = 0; f < L->nstab; ++f)
+            if (L->fcolour[f] == g) { L->node_of_face[f] = n; L->col_face[g][n++] = f; }
+    }
+    /* edges, visited in ascending edge id so adjacency lists are sorted */
+    for (int q = 0; q < L->nq; ++q) {
+        for (int comp = 0; comp < 2; ++comp) {
+            uint8_t code = comp == 0 ? 1 : 2; /* Z component, then X component */
+            int eid = 2 * q + comp;
+            int hit[4], nh = 0;
+            for (int f = 0; f < L->nstab; ++f)
+                for (int s = 0; s < 4; ++s)
+                    if (L->fq[4 * f + s] == q && anticommute(code, L->fm[4 * f + s])) {
+                        if (nh < 4) hit[nh] = f;
+                        ++nh;
+                    }
+            if (nh < 1 || nh > 2) { free_tables(L); return OR_EINVAL; }
+            int g = L->fcolour[hit[0]];
+            if (nh == 2 && L->fcolour[hit[1]] != g) { free_tables(L); return OR_EINVAL; }
+            int64_t w = (code == 2) ? wg[0] : wg[1];
+            for (int h = 0; h < nh; ++h) {
+                or_node *nd = &L->nodes[g][L->node_of_face[hit[h]]];
+                if (nd->nedge >= 8) { free_tables(L); return OR_EINVAL; }
+                nd->eid[nd->nedge] = eid;
+                nd->other[nd->nedge] = (nh == 2) ? L->node_of_face[hit[1 - h]] : -1;
+                nd->w[nd->nedge] = w;
+                nd->nedge++;
+            }
+        }
+    }
+    /* all-pairs interior distances (Dijkstra from every node), then the
+     * boundary distance d_b(u) = min over half-edges h at node v of
+     * d_int(u,v) + w(h) */
+    for (int g = 0; g < 2; ++g) {
+        int n = L->ncol[g];
+        int64_t *hk = (int64_t *)malloc(sizeof(int64_t) * 8 * (size_t)n + 8);
+        int *hv = (int *)malloc(sizeof(int) * 8 * (size_t)n + 8);
+        if (!hk || !hv) { free(hk); free(hv); free_tables(L); return OR_ENOMEM; }
+        for (int s = 0; s < n; ++s) {
+            int64_t *dist = &L->dint[g][(size_t)s * n];
+            for (int v = 0; v < n; ++v) dist[v] = INT64_MAX;
+            int hn = 0;
+            dist[s] = 0;
+            heap_push(hk, hv, &hn, 0, s);
+            while (hn > 0) {
+                int64_t k; int v;
+                heap_pop(hk, hv, &hn, &k, &v);
+                if (k != dist[v]) continue;
+                or_node *nd = &L->nodes[g][v];
+                for (int e = 0; e < nd->nedge; ++e) {
+                    int o = nd->other[e];
+                    if (o < 0) continue;
+                    int64_t nk = k + nd->w[e];
+                    if (nk < dist[o]) { dist[o] = nk; heap_push(hk, hv, &hn, nk, o); }
+                }
+            }
+            for (int v = 0; v < n; ++v) if (dist[v] == INT64_MAX) { free(hk); free(hv); free_tables(L); return OR_EINVAL; }
+        }
+        free(hk); free(hv);
+        for (int u = 0; u < n; ++u) {
+            int64_t best = INT64_MAX;
+            for (int v = 0; v < n; ++v) {
+                or_node *nd = &L->nodes[g][v];
+                for (int e = 0; e < nd->nedge; ++e) {
+                    if (nd->other[e] >= 0) continue;
+                    int64_t c = L->dint[g][(size_t)u * n + v] + nd->w[e];
+                    if (c < best) best = c;
+                }
+            }
+            L->db[g][u] = best;
+        }
+    }
+    L->have_tables = 1;
+    return OR_OK;
+}
+
+/* Export distance tables of colour g (for tests): dint [n][n], db [n],
+ * node -> face map. */
+int or_tables_export(or_lat *L, const int32_t wg[2], int g, int64_t *dint, int64_t *db, int32_t *col_face)
+{
+    int rc = or_build_tables(L, wg);
+    if (rc) return rc;
+    int n = L->ncol[g];
+    if (dint) memcpy(dint, L->dint[g], sizeof(int64_t) * (size_t)n * n);
+    if (db) memcpy(db, L->db[g], sizeof(int64_t) * n);
+    if (col_face) for (int i = 0; i < n; ++i) col_face[i] = L->col_face[g][i];
+    return n;
+}
+
+static void apply_edge(uint8_t *out, int eid)
+{
+    int q = eid >> 1;
+    out[q] ^= (eid & 1) ? 2 : 1;
+}
+
+/* Path of weight d_int(u,v) from v back to u: at each node take the tight
+ * incident edge (d_int(u,y) + w(e) == d_int(u,x)) with the smallest edge id. */
+static void interior_path(const or_lat *L, int g, int u, int v, uint8_t *out)
+{
+    int n = L->ncol[g];
+    const int64_t *du = &L->dint[g][(size_t)u * n];
+    int x = v;
+    while (x != u) {
+        const or_node *nd = &L->nodes[g][x];
+        int moved = 0;
+        for (int e = 0; e < nd->nedge; ++e) {
+            int y = nd->other[e];
+            if (y < 0) continue;
+            if (du[y] + nd->w[e] == du[x]) {
+                apply_edge(out, nd->eid[e]);
+                x = y;
+                moved = 1;
+                break;
+            }
+        }
+        if (!moved) return; /* unreachable for consistent tables */
+    }
+}
+
+/* Path of weight d_b(u) from u to the boundary: at each node take the tight
+ * edge with the smallest edge id; a tight half-edge ends the path. */
+static void boundary_path(const or_lat *L, int g, int u, uint8_t *out)
+{
+    const int64_t *db = L->db[g];
+    int x = u;
+    for (;;) {
+        const or_node *nd = &L->nodes[g][x];
+        int moved = 0;
+        for (int e = 0; e < nd->nedge; ++e) {
+            int y = nd->other[e];
+            if (y < 0) {
+                if (nd->w[e] == db[x]) { apply_edge(out, nd->eid[e]); return; }
+            } else if (db[y] + nd->w[e] == db[x]) {
+                apply_edge(out, nd->eid[e]);
+                x = y;
+                moved = 1;
+                break;
+            }
+        }
+        if (!moved) return;
+    }
+}
+
+typedef struct { int64_t w; uint32_t key; uint32_t id; int i, j; } or_pair;
+
+static int pair_cmp(const void *a, const void *b)
+{
+    const or_pair *p = (const or_pair *)a, *q = (const or_pair *)b;
+    if (p->w != q->w) return p->w < q->w ? -1 : 1;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    if (p->id != q->id) return p->id < q->id ? -1 : 1;
+    return 0;
+}
+
+/* Greedy matching of one colour.  mode 0: randomized tie breaking (Alg. 6);
+ * mode 1: deterministic (Alg. 5); mode 2: every defect to its nearest
+ * boundary (the "Boundary" reference of Sec. V.C).
+ *
+ * Alg. 6 repeatedly picks a pair uniformly at random among the remaining
+ * pairs of minimum weight and deletes the pairs that share a vertex with it.
+ * Reading used here: each pair carries a 32-bit key drawn from Philox with
+ * counter (uid, replica, 0x100 + colour, pair id); pairs are scanned once in
+ * ascending (weight, key, pair id) order and a pair is taken iff both ends are
+ * still free.  The first still-free pair of a uniformly random order is
+ * uniform over the free pairs, so this is the same distribution.  Alg. 5 is
+ * the same scan with every key equal to zero. */
+static int greedy_colour(or_lat *L, int g, const uint8_t *syn, uint32_t uid, uint32_t rep,
+                         uint64_t seed, int mode, uint8_t *out, int32_t *pairs, int *npairs)
+{
+    int n = L->ncol[g];
+    int *D = (int *)malloc(sizeof(int) * (n + 1));
+    if (!D) return OR_ENOMEM;
+    int nd = 0;
+    for (int v = 0; v < n; ++v) if (syn[L->col_face[g][v]] & 1) D[nd++] = v;
+    if (mode == 2) {
+        for (int i = 0; i < nd; ++i) boundary_path(L, g, D[i], out);
+        free(D);
+        return OR_OK;
+    }
+    int with_b = nd & 1;
+    int na = nd + with_b; /* augmented list: defects, then the virtual boundary */
+    size_t np = (size_t)na * (na - 1) / 2;
+    or_pair *P = (or_pair *)malloc(sizeof(or_pair) * (np ? np : 1));
+    int *matched = (int *)calloc(na ? na : 1, sizeof(int));
+    if (!P || !matched) { free(D); free(P); free(matched); return OR_ENOMEM; }
+    size_t k = 0;
+    for (int i = 0; i < na; ++i)
+        for (int j = i + 1; j < na; ++j) {
+            int64_t w;
+            if (j == nd) {
+                w = L->db[g][D[i]];
+            } else {
+                int64_t a = L->dint[g][(size_t)D[i] * n + D[j]];
+                int64_t b = L->db[g][D[i]] + L->db[g][D[j]];
+                w = a < b ? a : b;
+            }
+            uint32_t id = (uint32_t)(i * na + j);
+            P[k].w = w;
+            P[k].id = id;
+            P[k].key = (mode == 0) ? philox_word(seed, uid, rep, 0x100u + (uint32_t)g, id, 0) : 0u;
+            P[k].i = i;
+            P[k].j = j;
+            ++k;
+        }
+    qsort(P, np, sizeof(or_pair), pair_cmp);
+    for (size_t t = 0; t < np; ++t) {
+        int i = P[t].i, j = P[t].j;
+        if (matched[i] || matched[j]) continue;
+        matched[i] = matched[j] = 1;
+        if (pairs) { pairs[2 * *npairs] = i; pairs[2 * *npairs + 1] = j; }
+        if (npairs) ++*npairs;
+        if (j == nd) {
+            boundary_path(L, g, D[i], out);
+        } else {
+            int64_t a = L->dint[g][(size_t)D[i] * n + D[j]];
+            int64_t b = L->db[g][D[i]] + L->db[g][D[j]];
+            if (a <= b) {
+                interior_path(L, g, D[i], D[j], out);
+            } else {
+                boundary_path(L, g, D[i], out);
+                boundary_path(L, g, D[j], out);
+            }
+        }
+    }
+    free(D); free(P); free(matched);
+    return OR_OK;
+}
+
+/* Reference configuration R(S) from the greedy matchings of both colours
+ * (greedy_matching / greedy_matching_different of Algs. 5-6). */
+int or_greedy(or_lat *L, const int32_t wg[2], const uint8_t *syn, uint32_t uid, uint32_t rep,
+              uint64_t seed, int mode, uint8_t *out)
+{
+    if (mode < 0 || mode > 2) return OR_EINVAL;
+    int rc = or_build_tables(L, wg);
+    if (rc) return rc;
+    memset(out, 0, L->nq);
+    for (int g = 0; g < 2; ++g) {
+        rc = greedy_colour(L, g, syn, uid, rep, seed, mode, out, NULL, NULL);
+        if (rc) return rc;
+    }
+    return OR_OK;
+}
+
+/* Matched pairs of colour g in acceptance order, as indices into the
+ * augmented defect list (defects by ascending face id, then the virtual
+ * boundary); returns the number of pairs (for tests). */
+int or_greedy_pairs(or_lat *L, const int32_t wg[2], const uint8_t *syn, uint32_t uid, uint32_t rep,
+                    uint64_t seed, int mode, int g, int32_t *pairs)
+{
+    int rc = or_build_tables(L, wg);
+    if (rc) return rc;
+    uint8_t *out = (uint8_t *)calloc(L->nq, 1);
+    if (!out) return OR_ENOMEM;
+    int np = 0;
+    rc = greedy_colour(L, g, syn, uid, rep, seed, mode, out, pairs, &np);
+    free(out);
+    return rc ? rc : np;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Simulated annealing, Algs. 2-3.                                            */
+/*                                                                             */
+/* Sweep order (reading): Alg. 3 picks a generator uniformly at random and a  */
+/* sweep is N_stab such steps.  Here a sweep visits every generator once,     */
+/* class by class (k = 0..3); generators of one class act on disjoint qubits, */
+/* so their moves commute.  The draw for generator (k, m) -- rank m in class  */
+/* k -- in sweep t of chain c of syndrome uid is word (m mod 4) of           */
+/* Philox(seed; uid, c, 4t + k, m div 4).  E_min is updated after each class  */
+/* (the parallel counterpart of "after every step" in Alg. 2), strictly, so   */
+/* the snapshot is the first configuration attaining it; stop = 4t + k + 1    */
+/* records that phase (0 = the initial configuration).                         */
+/* ------------------------------------------------------------------------- */
+static int check_chain(const or_lat *L, const int32_t w[4], const uint8_t *cfg, const uint8_t *syn0,
+                       const uint8_t *cfg0, int64_t e, int64_t emin)
+{
+    uint8_t *s = (uint8_t *)malloc(L->nstab);
+    if (!s) return OR_ENOMEM;
+    or_syndrome(L, cfg, s);
+    int bad = memcmp(s, syn0, L->nstab) != 0;
+    free(s);
+    if (bad) return OR_EINVARIANT;                       /* syndrome preserved */
+    if (or_energy(L, w, cfg) != e) return OR_EINVARIANT;  /* incremental energy */
+    if (or_class(L, cfg, cfg0) != 0) return OR_EINVARIANT; /* coset preserved */
+    if (emin > e) return OR_EINVARIANT;
+    return OR_OK;
+}
+
+int or_anneal_chain(const or_lat *L, const int32_t w[4], const double *beta, int n_sweeps,
+                    uint64_t seed, uint32_t uid, uint32_t chain, uint8_t *cfg,
+                    int64_t *e_out, int64_t *emin_out, int32_t *stop_out, uint8_t *snap,
+                    int check)
+{
+    if (n_sweeps < 0) return OR_EINVAL;
+    uint8_t *syn0 = NULL, *cfg0 = NULL;
+    if (check) {
+        syn0 = (uint8_t *)malloc(L->nstab);
+        cfg0 = (uint8_t *)malloc(L->nq);
+        if (!syn0 || !cfg0) { free(syn0); free(cfg0); return OR_ENOMEM; }
+        or_syndrome(L, cfg, syn0);
+        memcpy(cfg0, cfg, L->nq);
+    }
+    int64_t e = or_energy(L, w, cfg);
+    int64_t emin = e;
+    int32_t stop = 0;
+    if (snap) memcpy(snap, cfg, L->nq);
+    int rc = OR_OK;
+    for (int t = 0; t < n_sweeps; ++t) {
+        double b = beta[t];
+        for (int k = 0; k < 4; ++k) {
+            for (int m = 0; m < L->ncls[k]; ++m) {
+                int f = L->cls_face[k][m];
+                int64_t dE = 0;
+                for (int s = 0; s < 4; ++s) {
+                    int q = L->fq[4 * f + s];
+                    if (q < 0) continue;
+                    uint8_t c = cfg[q];
+                    dE += (int64_t)w[c ^ L->fm[4 * f + s]] - (int64_t)w[c];
+                }
+                uint32_t u = philox_word(seed, uid, chain, 4u * (uint32_t)t + (uint32_t)k,
+                                         (uint32_t)m >> 2, m & 3);
+                if (accept_move(b, dE, u)) {
+                    for (int s = 0; s < 4; ++s) {
+                        int q = L->fq[4 * f + s];
+                        if (q >= 0) cfg[q] ^= L->fm[4 * f + s];
+                    }
+                    e += dE;
+                }
+            }
+            if (e < emin) {
+                emin = e;
+                stop = 4 * t + k + 1;
+                if (snap) memcpy(snap, cfg, L->nq);
+            }
+        }
+        if (check && (rc = check_chain(L, w, cfg, syn0, cfg0, e, emin)) != OR_OK) break;
+    }
+    free(syn0); free(cfg0);
+    if (e_out) *e_out = e;
+    if (emin_out) *emin_out = emin;
+    if (stop_out) *stop_out = stop;
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Decoder, Alg. 7 (Alg. 1 when every replica uses the same reference).       */
+/*                                                                             */
+/* Replica r (the paper's SA-run index i) gets reference R_r from the greedy  */
+/* matching; its class relative to R_0 (the paper's R_1) is Q_r = [R_r R_0].   */
+/* Chain c = 4r + P' starts at R_r L_P' and, by Eq. (36), estimates the coset */
+/* of L_{Q_r P'} relative to R_0.  E_P = min of E_min over chains of class P; */
+/* P* = argmin E_P (Eq. (21)), ties to the lowest index I<X<Y<Z.  The         */
+/* returned recovery is the minimum-energy configuration found: the snapshot  */
+/* of the lowest-index chain of class P* whose E_min equals E_P*.  R_0 L_P*,  */
+/* the output form of Alg. 7, is returned as well.                            */
+/* ------------------------------------------------------------------------- */
+int or_decode(or_lat *L, const int32_t w[4], const int32_t wg[2], const uint8_t *syn, uint32_t uid,
+              int n_rep, const double *beta, int n_sweeps, uint64_t greedy_seed,
+              uint64_t anneal_seed, int greedy_mode,
+              int64_t *e_best, int32_t *cls_best, int64_t e_cls[4], uint8_t *recovery,
+              uint8_t *paper_recovery, int32_t *best_chain,
+              uint8_t *refs /*[n_rep][nq] or NULL*/, int32_t *qcls /*[n_rep] or NULL*/,
+              int64_t *chain_emin /*[4 n_rep] or NULL*/, int32_t *chain_stop,
+              int64_t *chain_e, uint8_t *chain_final /*[4 n_rep][nq] or NULL*/,
+              int check)
+{
+    if (n_rep < 1) return OR_EINVAL;
+    int nq = L->nq;
+    int rc = OR_OK;
+    uint8_t *R = (uint8_t *)malloc((size_t)n_rep * nq);
+    uint8_t *cfg = (uint8_t *)malloc(nq);
+    uint8_t *snap = (uint8_t *)malloc(nq);
+    uint8_t *lp = (uint8_t *)malloc(nq);
+    int *Q = (int *)malloc(sizeof(int) * n_rep);
+    uint8_t *keep = (uint8_t *)malloc((size_t)4 * nq); /* snapshot of each class's best chain */
+    if (!R || !cfg || !snap || !lp || !Q || !keep) { rc = OR_ENOMEM; goto done; }
+    for (int r = 0; r < n_rep; ++r) {
+        rc = or_greedy(L, wg, syn, uid, (uint32_t)r, greedy_seed, greedy_mode, R + (size_t)r * nq);
+        if (rc) goto done;
+        Q[r] = or_class(L, R + (size_t)r * nq, R);
+        if (Q[r] < 0) { rc = OR_EINVARIANT; goto done; }
+        if (refs) memcpy(refs + (size_t)r * nq, R + (size_t)r * nq, nq);
+        if (qcls) qcls[r] = Q[r];
+    }
+    int64_t best[4] = {INT64_MAX, INT64_MAX, INT64_MAX, INT64_MAX};
+    int bestc[4] = {-1, -1, -1, -1};
+    for (int r = 0; r < n_rep; ++r) {
+        for (int P = 0; P < 4; ++P) {
+            int c = 4 * r + P;
+            or_logical(L, P, lp);
+            for (int q = 0; q < nq; ++q) cfg[q] = R[(size_t)r * nq + q] ^ lp[q];
+            int64_t e, emin;
+            int32_t stop;
+            rc = or_anneal_chain(L, w, beta, n_sweeps, anneal_seed, uid, (uint32_t)c, cfg, &e, &emin,
+                                 &stop, snap, check);
+            if (rc) goto done;
+            int cls = or_class_mul(Q[r], P);
+            if (emin < best[cls]) {
+                best[cls] = emin;
+                bestc[cls] = c;
+                memcpy(keep + (size_t)cls * nq, snap, nq);
+            }
+            if (chain_emin) chain_emin[c] = emin;
+            if (chain_stop) chain_stop[c] = stop;
+            if (chain_e) chain_e[c] = e;
+            if (chain_final) memcpy(chain_final + (size_t)c * nq, cfg, nq);
+        }
+    }
+    int ps = 0;
+    for (int P = 1; P < 4; ++P) if (best[P] < best[ps]) ps = P;
+    if (e_best) *e_best = best[ps];
+    if (cls_best) *cls_best = ps;
+    if (e_cls) for (int P = 0; P < 4; ++P) e_cls[P] = best[P];
+    if (best_chain) *best_chain = bestc[ps];
+    if (recovery) memcpy(recovery, keep + (size_t)ps * nq, nq);
+    if (paper_recovery) {
+        or_logical(L, ps, lp);
+        for (int q = 0; q < nq; ++q) paper_recovery[q] = R[q] ^ lp[q];
+    }
+done:
+    free(R); free(cfg); free(snap); free(lp); free(Q); free(keep);
+    return rc;
+}

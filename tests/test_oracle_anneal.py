@@ -1,0 +1,189 @@
+"""Pins for the oracle's simulated annealing (Algs. 2-3) and decoder (Alg. 7).
+
+Pins: exact coset minima by brute-force enumeration of the stabilizer group
+(Eqs. (18)-(21)), the beta = 0 and beta = infinity closed forms, the empty
+schedule, per-sweep invariants, the stationary Boltzmann law of Eq. (22) at a
+fixed beta (chi-square, with a negative control), and the coset relabelling
+of Eqs. (35)-(36).
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import oracle as O
+from tests import _gf2
+
+
+def random_problem(L, p, eta, rng):
+    pxyz = O.noise(p, eta)
+    u = rng.random(L.nq)
+    err = np.zeros(L.nq, np.uint8)
+    err[u < pxyz[0] + pxyz[1] + pxyz[2]] = 1
+    err[u < pxyz[0] + pxyz[1]] = 3
+    err[u < pxyz[0]] = 2
+    return err, L.syndrome(err)
+
+
+def test_zero_sweeps_returns_initial_energy():
+    L = O.Lattice(O.ROTATED, 5)
+    w, _ = O.weights(0.1, O.noise(0.1, 3.0))
+    rng = np.random.default_rng(1)
+    init = rng.integers(0, 4, L.nq).astype(np.uint8)
+    r = L.anneal_chain(w, np.zeros(0), 7, 3, 1, init)
+    e0 = int(w[init].sum())
+    assert r["e"] == r["emin"] == e0 and r["stop"] == 0
+    assert np.array_equal(r["final"], init) and np.array_equal(r["snap"], init)
+
+
+@pytest.mark.parametrize("layout,d", [(O.ROTATED, 3), (O.ROTATED, 7), (O.PLANAR, 5)])
+def test_beta_zero_closed_form(layout, d):
+    """beta = 0: every proposed flip is accepted (the draw u = 2^32-1, the only
+    exception, has probability 2^-32 per move), so phase k of each sweep
+    multiplies the configuration by the product of all class-k generators."""
+    L = O.Lattice(layout, d)
+    G = _gf2.generator_matrix(L.fq, L.fm, L.nq)
+    cls_prod = [np.bitwise_xor.reduce(G[L.fclass == k], axis=0) for k in range(4)]
+    w, _ = O.weights(0.12, O.noise(0.12, 10.0))
+    rng = np.random.default_rng(2)
+    init = rng.integers(0, 4, L.nq).astype(np.uint8)
+    n = 7
+    r = L.anneal_chain(w, np.zeros(n), 99, 5, 2, init)
+    cfg = init.copy()
+    e_min, stop, snap = int(w[cfg].sum()), 0, cfg.copy()
+    for t in range(n):
+        for k in range(4):
+            cfg = cfg ^ cls_prod[k]
+            e = int(w[cfg].sum())
+            if e < e_min:
+                e_min, stop, snap = e, 4 * t + k + 1, cfg.copy()
+    assert np.array_equal(r["final"], cfg)
+    assert r["e"] == int(w[cfg].sum())
+    assert (r["emin"], r["stop"]) == (e_min, stop)
+    assert np.array_equal(r["snap"], snap)
+
+
+@pytest.mark.parametrize("layout,d", [(O.ROTATED, 5), (O.PLANAR, 5)])
+def test_zero_temperature_descent(layout, d):
+    """beta -> infinity: only moves with dE <= 0 are accepted, so the energy is
+    non-increasing sweep by sweep and E_min is the final energy."""
+    L = O.Lattice(layout, d)
+    w, _ = O.weights(0.15, O.noise(0.15, 10.0))
+    rng = np.random.default_rng(3)
+    init = rng.integers(0, 4, L.nq).astype(np.uint8)
+    beta = np.full(12, 1e6)
+    es = [L.anneal_chain(w, beta[:s], 4, 1, 0, init)["e"] for s in range(13)]
+    assert all(a >= b for a, b in zip(es, es[1:]))
+    r = L.anneal_chain(w, beta, 4, 1, 0, init)
+    assert r["emin"] == r["e"] == es[-1] and es[-1] < es[0]
+
+
+@pytest.mark.parametrize("layout,d", [(O.ROTATED, 5), (O.ROTATED, 9), (O.PLANAR, 5), (O.PLANAR, 7)])
+def test_invariants_every_sweep(layout, d):
+    """After every sweep: syndrome unchanged, incremental energy equal to the
+    recomputed energy (Eq. (10)), coset unchanged, E_min <= E (oracle's check
+    mode returns an error code on any violation)."""
+    L = O.Lattice(layout, d)
+    w, _ = O.weights(0.2, O.noise(0.2, 10.0))
+    rng = np.random.default_rng(4)
+    beta = O.schedule(O.SCHED_GEOMETRIC, 0.05, 10.0, 40)
+    for c in range(6):
+        init = rng.integers(0, 4, L.nq).astype(np.uint8)
+        r = L.anneal_chain(w, beta, 17, 8, c, init, check=True)
+        assert L.energy(w, r["snap"]) == r["emin"] <= r["e"]
+        assert np.array_equal(L.syndrome(r["snap"]), L.syndrome(init))
+        assert L.cls(r["snap"], init) == 0 and L.cls(r["final"], init) == 0
+
+
+def test_boltzmann_law_fixed_beta():
+    """Eq. (22): each Metropolis move satisfies detailed balance for
+    pi_beta = exp(-beta H), so the class-by-class sweep leaves pi_beta
+    stationary.  Final states of many independent chains at a fixed beta are
+    compared with the exact law over the 256-element coset (d = 3)."""
+    L = O.Lattice(O.ROTATED, 3)
+    G = _gf2.generator_matrix(L.fq, L.fm, L.nq)
+    w, _ = O.weights(0.15, O.noise(0.15, 10.0))
+    rng = np.random.default_rng(6)
+    init = rng.integers(0, 4, L.nq).astype(np.uint8)
+    elems = _gf2.group_elements(G) ^ _gf2.pack(init)
+    index = {int(v): i for i, v in enumerate(elems)}
+    energies = _gf2.packed_energy(elems, w).astype(np.float64)
+    beta = 0.35
+    n_chains, n_sweeps = 12000, 25
+    counts = np.zeros(len(elems))
+    bs = np.full(n_sweeps, beta)
+    for c in range(n_chains):
+        r = L.anneal_chain(w, bs, 2024, 77, c, init, want_snap=False)
+        counts[index[int(_gf2.pack(r["final"]))]] += 1
+
+    def chi2_p(b):
+        pr = np.exp(-b * (energies - energies.min()) / 65536.0)
+        pr /= pr.sum()
+        exp = pr * n_chains
+        keep = exp >= 5
+        obs = np.append(counts[keep], counts[~keep].sum())
+        ex = np.append(exp[keep], exp[~keep].sum())
+        if ex[-1] == 0:
+            obs, ex = obs[:-1], ex[:-1]
+        return stats.chisquare(obs, ex).pvalue
+
+    assert chi2_p(beta) > 1e-3
+    # negative control: a beta off by 30 percent is rejected decisively
+    assert chi2_p(1.3 * beta) < 1e-6
+
+
+def _exact_coset_minima(L, w, ref):
+    G = _gf2.generator_matrix(L.fq, L.fm, L.nq)
+    group = _gf2.group_elements(G)
+    return _gf2.coset_minima(group, [ref ^ L.logical(P) for P in range(4)], w)
+
+
+@pytest.mark.parametrize("layout,d,n_syn", [(O.ROTATED, 3, 120), (O.PLANAR, 3, 40), (O.ROTATED, 5, 3)])
+def test_decoder_against_brute_force(layout, d, n_syn):
+    """Eqs. (18)-(21): E_P estimates the exact coset minimum from above; the
+    decoder's recovery is syndrome-consistent, has energy E_best and lies in
+    coset P* (relative to R_0); with a slow schedule E_best is the exact
+    minimum in nearly every sample."""
+    L = O.Lattice(layout, d)
+    p, eta = 0.15, 10.0
+    w, wg = O.weights(p, O.noise(p, eta))
+    beta = O.schedule(O.SCHED_LINEAR, 0.1, 5.0, 200)
+    rng = np.random.default_rng(10 + d)
+    hits = 0
+    for uid in range(n_syn):
+        _, syn = random_problem(L, p, eta, rng)
+        out = L.decode(w, wg, syn, uid, 2, beta, 5, 6)
+        r0 = out["refs"][0]
+        exact = _exact_coset_minima(L, w, r0)
+        for P in range(4):
+            assert out["e_cls"][P] >= exact[P]
+        assert out["e_best"] == min(out["e_cls"]) >= min(exact)
+        assert out["cls"] == int(np.argmin(out["e_cls"]))
+        rec = out["recovery"]
+        assert np.array_equal(L.syndrome(rec), syn)
+        assert L.energy(w, rec) == out["e_best"]
+        assert L.cls(rec, r0) == out["cls"]
+        assert L.cls(out["paper_recovery"], r0) == out["cls"]
+        hits += out["e_best"] == min(exact)
+    assert hits >= 0.95 * n_syn
+
+
+def test_coset_relabelling():
+    """Eqs. (35)-(36): Q_r = [R_r R_0] and chain (r, P) estimates coset Q_r P;
+    checked with an independent symplectic computation of the class."""
+    L = O.Lattice(O.ROTATED, 7)
+    p, eta = 0.2, 10.0
+    w, wg = O.weights(p, O.noise(p, eta))
+    rng = np.random.default_rng(8)
+    _, syn = random_problem(L, p, eta, rng)
+    out = L.decode(w, wg, syn, 3, 8, O.schedule(O.SCHED_GEOMETRIC, 0.05, 10.0, 20), 1, 2, chains=True)
+    refs = out["refs"]
+    logs = np.stack([L.lx, L.lz])
+    for r in range(8):
+        e = refs[r] ^ refs[0]
+        a, b = _gf2.symp_products(e[None], logs)[0]  # vs L_X, vs L_Z
+        expect = {(0, 0): 0, (0, 1): 1, (1, 1): 2, (1, 0): 3}[(int(a), int(b))]
+        assert out["qcls"][r] == expect
+        for P in range(4):
+            fin = out["chain_final"][4 * r + P]
+            assert np.array_equal(L.syndrome(fin), syn)
+            assert L.cls(fin, refs[0]) == O.lib().or_class_mul(expect, P)
