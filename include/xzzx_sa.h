@@ -1,0 +1,229 @@
+/*
+ * xzzx_sa.h -- C ABI of the MI355X (gfx950) simulated-annealing decoder for the
+ * XZZX surface code under Y-biased code-capacity noise (arXiv:2509.17837).
+ *
+ * The decoder follows Alg. 7 of the paper: randomized greedy matching
+ * (Alg. 6) gives one reference configuration R_r per replica r; every replica
+ * runs four annealing chains, one per logical coset (Alg. 2, Metropolis moves
+ * of Alg. 3 that multiply by one stabilizer generator); the minimum energy per
+ * coset (Eqs. (18)-(21)) selects the logical class P*, and the minimum-energy
+ * configuration found is returned as the recovery.
+ *
+ * Conventions
+ *   Pauli codes (footnote to Eq. (10)): upper bit X, lower bit Z:
+ *     I=0, Z=1, X=2, Y=3; one uint8_t per qubit.  Products are XOR.
+ *   Logical class indices: I=0, X=1, Y=2, Z=3 (loop order of Alg. 1),
+ *     always relative to the replica-0 reference R_0 (the paper's R_1).
+ *   Energies: int32 sums of integer weights W[code] = round(2^16 * -ln(p_P/(1-p)))
+ *     (Eqs. (8)-(12)); 2^16 units = 1 nat, so beta = 1 is the Nishimori point.
+ *   Chains: chain c = 4r + P' of a syndrome starts at R_r * L_P' (Eq. (36)).
+ *   Random numbers: Philox4x32-10.  Greedy tie key of pair id k of colour g in
+ *     replica r of syndrome uid: word 0 of Philox(greedy_seed; uid, r,
+ *     0x100+g, k).  Metropolis draw of generator rank m in colour class kc in
+ *     sweep t of chain c: word (m mod 4) of Philox(anneal_seed; uid, c,
+ *     4t+kc, m div 4).
+ *   Acceptance (Alg. 3): dE <= 0, or u < ceil(2^32 exp(-beta[t] dE 2^-16))
+ *     with that threshold clamped to 2^32-1.
+ *   E_min (Alg. 2) is taken after each colour class of each sweep; "stop"
+ *     4t+kc+1 names the first phase attaining it (0 = initial configuration).
+ *
+ * Memory and ownership
+ *   Pointers named d_* are device pointers (HIP device memory of the current
+ *   device); every other pointer is host memory.  The caller allocates and
+ *   owns every data buffer and the workspace; the library never frees them.
+ *   Handles (lattice, plan, graph, server) are created and destroyed only
+ *   through this API.  Host inputs are copied before the call returns.
+ *   Device work is enqueued on the given hipStream_t (passed as void*, NULL =
+ *   the null stream); outputs are valid once that stream has completed.
+ *
+ * Errors
+ *   Every int-returning call returns XZZX_OK (0) or a negative status; on
+ *   failure outputs are undefined and xzzx_last_error() returns a message
+ *   (thread-local).  No C++ exception crosses this interface.
+ *
+ * Thread safety
+ *   Calls on distinct handles may run concurrently.  A plan may be used by
+ *   several concurrent decode calls on different streams.  Server submit/poll
+ *   are thread-safe; other calls on one handle need external synchronisation.
+ */
+#ifndef XZZX_SA_H
+#define XZZX_SA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    XZZX_OK = 0,
+    XZZX_EINVAL = -1,   /* bad argument */
+    XZZX_ENOMEM = -2,   /* allocation failed or workspace too small */
+    XZZX_EDEVICE = -3,  /* HIP runtime error */
+    XZZX_ERANGE = -4,   /* energies or tables would overflow their integer types */
+    XZZX_EAGAIN = -5,   /* server over budget; retry later */
+    XZZX_ENOTREADY = -6 /* result not yet available */
+};
+
+enum { XZZX_ROTATED = 0, XZZX_PLANAR = 1 };
+enum { XZZX_BIAS_BASELINE = 0, XZZX_BIAS_PAPER = 1 };
+enum { XZZX_SCHED_LINEAR = 0, XZZX_SCHED_GEOMETRIC = 1, XZZX_SCHED_PAPER_LOG = 2 };
+enum { XZZX_GREEDY_RANDOM = 0, XZZX_GREEDY_SAME = 1, XZZX_GREEDY_BOUNDARY = 2 };
+
+/* decode flags */
+enum {
+    XZZX_FLAG_PLAIN = 1 /* one anneal launch per syndrome, no persistent queue */
+};
+
+typedef struct xzzx_lattice xzzx_lattice;
+typedef struct xzzx_plan xzzx_plan;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *xzzx_last_error(void);
+
+/* ABI version, currently 1. */
+int xzzx_version(void);
+
+/* ---- code model (Sec. II) ------------------------------------------------ */
+
+/* Lattice of odd distance 3 <= d <= 31.
+ *   XZZX_ROTATED: d^2 qubits, d^2-1 generators; qubit (x,y) has index y*d+x;
+ *     cell (i,j), -1 <= i,j <= d-1, holds X(i,j) Z(i+1,j) Z(i,j+1) X(i+1,j+1)
+ *     (Eq. (1)); every bulk cell is a generator, boundary cells alternate
+ *     (bottom j=-1: i odd; top j=d-1: i even; left i=-1: j even;
+ *     right i=d-1: j odd).  Generators are numbered row-major over (j,i).
+ *   XZZX_PLANAR: the paper's lattice, d^2+(d-1)^2 qubits, 2d(d-1) generators
+ *     (Sec. II, Sec. IV.B.1), generators numbered row-major in doubled
+ *     coordinates.
+ * Returns EINVAL for an unknown layout or an even/out-of-range d. */
+int xzzx_lattice_create(int layout, int d, xzzx_lattice **out);
+void xzzx_lattice_destroy(xzzx_lattice *lat);
+
+/* Sizes: qubits, generators, generators per colour class (= n_stabs/4). */
+int xzzx_lattice_info(const xzzx_lattice *lat, int *n_qubits, int *n_stabs, int *per_class);
+
+/* Generator tables (host arrays, any may be NULL): face_qubits[n_stabs][4]
+ * qubit on the X_left, Z_up, Z_down, X_right slots or -1; face_paulis
+ * [n_stabs][4] their codes (2, 1, 1, 2; 0 if absent); face_class (0..3,
+ * generators of one class share no qubit); face_colour (decoding-graph colour,
+ * Sec. III); face_rank (rank inside the class). */
+int xzzx_lattice_tables(const xzzx_lattice *lat, int32_t *face_qubits, uint8_t *face_paulis,
+                        int32_t *face_class, int32_t *face_colour, int32_t *face_rank);
+
+/* Logical representatives L_X (top-bottom) and L_Z (left-right), [n_qubits]. */
+int xzzx_lattice_logicals(const xzzx_lattice *lat, uint8_t *lx, uint8_t *lz);
+
+/* ---- noise, weights, schedules (Eqs. (5)-(12), (23)-(24)) ----------------- */
+
+/* convention XZZX_BIAS_BASELINE: p_Y = p eta/(eta+1), p_X = p_Z = p/(2(eta+1));
+ * XZZX_BIAS_PAPER: p_x:p_y:p_z = 1:eta:1 (Sec. V.A).  pxyz = (p_X, p_Y, p_Z).
+ * EINVAL unless 0 < p < 1/2 and eta > 0. */
+int xzzx_noise(double p, double eta, int convention, double pxyz[3]);
+
+/* w[4] by code (I,Z,X,Y) = llround(2^16 * -ln(p_P/(1-p))), w[0] = 0;
+ * wg[2] = greedy edge weights for X and Z components,
+ * llround(2^16 * -ln((p_X+p_Y)/(1-p))) and likewise with p_Z+p_Y (Eq. (27)). */
+int xzzx_weights(double p, const double pxyz[3], int32_t w[4], int32_t wg[2]);
+
+/* beta[n] in nats: LINEAR b0..b1 and GEOMETRIC b0..b1 include both ends;
+ * PAPER_LOG is Eqs. (23)-(24): b0 (1 + gamma ln i), i = 1..n,
+ * gamma = (b1/b0 - 1)/ln n (0 for n < 2). */
+int xzzx_schedule(int kind, double b0, double b1, int n, double *beta);
+
+/* Logical class (0..3) of a*b for host configurations with equal syndromes,
+ * via commutation with L_X and L_Z (Alg. 7); *cls = -1 if the syndromes
+ * differ. */
+int xzzx_class_host(const xzzx_lattice *lat, const uint8_t *a, const uint8_t *b, int *cls);
+
+/* ---- plans ---------------------------------------------------------------- */
+
+/* A plan holds, on the current device, everything the kernels need for one
+ * (lattice, w, wg, beta schedule): generator descriptors, the dE lookup, the
+ * acceptance-threshold table [n_sweeps][distinct dE], logicals and the
+ * greedy-matching distance tables (Eqs. (25)-(30)).  beta is copied.
+ * ERANGE if n_qubits * max(w) >= 2^31.  n_sweeps may be 0. */
+int xzzx_plan_create(const xzzx_lattice *lat, const int32_t w[4], const int32_t wg[2],
+                     const double *beta, int n_sweeps, xzzx_plan **out);
+void xzzx_plan_destroy(xzzx_plan *plan);
+
+/* Plan facts: number of distinct move energies, lanes per chain in use. */
+int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sweeps,
+                   int *n_dE, int *lanes_per_chain);
+
+/* Result-invariant tuning knob: lanes of a wavefront cooperating on one chain
+ * (1, 2, 4, ..., 64); chains per wavefront = 64 / lanes.  0 restores the
+ * built-in choice. */
+int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain);
+
+/* ---- device operations ---------------------------------------------------- */
+
+/* Syndrome (Eq. (2)) of n configurations d_cfg[n][n_qubits] -> d_syn[n][n_stabs]. */
+int xzzx_syndrome(const xzzx_plan *plan, const uint8_t *d_cfg, int64_t n, uint8_t *d_syn,
+                  void *stream);
+
+/* Greedy-matching references (Algs. 5-6): d_refs[n_syn][n_rep][n_qubits]
+ * and their classes relative to replica 0, d_qcls[n_syn][n_rep].
+ * mode: XZZX_GREEDY_RANDOM (Alg. 6), XZZX_GREEDY_SAME (Alg. 5),
+ * XZZX_GREEDY_BOUNDARY (each defect to its nearest boundary). */
+int xzzx_greedy_init(const xzzx_plan *plan, const uint8_t *d_syn, const uint32_t *d_uid,
+                     int64_t n_syn, int n_rep, uint64_t greedy_seed, int mode, uint8_t *d_refs,
+                     uint8_t *d_qcls, void *stream);
+
+/* One group of syndromes sharing a plan.  Inputs: d_uid, and either d_syn
+ * (decode) or d_refs + d_qcls (anneal only).  Required outputs: d_e_best,
+ * d_cls, d_recovery.  Optional outputs (NULL to skip) hold per-coset minima,
+ * the paper's output form R_0 L_P*, the best chain and per-chain results
+ * (chain c of syndrome s at index s*4*n_rep + c). */
+typedef struct {
+    const xzzx_plan *plan;
+    int64_t n_syn;
+    int n_rep;
+    const uint32_t *d_uid;       /* [n_syn] syndrome ids (RNG counters) */
+    const uint8_t *d_syn;        /* [n_syn][n_stabs] */
+    uint8_t *d_refs;             /* [n_syn][n_rep][n_qubits]; decode writes it if non-NULL */
+    uint8_t *d_qcls;             /* [n_syn][n_rep]; decode writes it if non-NULL */
+    int32_t *d_e_best;           /* [n_syn] min over cosets of E_P */
+    uint8_t *d_cls;              /* [n_syn] P* */
+    uint8_t *d_recovery;         /* [n_syn][n_qubits] minimum-energy configuration */
+    uint8_t *d_paper_recovery;   /* [n_syn][n_qubits] R_0 L_P* (optional) */
+    int32_t *d_e_cls;            /* [n_syn][4] E_P (optional) */
+    int32_t *d_best_chain;       /* [n_syn] (optional) */
+    int32_t *d_chain_emin;       /* [n_syn][4 n_rep] (optional) */
+    int32_t *d_chain_stop;       /* [n_syn][4 n_rep] (optional) */
+    int32_t *d_chain_e;          /* [n_syn][4 n_rep] final energies (optional) */
+    uint8_t *d_chain_final;      /* [n_syn][4 n_rep][n_qubits] final states (optional) */
+} xzzx_group;
+
+/* Device workspace needed by xzzx_decode / xzzx_anneal for these groups. */
+int xzzx_decode_workspace(const xzzx_group *groups, int n_groups, size_t *bytes);
+
+/* Full decoder (Alg. 7) for every group: greedy init, annealing of all
+ * chains of all groups in one persistent launch (uneven distances allowed),
+ * per-syndrome reduction and recovery.  d_workspace: caller-owned device
+ * memory of at least xzzx_decode_workspace() bytes.  ENOMEM if smaller. */
+int xzzx_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_seed,
+                uint64_t anneal_seed, int greedy_mode, int flags, void *d_workspace,
+                size_t workspace_bytes, void *stream);
+
+/* As xzzx_decode, from caller-supplied references d_refs / d_qcls (no greedy). */
+int xzzx_anneal(const xzzx_group *groups, int n_groups, uint64_t anneal_seed, int flags,
+                void *d_workspace, size_t workspace_bytes, void *stream);
+
+/* ---- captured decode (hipGraph) -------------------------------------------- */
+
+typedef struct xzzx_graph xzzx_graph;
+
+/* Capture one xzzx_decode call (same arguments) into an executable HIP graph;
+ * replaying it re-runs the decode on whatever the captured buffers hold. */
+int xzzx_graph_create(const xzzx_group *groups, int n_groups, uint64_t greedy_seed,
+                      uint64_t anneal_seed, int greedy_mode, int flags, void *d_workspace,
+                      size_t workspace_bytes, void *stream, xzzx_graph **out);
+int xzzx_graph_launch(xzzx_graph *graph, void *stream);
+void xzzx_graph_destroy(xzzx_graph *graph);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XZZX_SA_H */

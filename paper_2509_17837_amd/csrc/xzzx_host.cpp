@@ -1,0 +1,659 @@
+// Host side of the XZZX SA decoder library: lattice geometry, noise model,
+// energy weights, beta schedules, integer acceptance thresholds and the
+// per-plan tables uploaded to the GPU (generator descriptors, move-energy
+// lookup, threshold table, greedy-matching distance tables).
+//
+// Everything here runs once per plan (a lattice, a set of weights and a beta
+// schedule); the per-syndrome work runs in xzzx_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <queue>
+#include <tuple>
+
+#include "xzzx_internal.h"
+
+namespace xzzx {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------
+// Lattices (Sec. II).  Slot order of every generator: X_left, Z_up, Z_down,
+// X_right with Pauli codes 2, 1, 1, 2 (Eq. (1)).
+// ---------------------------------------------------------------------------
+static const uint8_t kSlotPauli[4] = {2, 1, 1, 2};
+
+namespace {
+struct FaceRec {
+    int sort_a, sort_b;   // row-major key (row, column)
+    int q[4];
+    int cls, colour;
+    int cx, cy;
+};
+}  // namespace
+
+static void finish_lattice(Lattice &L, std::vector<FaceRec> &faces)
+{
+    std::sort(faces.begin(), faces.end(), [](const FaceRec &a, const FaceRec &b) {
+        return std::tie(a.sort_a, a.sort_b) < std::tie(b.sort_a, b.sort_b);
+    });
+    L.nstab = (int)faces.size();
+    L.per_class = L.nstab / 4;
+    L.fq.assign(4 * L.nstab, -1);
+    L.fm.assign(4 * L.nstab, 0);
+    L.fclass.resize(L.nstab);
+    L.fcolour.resize(L.nstab);
+    L.frank.resize(L.nstab);
+    L.by_class.assign(4 * L.per_class, -1);
+    int seen[4] = {0, 0, 0, 0};
+    for (int f = 0; f < L.nstab; ++f) {
+        for (int s = 0; s < 4; ++s) {
+            L.fq[4 * f + s] = faces[f].q[s];
+            L.fm[4 * f + s] = faces[f].q[s] >= 0 ? kSlotPauli[s] : 0;
+        }
+        L.fclass[f] = faces[f].cls;
+        L.fcolour[f] = faces[f].colour;
+        int r = seen[faces[f].cls]++;
+        L.frank[f] = r;
+        if (r < L.per_class) L.by_class[faces[f].cls * L.per_class + r] = f;
+    }
+}
+
+int build_lattice(int layout, int d, Lattice &L)
+{
+    if (d < 3 || d > kMaxD || (d % 2) == 0) {
+        set_error("lattice distance must be odd and in [3, 31]");
+        return XZZX_EINVAL;
+    }
+    L = Lattice();
+    L.layout = layout;
+    L.d = d;
+    std::vector<FaceRec> faces;
+    if (layout == XZZX_ROTATED) {
+        L.nq = d * d;
+        auto qubit = [d](int x, int y) { return (x < 0 || y < 0 || x >= d || y >= d) ? -1 : y * d + x; };
+        for (int j = -1; j < d; ++j) {
+            for (int i = -1; i < d; ++i) {
+                const bool col_in = (i >= 0 && i <= d - 2), row_in = (j >= 0 && j <= d - 2);
+                bool gen;
+                if (col_in && row_in) gen = true;                        // bulk
+                else if (col_in && j == -1) gen = (i % 2) == 1;          // bottom edge
+                else if (col_in && j == d - 1) gen = (i % 2) == 0;       // top edge
+                else if (row_in && i == -1) gen = (j % 2) == 0;          // left edge
+                else if (row_in && i == d - 1) gen = (j % 2) == 1;       // right edge
+                else gen = false;                                        // corners
+                if (!gen) continue;
+                FaceRec r{};
+                r.sort_a = j;
+                r.sort_b = i;
+                r.q[0] = qubit(i, j);
+                r.q[1] = qubit(i + 1, j);
+                r.q[2] = qubit(i, j + 1);
+                r.q[3] = qubit(i + 1, j + 1);
+                r.cls = ((i + 1) & 1) | (((j + 1) & 1) << 1);
+                r.colour = ((i + j) % 2 + 2) % 2;
+                r.cx = i;
+                r.cy = j;
+                faces.push_back(r);
+            }
+        }
+        finish_lattice(L, faces);
+        L.lx.assign(L.nq, 0);
+        L.lz.assign(L.nq, 0);
+        for (int t = 0; t < d; ++t) {
+            L.lz[qubit(t, 0)] = (t % 2 == 0) ? 1 : 2;   // row y = 0, left to right
+            L.lx[qubit(0, t)] = (t % 2 == 0) ? 2 : 1;   // column x = 0, bottom to top
+        }
+    } else if (layout == XZZX_PLANAR) {
+        // Doubled coordinates; (odd, even) qubits first, then (even, odd).
+        L.nq = d * d + (d - 1) * (d - 1);
+        auto qubit = [d](int x, int y) -> int {
+            if ((x & 1) && !(y & 1) && x >= 3 && x <= 2 * d - 1 && y >= 2 && y <= 2 * d - 2)
+                return (y / 2 - 1) * (d - 1) + (x - 3) / 2;
+            if (!(x & 1) && (y & 1) && x >= 2 && x <= 2 * d && y >= 1 && y <= 2 * d - 1)
+                return (d - 1) * (d - 1) + (y / 2) * d + (x / 2 - 1);
+            return -1;
+        };
+        auto add = [&](int x, int y, int colour) {
+            FaceRec r{};
+            r.sort_a = y;
+            r.sort_b = x;
+            r.q[0] = qubit(x - 1, y);
+            r.q[1] = qubit(x, y + 1);
+            r.q[2] = qubit(x, y - 1);
+            r.q[3] = qubit(x + 1, y);
+            auto fl = [](int a) { return (a >= 0) ? a / 2 : -((1 - a) / 2); };
+            r.cls = (fl(x + y) & 1) | ((fl(x - y) & 1) << 1);
+            r.colour = colour;
+            r.cx = x;
+            r.cy = y;
+            faces.push_back(r);
+        };
+        for (int i = 1; i <= d; ++i)           // white faces (i, j) at (2i, 2j)
+            for (int j = 1; j <= d - 1; ++j) add(2 * i, 2 * j, 0);
+        for (int i = 1; i <= d - 1; ++i)       // gray faces (i, j) at (2i+1, 2j-1)
+            for (int j = 1; j <= d; ++j) add(2 * i + 1, 2 * j - 1, 1);
+        finish_lattice(L, faces);
+        L.lx.assign(L.nq, 0);
+        L.lz.assign(L.nq, 0);
+        for (int t = 1; t <= d; ++t) {
+            L.lz[qubit(2 * t, 1)] = 1;       // bottom row of (even, odd) qubits
+            L.lx[qubit(2, 2 * t - 1)] = 2;   // left column of (even, odd) qubits
+        }
+    } else {
+        set_error("unknown lattice layout");
+        return XZZX_EINVAL;
+    }
+    for (int k = 0; k < 4; ++k)
+        for (int m = 0; m < L.per_class; ++m)
+            if (L.by_class[k * L.per_class + m] < 0) {
+                set_error("colour classes are not of equal size");
+                return XZZX_EINVAL;
+            }
+    return XZZX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Acceptance threshold of Alg. 3 on a uint32 draw u (r = u / 2^32): a move
+// with dE > 0 (units of 2^-16 nats) is accepted iff
+// u < ceil(2^32 exp(-beta dE 2^-16)), threshold clamped to 2^32-1.
+// ---------------------------------------------------------------------------
+uint32_t accept_threshold(double beta, int64_t dE)
+{
+    if (dE <= 0) return 0xFFFFFFFFu;
+    const double prob = std::exp(-(beta * static_cast<double>(dE)) * 0x1p-16);
+    const double t = std::ceil(std::ldexp(prob, 32));
+    return t >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(t);
+}
+
+// ---------------------------------------------------------------------------
+// Plan tables.
+// ---------------------------------------------------------------------------
+size_t Plan::lds_bytes_anneal(int lanes_per_chain) const
+{
+    const int C = kWave / lanes_per_chain;
+    size_t off = 0;
+    off += sizeof(Desc) * 4 * lat.per_class;         // descriptors
+    off += 256 * (size_t)ntypes;                     // move-energy ranks
+    off = (off + 7) & ~size_t(7);
+    off += 8 * dE.size();                            // (dE, threshold) pairs
+    off = (off + 15) & ~size_t(15);
+    off += (size_t)(lat.nq + 1) * C;                 // states, one scratch byte per chain
+    return (off + 15) & ~size_t(15);
+}
+
+static int default_lanes(const Lattice &L)
+{
+    // Largest number of chains per wavefront whose interleaved states fit in
+    // 16 KiB of LDS; the remaining lanes split the generators of one class.
+    int C = kWave;
+    while (C > 1 && (size_t)(L.nq + 1) * C > 16384) C /= 2;
+    return kWave / C;
+}
+
+namespace {
+struct Graph {
+    int n = 0;
+    std::vector<int32_t> col_face;           // node -> face
+    std::vector<std::array<int32_t, 3>> adj;  // [n][4] (eid, other, w), eid -1 = none
+    std::vector<int32_t> dint, db;
+};
+}  // namespace
+
+static int build_graphs(const Lattice &L, const int32_t wg[2], Graph G[2])
+{
+    std::vector<int> node(L.nstab, -1);
+    for (int g = 0; g < 2; ++g) {
+        G[g] = Graph();
+        for (int f = 0; f < L.nstab; ++f)
+            if (L.fcolour[f] == g) { node[f] = G[g].n++; G[g].col_face.push_back(f); }
+        G[g].adj.assign(4 * G[g].n, {-1, -1, 0});
+    }
+    // A slot with Pauli m on qubit q is flipped by the component of q that
+    // anticommutes with m: the Z component (code 1) for m = X, the X component
+    // (code 2) for m = Z.  Collect, per (qubit, component), the faces it flips.
+    std::map<int, std::vector<int>> flips;  // edge id -> faces
+    for (int f = 0; f < L.nstab; ++f)
+        for (int s = 0; s < 4; ++s) {
+            const int q = L.fq[4 * f + s];
+            if (q < 0) continue;
+            const int comp_is_x = (L.fm[4 * f + s] == 1) ? 1 : 0;
+            flips[2 * q + comp_is_x].push_back(f);
+        }
+    for (auto &kv : flips) {
+        const int eid = kv.first;
+        const auto &fs = kv.second;
+        if (fs.size() > 2 || L.fcolour[fs[0]] != L.fcolour[fs.back()]) {
+            set_error("decoding graph is not a graph");
+            return XZZX_EINVAL;
+        }
+        const int g = L.fcolour[fs[0]];
+        const int32_t w = (eid & 1) ? wg[0] : wg[1];
+        for (size_t h = 0; h < fs.size(); ++h) {
+            const int u = node[fs[h]];
+            const int other = fs.size() == 2 ? node[fs[1 - h]] : -1;
+            int slot = 0;
+            while (slot < 4 && G[g].adj[4 * u + slot][0] >= 0) ++slot;
+            if (slot == 4) { set_error("node degree above 4"); return XZZX_EINVAL; }
+            G[g].adj[4 * u + slot] = {eid, other, w};   // edge ids arrive in ascending order
+        }
+    }
+    for (int g = 0; g < 2; ++g) {
+        const int n = G[g].n;
+        G[g].dint.assign((size_t)n * n, INT32_MAX);
+        G[g].db.assign(n, INT32_MAX);
+        using QE = std::pair<int64_t, int>;
+        auto dijkstra = [&](std::vector<int64_t> &dist, std::priority_queue<QE, std::vector<QE>, std::greater<QE>> &pq) {
+            while (!pq.empty()) {
+                auto [dv, v] = pq.top();
+                pq.pop();
+                if (dv != dist[v]) continue;
+                for (int s = 0; s < 4; ++s) {
+                    const auto &e = G[g].adj[4 * v + s];
+                    if (e[0] < 0 || e[1] < 0) continue;
+                    const int64_t nd = dv + e[2];
+                    if (nd < dist[e[1]]) { dist[e[1]] = nd; pq.push({nd, e[1]}); }
+                }
+            }
+        };
+        std::vector<int64_t> dist(n);
+        for (int src = 0; src < n; ++src) {
+            std::fill(dist.begin(), dist.end(), INT64_MAX);
+            std::priority_queue<QE, std::vector<QE>, std::greater<QE>> pq;
+            dist[src] = 0;
+            pq.push({0, src});
+            dijkstra(dist, pq);
+            for (int v = 0; v < n; ++v) {
+                if (dist[v] >= INT32_MAX) { set_error("decoding graph disconnected or too heavy"); return XZZX_ERANGE; }
+                G[g].dint[(size_t)src * n + v] = (int32_t)dist[v];
+            }
+        }
+        // distance to the boundary: shortest path to a virtual node joined by
+        // every half-edge
+        std::fill(dist.begin(), dist.end(), INT64_MAX);
+        std::priority_queue<QE, std::vector<QE>, std::greater<QE>> pq;
+        for (int v = 0; v < n; ++v)
+            for (int s = 0; s < 4; ++s) {
+                const auto &e = G[g].adj[4 * v + s];
+                if (e[0] >= 0 && e[1] < 0 && e[2] < dist[v]) { dist[v] = e[2]; pq.push({e[2], v}); }
+            }
+        dijkstra(dist, pq);
+        for (int v = 0; v < n; ++v) {
+            if (dist[v] >= INT32_MAX) { set_error("no boundary reachable"); return XZZX_ERANGE; }
+            G[g].db[v] = (int32_t)dist[v];
+        }
+    }
+    return XZZX_OK;
+}
+
+static inline Desc pack_desc(const Lattice &L, int f, int shape)
+{
+    uint32_t q[4];
+    for (int s = 0; s < 4; ++s) q[s] = L.fq[4 * f + s] >= 0 ? (uint32_t)L.fq[4 * f + s] : (uint32_t)L.nq;
+    Desc d;
+    d.x = q[0] | (q[1] << 16);
+    d.y = q[2] | (q[3] << 16) | ((uint32_t)shape << 27);
+    return d;
+}
+
+int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const double *beta,
+               int n_sweeps, Plan &P)
+{
+    if (n_sweeps < 0 || (n_sweeps > 0 && !beta)) { set_error("bad schedule"); return XZZX_EINVAL; }
+    if (w[0] != 0 || w[1] <= 0 || w[2] <= 0 || w[3] <= 0 || wg[0] <= 0 || wg[1] <= 0) {
+        set_error("weights must be positive (w[0] = 0)");
+        return XZZX_EINVAL;
+    }
+    const int32_t wmax = std::max(w[1], std::max(w[2], w[3]));
+    if ((int64_t)L.nq * wmax >= (int64_t)1 << 31) { set_error("energy would overflow int32"); return XZZX_ERANGE; }
+    if (L.nq + 1 >= 2048) { set_error("lattice too large for 11-bit qubit indices"); return XZZX_ERANGE; }
+    P.lat = L;
+    std::memcpy(P.W, w, sizeof(P.W));
+    std::memcpy(P.Wg, wg, sizeof(P.Wg));
+    P.n_sweeps = n_sweeps;
+    P.beta.assign(beta, beta + n_sweeps);
+    for (double b : P.beta)
+        if (!(b >= 0.0) || !std::isfinite(b)) { set_error("beta must be finite and >= 0"); return XZZX_EINVAL; }
+
+    // shapes = which of the four slots exist
+    std::vector<int> shape_of_face(L.nstab), shapes;
+    for (int f = 0; f < L.nstab; ++f) {
+        int mask = 0;
+        for (int s = 0; s < 4; ++s) if (L.fq[4 * f + s] >= 0) mask |= 1 << s;
+        auto it = std::find(shapes.begin(), shapes.end(), mask);
+        if (it == shapes.end()) { shapes.push_back(mask); it = shapes.end() - 1; }
+        shape_of_face[f] = (int)(it - shapes.begin());
+    }
+    P.ntypes = (int)shapes.size();
+    // move energy of every (shape, slot pattern); absent slots contribute 0,
+    // whatever their (scratch) byte holds
+    std::vector<int32_t> lut_de(256 * P.ntypes);
+    std::vector<int32_t> all;
+    for (int t = 0; t < P.ntypes; ++t)
+        for (int pat = 0; pat < 256; ++pat) {
+            int32_t de = 0;
+            for (int s = 0; s < 4; ++s) {
+                if (!(shapes[t] >> s & 1)) continue;
+                const int c = (pat >> (2 * s)) & 3;
+                de += w[c ^ kSlotPauli[s]] - w[c];
+            }
+            lut_de[256 * t + pat] = de;
+            all.push_back(de);
+        }
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    if ((int)all.size() > kMaxRanks) { set_error("too many distinct move energies"); return XZZX_ERANGE; }
+    P.dE = all;
+    P.kneg = (int)(std::upper_bound(all.begin(), all.end(), 0) - all.begin());
+    std::vector<uint8_t> lut(256 * P.ntypes);
+    for (size_t i = 0; i < lut.size(); ++i)
+        lut[i] = (uint8_t)(std::lower_bound(all.begin(), all.end(), lut_de[i]) - all.begin());
+    const int nranks = (int)all.size();
+    std::vector<uint32_t> thr((size_t)std::max(n_sweeps, 1) * nranks, 0xFFFFFFFFu);
+    for (int t = 0; t < n_sweeps; ++t)
+        for (int r = 0; r < nranks; ++r) thr[(size_t)t * nranks + r] = accept_threshold(P.beta[t], all[r]);
+
+    std::vector<Desc> desc(4 * L.per_class), fdesc(L.nstab);
+    for (int f = 0; f < L.nstab; ++f) fdesc[f] = pack_desc(L, f, shape_of_face[f]);
+    for (int k = 0; k < 4; ++k)
+        for (int m = 0; m < L.per_class; ++m) desc[k * L.per_class + m] = fdesc[L.by_class[k * L.per_class + m]];
+
+    Graph G[2];
+    int rc = build_graphs(L, wg, G);
+    if (rc) return rc;
+
+    // one device allocation: [PlanDev][tables...], 256-byte aligned pieces
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~size_t(255); return o; };
+    const size_t o_hdr = take(sizeof(PlanDev));
+    const size_t o_desc = take(desc.size() * sizeof(Desc));
+    const size_t o_fdesc = take(fdesc.size() * sizeof(Desc));
+    const size_t o_lut = take(lut.size());
+    const size_t o_de = take(all.size() * 4);
+    const size_t o_thr = take(thr.size() * 4);
+    const size_t o_lx = take(L.nq);
+    const size_t o_lz = take(L.nq);
+    size_t o_cf[2], o_dint[2], o_db[2], o_adj[2];
+    for (int g = 0; g < 2; ++g) {
+        o_cf[g] = take(G[g].n * 4);
+        o_dint[g] = take((size_t)G[g].n * G[g].n * 4);
+        o_db[g] = take(G[g].n * 4);
+        o_adj[g] = take((size_t)G[g].n * 4 * sizeof(int4));
+    }
+    P.dbytes = off;
+    if (hipGetDevice(&P.device) != hipSuccess) { set_error("hipGetDevice failed"); return XZZX_EDEVICE; }
+    if (hipMalloc(&P.dmem, P.dbytes) != hipSuccess) { P.dmem = nullptr; set_error("hipMalloc of plan tables failed"); return XZZX_ENOMEM; }
+    std::vector<uint8_t> host(P.dbytes, 0);
+    auto put = [&](size_t o, const void *src, size_t n) { if (n) std::memcpy(host.data() + o, src, n); };
+    put(o_desc, desc.data(), desc.size() * sizeof(Desc));
+    put(o_fdesc, fdesc.data(), fdesc.size() * sizeof(Desc));
+    put(o_lut, lut.data(), lut.size());
+    put(o_de, all.data(), all.size() * 4);
+    put(o_thr, thr.data(), thr.size() * 4);
+    put(o_lx, L.lx.data(), L.nq);
+    put(o_lz, L.lz.data(), L.nq);
+    for (int g = 0; g < 2; ++g) {
+        put(o_cf[g], G[g].col_face.data(), G[g].n * 4);
+        put(o_dint[g], G[g].dint.data(), (size_t)G[g].n * G[g].n * 4);
+        put(o_db[g], G[g].db.data(), G[g].n * 4);
+        std::vector<int4> adj(G[g].n * 4);
+        for (size_t i = 0; i < adj.size(); ++i) adj[i] = make_int4(G[g].adj[i][0], G[g].adj[i][1], G[g].adj[i][2], 0);
+        put(o_adj[g], adj.data(), adj.size() * sizeof(int4));
+    }
+    auto *base = static_cast<uint8_t *>(P.dmem);
+    PlanDev &h = P.hdev;
+    h = PlanDev{};
+    h.nq = L.nq;
+    h.nstab = L.nstab;
+    h.M = L.per_class;
+    h.nblk = (L.per_class + 3) / 4;
+    h.ntypes = P.ntypes;
+    h.nranks = nranks;
+    h.kneg = P.kneg;
+    h.n_sweeps = n_sweeps;
+    P.lanes_default = default_lanes(L);
+    P.lanes = P.lanes_default;
+    h.lanes = P.lanes;
+    h.layout = L.layout;
+    h.d = L.d;
+    std::memcpy(h.W, w, sizeof(h.W));
+    h.desc = reinterpret_cast<const Desc *>(base + o_desc);
+    h.face_desc = reinterpret_cast<const Desc *>(base + o_fdesc);
+    h.lut = base + o_lut;
+    h.dE = reinterpret_cast<const int32_t *>(base + o_de);
+    h.thr = reinterpret_cast<const uint32_t *>(base + o_thr);
+    h.lx = base + o_lx;
+    h.lz = base + o_lz;
+    for (int g = 0; g < 2; ++g) {
+        h.ncol[g] = G[g].n;
+        h.col_face[g] = reinterpret_cast<const int32_t *>(base + o_cf[g]);
+        h.dint[g] = reinterpret_cast<const int32_t *>(base + o_dint[g]);
+        h.db[g] = reinterpret_cast<const int32_t *>(base + o_db[g]);
+        h.adj[g] = reinterpret_cast<const int4 *>(base + o_adj[g]);
+    }
+    put(o_hdr, &h, sizeof(PlanDev));
+    P.ddev = reinterpret_cast<PlanDev *>(base + o_hdr);
+    if (hipMemcpy(P.dmem, host.data(), P.dbytes, hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("upload of plan tables failed");
+        return XZZX_EDEVICE;
+    }
+    return XZZX_OK;
+}
+
+}  // namespace xzzx
+
+using namespace xzzx;
+
+// ---------------------------------------------------------------------------
+// C ABI: host-side calls.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *xzzx_last_error(void) { return g_last_error.c_str(); }
+
+int xzzx_version(void) { return 1; }
+
+int xzzx_lattice_create(int layout, int d, xzzx_lattice **out)
+{
+    if (!out) { set_error("out is NULL"); return XZZX_EINVAL; }
+    *out = nullptr;
+    try {
+        auto *h = new xzzx_lattice();
+        int rc = build_lattice(layout, d, h->L);
+        if (rc) { delete h; return rc; }
+        *out = h;
+        return XZZX_OK;
+    } catch (...) {
+        set_error("out of host memory");
+        return XZZX_ENOMEM;
+    }
+}
+
+void xzzx_lattice_destroy(xzzx_lattice *lat) { delete lat; }
+
+int xzzx_lattice_info(const xzzx_lattice *lat, int *n_qubits, int *n_stabs, int *per_class)
+{
+    if (!lat) { set_error("lattice is NULL"); return XZZX_EINVAL; }
+    if (n_qubits) *n_qubits = lat->L.nq;
+    if (n_stabs) *n_stabs = lat->L.nstab;
+    if (per_class) *per_class = lat->L.per_class;
+    return XZZX_OK;
+}
+
+int xzzx_lattice_tables(const xzzx_lattice *lat, int32_t *face_qubits, uint8_t *face_paulis,
+                        int32_t *face_class, int32_t *face_colour, int32_t *face_rank)
+{
+    if (!lat) { set_error("lattice is NULL"); return XZZX_EINVAL; }
+    const Lattice &L = lat->L;
+    if (face_qubits) std::memcpy(face_qubits, L.fq.data(), L.fq.size() * 4);
+    if (face_paulis) std::memcpy(face_paulis, L.fm.data(), L.fm.size());
+    if (face_class) std::memcpy(face_class, L.fclass.data(), L.nstab * 4);
+    if (face_colour) std::memcpy(face_colour, L.fcolour.data(), L.nstab * 4);
+    if (face_rank) std::memcpy(face_rank, L.frank.data(), L.nstab * 4);
+    return XZZX_OK;
+}
+
+int xzzx_lattice_logicals(const xzzx_lattice *lat, uint8_t *lx, uint8_t *lz)
+{
+    if (!lat) { set_error("lattice is NULL"); return XZZX_EINVAL; }
+    if (lx) std::memcpy(lx, lat->L.lx.data(), lat->L.nq);
+    if (lz) std::memcpy(lz, lat->L.lz.data(), lat->L.nq);
+    return XZZX_OK;
+}
+
+int xzzx_noise(double p, double eta, int convention, double pxyz[3])
+{
+    if (!pxyz || !(p > 0.0 && p < 0.5) || !(eta > 0.0) || !std::isfinite(eta)) {
+        set_error("need 0 < p < 1/2 and finite eta > 0");
+        return XZZX_EINVAL;
+    }
+    double px, py;
+    if (convention == XZZX_BIAS_BASELINE) {
+        px = p / (2.0 * (eta + 1.0));
+        py = p * eta / (eta + 1.0);
+    } else if (convention == XZZX_BIAS_PAPER) {
+        px = p / (eta + 2.0);
+        py = p * eta / (eta + 2.0);
+    } else {
+        set_error("unknown bias convention");
+        return XZZX_EINVAL;
+    }
+    pxyz[0] = px;
+    pxyz[1] = py;
+    pxyz[2] = px;
+    return XZZX_OK;
+}
+
+int xzzx_weights(double p, const double pxyz[3], int32_t w[4], int32_t wg[2])
+{
+    if (!pxyz || !w || !wg || !(p > 0.0 && p < 0.5)) { set_error("need 0 < p < 1/2"); return XZZX_EINVAL; }
+    const double keep = 1.0 - p;
+    for (int i = 0; i < 3; ++i)
+        if (!(pxyz[i] > 0.0 && pxyz[i] < keep)) { set_error("need 0 < p_P < 1-p"); return XZZX_EINVAL; }
+    auto q16 = [](double ratio) { return (int32_t)std::llround(65536.0 * -std::log(ratio)); };
+    w[0] = 0;
+    w[1] = q16(pxyz[2] / keep);
+    w[2] = q16(pxyz[0] / keep);
+    w[3] = q16(pxyz[1] / keep);
+    wg[0] = q16((pxyz[0] + pxyz[1]) / keep);
+    wg[1] = q16((pxyz[2] + pxyz[1]) / keep);
+    return XZZX_OK;
+}
+
+int xzzx_schedule(int kind, double b0, double b1, int n, double *beta)
+{
+    if (n < 0 || (n > 0 && !beta) || !(b0 >= 0.0) || !(b1 >= 0.0)) { set_error("bad schedule arguments"); return XZZX_EINVAL; }
+    if ((kind == XZZX_SCHED_GEOMETRIC || kind == XZZX_SCHED_PAPER_LOG) && !(b0 > 0.0)) {
+        set_error("schedule needs b0 > 0");
+        return XZZX_EINVAL;
+    }
+    if (kind != XZZX_SCHED_LINEAR && kind != XZZX_SCHED_GEOMETRIC && kind != XZZX_SCHED_PAPER_LOG) {
+        set_error("unknown schedule kind");
+        return XZZX_EINVAL;
+    }
+    const double gamma = (kind == XZZX_SCHED_PAPER_LOG && n >= 2) ? (b1 / b0 - 1.0) / std::log((double)n) : 0.0;
+    for (int t = 0; t < n; ++t) {
+        const double frac = (n == 1) ? 0.0 : (double)t / (double)(n - 1);
+        switch (kind) {
+        case XZZX_SCHED_LINEAR: beta[t] = (n == 1) ? b0 : b0 + (b1 - b0) * frac; break;
+        case XZZX_SCHED_GEOMETRIC: beta[t] = (n == 1) ? b0 : b0 * std::pow(b1 / b0, frac); break;
+        default: beta[t] = b0 * (1.0 + gamma * std::log((double)(t + 1))); break;
+        }
+    }
+    return XZZX_OK;
+}
+
+int xzzx_class_host(const xzzx_lattice *lat, const uint8_t *a, const uint8_t *b, int *cls)
+{
+    if (!lat || !a || !b || !cls) { set_error("NULL argument"); return XZZX_EINVAL; }
+    const Lattice &L = lat->L;
+    auto anti = [](int p, int q) { return (((p >> 1) & q) ^ (p & (q >> 1))) & 1; };
+    for (int f = 0; f < L.nstab; ++f) {
+        int s = 0;
+        for (int k = 0; k < 4; ++k) {
+            const int q = L.fq[4 * f + k];
+            if (q >= 0) s ^= anti((a[q] ^ b[q]) & 3, L.fm[4 * f + k]);
+        }
+        if (s) { *cls = -1; return XZZX_OK; }
+    }
+    int vz = 0, vx = 0;
+    for (int q = 0; q < L.nq; ++q) {
+        const int e = (a[q] ^ b[q]) & 3;
+        vz ^= anti(e, L.lz[q]);
+        vx ^= anti(e, L.lx[q]);
+    }
+    static const int tab[2][2] = {{0, 3}, {1, 2}};   // [anticommutes with L_Z][with L_X]
+    *cls = tab[vz][vx];
+    return XZZX_OK;
+}
+
+int xzzx_plan_create(const xzzx_lattice *lat, const int32_t w[4], const int32_t wg[2],
+                     const double *beta, int n_sweeps, xzzx_plan **out)
+{
+    if (!lat || !w || !wg || !out) { set_error("NULL argument"); return XZZX_EINVAL; }
+    *out = nullptr;
+    xzzx_plan *h = nullptr;
+    try {
+        h = new xzzx_plan();
+    } catch (...) {
+        set_error("out of host memory");
+        return XZZX_ENOMEM;
+    }
+    int rc = build_plan(lat->L, w, wg, beta, n_sweeps, h->P);
+    if (rc) {
+        if (h->P.dmem) (void)hipFree(h->P.dmem);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return XZZX_OK;
+}
+
+void xzzx_plan_destroy(xzzx_plan *plan)
+{
+    if (!plan) return;
+    if (plan->P.dmem) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(plan->P.device);
+        (void)hipFree(plan->P.dmem);
+        (void)hipSetDevice(cur);
+    }
+    delete plan;
+}
+
+int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sweeps, int *n_dE,
+                   int *lanes_per_chain)
+{
+    if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
+    if (n_qubits) *n_qubits = plan->P.lat.nq;
+    if (n_stabs) *n_stabs = plan->P.lat.nstab;
+    if (n_sweeps) *n_sweeps = plan->P.n_sweeps;
+    if (n_dE) *n_dE = (int)plan->P.dE.size();
+    if (lanes_per_chain) *lanes_per_chain = plan->P.lanes;
+    return XZZX_OK;
+}
+
+int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain)
+{
+    if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
+    int g = lanes_per_chain == 0 ? plan->P.lanes_default : lanes_per_chain;
+    if (g < 1 || g > kWave || (g & (g - 1))) { set_error("lanes per chain must be a power of two in [1, 64]"); return XZZX_EINVAL; }
+    if (plan->P.lds_bytes_anneal(g) > 65536) { set_error("chains per wavefront do not fit in LDS"); return XZZX_ERANGE; }
+    plan->P.lanes = g;
+    plan->P.hdev.lanes = g;
+    if (hipMemcpy(&plan->P.ddev->lanes, &g, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("plan update failed");
+        return XZZX_EDEVICE;
+    }
+    return XZZX_OK;
+}
+
+}  // extern "C"

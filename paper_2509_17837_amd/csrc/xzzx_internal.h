@@ -1,0 +1,94 @@
+// Internal data structures shared by the host plan builder (xzzx_host.cpp) and
+// the gfx950 kernels (xzzx_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/xzzx_sa.h"
+
+namespace xzzx {
+
+constexpr int kWave = 64;
+constexpr int kMaxD = 31;
+constexpr int kMaxGroups = 16;   // syndrome groups per persistent launch
+constexpr int kMaxRanks = 255;   // distinct move energies per plan (u8 rank)
+constexpr int kMaxTypes = 16;    // generator shapes (subset of the four slots)
+
+// Generator descriptor, 8 bytes: the four slot qubits (X_left, Z_up, Z_down,
+// X_right), an absent slot pointing at the per-chain scratch byte n_q, and the
+// shape index used by the move-energy lookup.
+//   x = q0 | q1 << 16,  y = q2 | (q3 << 16) | (shape << 27)
+struct Desc {
+    uint32_t x, y;
+};
+
+// Host-side lattice: geometry shared by every plan built on it.
+struct Lattice {
+    int layout = 0, d = 0, nq = 0, nstab = 0, per_class = 0;
+    std::vector<int32_t> fq;      // [nstab][4], -1 absent
+    std::vector<uint8_t> fm;      // [nstab][4] Pauli code of the generator on the slot
+    std::vector<int32_t> fclass, fcolour, frank;
+    std::vector<uint8_t> lx, lz;
+    std::vector<int32_t> by_class;  // [4][per_class] face id
+};
+
+// Device-resident plan tables (one contiguous allocation) and their layout.
+struct PlanDev {
+    int nq, nstab, M, nblk;        // M generators per colour class, nblk = ceil(M/4)
+    int ntypes, nranks, kneg;      // ranks [0, kneg) have dE <= 0
+    int n_sweeps;
+    int lanes;                     // lanes per chain (1..64)
+    int layout, d;
+    int32_t W[4];
+    const Desc *desc;              // [4][M] by (class, rank)
+    const Desc *face_desc;         // [nstab] by face id
+    const uint8_t *lut;            // [ntypes][256] move-energy rank of a slot pattern
+    const int32_t *dE;             // [nranks] ascending
+    const uint32_t *thr;           // [n_sweeps][nranks]
+    const uint8_t *lx, *lz;        // [nq]
+    // greedy matching, per decoding-graph colour g
+    int ncol[2];
+    const int32_t *col_face[2];    // node -> face id (ascending)
+    const int32_t *dint[2];        // [n][n] interior distance
+    const int32_t *db[2];          // [n] boundary distance
+    const int4 *adj[2];            // [n][4] (edge id, other node or -1, weight, 0), by edge id
+};
+
+struct Plan {
+    Lattice lat;
+    int32_t W[4], Wg[2];
+    int n_sweeps = 0;
+    std::vector<double> beta;
+    std::vector<int32_t> dE;       // distinct move energies, ascending
+    int kneg = 0;
+    int ntypes = 0;
+    int lanes_default = 1, lanes = 1;
+    int device = 0;
+    void *dmem = nullptr;          // device allocation holding every table
+    size_t dbytes = 0;
+    PlanDev hdev{};                // host copy with device pointers
+    PlanDev *ddev = nullptr;       // device copy of hdev (inside dmem)
+    size_t lds_bytes_anneal(int lanes) const;
+};
+
+// ---- host helpers (xzzx_host.cpp) ----
+void set_error(const std::string &msg);
+int build_lattice(int layout, int d, Lattice &L);
+int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const double *beta,
+               int n_sweeps, Plan &P);
+uint32_t accept_threshold(double beta, int64_t dE);
+
+}  // namespace xzzx
+
+struct xzzx_lattice {
+    xzzx::Lattice L;
+};
+
+struct xzzx_plan {
+    xzzx::Plan P;
+};

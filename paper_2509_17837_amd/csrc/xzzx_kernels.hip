@@ -1,0 +1,940 @@
+// gfx950 kernels of the XZZX simulated-annealing decoder and the device-side
+// entry points of the C ABI.
+//
+//   k_syndrome  Eq. (2): syndrome of a batch of configurations.
+//   k_greedy    Algs. 5-6: greedy matching per (syndrome, replica), both
+//               decoding-graph colours, paths XOR-ed into an LDS configuration.
+//   k_qcls      Alg. 7: class Q_r of each reference relative to replica 0.
+//   k_anneal    Algs. 2-3: the hot loop.  Persistent wavefronts pull tasks of
+//               C = 64/G chains from an atomic queue spanning every syndrome
+//               group of the launch (uneven distances allowed).  Each chain's
+//               byte-per-qubit state lives in LDS, interleaved across the C
+//               chains of the wavefront; the G lanes of a chain split the
+//               generators of one colour class (qubit-disjoint, so they update
+//               concurrently).  Replay mode re-runs the best chain of each
+//               syndrome up to the phase of its minimum and stores that state.
+//   k_reduce    Eqs. (18)-(21): per-coset minima, P*, best chain.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "xzzx_internal.h"
+
+namespace xzzx {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// by the Philox multipliers, high/low halves crossed with the other words and
+// the round key; the key advances by the two Weyl increments.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)c.x * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c.z * 0xCD9E8D57u;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ void wave_lds_fence()
+{
+    // Orders this wavefront's LDS traffic across a phase boundary: all lanes
+    // see the stores of the previous phase before any load of the next one.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int32_t weight_of(const int32_t W[4], uint32_t code)
+{
+    return code == 0 ? 0 : code == 1 ? W[1] : code == 2 ? W[2] : W[3];
+}
+
+// Sum over the G lanes of one chain (lanes c*G .. c*G+G-1 of the wavefront).
+template <int LOGG>
+__device__ __forceinline__ int32_t chain_sum(int32_t v)
+{
+#pragma unroll
+    for (int s = 1; s < (1 << LOGG); s <<= 1) v += __shfl_xor(v, s, kWave);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Syndrome, Eq. (2): s_f = 1 iff the configuration anticommutes with G_f.
+// Slots 0 and 3 carry X (detect a Z component), slots 1 and 2 carry Z (detect
+// an X component).
+// ---------------------------------------------------------------------------
+__global__ void k_syndrome(const PlanDev *__restrict__ pl, const uint8_t *__restrict__ cfg,
+                           int64_t n, uint8_t *__restrict__ syn)
+{
+    const int nstab = pl->nstab, nq = pl->nq;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nstab) return;
+    const int64_t s = idx / nstab;
+    const int f = (int)(idx - s * nstab);
+    const Desc d = pl->face_desc[f];
+    const int q[4] = {(int)(d.x & 0xFFFF), (int)(d.x >> 16), (int)(d.y & 0xFFFF), (int)((d.y >> 16) & 0x7FF)};
+    const uint8_t *c = cfg + s * nq;
+    uint32_t bit = 0;
+    if (q[0] < nq) bit ^= c[q[0]] & 1;
+    if (q[1] < nq) bit ^= (c[q[1]] >> 1) & 1;
+    if (q[2] < nq) bit ^= (c[q[2]] >> 1) & 1;
+    if (q[3] < nq) bit ^= c[q[3]] & 1;
+    syn[idx] = (uint8_t)bit;
+}
+
+// ---------------------------------------------------------------------------
+// Greedy matching (Algs. 5-6) -- one wavefront per (syndrome, replica).
+//
+// The sequential rule "take the free pair of least (weight, key, pair id)"
+// is evaluated as repeated mutual-best elimination: every free defect finds
+// its least free partner, and pairs that are each other's least are matched.
+// Under a strict total order the pair taken first by the sequential scan is
+// always mutual-best, and removing matched defects never changes the order of
+// the rest, so both procedures produce the same matching.  Paths follow the
+// canonical tight-edge walk (smallest edge id) and are XOR-ed into the
+// configuration with LDS atomics (paths may overlap).
+// ---------------------------------------------------------------------------
+struct GreedyArgs {
+    const PlanDev *plan;
+    const uint8_t *syn;
+    const uint32_t *uid;
+    uint8_t *refs;
+    uint8_t *qraw;
+    int64_t n_syn;
+    int n_rep;
+    int mode;
+    uint32_t seed_lo, seed_hi;
+    int max_nodes;
+};
+
+__device__ __forceinline__ void xor_edge(uint32_t *cfgw, int eid)
+{
+    const int q = eid >> 1;
+    const uint32_t code = (eid & 1) ? 2u : 1u;
+    atomicXor(&cfgw[q >> 2], code << (8 * (q & 3)));
+}
+
+__device__ void walk_interior(const PlanDev *pl, int g, int u, int v, uint32_t *cfgw)
+{
+    const int n = pl->ncol[g];
+    const int32_t *du = pl->dint[g] + (size_t)u * n;
+    const int4 *adj = pl->adj[g];
+    int x = v;
+    for (int step = 0; step < n && x != u; ++step) {
+        const int32_t dx = du[x];
+        int nxt = -1;
+        for (int s = 0; s < 4; ++s) {
+            const int4 e = adj[4 * x + s];
+            if (e.x < 0 || e.y < 0) continue;
+            if (du[e.y] + e.z == dx) { xor_edge(cfgw, e.x); nxt = e.y; break; }
+        }
+        if (nxt < 0) return;
+        x = nxt;
+    }
+}
+
+__device__ void walk_boundary(const PlanDev *pl, int g, int u, uint32_t *cfgw)
+{
+    const int n = pl->ncol[g];
+    const int32_t *db = pl->db[g];
+    const int4 *adj = pl->adj[g];
+    int x = u;
+    for (int step = 0; step <= n; ++step) {
+        const int32_t dx = db[x];
+        int nxt = -1;
+        for (int s = 0; s < 4; ++s) {
+            const int4 e = adj[4 * x + s];
+            if (e.x < 0) continue;
+            if (e.y < 0) {
+                if (e.z == dx) { xor_edge(cfgw, e.x); return; }
+            } else if (db[e.y] + e.z == dx) {
+                xor_edge(cfgw, e.x);
+                nxt = e.y;
+                break;
+            }
+        }
+        if (nxt < 0) return;
+        x = nxt;
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const PlanDev *pl = A.plan;
+    const int lane = threadIdx.x;
+    const int nq = pl->nq, nstab = pl->nstab;
+    const int64_t sr = blockIdx.x;
+    const int64_t s = sr / A.n_rep;
+    const uint32_t r = (uint32_t)(sr - s * A.n_rep);
+    const uint32_t uid = A.uid[s];
+    const int nwords = (nq + 3) / 4;
+    uint32_t *cfgw = reinterpret_cast<uint32_t *>(smem);
+    int32_t *D = reinterpret_cast<int32_t *>(smem + 4 * nwords);
+    int32_t *best = D + A.max_nodes + 1;
+    int32_t *pairs = best + A.max_nodes + 1;
+    uint8_t *freef = reinterpret_cast<uint8_t *>(pairs + A.max_nodes + 1);
+    __shared__ int s_count;
+
+    for (int i = lane; i < nwords; i += kWave) cfgw[i] = 0;
+    const uint8_t *sy = A.syn + s * nstab;
+    for (int g = 0; g < 2; ++g) {
+        const int n = pl->ncol[g];
+        const int32_t *cf = pl->col_face[g];
+        const int32_t *dint = pl->dint[g];
+        const int32_t *db = pl->db[g];
+        // defects of this colour, ascending node index
+        int nd = 0;
+        for (int base = 0; base < n; base += kWave) {
+            const int v = base + lane;
+            const bool flag = v < n && sy[cf[v]];
+            const uint64_t mask = __ballot(flag);
+            const int pos = nd + __popcll(mask & ((1ull << lane) - 1ull));
+            if (flag) D[pos] = v;
+            nd += __popcll(mask);
+        }
+        __syncthreads();
+        if (A.mode == XZZX_GREEDY_BOUNDARY) {
+            for (int i = lane; i < nd; i += kWave) walk_boundary(pl, g, D[i], cfgw);
+            __syncthreads();
+            continue;
+        }
+        const int na = nd + (nd & 1);   // odd count: the virtual boundary joins as node nd
+        for (int i = lane; i < na; i += kWave) freef[i] = 1;
+        if (lane == 0) s_count = 0;
+        __syncthreads();
+        int nfree = na;
+        const bool randomized = A.mode == XZZX_GREEDY_RANDOM;
+        // every round matches at least the least free pair, so na/2 rounds suffice
+        for (int round = 0; nfree > 0 && round <= na / 2; ++round) {
+            for (int i = lane; i < na; i += kWave) {
+                if (!freef[i]) continue;
+                uint32_t bw = 0xFFFFFFFFu, bk = 0xFFFFFFFFu, bid = 0xFFFFFFFFu;
+                int bj = -1;
+                for (int j = 0; j < na; ++j) {
+                    if (j == i || !freef[j]) continue;
+                    const int lo = min(i, j), hi = max(i, j);
+                    uint32_t w;
+                    if (hi == nd) {
+                        w = (uint32_t)db[D[lo]];
+                    } else {
+                        const int u = D[lo], v = D[hi];
+                        w = (uint32_t)min(dint[(size_t)u * n + v], db[u] + db[v]);
+                    }
+                    const uint32_t id = (uint32_t)(lo * na + hi);
+                    if (w > bw) continue;
+                    const uint32_t key = randomized
+                        ? philox4x32_10(make_uint4(uid, r, 0x100u + (uint32_t)g, id), A.seed_lo, A.seed_hi).x
+                        : 0u;
+                    if (w < bw || key < bk || (key == bk && id < bid)) { bw = w; bk = key; bid = id; bj = j; }
+                }
+                best[i] = bj;
+            }
+            __syncthreads();
+            for (int i = lane; i < na; i += kWave) {
+                if (!freef[i]) continue;
+                const int j = best[i];
+                if (j > i && best[j] == i) {
+                    const int p = atomicAdd(&s_count, 1);
+                    pairs[p] = i | (j << 16);
+                }
+            }
+            __syncthreads();
+            const int np = s_count;
+            for (int p = lane; p < np; p += kWave) {
+                freef[pairs[p] & 0xFFFF] = 0;
+                freef[pairs[p] >> 16] = 0;
+            }
+            __syncthreads();
+            nfree = na - 2 * np;
+        }
+        const int np = s_count;
+        for (int p = lane; p < np; p += kWave) {
+            const int i = pairs[p] & 0xFFFF, j = pairs[p] >> 16;
+            if (j == nd) {
+                walk_boundary(pl, g, D[i], cfgw);
+            } else {
+                const int u = D[i], v = D[j];
+                if (dint[(size_t)u * n + v] <= db[u] + db[v]) {
+                    walk_interior(pl, g, u, v, cfgw);
+                } else {
+                    walk_boundary(pl, g, u, cfgw);
+                    walk_boundary(pl, g, v, cfgw);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // write the reference and its symplectic products with L_Z and L_X
+    uint8_t *out = A.refs + (size_t)sr * nq;
+    const uint8_t *cb = reinterpret_cast<const uint8_t *>(cfgw);
+    uint32_t vz = 0, vx = 0;
+    for (int q = lane; q < nq; q += kWave) {
+        const uint32_t c = cb[q];
+        out[q] = (uint8_t)c;
+        const uint32_t z = pl->lz[q], x = pl->lx[q];
+        vz ^= (((c >> 1) & z) ^ (c & (z >> 1))) & 1;
+        vx ^= (((c >> 1) & x) ^ (c & (x >> 1))) & 1;
+    }
+    const int az = __popcll(__ballot(vz)) & 1;
+    const int ax = __popcll(__ballot(vx)) & 1;
+    if (lane == 0) A.qraw[sr] = (uint8_t)(az | (ax << 1));
+}
+
+// Pauli class index (I=0, X=1, Y=2, Z=3) <-> (x, z) bits, and products.
+__device__ __forceinline__ int cls_from_bits(int x, int z) { return x ? (z ? 2 : 1) : (z ? 3 : 0); }
+__device__ __forceinline__ int cls_x(int c) { return (c == 1) | (c == 2); }
+__device__ __forceinline__ int cls_z(int c) { return (c == 2) | (c == 3); }
+__device__ __forceinline__ int cls_mul(int a, int b) { return cls_from_bits(cls_x(a) ^ cls_x(b), cls_z(a) ^ cls_z(b)); }
+
+// Class of R_r relative to R_0 from the symplectic products with L_Z (bit 0:
+// an X-type logical anticommutes with L_Z) and L_X (bit 1).  One thread per
+// syndrome reads replica 0 first, so qcls may alias qraw.
+__global__ void k_qcls(const uint8_t *qraw, int64_t n_syn, int n_rep, uint8_t *qcls)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_syn) return;
+    const int r0 = qraw[s * n_rep] & 3;
+    for (int r = 0; r < n_rep; ++r) {
+        const int v = (qraw[s * n_rep + r] & 3) ^ r0;
+        qcls[s * n_rep + r] = (uint8_t)cls_from_bits(v & 1, v >> 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Annealing (Algs. 2-3).
+// ---------------------------------------------------------------------------
+struct GroupArgs {
+    const PlanDev *plan;
+    const uint32_t *uid;
+    const uint8_t *refs;          // [n_syn][n_rep][nq]
+    int32_t *emin, *stop, *efin;  // [n_syn][4 n_rep]
+    uint8_t *final;               // optional [n_syn][4 n_rep][nq]
+    const int32_t *best_chain;    // replay: [n_syn]
+    uint8_t *recovery;            // replay: [n_syn][nq]
+    int64_t unit_offset;          // first unit (chain or syndrome) of this launch
+    int64_t n_units;              // units handled by this launch
+    int64_t task_begin;           // first task index of this group
+    int n_rep;
+    int log_lanes;
+};
+
+struct AnnealArgs {
+    GroupArgs g[kMaxGroups];
+    int n_groups;
+    int replay;
+    uint32_t n_tasks;
+    uint32_t *counter;
+    uint32_t seed_lo, seed_hi;
+};
+
+struct LdsLayout {
+    uint32_t desc, lut, et, state;
+};
+
+__device__ __forceinline__ LdsLayout lds_layout(int M, int ntypes, int nranks)
+{
+    LdsLayout o;
+    o.desc = 0;
+    o.lut = 8u * 4u * (uint32_t)M;
+    o.et = (o.lut + 256u * (uint32_t)ntypes + 7u) & ~7u;
+    o.state = (o.et + 8u * (uint32_t)nranks + 15u) & ~15u;
+    return o;
+}
+
+template <int LOGG>
+__device__ void anneal_task(const AnnealArgs &A, const GroupArgs &G, int64_t unit0, uint8_t *smem)
+{
+    constexpr int LOGC = 6 - LOGG;
+    const PlanDev *pl = G.plan;
+    const int lane = threadIdx.x;
+    const int c = lane >> LOGG;          // chain slot in this wavefront
+    const int gl = lane & ((1 << LOGG) - 1);
+    const int nq = pl->nq, M = pl->M, nblk = pl->nblk, nranks = pl->nranks, n_sweeps = pl->n_sweeps;
+    const uint32_t kneg = (uint32_t)pl->kneg;
+    int32_t W[4];
+    W[0] = pl->W[0]; W[1] = pl->W[1]; W[2] = pl->W[2]; W[3] = pl->W[3];
+    const LdsLayout lo = lds_layout(M, pl->ntypes, nranks);
+    const uint2 *desc_s = reinterpret_cast<const uint2 *>(smem + lo.desc);
+    const uint8_t *lut_s = smem + lo.lut;
+    int2 *et_s = reinterpret_cast<int2 *>(smem + lo.et);
+    uint8_t *st = smem + lo.state;
+
+    const int nc = 4 * G.n_rep;
+    const int64_t unit = unit0 + c;
+    const bool active = unit < G.n_units;
+    const int64_t u_abs = G.unit_offset + (active ? unit : 0);
+    int64_t s;
+    int cc;
+    int32_t target = -1;
+    if (A.replay) {
+        s = u_abs;
+        cc = G.best_chain[s];
+        target = G.stop[s * nc + cc];
+    } else {
+        s = u_abs / nc;
+        cc = (int)(u_abs - s * nc);
+    }
+    const int r = cc >> 2, lp = cc & 3;
+    const uint32_t uid = G.uid[s];
+
+    // initial state R_r * L_P' (Alg. 7), interleaved: qubit q of slot c at q*C + c
+    const uint8_t *ref = G.refs + ((size_t)s * G.n_rep + r) * nq;
+    const bool use_x = (lp == 1 || lp == 2), use_z = (lp == 2 || lp == 3);
+    int32_t part = 0;
+    for (int q = gl; q < nq; q += (1 << LOGG)) {
+        uint32_t v = ref[q] & 3u;
+        if (use_x) v ^= pl->lx[q];
+        if (use_z) v ^= pl->lz[q];
+        st[(q << LOGC) + c] = (uint8_t)v;
+        part += weight_of(W, v);
+    }
+    if (gl == 0) st[(nq << LOGC) + c] = 0;
+    int32_t E = chain_sum<LOGG>(part);
+    int32_t Emin = E;
+    int32_t stop = 0;
+    wave_lds_fence();
+
+    auto save_state = [&](uint8_t *dst) {
+        for (int q = gl; q < nq; q += (1 << LOGG)) dst[q] = st[(q << LOGC) + c];
+    };
+    int32_t last_phase = 4 * n_sweeps;
+    if (A.replay) {
+        if (active && target == 0) save_state(G.recovery + (size_t)s * nq);
+        int32_t tmax = active ? target : 0;
+#pragma unroll
+        for (int sh = 1; sh < kWave; sh <<= 1) tmax = max(tmax, __shfl_xor(tmax, sh, kWave));
+        last_phase = tmax;
+    }
+
+    for (int t = 0; t < n_sweeps && 4 * t < last_phase; ++t) {
+        for (int i = lane; i < nranks; i += kWave) et_s[i].y = (int)pl->thr[(size_t)t * nranks + i];
+        wave_lds_fence();
+        for (int k = 0; k < 4; ++k) {
+            const uint2 *dk = desc_s + k * M;
+            int32_t acc_de = 0;
+            for (int b = gl; b < nblk; b += (1 << LOGG)) {
+                const uint4 rnd = philox4x32_10(make_uint4(uid, (uint32_t)cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
+                                                A.seed_lo, A.seed_hi);
+                const uint32_t uw[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int m = 4 * b + w;
+                    if (m >= M) break;
+                    const uint2 d = dk[m];
+                    const uint32_t a0 = ((d.x & 0xFFFFu) << LOGC) + c;
+                    const uint32_t a1 = ((d.x >> 16) << LOGC) + c;
+                    const uint32_t a2 = ((d.y & 0xFFFFu) << LOGC) + c;
+                    const uint32_t a3 = (((d.y >> 16) & 0x7FFu) << LOGC) + c;
+                    const uint32_t c0 = st[a0], c1 = st[a1], c2 = st[a2], c3 = st[a3];
+                    const uint32_t pat = c0 | (c1 << 2) | (c2 << 4) | (c3 << 6);
+                    const uint32_t rank = lut_s[((d.y >> 27) << 8) | pat];
+                    const int2 et = et_s[rank];
+                    if (rank < kneg || uw[w] < (uint32_t)et.y) {
+                        st[a0] = (uint8_t)(c0 ^ 2u);
+                        st[a1] = (uint8_t)(c1 ^ 1u);
+                        st[a2] = (uint8_t)(c2 ^ 1u);
+                        st[a3] = (uint8_t)(c3 ^ 2u);
+                        acc_de += et.x;
+                    }
+                }
+            }
+            wave_lds_fence();
+            E += chain_sum<LOGG>(acc_de);
+            const int32_t phase = 4 * t + k + 1;
+            if (E < Emin) { Emin = E; stop = phase; }
+            if (A.replay && active && phase == target) save_state(G.recovery + (size_t)s * nq);
+        }
+    }
+    if (!A.replay && active && gl == 0) {
+        const int64_t ci = u_abs;
+        G.emin[ci] = Emin;
+        G.stop[ci] = stop;
+        G.efin[ci] = E;
+    }
+    if (!A.replay && active && G.final) save_state(G.final + (size_t)u_abs * nq);
+    wave_lds_fence();
+}
+
+__device__ void load_plan_tables(const PlanDev *pl, uint8_t *smem)
+{
+    const int lane = threadIdx.x;
+    const LdsLayout lo = lds_layout(pl->M, pl->ntypes, pl->nranks);
+    uint2 *desc_s = reinterpret_cast<uint2 *>(smem + lo.desc);
+    const uint2 *desc_g = reinterpret_cast<const uint2 *>(pl->desc);
+    for (int i = lane; i < 4 * pl->M; i += kWave) desc_s[i] = desc_g[i];
+    const uint32_t *lut_g = reinterpret_cast<const uint32_t *>(pl->lut);
+    uint32_t *lut_s = reinterpret_cast<uint32_t *>(smem + lo.lut);
+    for (int i = lane; i < 64 * pl->ntypes; i += kWave) lut_s[i] = lut_g[i];
+    int2 *et_s = reinterpret_cast<int2 *>(smem + lo.et);
+    for (int i = lane; i < pl->nranks; i += kWave) et_s[i] = make_int2(pl->dE[i], 0);
+    wave_lds_fence();
+}
+
+__global__ __launch_bounds__(kWave) void k_anneal(AnnealArgs A)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const PlanDev *loaded = nullptr;
+    for (;;) {
+        uint32_t task = 0;
+        if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
+        task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
+        if (task >= A.n_tasks) break;
+        int gi = 0;
+        while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
+        const GroupArgs &G = A.g[gi];
+        const int64_t unit0 = ((int64_t)task - G.task_begin) << (6 - G.log_lanes);
+        if (G.plan != loaded) {
+            wave_lds_fence();
+            load_plan_tables(G.plan, smem);
+            loaded = G.plan;
+        }
+        switch (G.log_lanes) {
+        case 0: anneal_task<0>(A, G, unit0, smem); break;
+        case 1: anneal_task<1>(A, G, unit0, smem); break;
+        case 2: anneal_task<2>(A, G, unit0, smem); break;
+        case 3: anneal_task<3>(A, G, unit0, smem); break;
+        case 4: anneal_task<4>(A, G, unit0, smem); break;
+        case 5: anneal_task<5>(A, G, unit0, smem); break;
+        default: anneal_task<6>(A, G, unit0, smem); break;
+        }
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Reduction (Alg. 7, Eq. (21)) -- one wavefront per syndrome.  Chain c of
+// replica r = c/4 runs in coset Q_r * P' (P' = c mod 4); E_P is the minimum
+// E_min over the chains of coset P; P* = argmin with ties to the lowest index;
+// the best chain is the lowest chain of coset P* attaining E_P*.
+// ---------------------------------------------------------------------------
+struct ReduceArgs {
+    const PlanDev *plan;
+    const uint8_t *qcls;
+    const uint8_t *refs;
+    const int32_t *emin;
+    int32_t *e_best;
+    uint8_t *cls;
+    int32_t *best_chain;
+    int32_t *e_cls;
+    uint8_t *paper_recovery;
+    int64_t n_syn;
+    int n_rep;
+};
+
+__global__ __launch_bounds__(kWave) void k_reduce(ReduceArgs A)
+{
+    const int lane = threadIdx.x;
+    const int64_t s = blockIdx.x;
+    const int nc = 4 * A.n_rep;
+    uint64_t best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+    for (int c = lane; c < nc; c += kWave) {
+        const int cls = cls_mul(A.qcls[s * A.n_rep + (c >> 2)], c & 3);
+        const uint64_t key = ((uint64_t)(uint32_t)A.emin[s * nc + c] << 32) | (uint32_t)c;
+#pragma unroll
+        for (int P = 0; P < 4; ++P)
+            if (cls == P) best[P] = min(best[P], key);
+    }
+#pragma unroll
+    for (int P = 0; P < 4; ++P)
+#pragma unroll
+        for (int sh = 1; sh < kWave; sh <<= 1) {
+            const uint64_t o = __shfl_xor(best[P], sh, kWave);
+            best[P] = min(best[P], o);
+        }
+    int ps = 0;
+#pragma unroll
+    for (int P = 1; P < 4; ++P)
+        if ((best[P] >> 32) < (best[ps] >> 32)) ps = P;
+    if (lane == 0) {
+        A.e_best[s] = (int32_t)(best[ps] >> 32);
+        A.cls[s] = (uint8_t)ps;
+        A.best_chain[s] = (int32_t)(best[ps] & 0xFFFFFFFFu);
+        if (A.e_cls)
+            for (int P = 0; P < 4; ++P) A.e_cls[s * 4 + P] = best[P] == ~0ull ? INT32_MAX : (int32_t)(best[P] >> 32);
+    }
+    if (A.paper_recovery) {
+        const PlanDev *pl = A.plan;
+        const int nq = pl->nq;
+        const bool ux = (ps == 1 || ps == 2), uz = (ps == 2 || ps == 3);
+        const uint8_t *r0 = A.refs + (size_t)s * A.n_rep * nq;
+        for (int q = lane; q < nq; q += kWave)
+            A.paper_recovery[(size_t)s * nq + q] = r0[q] ^ (ux ? pl->lx[q] : 0) ^ (uz ? pl->lz[q] : 0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch logic.
+// ---------------------------------------------------------------------------
+static int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return XZZX_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return XZZX_EDEVICE;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int greedy_lds(const Plan &P, int *max_nodes)
+{
+    const int mn = std::max(P.hdev.ncol[0], P.hdev.ncol[1]);
+    *max_nodes = mn;
+    return 4 * ((P.lat.nq + 3) / 4) + 3 * 4 * (mn + 1) + (mn + 1) + 16;
+}
+
+static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_uid, int64_t n_syn,
+                         int n_rep, uint64_t seed, int mode, uint8_t *d_refs, uint8_t *d_qraw,
+                         hipStream_t stream)
+{
+    if (n_syn == 0) return XZZX_OK;
+    GreedyArgs A{};
+    A.plan = P.ddev;
+    A.syn = d_syn;
+    A.uid = d_uid;
+    A.refs = d_refs;
+    A.qraw = d_qraw;
+    A.n_syn = n_syn;
+    A.n_rep = n_rep;
+    A.mode = mode;
+    A.seed_lo = (uint32_t)seed;
+    A.seed_hi = (uint32_t)(seed >> 32);
+    const int lds = greedy_lds(P, &A.max_nodes);
+    const int64_t blocks = n_syn * n_rep;
+    if (blocks > 0x7FFFFFFF) { set_error("too many (syndrome, replica) pairs"); return XZZX_ERANGE; }
+    hipLaunchKernelGGL(k_greedy, dim3((unsigned)blocks), dim3(kWave), lds, stream, A);
+    return check_hip(hipGetLastError(), "k_greedy launch");
+}
+
+static int launch_qcls(const uint8_t *d_qraw, int64_t n_syn, int n_rep, uint8_t *d_qcls, hipStream_t stream)
+{
+    if (n_syn == 0) return XZZX_OK;
+    hipLaunchKernelGGL(k_qcls, dim3((unsigned)((n_syn + 255) / 256)), dim3(256), 0, stream, d_qraw, n_syn, n_rep, d_qcls);
+    return check_hip(hipGetLastError(), "k_qcls launch");
+}
+
+// Per-group workspace layout.
+struct GroupWs {
+    uint8_t *refs, *qraw, *qcls;
+    int32_t *emin, *stop, *efin, *best_chain;
+};
+
+static size_t group_ws_bytes(const xzzx_group &g, bool decode)
+{
+    const Plan &P = g.plan->P;
+    const size_t nq = P.lat.nq, ns = (size_t)g.n_syn, R = (size_t)g.n_rep, nc = 4 * R * ns;
+    size_t b = 0;
+    if (decode && !g.d_refs) b += align256(ns * R * nq);
+    b += align256(ns * R);                                  // qraw
+    if (decode && !g.d_qcls) b += align256(ns * R);
+    if (!g.d_chain_emin) b += align256(nc * 4);
+    if (!g.d_chain_stop) b += align256(nc * 4);
+    if (!g.d_chain_e) b += align256(nc * 4);
+    if (!g.d_best_chain) b += align256(ns * 4);
+    return b;
+}
+
+static GroupWs carve_group(const xzzx_group &g, bool decode, uint8_t *&p)
+{
+    const Plan &P = g.plan->P;
+    const size_t nq = P.lat.nq, ns = (size_t)g.n_syn, R = (size_t)g.n_rep, nc = 4 * R * ns;
+    GroupWs w{};
+    auto take = [&](size_t bytes) { uint8_t *r = p; p += align256(bytes); return r; };
+    w.refs = g.d_refs ? g.d_refs : (decode ? take(ns * R * nq) : nullptr);
+    w.qraw = take(ns * R);
+    w.qcls = g.d_qcls ? g.d_qcls : (decode ? take(ns * R) : nullptr);
+    w.emin = g.d_chain_emin ? g.d_chain_emin : reinterpret_cast<int32_t *>(take(nc * 4));
+    w.stop = g.d_chain_stop ? g.d_chain_stop : reinterpret_cast<int32_t *>(take(nc * 4));
+    w.efin = g.d_chain_e ? g.d_chain_e : reinterpret_cast<int32_t *>(take(nc * 4));
+    w.best_chain = g.d_best_chain ? g.d_best_chain : reinterpret_cast<int32_t *>(take(ns * 4));
+    return w;
+}
+
+static int validate_groups(const xzzx_group *groups, int n_groups, bool decode)
+{
+    if (!groups || n_groups < 1 || n_groups > kMaxGroups) {
+        set_error("need 1..16 groups");
+        return XZZX_EINVAL;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { set_error("hipGetDevice failed"); return XZZX_EDEVICE; }
+    for (int i = 0; i < n_groups; ++i) {
+        const xzzx_group &g = groups[i];
+        if (!g.plan || g.n_syn < 0 || g.n_rep < 1 || g.n_rep > (1 << 20)) { set_error("bad group (plan, n_syn or n_rep)"); return XZZX_EINVAL; }
+        if (g.plan->P.device != dev) { set_error("plan was created on another device"); return XZZX_EINVAL; }
+        if (g.n_syn == 0) continue;
+        if (!g.d_uid || !g.d_e_best || !g.d_cls || !g.d_recovery) { set_error("missing required group buffer"); return XZZX_EINVAL; }
+        if (decode && !g.d_syn) { set_error("decode needs d_syn"); return XZZX_EINVAL; }
+        if (!decode && (!g.d_refs || !g.d_qcls)) { set_error("anneal needs d_refs and d_qcls"); return XZZX_EINVAL; }
+        if ((int64_t)g.n_syn * 4 * g.n_rep >= ((int64_t)1 << 31)) { set_error("too many chains in one group"); return XZZX_ERANGE; }
+    }
+    return XZZX_OK;
+}
+
+static int anneal_grid(size_t lds_bytes, uint32_t n_tasks, unsigned *grid)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return check_hip(hipErrorInvalidDevice, "hipGetDevice");
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_anneal, kWave, lds_bytes) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    const uint64_t full = (uint64_t)cus * (uint64_t)per_cu;
+    *grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(full, n_tasks));
+    return XZZX_OK;
+}
+
+// Launch k_anneal over `units` of each group (chains, or syndromes in replay).
+static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, bool replay,
+                         uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counter,
+                         hipStream_t stream, bool plain_grid)
+{
+    AnnealArgs A{};
+    A.replay = replay ? 1 : 0;
+    A.seed_lo = (uint32_t)seed;
+    A.seed_hi = (uint32_t)(seed >> 32);
+    A.counter = d_counter;
+    // order groups by work per task (largest first) so the queue is LPT-like
+    std::vector<int> order;
+    for (int i = 0; i < n_groups; ++i)
+        if (groups[i].n_syn > 0) order.push_back(i);
+    auto cost = [&](int i) {
+        const Plan &P = groups[i].plan->P;
+        return (double)P.n_sweeps * P.lat.nstab * (kWave / P.lanes);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    uint64_t tasks = 0;
+    size_t lds = 0;
+    int ng = 0;
+    for (int i : order) {
+        const xzzx_group &g = groups[i];
+        const Plan &P = g.plan->P;
+        GroupArgs &G = A.g[ng++];
+        G.plan = P.ddev;
+        G.uid = g.d_uid;
+        G.refs = ws[i].refs;
+        G.emin = ws[i].emin;
+        G.stop = ws[i].stop;
+        G.efin = ws[i].efin;
+        G.final = replay ? nullptr : g.d_chain_final;
+        G.best_chain = ws[i].best_chain;
+        G.recovery = g.d_recovery;
+        G.n_rep = g.n_rep;
+        int lg = 0;
+        while ((1 << lg) < P.lanes) ++lg;
+        G.log_lanes = lg;
+        G.unit_offset = unit_offset;
+        const int64_t units = units_override >= 0 ? units_override : (replay ? g.n_syn : g.n_syn * 4 * g.n_rep);
+        G.n_units = units;
+        G.task_begin = (int64_t)tasks;
+        const int C = kWave / P.lanes;
+        tasks += (uint64_t)((units + C - 1) / C);
+        lds = std::max(lds, P.lds_bytes_anneal(P.lanes));
+    }
+    if (ng == 0 || tasks == 0) return XZZX_OK;
+    if (tasks >= 0xFFFFFFF0ull) { set_error("too many anneal tasks in one launch"); return XZZX_ERANGE; }
+    A.n_groups = ng;
+    A.n_tasks = (uint32_t)tasks;
+    if (lds > 65536) { set_error("LDS demand above 64 KiB"); return XZZX_ERANGE; }
+    unsigned grid = (unsigned)tasks;
+    if (!plain_grid) {
+        int rc = anneal_grid(lds, A.n_tasks, &grid);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_counter, 1);
+    hipLaunchKernelGGL(k_anneal, dim3(grid), dim3(kWave), lds, stream, A);
+    return check_hip(hipGetLastError(), "k_anneal launch");
+}
+
+static int launch_reduce(const xzzx_group &g, const GroupWs &w, hipStream_t stream)
+{
+    if (g.n_syn == 0) return XZZX_OK;
+    ReduceArgs A{};
+    A.plan = g.plan->P.ddev;
+    A.qcls = w.qcls;
+    A.refs = w.refs;
+    A.emin = w.emin;
+    A.e_best = g.d_e_best;
+    A.cls = g.d_cls;
+    A.best_chain = w.best_chain;
+    A.e_cls = g.d_e_cls;
+    A.paper_recovery = g.d_paper_recovery;
+    A.n_syn = g.n_syn;
+    A.n_rep = g.n_rep;
+    if (g.n_syn > 0x7FFFFFFF) { set_error("too many syndromes"); return XZZX_ERANGE; }
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)g.n_syn), dim3(kWave), 0, stream, A);
+    return check_hip(hipGetLastError(), "k_reduce launch");
+}
+
+static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_seed, uint64_t anneal_seed,
+                      int greedy_mode, int flags, void *d_workspace, size_t workspace_bytes,
+                      hipStream_t stream, bool decode)
+{
+    int rc = validate_groups(groups, n_groups, decode);
+    if (rc) return rc;
+    if (decode && greedy_mode != XZZX_GREEDY_RANDOM && greedy_mode != XZZX_GREEDY_SAME &&
+        greedy_mode != XZZX_GREEDY_BOUNDARY) {
+        set_error("unknown greedy mode");
+        return XZZX_EINVAL;
+    }
+    size_t need = 256;
+    for (int i = 0; i < n_groups; ++i) need += group_ws_bytes(groups[i], decode);
+    if (!d_workspace || workspace_bytes < need) { set_error("workspace too small"); return XZZX_ENOMEM; }
+    uint8_t *p = static_cast<uint8_t *>(d_workspace);
+    uint32_t *counter = reinterpret_cast<uint32_t *>(p);
+    p += 256;
+    std::vector<GroupWs> ws(n_groups);
+    for (int i = 0; i < n_groups; ++i) ws[i] = carve_group(groups[i], decode, p);
+    for (int i = 0; i < n_groups; ++i) {
+        const xzzx_group &g = groups[i];
+        if (!decode || g.n_syn == 0) continue;
+        rc = launch_greedy(g.plan->P, g.d_syn, g.d_uid, g.n_syn, g.n_rep, greedy_seed, greedy_mode, ws[i].refs,
+                           ws[i].qraw, stream);
+        if (!rc) rc = launch_qcls(ws[i].qraw, g.n_syn, g.n_rep, ws[i].qcls, stream);
+        if (rc) return rc;
+    }
+    if (flags & XZZX_FLAG_PLAIN) {
+        // one launch per syndrome, grid = its own tasks, no persistence
+        for (int i = 0; i < n_groups; ++i) {
+            const xzzx_group &g = groups[i];
+            for (int64_t s = 0; s < g.n_syn; ++s) {
+                rc = launch_anneal(&g, &ws[i], 1, false, anneal_seed, s * 4 * g.n_rep, 4 * g.n_rep, counter, stream, true);
+                if (rc) return rc;
+            }
+        }
+    } else {
+        rc = launch_anneal(groups, ws.data(), n_groups, false, anneal_seed, 0, -1, counter, stream, false);
+        if (rc) return rc;
+    }
+    for (int i = 0; i < n_groups; ++i) {
+        rc = launch_reduce(groups[i], ws[i], stream);
+        if (rc) return rc;
+    }
+    return launch_anneal(groups, ws.data(), n_groups, true, anneal_seed, 0, -1, counter + 1, stream, false);
+}
+
+}  // namespace xzzx
+
+using namespace xzzx;
+
+extern "C" {
+
+int xzzx_syndrome(const xzzx_plan *plan, const uint8_t *d_cfg, int64_t n, uint8_t *d_syn, void *stream)
+{
+    if (!plan || n < 0 || (n > 0 && (!d_cfg || !d_syn))) { set_error("bad syndrome arguments"); return XZZX_EINVAL; }
+    if (n == 0) return XZZX_OK;
+    const int64_t total = n * plan->P.lat.nstab;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7FFFFFFF) { set_error("batch too large"); return XZZX_ERANGE; }
+    hipLaunchKernelGGL(k_syndrome, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, plan->P.ddev, d_cfg, n, d_syn);
+    return check_hip(hipGetLastError(), "k_syndrome launch");
+}
+
+int xzzx_greedy_init(const xzzx_plan *plan, const uint8_t *d_syn, const uint32_t *d_uid, int64_t n_syn,
+                     int n_rep, uint64_t greedy_seed, int mode, uint8_t *d_refs, uint8_t *d_qcls, void *stream)
+{
+    if (!plan || n_syn < 0 || n_rep < 1) { set_error("bad greedy arguments"); return XZZX_EINVAL; }
+    if (mode != XZZX_GREEDY_RANDOM && mode != XZZX_GREEDY_SAME && mode != XZZX_GREEDY_BOUNDARY) {
+        set_error("unknown greedy mode");
+        return XZZX_EINVAL;
+    }
+    if (n_syn == 0) return XZZX_OK;
+    if (!d_syn || !d_uid || !d_refs || !d_qcls) { set_error("NULL buffer"); return XZZX_EINVAL; }
+    // the raw symplectic bits land in d_qcls and are turned into classes in place
+    int rc = launch_greedy(plan->P, d_syn, d_uid, n_syn, n_rep, greedy_seed, mode, d_refs, d_qcls, (hipStream_t)stream);
+    if (rc) return rc;
+    return launch_qcls(d_qcls, n_syn, n_rep, d_qcls, (hipStream_t)stream);
+}
+
+int xzzx_decode_workspace(const xzzx_group *groups, int n_groups, size_t *bytes)
+{
+    if (!groups || !bytes || n_groups < 1 || n_groups > kMaxGroups) { set_error("bad arguments"); return XZZX_EINVAL; }
+    size_t need = 256;
+    for (int i = 0; i < n_groups; ++i) {
+        if (!groups[i].plan) { set_error("group without plan"); return XZZX_EINVAL; }
+        need += group_ws_bytes(groups[i], true);
+    }
+    *bytes = need;
+    return XZZX_OK;
+}
+
+int xzzx_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_seed, uint64_t anneal_seed,
+                int greedy_mode, int flags, void *d_workspace, size_t workspace_bytes, void *stream)
+{
+    return run_decode(groups, n_groups, greedy_seed, anneal_seed, greedy_mode, flags, d_workspace, workspace_bytes,
+                      (hipStream_t)stream, true);
+}
+
+int xzzx_anneal(const xzzx_group *groups, int n_groups, uint64_t anneal_seed, int flags, void *d_workspace,
+                size_t workspace_bytes, void *stream)
+{
+    return run_decode(groups, n_groups, 0, anneal_seed, XZZX_GREEDY_RANDOM, flags, d_workspace, workspace_bytes,
+                      (hipStream_t)stream, false);
+}
+
+}  // extern "C"
+
+struct xzzx_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int xzzx_graph_create(const xzzx_group *groups, int n_groups, uint64_t greedy_seed, uint64_t anneal_seed,
+                      int greedy_mode, int flags, void *d_workspace, size_t workspace_bytes, void *stream,
+                      xzzx_graph **out)
+{
+    if (!out) { set_error("out is NULL"); return XZZX_EINVAL; }
+    *out = nullptr;
+    if (!stream) { set_error("graph capture needs a non-null stream"); return XZZX_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    int rc = check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (rc) return rc;
+    const int drc = run_decode(groups, n_groups, greedy_seed, anneal_seed, greedy_mode, flags, d_workspace,
+                               workspace_bytes, s, true);
+    hipGraph_t g = nullptr;
+    rc = check_hip(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
+    if (drc) {
+        if (g) (void)hipGraphDestroy(g);
+        return drc;
+    }
+    if (rc) return rc;
+    auto *h = new xzzx_graph();
+    h->graph = g;
+    rc = check_hip(hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (rc) {
+        (void)hipGraphDestroy(g);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return XZZX_OK;
+}
+
+int xzzx_graph_launch(xzzx_graph *graph, void *stream)
+{
+    if (!graph || !graph->exec) { set_error("graph is NULL"); return XZZX_EINVAL; }
+    return check_hip(hipGraphLaunch(graph->exec, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+void xzzx_graph_destroy(xzzx_graph *graph)
+{
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle
+checks.  This module holds only workload definitions and random sampling --
+none of the decoder's arithmetic.
+
+The workload is code-capacity Pauli noise (the paper's Sec. IV.A channel):
+each qubit independently suffers X, Y or Z with probabilities (p_x, p_y, p_z).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Pauli codes: I=0, Z=1, X=2, Y=3
+CODE_X, CODE_Y, CODE_Z = 2, 3, 1
+
+
+def channel(p: float, eta: float, convention: int = 0):
+    """(p_x, p_y, p_z) of the sampled channel.  convention 0: p_y = p eta/(eta+1),
+    p_x = p_z = p/(2(eta+1)); convention 1: p_x:p_y:p_z = 1:eta:1."""
+    if convention == 0:
+        return (p / (2 * (eta + 1)), p * eta / (eta + 1), p / (2 * (eta + 1)))
+    return (p / (eta + 2), p * eta / (eta + 2), p / (eta + 2))
+
+
+def sample_errors(n: int, nq: int, pxyz, seed: int, stream: int = 0) -> np.ndarray:
+    """n i.i.d. error configurations [n][nq] (uint8 Pauli codes), reproducible
+    from (seed, stream)."""
+    rng = np.random.default_rng([int(seed), int(stream)])
+    u = rng.random((n, nq))
+    px, py, pz = pxyz
+    out = np.zeros((n, nq), np.uint8)
+    out[u < px + py + pz] = CODE_Z
+    out[u < px + py] = CODE_Y
+    out[u < px] = CODE_X
+    return out
+
+
+def sample_uids(n: int, first: int = 0) -> np.ndarray:
+    return np.arange(first, first + n, dtype=np.uint32)
+
+
+# The five measured workloads (rotated layout).  Seeds: sample 1000+k,
+# greedy 2000+k, anneal 3000+k for workload k.
+WORKLOADS = {
+    "d3_small": dict(d=[3], p=[0.15], eta=[10.0], n_syn=1000, n_rep=1, sweeps=200,
+                     schedule=("linear", 0.1, 5.0)),
+    "d11_bias100": dict(d=[11], p=[0.10, 0.15, 0.20, 0.25], eta=[100.0], n_syn=100000, n_rep=32,
+                        sweeps=2000, schedule=("geometric", 0.05, 10.0)),
+    "mixed_d5_21": dict(d=[5, 9, 13, 17, 21], p=[0.18], eta=[10.0], n_syn=20000, n_rep=64, sweeps=5000,
+                        schedule=("geometric", 0.05, 10.0)),
+    "serving_d7_25": dict(d=[7, 11, 15, 19, 25], p=[0.12], eta=[1.0, 10.0, 1000.0], n_syn=20000, n_rep=16,
+                          sweeps=1000, schedule=("geometric", 0.05, 10.0),
+                          rates=[1e3, 3e3, 1e4, 3e4, 1e5]),
+    "d31_large": dict(d=[31], p=[0.20], eta=[10.0], n_syn=10000, n_rep=128, sweeps=10000,
+                      schedule=("geometric", 0.02, 20.0)),
+}
+WORKLOAD_INDEX = {name: k for k, name in enumerate(WORKLOADS)}
+SCHEDULE_KIND = {"linear": 0, "geometric": 1, "paper_log": 2}
+
+
+def seeds(name: str):
+    k = WORKLOAD_INDEX[name]
+    return dict(sample=1000 + k, greedy=2000 + k, anneal=3000 + k)
+
+
+def poisson_arrivals(rate: float, n: int, seed: int) -> np.ndarray:
+    """Arrival times (s) of n requests of a Poisson process."""
+    rng = np.random.default_rng([int(seed), 7])
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))

@@ -1,0 +1,193 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the oracle.
+
+Every integer output is compared element by element: greedy references and
+their classes, per-chain E_min / phase of the minimum / final energy / final
+state, per-coset minima, P*, the best chain, the minimum-energy recovery and
+R_0 L_P*.  Sizes span several wavefront tasks with ragged tails; the full
+workload shapes are covered by sampled chains (test_gpu_fullsize.py)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2509_17837_amd import _lib as X
+from paper_2509_17837_amd import decoder as D
+from tests._parity import Problem, compare_decode, gpu_plan, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm GPU visible")
+    X.lib()
+    torch.cuda.synchronize()
+
+
+def run_decode(prob, plan=None, flags=0, mode=X.GREEDY_RANDOM, want_final=True):
+    plan = plan or gpu_plan(prob)
+    print(f"[decode] layout={prob.layout} d={prob.d} n_syn={prob.n_syn} R={prob.n_rep} "
+          f"sweeps={prob.n_sweeps} lanes={plan.info()['lanes_per_chain']} flags={flags}", flush=True)
+    out = D.decode(plan, to_dev(prob.syn), to_dev(prob.uid.view(np.int32)), prob.n_rep, prob.greedy_seed,
+                   prob.anneal_seed, greedy_mode=mode, flags=flags, want_chains=True, want_final=want_final)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_syndrome_kernel():
+    for layout, d in [(0, 3), (0, 11), (0, 31), (1, 5), (1, 9)]:
+        prob = Problem(layout, d, 0.2, 3.0, 97, 1, 0)
+        plan = gpu_plan(prob)
+        rng = np.random.default_rng(d)
+        cfg = rng.integers(0, 4, (97, prob.olat.nq)).astype(np.uint8)
+        got = D.syndrome(plan, to_dev(cfg)).cpu().numpy()
+        assert np.array_equal(got, prob.olat.syndrome(cfg))
+
+
+@pytest.mark.parametrize("layout,d,p,eta", [(0, 3, 0.15, 10.0), (0, 11, 0.25, 100.0), (0, 21, 0.18, 10.0),
+                                            (0, 31, 0.2, 10.0), (1, 7, 0.1, 1.0)])
+@pytest.mark.parametrize("mode", [X.GREEDY_RANDOM, X.GREEDY_SAME, X.GREEDY_BOUNDARY])
+def test_greedy_kernel(layout, d, p, eta, mode):
+    n_syn, R = (12, 5) if d < 31 else (3, 4)
+    prob = Problem(layout, d, p, eta, n_syn, R, 0, seed=d + 3)
+    plan = gpu_plan(prob)
+    refs, qcls = D.greedy_init(plan, to_dev(prob.syn), to_dev(prob.uid.view(np.int32)), R, prob.greedy_seed, mode)
+    refs = refs.cpu().numpy()
+    qcls = qcls.cpu().numpy()
+    for i in range(n_syn):
+        for r in range(R):
+            exp = prob.oracle_greedy(i, r, mode)
+            assert np.array_equal(refs[i, r], exp), f"syndrome {i} replica {r}"
+            assert qcls[i, r] == prob.olat.cls(refs[i, r], refs[i, 0])
+
+
+def test_decode_small_d3_all():
+    """Distance 3, one replica, 200 linear sweeps, 1000 syndromes."""
+    prob = Problem(0, 3, 0.15, 10.0, 1000, 1, 200, sched=("linear", 0.1, 5.0), seed=1000)
+    out = run_decode(prob)
+    compare_decode(prob, out, prob.oracle_decode())
+
+
+@pytest.mark.parametrize("p", [0.10, 0.25])
+def test_decode_d11(p):
+    prob = Problem(0, 11, p, 100.0, 24, 32, 150, seed=int(p * 100))
+    out = run_decode(prob)
+    compare_decode(prob, out, prob.oracle_decode())
+
+
+@pytest.mark.parametrize("layout,d", [(1, 5), (1, 7), (0, 5), (0, 9)])
+def test_decode_layouts(layout, d):
+    prob = Problem(layout, d, 0.12, 5.0, 40, 3, 60, seed=d)
+    out = run_decode(prob)
+    compare_decode(prob, out, prob.oracle_decode())
+
+
+@pytest.mark.parametrize("d", [9, 25])
+def test_all_lane_counts_agree(d):
+    """Lanes per chain (chains per wavefront) is a result-invariant knob."""
+    prob = Problem(0, d, 0.2, 10.0, 5, 16, 12, seed=50 + d)
+    ref = prob.oracle_decode()
+    for lanes in (1, 2, 4, 8, 16, 32, 64):
+        plan = gpu_plan(prob)
+        try:
+            plan.set_lanes(lanes)
+        except X.XzzxError as e:
+            assert e.rc == X.XZZX_ERANGE   # too many chains for LDS at this d
+            continue
+        out = run_decode(prob, plan)
+        compare_decode(prob, out, ref)
+
+
+def test_plain_form_matches_persistent():
+    prob = Problem(0, 7, 0.15, 10.0, 9, 4, 40, seed=77)
+    ref = prob.oracle_decode()
+    compare_decode(prob, run_decode(prob, flags=X.FLAG_PLAIN), ref)
+    compare_decode(prob, run_decode(prob, flags=0), ref)
+
+
+def test_mixed_distances_one_launch():
+    """Uneven distances in one persistent launch (groups of d = 5..21)."""
+    probs = [Problem(0, d, 0.18, 10.0, n, 4, 30, seed=200 + d) for d, n in [(5, 7), (9, 5), (13, 3), (17, 2), (21, 2)]]
+    groups, outs = [], []
+    for prob in probs:
+        plan = gpu_plan(prob)
+        g, o = D.make_group(plan, prob.n_rep, to_dev(prob.uid.view(np.int32)), syn=to_dev(prob.syn),
+                            want_chains=True, want_final=True)
+        groups.append(g)
+        outs.append(o)
+    # one seed pair for the whole launch
+    for p in probs:
+        p.greedy_seed, p.anneal_seed = probs[0].greedy_seed, probs[0].anneal_seed
+    D.decode_groups(groups, probs[0].greedy_seed, probs[0].anneal_seed)
+    torch.cuda.synchronize()
+    for prob, o in zip(probs, outs):
+        compare_decode(prob, o, prob.oracle_decode())
+
+
+def test_edge_cases():
+    # no sweeps: E_min is the initial energy of each chain
+    prob = Problem(0, 5, 0.2, 10.0, 6, 3, 0, seed=5)
+    compare_decode(prob, run_decode(prob), prob.oracle_decode())
+    # beta = 0 everywhere: every move accepted
+    prob = Problem(0, 5, 0.2, 10.0, 4, 2, 9, seed=6, beta=np.zeros(9))
+    compare_decode(prob, run_decode(prob), prob.oracle_decode())
+    # very cold: only dE <= 0 moves
+    prob = Problem(0, 7, 0.2, 10.0, 4, 2, 9, seed=7, beta=np.full(9, 1e6))
+    compare_decode(prob, run_decode(prob), prob.oracle_decode())
+    # single chain group tail: n_syn * 4R not a multiple of the chains per wave
+    prob = Problem(0, 11, 0.2, 100.0, 3, 3, 20, seed=8)
+    compare_decode(prob, run_decode(prob), prob.oracle_decode())
+    # empty batch is a no-op
+    prob = Problem(0, 5, 0.2, 10.0, 0, 2, 5, seed=9)
+    plan = gpu_plan(prob)
+    out = D.decode(plan, torch.zeros((0, prob.olat.nstab), dtype=torch.uint8, device="cuda"),
+                   torch.zeros(0, dtype=torch.int32, device="cuda"), 2, 1, 2)
+    torch.cuda.synchronize()
+    assert out.e_best.numel() == 0
+
+
+def test_anneal_from_given_references():
+    """xzzx_anneal: annealing from caller-supplied references (here the
+    oracle's own greedy output) without the greedy stage."""
+    prob = Problem(0, 9, 0.15, 10.0, 6, 4, 30, seed=31)
+    ref = prob.oracle_decode()
+    plan = gpu_plan(prob)
+    refs = to_dev(np.stack([r["refs"] for r in ref]))
+    qcls = to_dev(np.stack([r["qcls"] for r in ref]).astype(np.uint8))
+    g, o = D.make_group(plan, prob.n_rep, to_dev(prob.uid.view(np.int32)), refs=refs, qcls=qcls,
+                        want_chains=True, want_final=True)
+    D.anneal_groups([g], prob.anneal_seed)
+    torch.cuda.synchronize()
+    compare_decode(prob, o, ref)
+
+
+def test_graph_replays_match_eager():
+    prob = Problem(0, 9, 0.2, 10.0, 10, 8, 25, seed=44)
+    ref = prob.oracle_decode()
+    plan = gpu_plan(prob)
+    syn = to_dev(prob.syn)
+    uid = to_dev(prob.uid.view(np.int32))
+    g, o = D.make_group(plan, prob.n_rep, uid, syn=syn, want_chains=True, want_final=True)
+    graph = D.Graph([g], prob.greedy_seed, prob.anneal_seed)
+    for rep in range(3):
+        for t in (o.e_best, o.recovery, o.chain_emin, o.chain_final):
+            t.fill_(0x55 if t.dtype == torch.uint8 else -7)
+        graph.launch()
+        graph.stream.synchronize()
+        compare_decode(prob, o, ref)
+        # eager work in between replays
+        out2 = run_decode(prob, plan)
+        compare_decode(prob, out2, ref)
+
+
+def test_bad_arguments_raise():
+    prob = Problem(0, 5, 0.2, 10.0, 4, 2, 5, seed=3)
+    plan = gpu_plan(prob)
+    with pytest.raises(X.XzzxError):
+        plan.set_lanes(3)
+    g, o = D.make_group(plan, 2, to_dev(prob.uid.view(np.int32)), syn=to_dev(prob.syn))
+    tiny = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(X.XzzxError) as e:
+        D.decode_groups([g], 1, 2, ws=tiny)
+    assert e.value.rc == X.XZZX_ENOMEM
