@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the XZZX simulated-annealing decoder on one MI355X.
+
+A step is one pass of the whole decoder (greedy references, annealing of
+every chain, per-syndrome reduction and recovery) over one batch of freshly
+sampled syndromes already resident in HBM.  Default workload: rotated XZZX
+d = 11, eta = 100, p in {0.10, 0.15, 0.20, 0.25} (one syndrome group per p,
+all four in one persistent launch), 32 replicas (128 chains) per syndrome,
+2000 sweeps of a geometric beta schedule 0.05 -> 10.
+
+Prints one JSON line: flip attempts/s (value), decodes/s, the annealing
+kernel's share of the ALU roofline (timed with HIP events on its own stream),
+a CPU-oracle baseline on a bounded sample, and the plain one-launch-per-
+syndrome form on the same GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic integer lane-operations per flip attempt:
+#   Philox4x32-10 share: 10 rounds x (2 mul-lo + 2 mul-hi + 4 xor + 2 key adds)
+#   per 4 draws = 25; move evaluation: 3 pattern shifts/ors + 1 table index +
+#   3 acceptance compare/or + 1 energy add + 4 flips (xor) = 12; total 37.
+OPS_PER_ATTEMPT = 37
+# MI355X int32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_OPS = 256 * 64 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="d11_bias100")
+    ap.add_argument("--batch", type=int, default=2048, help="syndromes per group per step")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-syndromes", type=int, default=32)
+    ap.add_argument("--eager", action="store_true", help="no hipGraph capture")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this decoder shards by syndrome with no communication, "
+              "and multi-GPU runs are not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2509_17837_amd import _lib as X
+    from paper_2509_17837_amd import decoder as D
+    from paper_2509_17837_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    wl = inputs.WORKLOADS[args.workload]
+    seeds = inputs.seeds(args.workload)
+    sched_kind = inputs.SCHEDULE_KIND[wl["schedule"][0]]
+    sweeps = wl["sweeps"]
+    R = wl["n_rep"]
+    B = args.batch
+    steps, warm = args.steps, args.warmup
+    dev = torch.device("cuda:0")
+
+    # ---- plans: one group per (d, p, eta) --------------------------------
+    specs = [(d, p, eta) for d in wl["d"] for p in wl["p"] for eta in wl["eta"]]
+    plans, lats = [], {}
+    beta = D.schedule(sched_kind, wl["schedule"][1], wl["schedule"][2], sweeps)
+    for d, p, eta in specs:
+        if d not in lats:
+            lats[d] = D.Lattice(X.ROTATED, d)
+        w, wg = D.weights(p, D.noise(p, eta))
+        plans.append(D.Plan(lats[d], w, wg, beta))
+    ng = len(plans)
+
+    # ---- inputs for every step, resident in HBM before timing ------------
+    syn_all, uid_all, err_all = [], [], []
+    for k in range(steps + warm):
+        row_s, row_u, row_e = [], [], []
+        for gi, ((d, p, eta), plan) in enumerate(zip(specs, plans)):
+            err = inputs.sample_errors(B, plan.nq, inputs.channel(p, eta), seeds["sample"], stream=k * 64 + gi)
+            e_dev = torch.from_numpy(err).to(dev)
+            row_s.append(D.syndrome(plan, e_dev))
+            row_u.append(torch.from_numpy(inputs.sample_uids(B, (k * ng + gi) * B).view(np.int32)).to(dev))
+            row_e.append(err)
+        syn_all.append(row_s)
+        uid_all.append(row_u)
+        err_all.append(row_e)
+    torch.cuda.synchronize()
+
+    syn_buf = [torch.empty_like(syn_all[0][g]) for g in range(ng)]
+    uid_buf = [torch.empty_like(uid_all[0][g]) for g in range(ng)]
+    groups, outs = [], []
+    for g in range(ng):
+        grp, o = D.make_group(plans[g], R, uid_buf[g], syn=syn_buf[g], want_extra=False)
+        groups.append(grp)
+        outs.append(o)
+    gs, as_ = seeds["greedy"], seeds["anneal"]
+    stage_flags = [X.STAGE_GREEDY, X.STAGE_ANNEAL, X.STAGE_FINISH]
+    ws = D.workspace(groups)
+    graphs = None
+    if not args.eager:
+        cap = torch.cuda.Stream()
+        graphs = [D.Graph(groups, gs, as_, X.GREEDY_RANDOM, f, stream=cap, ws=ws) for f in stage_flags]
+        torch.cuda.synchronize()
+
+    cur = torch.cuda.current_stream()
+
+    def run_step(k, ev=None):
+        for g in range(ng):
+            syn_buf[g].copy_(syn_all[k][g], non_blocking=True)
+            uid_buf[g].copy_(uid_all[k][g], non_blocking=True)
+        for si, f in enumerate(stage_flags):
+            if ev is not None:
+                ev[si].record(cur)
+            if graphs is not None:
+                graphs[si].launch(cur)
+            else:
+                D.decode_groups(groups, gs, as_, X.GREEDY_RANDOM, f, ws=ws)
+        if ev is not None:
+            ev[3].record(cur)
+
+    for k in range(warm):
+        run_step(k)
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        run_step(warm + k, events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    stage_ms = [float(np.mean([events[k][i].elapsed_time(events[k][i + 1]) for k in range(steps)])) for i in range(3)]
+
+    nstab = [plan.nstab for plan in plans]
+    attempts_step = sum(B * 4 * R * sweeps * ns for ns in nstab)
+    syndromes_step = B * ng
+    value = steps * attempts_step / elapsed
+    decodes = steps * syndromes_step / elapsed
+    anneal_s = stage_ms[1] / 1e3
+    achieved_ops = attempts_step * OPS_PER_ATTEMPT / anneal_s
+
+    # logical error rate of the last timed batch: [C_true * recovery] != I
+    last = warm + steps - 1
+    ler = {}
+    for g, (d, p, eta) in enumerate(specs):
+        rec = outs[g].recovery.cpu().numpy()
+        err = err_all[last][g]
+        fails = sum(1 for i in range(B) if lats[d].cls(err[i], rec[i]) != 0)
+        ler[f"d{d}_p{p}_eta{eta:g}"] = fails / B
+
+    result = {
+        "metric": "stabilizer-flip attempts/s",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"rotated XZZX d={','.join(str(d) for d in wl['d'])}, eta={wl['eta']}, p={wl['p']}, "
+                        f"{R} replicas ({4 * R} chains)/syndrome, {sweeps} sweeps {wl['schedule'][0]} "
+                        f"{wl['schedule'][1]}->{wl['schedule'][2]}",
+            "name": args.workload,
+            "syndromes_per_step": syndromes_step,
+            "attempts_per_step": attempts_step,
+            "graphs": graphs is not None,
+            "seeds": seeds,
+        },
+        "decodes_per_s": decodes,
+        "stage_ms": {"greedy": stage_ms[0], "anneal": stage_ms[1], "finish": stage_ms[2]},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_anneal",
+            "achieved": achieved_ops / 1e12,
+            "peak": ALU_PEAK_OPS / 1e12,
+            "unit": "Tops/s (int32 lane-ops)",
+            "frac": achieved_ops / ALU_PEAK_OPS,
+            "traffic": None,
+            "ops_per_attempt": OPS_PER_ATTEMPT,
+            "anneal_ms_per_launch": stage_ms[1],
+        },
+        "logical_error_rate": ler,
+    }
+
+    if not args.no_plain:
+        # plain form: one annealing launch per syndrome (no persistence, no graph)
+        g0 = 0
+        n = min(args.plain_syndromes, B)
+        pg, po = D.make_group(plans[g0], R, uid_all[last][g0][:n].contiguous(), syn=syn_all[last][g0][:n].contiguous(),
+                              want_extra=False)
+        pws = D.workspace([pg])
+        D.decode_groups([pg], gs, as_, X.GREEDY_RANDOM, X.STAGE_GREEDY, ws=pws)
+        torch.cuda.synchronize()
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(cur)
+        D.decode_groups([pg], gs, as_, X.GREEDY_RANDOM, X.STAGE_ANNEAL | X.FLAG_PLAIN, ws=pws)
+        eb.record(cur)
+        torch.cuda.synchronize()
+        plain_s = ea.elapsed_time(eb) / 1e3
+        D.decode_groups([pg], gs, as_, X.GREEDY_RANDOM, X.STAGE_FINISH, ws=pws)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(po.recovery, outs[g0].recovery[:n]) and torch.equal(po.e_best, outs[g0].e_best[:n]))
+        plain_rate = n * 4 * R * sweeps * nstab[g0] / plain_s
+        result["plain_form"] = {
+            "value": plain_rate, "unit": "attempts/s", "syndromes": n,
+            "batched_over_plain": (attempts_step / anneal_s) / plain_rate,
+            "same_results_as_batched": same,
+        }
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(args, wl, specs, plans, syn_all[last], uid_all[last], outs,
+                                              R, sweeps, gs, as_)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(args, wl, specs, plans, syn0, uid0, outs, R, sweeps, gs, as_):
+    """Time the oracle (plain C, one thread per syndrome) on a bounded sample
+    of the last timed batch, and check the sample against the GPU results."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as O
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    ng = len(specs)
+    sched = wl["schedule"]
+    obeta = O.schedule({"linear": 0, "geometric": 1, "paper_log": 2}[sched[0]], sched[1], sched[2], sweeps)
+    owts = [O.weights(p, O.noise(p, eta)) for (_, p, eta) in specs]
+    syn = [s.cpu().numpy() for s in syn0]
+    uid = [u.cpu().numpy().view(np.uint32) for u in uid0]
+
+    def one(job):
+        g, i = job
+        d = specs[g][0]
+        lat = O.Lattice(O.ROTATED, d)
+        return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, gs, as_)
+
+    # size the sample from one timed syndrome
+    t = time.perf_counter()
+    one((0, 0))
+    per = time.perf_counter() - t
+    n = max(threads, int(args.cpu_seconds * threads / max(per, 1e-6)))
+    n = min(n, 4 * len(syn[0]))
+    jobs = [(i % ng, i // ng) for i in range(n)]
+    t = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(one, jobs))
+    wall = time.perf_counter() - t
+    attempts = sum(4 * R * sweeps * plans[g].nstab for g, _ in jobs)
+    out = {
+        "value": attempts / wall,
+        "unit": "attempts/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{n} syndromes of the last timed batch (groups round-robin), full decode "
+                  f"({R} replicas, {sweeps} sweeps), {wall:.1f} s wall",
+        "decodes_per_s": n / wall,
+    }
+    ok = 0
+    for (g, i), r in zip(jobs, res):
+        ok += int(outs[g].e_best[i].item() == r["e_best"] and outs[g].cls[i].item() == r["cls"] and
+                  np.array_equal(outs[g].recovery[i].cpu().numpy(), r["recovery"]))
+    out["bitexact_with_gpu"] = f"{ok}/{n}"
+    return out
+
+
+if __name__ == "__main__":
+    main()

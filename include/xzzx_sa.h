@@ -73,7 +73,13 @@ enum { XZZX_GREEDY_RANDOM = 0, XZZX_GREEDY_SAME = 1, XZZX_GREEDY_BOUNDARY = 2 };
 
 /* decode flags */
 enum {
-    XZZX_FLAG_PLAIN = 1 /* one anneal launch per syndrome, no persistent queue */
+    XZZX_FLAG_PLAIN = 1,         /* one anneal launch per syndrome, no persistent queue */
+    /* Stage selection (none set = all stages).  Stages communicate through the
+     * workspace, so a split decode passes the same groups and workspace to
+     * each call, in this order. */
+    XZZX_FLAG_STAGE_GREEDY = 2,  /* greedy references and their classes */
+    XZZX_FLAG_STAGE_ANNEAL = 4,  /* annealing of every chain */
+    XZZX_FLAG_STAGE_FINISH = 8   /* per-syndrome reduction and recovery */
 };
 
 typedef struct xzzx_lattice xzzx_lattice;

@@ -18,6 +18,7 @@ BIAS_BASELINE, BIAS_PAPER = 0, 1
 SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
 FLAG_PLAIN = 1
+STAGE_GREEDY, STAGE_ANNEAL, STAGE_FINISH = 2, 4, 8
 
 _STATUS = {
     XZZX_EINVAL: "EINVAL", XZZX_ENOMEM: "ENOMEM", XZZX_EDEVICE: "EDEVICE",

@@ -796,15 +796,19 @@ static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_se
     p += 256;
     std::vector<GroupWs> ws(n_groups);
     for (int i = 0; i < n_groups; ++i) ws[i] = carve_group(groups[i], decode, p);
+    const int stage_bits = XZZX_FLAG_STAGE_GREEDY | XZZX_FLAG_STAGE_ANNEAL | XZZX_FLAG_STAGE_FINISH;
+    const int stages = (flags & stage_bits) ? (flags & stage_bits) : stage_bits;
     for (int i = 0; i < n_groups; ++i) {
         const xzzx_group &g = groups[i];
-        if (!decode || g.n_syn == 0) continue;
+        if (!decode || g.n_syn == 0 || !(stages & XZZX_FLAG_STAGE_GREEDY)) continue;
         rc = launch_greedy(g.plan->P, g.d_syn, g.d_uid, g.n_syn, g.n_rep, greedy_seed, greedy_mode, ws[i].refs,
                            ws[i].qraw, stream);
         if (!rc) rc = launch_qcls(ws[i].qraw, g.n_syn, g.n_rep, ws[i].qcls, stream);
         if (rc) return rc;
     }
-    if (flags & XZZX_FLAG_PLAIN) {
+    if (!(stages & XZZX_FLAG_STAGE_ANNEAL)) {
+        // annealing skipped in this call
+    } else if (flags & XZZX_FLAG_PLAIN) {
         // one launch per syndrome, grid = its own tasks, no persistence
         for (int i = 0; i < n_groups; ++i) {
             const xzzx_group &g = groups[i];
@@ -817,6 +821,7 @@ static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_se
         rc = launch_anneal(groups, ws.data(), n_groups, false, anneal_seed, 0, -1, counter, stream, false);
         if (rc) return rc;
     }
+    if (!(stages & XZZX_FLAG_STAGE_FINISH)) return XZZX_OK;
     for (int i = 0; i < n_groups; ++i) {
         rc = launch_reduce(groups[i], ws[i], stream);
         if (rc) return rc;

@@ -249,10 +249,10 @@ def decode(plan: Plan, syn: torch.Tensor, uid: torch.Tensor, n_rep: int, greedy_
 class Graph:
     """One captured decode (hipGraph) over fixed buffers."""
 
-    def __init__(self, groups, greedy_seed, anneal_seed, greedy_mode=X.GREEDY_RANDOM, flags=0, stream=None):
+    def __init__(self, groups, greedy_seed, anneal_seed, greedy_mode=X.GREEDY_RANDOM, flags=0, stream=None, ws=None):
         self.groups = groups
         self.arr = _groups_array(groups)
-        self.ws = workspace(groups)
+        self.ws = ws if ws is not None else workspace(groups)
         self.stream = stream if stream is not None else torch.cuda.Stream()
         h = C.c_void_p()
         call("xzzx_graph_create", self.arr, len(groups), greedy_seed, anneal_seed, greedy_mode, flags,
