@@ -26,13 +26,16 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic integer lane-operations per flip attempt (see DESIGN.md):
-#   Philox4x32-10 share: 10 rounds x (2 mul-lo + 2 mul-hi + 4 xor + 2 key adds)
-#   per 4 draws = 25; move evaluation: 3 pattern shifts/ors + 1 table index +
-#   3 acceptance compare/or + 1 energy add + 4 flips (xor) = 12; total 37.
-OPS_PER_ATTEMPT = 37
-# MI355X int32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-ALU_PEAK_OPS = 256 * 64 * 2.4e9
+# Algorithmic integer lane-operations per flip attempt:
+#   random draw: a quarter of a Philox4x32-10 block = 2.5 rounds x (2 widening
+#   32x32 multiplies + 2 three-input XORs) = 10;
+#   move: 8-bit pattern of the generator's four 2-bit codes (3), energy-table
+#   index (1), acceptance compares (2), energy update (1), flip of the two row
+#   words (2) = 9;  total 19.
+OPS_PER_ATTEMPT = 19
+# MI355X int32 vector issue peak: 256 CUs x 128 lane-ops per clock x 2.4 GHz
+# (the rate of its 157.3 TFLOP/s fp32 vector figure, counting an FMA as 2).
+ALU_PEAK_OPS = 256 * 128 * 2.4e9
 
 
 def parse():
@@ -187,7 +190,7 @@ def main():
         "stage_ms": {"greedy": stage_ms[0], "anneal": stage_ms[1], "finish": stage_ms[2]},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_anneal",
+            "kernel": "k_anneal_rows" if all(pl.info()["kernel"] == X.KERNEL_ROWS for pl in plans) else "k_anneal",
             "achieved": achieved_ops / 1e12,
             "peak": ALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (int32 lane-ops)",

@@ -153,14 +153,26 @@ int xzzx_plan_create(const xzzx_lattice *lat, const int32_t w[4], const int32_t 
                      const double *beta, int n_sweeps, xzzx_plan **out);
 void xzzx_plan_destroy(xzzx_plan *plan);
 
-/* Plan facts: number of distinct move energies, lanes per chain in use. */
+/* Plan facts (any pointer may be NULL): sizes, number of distinct move
+ * energies, lanes per chain of the byte-state kernel, and the annealing kernel
+ * in use (XZZX_KERNEL_ROWS or XZZX_KERNEL_BYTES). */
 int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sweeps,
-                   int *n_dE, int *lanes_per_chain);
+                   int *n_dE, int *lanes_per_chain, int *kernel);
 
-/* Result-invariant tuning knob: lanes of a wavefront cooperating on one chain
- * (1, 2, 4, ..., 64); chains per wavefront = 64 / lanes.  0 restores the
- * built-in choice. */
+/* Result-invariant tuning knob of the byte-state kernel: lanes of a wavefront
+ * cooperating on one chain (1, 2, 4, ..., 64); chains per wavefront =
+ * 64 / lanes.  A non-zero value also selects that kernel; 0 restores the
+ * built-in choice (and the default kernel). */
 int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain);
+
+/* Which annealing kernel a plan uses (results are identical):
+ *   XZZX_KERNEL_ROWS: one chain per lane, 2-bit codes packed row by row in
+ *     LDS and staged through registers (rotated lattices with d <= 29);
+ *   XZZX_KERNEL_BYTES: byte-per-qubit states, lanes_per_chain lanes per chain;
+ *   XZZX_KERNEL_AUTO: ROWS where it applies, else BYTES (the default).
+ * EINVAL for ROWS on a lattice it does not cover. */
+enum { XZZX_KERNEL_AUTO = 0, XZZX_KERNEL_ROWS = 1, XZZX_KERNEL_BYTES = 2 };
+int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel);
 
 /* ---- device operations ---------------------------------------------------- */
 

@@ -19,6 +19,7 @@ SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
 FLAG_PLAIN = 1
 STAGE_GREEDY, STAGE_ANNEAL, STAGE_FINISH = 2, 4, 8
+KERNEL_AUTO, KERNEL_ROWS, KERNEL_BYTES = 0, 1, 2
 
 _STATUS = {
     XZZX_EINVAL: "EINVAL", XZZX_ENOMEM: "ENOMEM", XZZX_EDEVICE: "EDEVICE",
@@ -114,8 +115,9 @@ def lib():
         "xzzx_class_host": (I, [V, V, V, P(I)]),
         "xzzx_plan_create": (I, [V, V, V, V, I, P(V)]),
         "xzzx_plan_destroy": (None, [V]),
-        "xzzx_plan_info": (I, [V, P(I), P(I), P(I), P(I), P(I)]),
+        "xzzx_plan_info": (I, [V, P(I), P(I), P(I), P(I), P(I), P(I)]),
         "xzzx_plan_set_lanes": (I, [V, I]),
+        "xzzx_plan_set_kernel": (I, [V, I]),
         "xzzx_syndrome": (I, [V, V, I64, V, V]),
         "xzzx_greedy_init": (I, [V, V, V, I64, I, U64, I, V, V, V]),
         "xzzx_decode_workspace": (I, [P(Group), I, P(C.c_size_t)]),

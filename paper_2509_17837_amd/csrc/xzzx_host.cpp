@@ -51,6 +51,8 @@ static void finish_lattice(Lattice &L, std::vector<FaceRec> &faces)
     L.fclass.resize(L.nstab);
     L.fcolour.resize(L.nstab);
     L.frank.resize(L.nstab);
+    L.fcx.resize(L.nstab);
+    L.fcy.resize(L.nstab);
     L.by_class.assign(4 * L.per_class, -1);
     int seen[4] = {0, 0, 0, 0};
     for (int f = 0; f < L.nstab; ++f) {
@@ -60,6 +62,8 @@ static void finish_lattice(Lattice &L, std::vector<FaceRec> &faces)
         }
         L.fclass[f] = faces[f].cls;
         L.fcolour[f] = faces[f].colour;
+        L.fcx[f] = faces[f].cx;
+        L.fcy[f] = faces[f].cy;
         int r = seen[faces[f].cls]++;
         L.frank[f] = r;
         if (r < L.per_class) L.by_class[faces[f].cls * L.per_class + r] = f;
@@ -187,6 +191,26 @@ size_t Plan::lds_bytes_anneal(int lanes_per_chain) const
     off = (off + 15) & ~size_t(15);
     off += (size_t)(lat.nq + 1) * C;                 // states, one scratch byte per chain
     return (off + 15) & ~size_t(15);
+}
+
+size_t Plan::lds_bytes_rows() const
+{
+    size_t off = 256 * (size_t)ntypes;               // move-energy ranks
+    off = (off + 7) & ~size_t(7);
+    off += 8 * dE.size();                            // (dE, threshold) pairs
+    off = (off + 15) & ~size_t(15);
+    off += (size_t)4 * kWave * row_words * (lat.d + 2);
+    return (off + 15) & ~size_t(15);
+}
+
+// Packed-row layout (rotated lattice): the padded grid has columns and rows
+// -1..d; a row of 2-bit codes takes 2(d+2) bits, so 1 word for d <= 13 and 2
+// words for d <= 29.
+static int row_words_for(const Lattice &L)
+{
+    if (L.layout != XZZX_ROTATED) return 0;
+    const int bits = 2 * (L.d + 2);
+    return bits <= 32 ? 1 : (bits <= 64 ? 2 : 0);
 }
 
 static int default_lanes(const Lattice &L)
@@ -360,6 +384,19 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     for (int t = 0; t < n_sweeps; ++t)
         for (int r = 0; r < nranks; ++r) thr[(size_t)t * nranks + r] = accept_threshold(P.beta[t], all[r]);
 
+    P.row_words = row_words_for(L);
+    // packed-row descriptors by (class, rank), each class padded to a
+    // multiple of 4 entries so a block of four is read at once
+    const int mpad = 4 * ((L.per_class + 3) / 4);
+    std::vector<uint32_t> rowface(4 * mpad, 0);
+    if (P.row_words) {
+        for (int k = 0; k < 4; ++k)
+            for (int m = 0; m < L.per_class; ++m) {
+                const int f = L.by_class[k * L.per_class + m];
+                const uint32_t Y = (uint32_t)(L.fcy[f] + 1), X = (uint32_t)(L.fcx[f] + 1);
+                rowface[k * mpad + m] = Y | ((2u * X) << 8) | ((uint32_t)shape_of_face[f] << 16);
+            }
+    }
     std::vector<Desc> desc(4 * L.per_class), fdesc(L.nstab);
     for (int f = 0; f < L.nstab; ++f) fdesc[f] = pack_desc(L, f, shape_of_face[f]);
     for (int k = 0; k < 4; ++k)
@@ -373,6 +410,7 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~size_t(255); return o; };
     const size_t o_hdr = take(sizeof(PlanDev));
+    const size_t o_rowface = take(rowface.size() * 4);
     const size_t o_desc = take(desc.size() * sizeof(Desc));
     const size_t o_fdesc = take(fdesc.size() * sizeof(Desc));
     const size_t o_lut = take(lut.size());
@@ -392,6 +430,7 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     if (hipMalloc(&P.dmem, P.dbytes) != hipSuccess) { P.dmem = nullptr; set_error("hipMalloc of plan tables failed"); return XZZX_ENOMEM; }
     std::vector<uint8_t> host(P.dbytes, 0);
     auto put = [&](size_t o, const void *src, size_t n) { if (n) std::memcpy(host.data() + o, src, n); };
+    put(o_rowface, rowface.data(), rowface.size() * 4);
     put(o_desc, desc.data(), desc.size() * sizeof(Desc));
     put(o_fdesc, fdesc.data(), fdesc.size() * sizeof(Desc));
     put(o_lut, lut.data(), lut.size());
@@ -423,6 +462,10 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     h.lanes = P.lanes;
     h.layout = L.layout;
     h.d = L.d;
+    h.row_words = P.row_words;
+    h.rows = L.d + 2;
+    P.use_rows = P.row_words ? 1 : 0;
+    h.rowface = reinterpret_cast<const uint32_t *>(base + o_rowface);
     std::memcpy(h.W, w, sizeof(h.W));
     h.desc = reinterpret_cast<const Desc *>(base + o_desc);
     h.face_desc = reinterpret_cast<const Desc *>(base + o_fdesc);
@@ -629,9 +672,27 @@ void xzzx_plan_destroy(xzzx_plan *plan)
     delete plan;
 }
 
-int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sweeps, int *n_dE,
-                   int *lanes_per_chain)
+int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel)
 {
+    if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
+    if (kernel == XZZX_KERNEL_AUTO) {
+        plan->P.use_rows = plan->P.row_words ? 1 : 0;
+    } else if (kernel == XZZX_KERNEL_ROWS) {
+        if (!plan->P.row_words) { set_error("the packed-row kernel needs a rotated lattice with d <= 29"); return XZZX_EINVAL; }
+        plan->P.use_rows = 1;
+    } else if (kernel == XZZX_KERNEL_BYTES) {
+        plan->P.use_rows = 0;
+    } else {
+        set_error("unknown kernel");
+        return XZZX_EINVAL;
+    }
+    return XZZX_OK;
+}
+
+int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sweeps, int *n_dE,
+                   int *lanes_per_chain, int *kernel)
+{
+    if (plan && kernel) *kernel = plan->P.use_rows ? XZZX_KERNEL_ROWS : XZZX_KERNEL_BYTES;
     if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
     if (n_qubits) *n_qubits = plan->P.lat.nq;
     if (n_stabs) *n_stabs = plan->P.lat.nstab;
@@ -649,6 +710,7 @@ int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain)
     if (plan->P.lds_bytes_anneal(g) > 65536) { set_error("chains per wavefront do not fit in LDS"); return XZZX_ERANGE; }
     plan->P.lanes = g;
     plan->P.hdev.lanes = g;
+    plan->P.use_rows = (lanes_per_chain == 0 && plan->P.row_words) ? 1 : 0;
     if (hipMemcpy(&plan->P.ddev->lanes, &g, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
         set_error("plan update failed");
         return XZZX_EDEVICE;

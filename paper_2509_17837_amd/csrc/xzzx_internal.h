@@ -33,6 +33,7 @@ struct Lattice {
     std::vector<int32_t> fq;      // [nstab][4], -1 absent
     std::vector<uint8_t> fm;      // [nstab][4] Pauli code of the generator on the slot
     std::vector<int32_t> fclass, fcolour, frank;
+    std::vector<int32_t> fcx, fcy;  // face coordinates (rotated: cell (i,j); planar: doubled (x,y))
     std::vector<uint8_t> lx, lz;
     std::vector<int32_t> by_class;  // [4][per_class] face id
 };
@@ -44,7 +45,10 @@ struct PlanDev {
     int n_sweeps;
     int lanes;                     // lanes per chain (1..64)
     int layout, d;
+    int row_words;                 // packed-row kernel: 32-bit words per lattice row (0 = unavailable)
+    int rows;                      // rows of the padded grid (d + 2)
     int32_t W[4];
+    const uint32_t *rowface;       // [4][4*nblk] row | bit offset << 8 | shape << 16 (packed-row kernel)
     const Desc *desc;              // [4][M] by (class, rank)
     const Desc *face_desc;         // [nstab] by face id
     const uint8_t *lut;            // [ntypes][256] move-energy rank of a slot pattern
@@ -68,12 +72,15 @@ struct Plan {
     int kneg = 0;
     int ntypes = 0;
     int lanes_default = 1, lanes = 1;
+    int row_words = 0;             // 0: the packed-row kernel does not apply to this lattice
+    int use_rows = 0;              // 1: annealing runs on the packed-row kernel
     int device = 0;
     void *dmem = nullptr;          // device allocation holding every table
     size_t dbytes = 0;
     PlanDev hdev{};                // host copy with device pointers
     PlanDev *ddev = nullptr;       // device copy of hdev (inside dmem)
     size_t lds_bytes_anneal(int lanes) const;
+    size_t lds_bytes_rows() const;
 };
 
 // ---- host helpers (xzzx_host.cpp) ----

@@ -29,14 +29,20 @@ namespace xzzx {
 // by the Philox multipliers, high/low halves crossed with the other words and
 // the round key; the key advances by the two Weyl increments.
 // ---------------------------------------------------------------------------
+// Three-input XOR as one gfx950 v_bitop3_b32 (truth table 0x96 = odd parity).
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t key)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, key, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
         const uint64_t p0 = (uint64_t)c.x * 0xD2511F53u;
         const uint64_t p1 = (uint64_t)c.z * 0xCD9E8D57u;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
-                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        c = make_uint4(xor3_key((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                       xor3_key((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -325,12 +331,12 @@ struct GroupArgs {
     int64_t task_begin;           // first task index of this group
     int n_rep;
     int log_lanes;
+    int row_words;                // packed-row kernel: words per row (1 or 2)
 };
 
 struct AnnealArgs {
     GroupArgs g[kMaxGroups];
     int n_groups;
-    int replay;
     uint32_t n_tasks;
     uint32_t *counter;
     uint32_t seed_lo, seed_hi;
@@ -350,7 +356,7 @@ __device__ __forceinline__ LdsLayout lds_layout(int M, int ntypes, int nranks)
     return o;
 }
 
-template <int LOGG>
+template <int LOGG, bool REPLAY>
 __device__ void anneal_task(const AnnealArgs &A, const GroupArgs &G, int64_t unit0, uint8_t *smem)
 {
     constexpr int LOGC = 6 - LOGG;
@@ -375,7 +381,7 @@ __device__ void anneal_task(const AnnealArgs &A, const GroupArgs &G, int64_t uni
     int64_t s;
     int cc;
     int32_t target = -1;
-    if (A.replay) {
+    if (REPLAY) {
         s = u_abs;
         cc = G.best_chain[s];
         target = G.stop[s * nc + cc];
@@ -407,7 +413,7 @@ __device__ void anneal_task(const AnnealArgs &A, const GroupArgs &G, int64_t uni
         for (int q = gl; q < nq; q += (1 << LOGG)) dst[q] = st[(q << LOGC) + c];
     };
     int32_t last_phase = 4 * n_sweeps;
-    if (A.replay) {
+    if (REPLAY) {
         if (active && target == 0) save_state(G.recovery + (size_t)s * nq);
         int32_t tmax = active ? target : 0;
 #pragma unroll
@@ -451,18 +457,253 @@ __device__ void anneal_task(const AnnealArgs &A, const GroupArgs &G, int64_t uni
             E += chain_sum<LOGG>(acc_de);
             const int32_t phase = 4 * t + k + 1;
             if (E < Emin) { Emin = E; stop = phase; }
-            if (A.replay && active && phase == target) save_state(G.recovery + (size_t)s * nq);
+            if (REPLAY && active && phase == target) save_state(G.recovery + (size_t)s * nq);
         }
     }
-    if (!A.replay && active && gl == 0) {
+    if (!REPLAY && active && gl == 0) {
         const int64_t ci = u_abs;
         G.emin[ci] = Emin;
         G.stop[ci] = stop;
         G.efin[ci] = E;
     }
-    if (!A.replay && active && G.final) save_state(G.final + (size_t)u_abs * nq);
+    if (!REPLAY && active && G.final) save_state(G.final + (size_t)u_abs * nq);
     wave_lds_fence();
 }
+
+
+// ---------------------------------------------------------------------------
+// Packed-row annealing (rotated lattices, d <= 29): one chain per lane.  The
+// padded grid (columns and rows -1..d) is stored as 2-bit codes, each lattice
+// row in NW 32-bit words; word w of row Y of the chain in lane l sits at
+// rows_s[(Y*NW + w)*64 + l], so a wavefront's row accesses are 64 consecutive
+// dwords.  The generators of a colour class are visited in rank order; a
+// generator at cell (i,j) covers the 4-bit nibble at bit 2(i+1) of rows j+1
+// (slots X_left, Z_up) and j+2 (slots Z_down, X_right).  The two rows are held
+// in registers while the class visits that row, so LDS traffic per move is
+// the two table lookups.  Generator tables are uniform across the wavefront
+// and read through the scalar cache.
+// ---------------------------------------------------------------------------
+typedef const __attribute__((address_space(4))) uint32_t const_u32;
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+struct RowsLds {
+    uint32_t lut, et, rows;
+};
+
+__device__ __forceinline__ RowsLds rows_layout(int ntypes, int nranks)
+{
+    RowsLds o;
+    o.lut = 0;
+    o.et = (256u * (uint32_t)ntypes + 7u) & ~7u;
+    o.rows = (o.et + 8u * (uint32_t)nranks + 15u) & ~15u;
+    return o;
+}
+
+template <int NW>
+__device__ __forceinline__ uint32_t row_nibble(const uint32_t (&r)[NW], uint32_t bo)
+{
+    if (NW == 1) return __builtin_amdgcn_ubfe(r[0], bo, 4);
+    if (bo < 32) return __builtin_amdgcn_alignbit(r[NW > 1 ? 1 : 0], r[0], bo) & 0xFu;
+    return __builtin_amdgcn_ubfe(r[NW > 1 ? 1 : 0], bo - 32, 4);
+}
+
+template <int NW>
+__device__ __forceinline__ void row_flip(uint32_t (&r)[NW], uint32_t bo, uint32_t mask)
+{
+    if (NW == 1) {
+        r[0] ^= mask << bo;
+        return;
+    }
+    if (bo < 32) {
+        r[0] ^= mask << bo;
+        if (bo > 28) r[NW > 1 ? 1 : 0] ^= mask >> (32 - bo);
+    } else {
+        r[NW > 1 ? 1 : 0] ^= mask << (bo - 32);
+    }
+}
+
+template <int NW, bool PLAIN>
+__device__ void rows_task(const AnnealArgs &A, const GroupArgs &G, int64_t unit0, uint8_t *smem)
+{
+    const PlanDev *pl = G.plan;
+    const int lane = threadIdx.x;
+    const int d = (int)uni(pl->d), nq = (int)uni(pl->nq), M = (int)uni(pl->M), nblk = (int)uni(pl->nblk);
+    const int nranks = (int)uni(pl->nranks), n_sweeps = (int)uni(pl->n_sweeps), ntypes = (int)uni(pl->ntypes);
+    const uint32_t kneg = uni(pl->kneg);
+    const int rows = d + 2;
+    const int Mpad = 4 * nblk;
+    int32_t W[4];
+    W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
+    const RowsLds lo = rows_layout(ntypes, nranks);
+    const uint8_t *lut_s = smem + lo.lut;
+    int2 *et_s = reinterpret_cast<int2 *>(__builtin_assume_aligned(smem + lo.et, 8));
+    uint32_t *rw = reinterpret_cast<uint32_t *>(smem + lo.rows) + lane;   // this lane's column
+
+    const int nc = 4 * G.n_rep;
+    const int64_t unit = unit0 + lane;
+    const bool active = unit < G.n_units;
+    const int64_t u_abs = G.unit_offset + (active ? unit : 0);
+    const int64_t s = u_abs / nc;
+    const int cc = (int)(u_abs - s * nc);
+    const int r = cc >> 2, lp = cc & 3;
+    const uint32_t uid = G.uid[s];
+    const uint8_t *ref = G.refs + ((size_t)s * G.n_rep + r) * nq;
+    const bool use_x = (lp == 1 || lp == 2), use_z = (lp == 2 || lp == 3);
+
+    // pack R_r * L_P' into rows; E_0 on the way
+    int32_t E = 0;
+    for (int Y = 0; Y < rows; ++Y) {
+        const int y = Y - 1;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            uint32_t word = 0;
+            if (y >= 0 && y < d) {
+                for (int j = 0; j < 16; ++j) {
+                    const int x = 16 * w + j - 1;
+                    if (x >= 0 && x < d) {
+                        const int q = y * d + x;
+                        uint32_t v = ref[q] & 3u;
+                        if (use_x) v ^= pl->lx[q];
+                        if (use_z) v ^= pl->lz[q];
+                        word |= v << (2 * j);
+                        E += weight_of(W, v);
+                    }
+                }
+            }
+            rw[(Y * NW + w) * kWave] = word;
+        }
+    }
+    int32_t Emin = E, stop = 0;
+    wave_lds_fence();
+
+    for (int t = 0; t < n_sweeps; ++t) {
+        for (int i = lane; i < nranks; i += kWave) et_s[i].y = (int)pl->thr[(size_t)t * nranks + i];
+        wave_lds_fence();
+        for (int k = 0; k < 4; ++k) {
+            // descriptors of class k; the table is padded to a multiple of 4
+            const_u32 *tab = (const_u32 *)(uintptr_t)(pl->rowface + k * Mpad);
+            int32_t acc_de = 0;
+            int curY = -1;
+            // rA/rB: the two rows of the current row pair; fA/fB: accumulated
+            // flips.  Generators of one class in one row touch disjoint bits,
+            // so patterns are read from rA/rB and flips are merged at the end
+            // of the row, which keeps the moves of a row independent.
+            uint32_t rA[NW], rB[NW], fA[NW], fB[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) rA[w] = rB[w] = fA[w] = fB[w] = 0;
+            for (int b = 0; b < nblk; ++b) {
+                const uint4 rnd = philox4x32_10(make_uint4(uid, (uint32_t)cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
+                                                A.seed_lo, A.seed_hi);
+                const uint32_t uw[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
+                const uint32_t fdv[4] = {tab[4 * b], tab[4 * b + 1], tab[4 * b + 2], tab[4 * b + 3]};
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int m = 4 * b + w;
+                    if (m >= M) break;
+                    const uint32_t fd = fdv[w];
+                    const int Y = (int)(fd & 0xFFu);
+                    const uint32_t bo = (fd >> 8) & 0xFFu;
+                    const uint32_t shp = fd >> 16;
+                    if (Y != curY) {
+                        if (curY >= 0) {
+#pragma unroll
+                            for (int v = 0; v < NW; ++v) {
+                                rw[(curY * NW + v) * kWave] = rA[v] ^ fA[v];
+                                rw[((curY + 1) * NW + v) * kWave] = rB[v] ^ fB[v];
+                            }
+                        }
+#pragma unroll
+                        for (int v = 0; v < NW; ++v) {
+                            rA[v] = rw[(Y * NW + v) * kWave];
+                            rB[v] = rw[((Y + 1) * NW + v) * kWave];
+                            fA[v] = fB[v] = 0;
+                        }
+                        curY = Y;
+                    }
+                    const uint32_t pat = row_nibble<NW>(rA, bo) | (row_nibble<NW>(rB, bo) << 4);
+                    const uint32_t rank = lut_s[(shp << 8) | pat];
+                    const int2 et = et_s[rank];
+                    if (rank < kneg || uw[w] < (uint32_t)et.y) {
+                        row_flip<NW>(fA, bo, 6u);   // X_left (2) | Z_up (1 << 2)
+                        row_flip<NW>(fB, bo, 9u);   // Z_down (1) | X_right (2 << 2)
+                        acc_de += et.x;
+                    }
+                }
+            }
+            if (curY >= 0) {
+#pragma unroll
+                for (int v = 0; v < NW; ++v) {
+                    rw[(curY * NW + v) * kWave] = rA[v] ^ fA[v];
+                    rw[((curY + 1) * NW + v) * kWave] = rB[v] ^ fB[v];
+                }
+            }
+            wave_lds_fence();
+            E += acc_de;
+            if (E < Emin) { Emin = E; stop = 4 * t + k + 1; }
+        }
+    }
+    if (active) {
+        G.emin[u_abs] = Emin;
+        G.stop[u_abs] = stop;
+        G.efin[u_abs] = E;
+        if (G.final) {
+            uint8_t *dst = G.final + (size_t)u_abs * nq;
+            for (int q = 0; q < nq; ++q) {
+                const int y = q / d, x = q - y * d;
+                const uint32_t word = rw[((y + 1) * NW + (x + 1) / 16) * kWave];
+                dst[q] = (uint8_t)((word >> (2 * ((x + 1) % 16))) & 3u);
+            }
+        }
+    }
+    wave_lds_fence();
+}
+
+__device__ void load_rows_tables(const PlanDev *pl, uint8_t *smem)
+{
+    const int lane = threadIdx.x;
+    const RowsLds lo = rows_layout(pl->ntypes, pl->nranks);
+    const uint32_t *lut_g = reinterpret_cast<const uint32_t *>(pl->lut);
+    uint32_t *lut_s = reinterpret_cast<uint32_t *>(smem + lo.lut);
+    for (int i = lane; i < 64 * pl->ntypes; i += kWave) lut_s[i] = lut_g[i];
+    int2 *et_s = reinterpret_cast<int2 *>(smem + lo.et);
+    for (int i = lane; i < pl->nranks; i += kWave) et_s[i] = make_int2(pl->dE[i], 0);
+    wave_lds_fence();
+}
+
+template <bool PLAIN>
+__device__ __forceinline__ void rows_kernel_body(const AnnealArgs &A)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const PlanDev *loaded = nullptr;
+    for (int iter = 0;; ++iter) {
+        uint32_t task = 0;
+        if (PLAIN) {
+            if (iter > 0) break;
+            task = blockIdx.x;
+        } else {
+            if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
+            task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
+        }
+        if (task >= A.n_tasks) break;
+        int gi = 0;
+        while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
+        const GroupArgs &G = A.g[gi];
+        const int64_t unit0 = ((int64_t)task - G.task_begin) * kWave;
+        if (G.plan != loaded) {
+            wave_lds_fence();
+            load_rows_tables(G.plan, smem);
+            loaded = G.plan;
+        }
+        if (G.row_words == 1)
+            rows_task<1, PLAIN>(A, G, unit0, smem);
+        else
+            rows_task<2, PLAIN>(A, G, unit0, smem);
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_anneal_rows(AnnealArgs A) { rows_kernel_body<false>(A); }
+__global__ __launch_bounds__(kWave) void k_anneal_rows_plain(AnnealArgs A) { rows_kernel_body<true>(A); }
 
 __device__ void load_plan_tables(const PlanDev *pl, uint8_t *smem)
 {
@@ -479,14 +720,23 @@ __device__ void load_plan_tables(const PlanDev *pl, uint8_t *smem)
     wave_lds_fence();
 }
 
-__global__ __launch_bounds__(kWave) void k_anneal(AnnealArgs A)
+// MODE 0: persistent annealing (atomic task queue); 1: persistent replay of
+// the best chains; 2: plain form (one task per workgroup, no queue).
+template <int MODE>
+__device__ __forceinline__ void anneal_kernel_body(const AnnealArgs &A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
+    constexpr bool REPLAY = MODE == 1;
     const PlanDev *loaded = nullptr;
-    for (;;) {
+    for (int iter = 0;; ++iter) {
         uint32_t task = 0;
-        if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
-        task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
+        if (MODE == 2) {
+            if (iter > 0) break;
+            task = blockIdx.x;
+        } else {
+            if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
+            task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
+        }
         if (task >= A.n_tasks) break;
         int gi = 0;
         while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
@@ -498,16 +748,20 @@ __global__ __launch_bounds__(kWave) void k_anneal(AnnealArgs A)
             loaded = G.plan;
         }
         switch (G.log_lanes) {
-        case 0: anneal_task<0>(A, G, unit0, smem); break;
-        case 1: anneal_task<1>(A, G, unit0, smem); break;
-        case 2: anneal_task<2>(A, G, unit0, smem); break;
-        case 3: anneal_task<3>(A, G, unit0, smem); break;
-        case 4: anneal_task<4>(A, G, unit0, smem); break;
-        case 5: anneal_task<5>(A, G, unit0, smem); break;
-        default: anneal_task<6>(A, G, unit0, smem); break;
+        case 0: anneal_task<0, REPLAY>(A, G, unit0, smem); break;
+        case 1: anneal_task<1, REPLAY>(A, G, unit0, smem); break;
+        case 2: anneal_task<2, REPLAY>(A, G, unit0, smem); break;
+        case 3: anneal_task<3, REPLAY>(A, G, unit0, smem); break;
+        case 4: anneal_task<4, REPLAY>(A, G, unit0, smem); break;
+        case 5: anneal_task<5, REPLAY>(A, G, unit0, smem); break;
+        default: anneal_task<6, REPLAY>(A, G, unit0, smem); break;
         }
     }
 }
+
+__global__ __launch_bounds__(kWave) void k_anneal(AnnealArgs A) { anneal_kernel_body<0>(A); }
+__global__ __launch_bounds__(kWave) void k_replay(AnnealArgs A) { anneal_kernel_body<1>(A); }
+__global__ __launch_bounds__(kWave) void k_anneal_plain(AnnealArgs A) { anneal_kernel_body<2>(A); }
 
 __global__ void k_zero_u32(uint32_t *p, int n)
 {
@@ -683,35 +937,66 @@ static int validate_groups(const xzzx_group *groups, int n_groups, bool decode)
     return XZZX_OK;
 }
 
-static int anneal_grid(size_t lds_bytes, uint32_t n_tasks, unsigned *grid)
+static int device_cus()
 {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return check_hip(hipErrorInvalidDevice, "hipGetDevice");
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_anneal, kWave, lds_bytes) != hipSuccess || per_cu <= 0)
+    return cus;
+}
+
+static int anneal_grid(const void *kernel, size_t lds_bytes, uint32_t n_tasks, unsigned *grid)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, lds_bytes) != hipSuccess || per_cu <= 0)
         per_cu = 1;
-    const uint64_t full = (uint64_t)cus * (uint64_t)per_cu;
+    const uint64_t full = (uint64_t)device_cus() * (uint64_t)per_cu;
     *grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(full, n_tasks));
     return XZZX_OK;
 }
 
-// Launch k_anneal over `units` of each group (chains, or syndromes in replay).
-static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, bool replay,
-                         uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counter,
-                         hipStream_t stream, bool plain_grid)
+static int log2_int(int v)
 {
+    int lg = 0;
+    while ((1 << lg) < v) ++lg;
+    return lg;
+}
+
+enum class AnnealMode { Persistent, Replay, Plain };
+
+// Launch one annealing kernel over `units` of the selected groups (chains, or
+// syndromes in replay mode).  rows: packed-row kernel (one chain per lane);
+// otherwise the byte-state kernel with the plan's lanes per chain.  The replay
+// re-runs one chain per syndrome with the byte-state kernel, spreading a chain
+// over more lanes when that is needed to give every CU several wavefronts.
+static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::vector<int> &sel, bool rows,
+                      AnnealMode mode, uint64_t seed, int64_t unit_offset, int64_t units_override,
+                      uint32_t *d_counter, hipStream_t stream)
+{
+    const bool replay = mode == AnnealMode::Replay;
     AnnealArgs A{};
-    A.replay = replay ? 1 : 0;
     A.seed_lo = (uint32_t)seed;
     A.seed_hi = (uint32_t)(seed >> 32);
     A.counter = d_counter;
+    auto units_of = [&](int i) -> int64_t {
+        return units_override >= 0 ? units_override : (replay ? groups[i].n_syn : groups[i].n_syn * 4 * groups[i].n_rep);
+    };
+    int64_t total_units = 0;
+    for (int i : sel) total_units += units_of(i);
+    auto lanes_of = [&](int i) {
+        const Plan &P = groups[i].plan->P;
+        if (rows) return 1;
+        if (!replay) return P.lanes;
+        const int64_t want_waves = 8LL * device_cus();
+        int C = kWave / P.lanes;
+        while (C > 1 && total_units / C < want_waves) C >>= 1;
+        return kWave / C;
+    };
     // order groups by work per task (largest first) so the queue is LPT-like
-    std::vector<int> order;
-    for (int i = 0; i < n_groups; ++i)
-        if (groups[i].n_syn > 0) order.push_back(i);
+    std::vector<int> order = sel;
     auto cost = [&](int i) {
         const Plan &P = groups[i].plan->P;
-        return (double)P.n_sweeps * P.lat.nstab * (kWave / P.lanes);
+        return (double)P.n_sweeps * P.lat.nstab * (kWave / lanes_of(i));
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
     uint64_t tasks = 0;
@@ -731,30 +1016,61 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         G.best_chain = ws[i].best_chain;
         G.recovery = g.d_recovery;
         G.n_rep = g.n_rep;
-        int lg = 0;
-        while ((1 << lg) < P.lanes) ++lg;
-        G.log_lanes = lg;
+        const int lanes = lanes_of(i);
+        G.log_lanes = log2_int(lanes);
+        G.row_words = rows ? P.row_words : 0;
         G.unit_offset = unit_offset;
-        const int64_t units = units_override >= 0 ? units_override : (replay ? g.n_syn : g.n_syn * 4 * g.n_rep);
+        const int64_t units = units_of(i);
         G.n_units = units;
         G.task_begin = (int64_t)tasks;
-        const int C = kWave / P.lanes;
+        const int C = kWave / lanes;
         tasks += (uint64_t)((units + C - 1) / C);
-        lds = std::max(lds, P.lds_bytes_anneal(P.lanes));
+        lds = std::max(lds, rows ? P.lds_bytes_rows() : P.lds_bytes_anneal(lanes));
     }
     if (ng == 0 || tasks == 0) return XZZX_OK;
     if (tasks >= 0xFFFFFFF0ull) { set_error("too many anneal tasks in one launch"); return XZZX_ERANGE; }
     A.n_groups = ng;
     A.n_tasks = (uint32_t)tasks;
     if (lds > 65536) { set_error("LDS demand above 64 KiB"); return XZZX_ERANGE; }
-    unsigned grid = (unsigned)tasks;
-    if (!plain_grid) {
-        int rc = anneal_grid(lds, A.n_tasks, &grid);
-        if (rc) return rc;
+    if (mode == AnnealMode::Plain) {
+        if (rows)
+            hipLaunchKernelGGL(k_anneal_rows_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
+        else
+            hipLaunchKernelGGL(k_anneal_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
+        return check_hip(hipGetLastError(), "plain anneal launch");
     }
+    const void *kern = replay ? (const void *)k_replay : rows ? (const void *)k_anneal_rows : (const void *)k_anneal;
+    unsigned grid = 0;
+    int rc = anneal_grid(kern, lds, A.n_tasks, &grid);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_counter, 1);
-    hipLaunchKernelGGL(k_anneal, dim3(grid), dim3(kWave), lds, stream, A);
-    return check_hip(hipGetLastError(), "k_anneal launch");
+    if (replay)
+        hipLaunchKernelGGL(k_replay, dim3(grid), dim3(kWave), lds, stream, A);
+    else if (rows)
+        hipLaunchKernelGGL(k_anneal_rows, dim3(grid), dim3(kWave), lds, stream, A);
+    else
+        hipLaunchKernelGGL(k_anneal, dim3(grid), dim3(kWave), lds, stream, A);
+    return check_hip(hipGetLastError(), "anneal launch");
+}
+
+// Annealing of every non-empty group: packed-row groups and byte-state groups
+// go to their own persistent launches (counters[0] and counters[2]); replay
+// uses counters[1].
+static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
+                         uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
+                         hipStream_t stream)
+{
+    std::vector<int> rows_sel, bytes_sel;
+    for (int i = 0; i < n_groups; ++i) {
+        if (groups[i].n_syn <= 0) continue;
+        if (mode != AnnealMode::Replay && groups[i].plan->P.use_rows) rows_sel.push_back(i);
+        else bytes_sel.push_back(i);
+    }
+    if (mode == AnnealMode::Replay)
+        return launch_set(groups, ws, bytes_sel, false, mode, seed, unit_offset, units_override, d_counters + 1, stream);
+    int rc = launch_set(groups, ws, rows_sel, true, mode, seed, unit_offset, units_override, d_counters, stream);
+    if (rc) return rc;
+    return launch_set(groups, ws, bytes_sel, false, mode, seed, unit_offset, units_override, d_counters + 2, stream);
 }
 
 static int launch_reduce(const xzzx_group &g, const GroupWs &w, hipStream_t stream)
@@ -813,12 +1129,13 @@ static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_se
         for (int i = 0; i < n_groups; ++i) {
             const xzzx_group &g = groups[i];
             for (int64_t s = 0; s < g.n_syn; ++s) {
-                rc = launch_anneal(&g, &ws[i], 1, false, anneal_seed, s * 4 * g.n_rep, 4 * g.n_rep, counter, stream, true);
+                rc = launch_anneal(&g, &ws[i], 1, AnnealMode::Plain, anneal_seed, s * 4 * g.n_rep, 4 * g.n_rep, counter,
+                                   stream);
                 if (rc) return rc;
             }
         }
     } else {
-        rc = launch_anneal(groups, ws.data(), n_groups, false, anneal_seed, 0, -1, counter, stream, false);
+        rc = launch_anneal(groups, ws.data(), n_groups, AnnealMode::Persistent, anneal_seed, 0, -1, counter, stream);
         if (rc) return rc;
     }
     if (!(stages & XZZX_FLAG_STAGE_FINISH)) return XZZX_OK;
@@ -826,7 +1143,7 @@ static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_se
         rc = launch_reduce(groups[i], ws[i], stream);
         if (rc) return rc;
     }
-    return launch_anneal(groups, ws.data(), n_groups, true, anneal_seed, 0, -1, counter + 1, stream, false);
+    return launch_anneal(groups, ws.data(), n_groups, AnnealMode::Replay, anneal_seed, 0, -1, counter, stream);
 }
 
 }  // namespace xzzx

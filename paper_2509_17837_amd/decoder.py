@@ -116,13 +116,16 @@ class Plan:
         self.n_sweeps = len(beta)
 
     def info(self):
-        vals = [C.c_int() for _ in range(5)]
+        vals = [C.c_int() for _ in range(6)]
         call("xzzx_plan_info", self.h, *[C.byref(v) for v in vals])
-        keys = ["n_qubits", "n_stabs", "n_sweeps", "n_dE", "lanes_per_chain"]
+        keys = ["n_qubits", "n_stabs", "n_sweeps", "n_dE", "lanes_per_chain", "kernel"]
         return {k: v.value for k, v in zip(keys, vals)}
 
     def set_lanes(self, lanes):
         call("xzzx_plan_set_lanes", self.h, int(lanes))
+
+    def set_kernel(self, kernel):
+        call("xzzx_plan_set_kernel", self.h, int(kernel))
 
     def __del__(self):
         h = getattr(self, "h", None)

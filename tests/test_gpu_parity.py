@@ -99,11 +99,28 @@ def test_all_lane_counts_agree(d):
         compare_decode(prob, out, ref)
 
 
+@pytest.mark.parametrize("d", [3, 11, 13, 15, 21, 29])
+def test_row_and_byte_kernels_agree(d):
+    """The packed-row kernel (1 or 2 words per row) and the byte-state kernel
+    give identical chains; both match the oracle."""
+    prob = Problem(0, d, 0.2, 10.0, 3 if d > 15 else 7, 5, 10 if d > 15 else 30, seed=300 + d)
+    ref = prob.oracle_decode()
+    for kernel in (X.KERNEL_ROWS, X.KERNEL_BYTES):
+        plan = gpu_plan(prob)
+        plan.set_kernel(kernel)
+        compare_decode(prob, run_decode(prob, plan), ref)
+    with pytest.raises(X.XzzxError):
+        gpu_plan(Problem(1, 5, 0.2, 10.0, 1, 1, 1)).set_kernel(X.KERNEL_ROWS)
+
+
 def test_plain_form_matches_persistent():
     prob = Problem(0, 7, 0.15, 10.0, 9, 4, 40, seed=77)
     ref = prob.oracle_decode()
-    compare_decode(prob, run_decode(prob, flags=X.FLAG_PLAIN), ref)
-    compare_decode(prob, run_decode(prob, flags=0), ref)
+    for kernel in (X.KERNEL_ROWS, X.KERNEL_BYTES):
+        plan = gpu_plan(prob)
+        plan.set_kernel(kernel)
+        compare_decode(prob, run_decode(prob, plan, flags=X.FLAG_PLAIN), ref)
+        compare_decode(prob, run_decode(prob, plan, flags=0), ref)
 
 
 def test_mixed_distances_one_launch():
