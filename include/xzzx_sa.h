@@ -240,6 +240,82 @@ int xzzx_graph_create(const xzzx_group *groups, int n_groups, uint64_t greedy_se
 int xzzx_graph_launch(xzzx_graph *graph, void *stream);
 void xzzx_graph_destroy(xzzx_graph *graph);
 
+/* ---- serving loop (continuous batching) ------------------------------------ */
+
+/* A server decodes single-syndrome requests as they arrive.  A scheduler
+ * thread owns a HIP stream on the device current at creation and runs time
+ * slices: at each slice boundary it admits queued requests (greedy references
+ * computed on the device), advances every resident request by
+ * sweeps_per_slice sweeps in one launch per kernel family (requests of
+ * different distance and noise mix freely), and finishes requests whose
+ * schedule is complete (reduction and recovery on the device).  Chain states
+ * stay in device memory between slices; counter-based random numbers make a
+ * resumed chain identical to an uninterrupted one, so a request's result is
+ * the same as from xzzx_decode with the same seeds, alone or in any mix.
+ *
+ * Admission: a request is admitted when a device slot is free (max_slots
+ * slots of max_rep replicas on at most max_qubits qubits are allocated at
+ * creation: the HBM budget) and the LDS its tasks need, summed over resident
+ * requests, stays within lds_budget_bytes (0 = the device's total LDS), so
+ * every resident task of a slice runs concurrently. */
+typedef struct xzzx_server xzzx_server;
+
+typedef struct {
+    int max_slots;            /* resident requests (device slots) */
+    int max_rep;              /* largest n_rep of a request */
+    int max_qubits;           /* largest lattice (qubits) of a request */
+    int sweeps_per_slice;     /* sweeps a resident request advances per slice (>= 1) */
+    int max_pending;          /* queued requests before submit returns EAGAIN */
+    int greedy_mode;          /* XZZX_GREEDY_* */
+    int64_t lds_budget_bytes; /* 0: the device's total LDS */
+    uint64_t greedy_seed;
+    uint64_t anneal_seed;
+} xzzx_server_cfg;
+
+typedef struct {
+    const xzzx_plan *plan;    /* lattice, weights and schedule; must outlive the request */
+    const uint8_t *syndrome;  /* host [n_stabs], copied by submit */
+    uint32_t uid;             /* syndrome id (RNG counter) */
+    int n_rep;
+} xzzx_request;
+
+typedef struct {
+    int32_t e_best;           /* min over cosets of E_P */
+    int32_t cls;              /* P*, relative to the replica-0 reference */
+    int32_t e_cls[4];         /* E_P */
+    uint8_t *recovery;        /* caller's host buffer [n_qubits] filled by poll (may be NULL) */
+    double latency_s;         /* submit to result available on the host */
+    double queue_s;           /* submit to admission */
+} xzzx_result;
+
+typedef struct {
+    int64_t submitted, completed, rejected, slices;
+    double p50_latency_s, p99_latency_s, mean_latency_s;
+    double decodes_per_s;     /* completed requests over the busy interval */
+    double attempts_per_s;    /* flip attempts of completed requests over the busy interval */
+    double busy_s;            /* first admission to last completion */
+} xzzx_serve_stats;
+
+/* EINVAL for a bad configuration, ENOMEM if the slots do not fit. */
+int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out);
+
+/* Queue a request; *ticket identifies it.  EAGAIN when max_pending requests
+ * are queued, EINVAL if it does not fit the server's slots. */
+int xzzx_server_submit(xzzx_server *srv, const xzzx_request *req, uint64_t *ticket);
+
+/* XZZX_OK and the result (released by this call) if done; ENOTREADY while
+ * queued or resident; EINVAL for an unknown or already collected ticket. */
+int xzzx_server_poll(xzzx_server *srv, uint64_t ticket, xzzx_result *out);
+
+/* Blocks until every submitted request has completed. */
+int xzzx_server_drain(xzzx_server *srv);
+
+/* Latency percentiles and throughput over the requests completed so far. */
+int xzzx_server_stats(xzzx_server *srv, xzzx_serve_stats *out);
+
+/* Finishes resident work, stops the scheduler and frees the device slots. */
+void xzzx_server_destroy(xzzx_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,11 +58,14 @@ class Group(C.Structure):
 class ServerCfg(C.Structure):
     _fields_ = [
         ("max_slots", C.c_int),
+        ("max_rep", C.c_int),
+        ("max_qubits", C.c_int),
         ("sweeps_per_slice", C.c_int),
         ("max_pending", C.c_int),
+        ("greedy_mode", C.c_int),
+        ("lds_budget_bytes", C.c_int64),
         ("greedy_seed", C.c_uint64),
         ("anneal_seed", C.c_uint64),
-        ("hbm_budget_bytes", C.c_int64),
     ]
 
 
@@ -79,10 +82,25 @@ class Result(C.Structure):
     _fields_ = [
         ("e_best", C.c_int32),
         ("cls", C.c_int32),
+        ("e_cls", C.c_int32 * 4),
         ("recovery", C.c_void_p),
-        ("submit_ns", C.c_int64),
-        ("admit_ns", C.c_int64),
-        ("done_ns", C.c_int64),
+        ("latency_s", C.c_double),
+        ("queue_s", C.c_double),
+    ]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_int64),
+        ("completed", C.c_int64),
+        ("rejected", C.c_int64),
+        ("slices", C.c_int64),
+        ("p50_latency_s", C.c_double),
+        ("p99_latency_s", C.c_double),
+        ("mean_latency_s", C.c_double),
+        ("decodes_per_s", C.c_double),
+        ("attempts_per_s", C.c_double),
+        ("busy_s", C.c_double),
     ]
 
 
@@ -128,9 +146,9 @@ def lib():
         "xzzx_graph_destroy": (None, [V]),
         "xzzx_server_create": (I, [P(ServerCfg), P(V)]),
         "xzzx_server_submit": (I, [V, P(Request), P(U64)]),
-        "xzzx_server_poll": (I, [V, U64, P(Result), P(I)]),
+        "xzzx_server_poll": (I, [V, U64, P(Result)]),
         "xzzx_server_drain": (I, [V]),
-        "xzzx_server_stats": (I, [V, V]),
+        "xzzx_server_stats": (I, [V, P(ServeStats)]),
         "xzzx_server_destroy": (None, [V]),
     }
     for name, (res, args) in sig.items():

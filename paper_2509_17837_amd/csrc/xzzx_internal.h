@@ -83,6 +83,41 @@ struct Plan {
     size_t lds_bytes_rows() const;
 };
 
+
+// Serving-loop task: consecutive chains of one resident request, all at the
+// same sweep range (see k_serve_* in xzzx_kernels.hip).
+struct ServeTask {
+    const PlanDev *plan;
+    const uint8_t *refs;     // request references [n_rep][nq]
+    uint8_t *states;         // request chain states [4 n_rep][nq]
+    int32_t *e3;             // request chain words [3][4 n_rep]: E, E_min, phase of E_min
+    uint8_t *snap;           // replay: recovery destination [nq]
+    const int32_t *best;     // replay: the request's best chain
+    uint32_t uid;
+    int32_t n_rep;
+    int32_t chain0, nchains; // chains [chain0, chain0 + nchains) of the request
+    int32_t t_begin, t_end;  // sweep range; t_begin == 0 starts from the references
+    int32_t log_lanes;       // byte-state core: lanes per chain
+    int32_t row_words;       // packed-row core: words per row
+};
+
+// Serving-loop finish entry: per-coset reduction of one finished request.
+struct ServeFinish {
+    const int32_t *e3;       // request chain words [3][4 n_rep]
+    const uint8_t *qraw;     // request raw symplectic bits [n_rep]
+    int32_t *result;         // [8]: E_best, P*, best chain, unused, E_P[4]
+    int32_t n_rep;
+    int32_t pad;
+};
+
+int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const uint32_t *d_uid,
+                 const int32_t *d_slot_map, int n, int n_rep, uint8_t *refs_base, int64_t refs_stride,
+                 uint8_t *qraw_base, int64_t qraw_stride, uint64_t seed, int mode, hipStream_t stream);
+int serve_slice(const ServeTask *d_rows, int n_rows, size_t lds_rows, const ServeTask *d_bytes, int n_bytes,
+                size_t lds_bytes, uint64_t seed, hipStream_t stream);
+int serve_finish(const ServeFinish *d_fin, const ServeTask *d_replay, int n, size_t lds_replay, uint64_t seed,
+                 hipStream_t stream);
+
 // ---- host helpers (xzzx_host.cpp) ----
 void set_error(const std::string &msg);
 int build_lattice(int layout, int d, Lattice &L);

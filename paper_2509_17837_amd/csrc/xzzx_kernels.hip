@@ -114,6 +114,10 @@ struct GreedyArgs {
     const uint32_t *uid;
     uint8_t *refs;
     uint8_t *qraw;
+    int64_t syn_stride;        // bytes between syndromes
+    const int32_t *slot_map;   // optional: syndrome s writes to slot slot_map[s]
+    int64_t refs_stride;       // bytes between slots (with slot_map)
+    int64_t qraw_stride;
     int64_t n_syn;
     int n_rep;
     int mode;
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     __shared__ int s_count;
 
     for (int i = lane; i < nwords; i += kWave) cfgw[i] = 0;
-    const uint8_t *sy = A.syn + s * nstab;
+    const uint8_t *sy = A.syn + s * A.syn_stride;
     for (int g = 0; g < 2; ++g) {
         const int n = pl->ncol[g];
         const int32_t *cf = pl->col_face[g];
@@ -280,7 +284,8 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
         __syncthreads();
     }
     // write the reference and its symplectic products with L_Z and L_X
-    uint8_t *out = A.refs + (size_t)sr * nq;
+    uint8_t *out = A.slot_map ? A.refs + A.slot_map[s] * A.refs_stride + (size_t)r * nq : A.refs + (size_t)sr * nq;
+    uint8_t *qraw_out = A.slot_map ? A.qraw + A.slot_map[s] * A.qraw_stride + r : A.qraw + sr;
     const uint8_t *cb = reinterpret_cast<const uint8_t *>(cfgw);
     uint32_t vz = 0, vx = 0;
     for (int q = lane; q < nq; q += kWave) {
@@ -292,7 +297,7 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     }
     const int az = __popcll(__ballot(vz)) & 1;
     const int ax = __popcll(__ballot(vx)) & 1;
-    if (lane == 0) A.qraw[sr] = (uint8_t)(az | (ax << 1));
+    if (lane == 0) *qraw_out = (uint8_t)(az | (ax << 1));
 }
 
 // Pauli class index (I=0, X=1, Y=2, Z=3) <-> (x, z) bits, and products.
@@ -317,7 +322,29 @@ __global__ void k_qcls(const uint8_t *qraw, int64_t n_syn, int n_rep, uint8_t *q
 
 // ---------------------------------------------------------------------------
 // Annealing (Algs. 2-3).
+//
+// Both annealing kernels run a chain from a per-lane ChainJob: start at the
+// replica reference R_r times the coset's logical L_P' (or resume from a
+// saved state with its E, E_min and phase of the minimum), run sweeps
+// [t_begin, t_end) of the plan's schedule, then store E, E_min, the phase of
+// E_min and optionally the state.  Replay jobs stop at the phase of the
+// chain's minimum and store that state (the recovery).  A task is a set of
+// chains sharing a plan and a sweep range; the batch launch builds its tasks
+// from syndrome groups, the serving loop from its resident requests.
 // ---------------------------------------------------------------------------
+struct ChainJob {
+    const uint8_t *src;    // start: reference R_r; resume: saved state
+    int32_t *emin, *stop, *efin;   // result word arrays (wave-uniform bases), entry ci
+    uint8_t *states;       // end-of-range states (wave-uniform base, stride nq), entry ci; nullable
+    uint8_t *snap;         // replay: destination of the state at `target`
+    int64_t ci;            // this chain's entry in the result arrays
+    uint32_t uid;          // syndrome id (RNG counter word 0)
+    uint32_t cc;           // chain index in its syndrome (RNG counter word 1)
+    int32_t lp;            // coset logical applied at start (0..3)
+    int32_t target;        // replay: phase whose state is stored (-1 = none)
+    bool active, resume;
+};
+
 struct GroupArgs {
     const PlanDev *plan;
     const uint32_t *uid;
@@ -342,6 +369,40 @@ struct AnnealArgs {
     uint32_t seed_lo, seed_hi;
 };
 
+// Batch job of the chain (or, in replay, syndrome) `unit` of group G.
+__device__ __forceinline__ ChainJob batch_job(const GroupArgs &G, int64_t unit, bool replay)
+{
+    ChainJob j;
+    const int nc = 4 * G.n_rep;
+    j.active = unit < G.n_units;
+    const int64_t u_abs = G.unit_offset + (j.active ? unit : 0);
+    int64_t s, ci;
+    if (replay) {
+        s = u_abs;
+        j.cc = (uint32_t)G.best_chain[s];
+        ci = s * nc + j.cc;
+        j.target = G.stop[ci];
+        j.snap = G.recovery + (size_t)s * G.plan->nq;
+    } else {
+        s = u_abs / nc;
+        ci = u_abs;
+        j.cc = (uint32_t)(u_abs - s * nc);
+        j.target = -1;
+        j.snap = nullptr;
+    }
+    const int r = (int)(j.cc >> 2);
+    j.lp = (int)(j.cc & 3);
+    j.uid = G.uid[s];
+    j.src = G.refs + ((size_t)s * G.n_rep + r) * G.plan->nq;
+    j.resume = false;
+    j.ci = ci;
+    j.emin = G.emin;
+    j.stop = G.stop;
+    j.efin = G.efin;
+    j.states = replay ? nullptr : G.final;
+    return j;
+}
+
 struct LdsLayout {
     uint32_t desc, lut, et, state;
 };
@@ -356,15 +417,17 @@ __device__ __forceinline__ LdsLayout lds_layout(int M, int ntypes, int nranks)
     return o;
 }
 
+// Byte-state core: C = 64/G chains per wavefront, chain c on lanes c*G..c*G+G-1;
+// the G lanes of a chain split the generators of each colour class.
 template <int LOGG, bool REPLAY>
-__device__ void anneal_task(const AnnealArgs &A, const GroupArgs &G, int64_t unit0, uint8_t *smem)
+__device__ void bytes_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
+                           uint32_t seed_hi, uint8_t *smem)
 {
     constexpr int LOGC = 6 - LOGG;
-    const PlanDev *pl = G.plan;
     const int lane = threadIdx.x;
     const int c = lane >> LOGG;          // chain slot in this wavefront
     const int gl = lane & ((1 << LOGG) - 1);
-    const int nq = pl->nq, M = pl->M, nblk = pl->nblk, nranks = pl->nranks, n_sweeps = pl->n_sweeps;
+    const int nq = pl->nq, M = pl->M, nblk = pl->nblk, nranks = pl->nranks;
     const uint32_t kneg = (uint32_t)pl->kneg;
     int32_t W[4];
     W[0] = pl->W[0]; W[1] = pl->W[1]; W[2] = pl->W[2]; W[3] = pl->W[3];
@@ -373,63 +436,51 @@ __device__ void anneal_task(const AnnealArgs &A, const GroupArgs &G, int64_t uni
     const uint8_t *lut_s = smem + lo.lut;
     int2 *et_s = reinterpret_cast<int2 *>(smem + lo.et);
     uint8_t *st = smem + lo.state;
+    const uint32_t uid = J.uid, cc = J.cc;
 
-    const int nc = 4 * G.n_rep;
-    const int64_t unit = unit0 + c;
-    const bool active = unit < G.n_units;
-    const int64_t u_abs = G.unit_offset + (active ? unit : 0);
-    int64_t s;
-    int cc;
-    int32_t target = -1;
-    if (REPLAY) {
-        s = u_abs;
-        cc = G.best_chain[s];
-        target = G.stop[s * nc + cc];
-    } else {
-        s = u_abs / nc;
-        cc = (int)(u_abs - s * nc);
-    }
-    const int r = cc >> 2, lp = cc & 3;
-    const uint32_t uid = G.uid[s];
-
-    // initial state R_r * L_P' (Alg. 7), interleaved: qubit q of slot c at q*C + c
-    const uint8_t *ref = G.refs + ((size_t)s * G.n_rep + r) * nq;
-    const bool use_x = (lp == 1 || lp == 2), use_z = (lp == 2 || lp == 3);
+    // initial state, interleaved: qubit q of slot c at q*C + c
+    const bool use_x = (J.lp == 1 || J.lp == 2), use_z = (J.lp == 2 || J.lp == 3);
     int32_t part = 0;
     for (int q = gl; q < nq; q += (1 << LOGG)) {
-        uint32_t v = ref[q] & 3u;
-        if (use_x) v ^= pl->lx[q];
-        if (use_z) v ^= pl->lz[q];
+        uint32_t v = J.active ? (J.src[q] & 3u) : 0u;
+        if (!J.resume) {
+            if (use_x) v ^= pl->lx[q];
+            if (use_z) v ^= pl->lz[q];
+        }
         st[(q << LOGC) + c] = (uint8_t)v;
         part += weight_of(W, v);
     }
     if (gl == 0) st[(nq << LOGC) + c] = 0;
     int32_t E = chain_sum<LOGG>(part);
-    int32_t Emin = E;
-    int32_t stop = 0;
+    int32_t Emin = E, stop = 0;
+    if (J.resume && J.active) {
+        E = J.efin[J.ci];
+        Emin = J.emin[J.ci];
+        stop = J.stop[J.ci];
+    }
     wave_lds_fence();
 
     auto save_state = [&](uint8_t *dst) {
         for (int q = gl; q < nq; q += (1 << LOGG)) dst[q] = st[(q << LOGC) + c];
     };
-    int32_t last_phase = 4 * n_sweeps;
+    int32_t last_phase = 4 * t_end;
     if (REPLAY) {
-        if (active && target == 0) save_state(G.recovery + (size_t)s * nq);
-        int32_t tmax = active ? target : 0;
+        if (J.active && J.target == 0) save_state(J.snap);
+        int32_t tmax = J.active ? J.target : 0;
 #pragma unroll
         for (int sh = 1; sh < kWave; sh <<= 1) tmax = max(tmax, __shfl_xor(tmax, sh, kWave));
         last_phase = tmax;
     }
 
-    for (int t = 0; t < n_sweeps && 4 * t < last_phase; ++t) {
+    for (int t = t_begin; t < t_end && 4 * t < last_phase; ++t) {
         for (int i = lane; i < nranks; i += kWave) et_s[i].y = (int)pl->thr[(size_t)t * nranks + i];
         wave_lds_fence();
         for (int k = 0; k < 4; ++k) {
             const uint2 *dk = desc_s + k * M;
             int32_t acc_de = 0;
             for (int b = gl; b < nblk; b += (1 << LOGG)) {
-                const uint4 rnd = philox4x32_10(make_uint4(uid, (uint32_t)cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
-                                                A.seed_lo, A.seed_hi);
+                const uint4 rnd = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
+                                                seed_lo, seed_hi);
                 const uint32_t uw[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
@@ -457,31 +508,31 @@ __device__ void anneal_task(const AnnealArgs &A, const GroupArgs &G, int64_t uni
             E += chain_sum<LOGG>(acc_de);
             const int32_t phase = 4 * t + k + 1;
             if (E < Emin) { Emin = E; stop = phase; }
-            if (REPLAY && active && phase == target) save_state(G.recovery + (size_t)s * nq);
+            if (REPLAY && J.active && phase == J.target) save_state(J.snap);
         }
     }
-    if (!REPLAY && active && gl == 0) {
-        const int64_t ci = u_abs;
-        G.emin[ci] = Emin;
-        G.stop[ci] = stop;
-        G.efin[ci] = E;
+    if (!REPLAY && J.active) {
+        if (gl == 0) {
+            J.emin[J.ci] = Emin;
+            J.stop[J.ci] = stop;
+            J.efin[J.ci] = E;
+        }
+        if (J.states) save_state(J.states + (size_t)J.ci * nq);
     }
-    if (!REPLAY && active && G.final) save_state(G.final + (size_t)u_abs * nq);
     wave_lds_fence();
 }
 
-
 // ---------------------------------------------------------------------------
-// Packed-row annealing (rotated lattices, d <= 29): one chain per lane.  The
-// padded grid (columns and rows -1..d) is stored as 2-bit codes, each lattice
-// row in NW 32-bit words; word w of row Y of the chain in lane l sits at
+// Packed-row core (rotated lattices, d <= 29): one chain per lane.  The padded
+// grid (columns and rows -1..d) is stored as 2-bit codes, each lattice row in
+// NW 32-bit words; word w of row Y of the chain in lane l sits at
 // rows_s[(Y*NW + w)*64 + l], so a wavefront's row accesses are 64 consecutive
 // dwords.  The generators of a colour class are visited in rank order; a
 // generator at cell (i,j) covers the 4-bit nibble at bit 2(i+1) of rows j+1
 // (slots X_left, Z_up) and j+2 (slots Z_down, X_right).  The two rows are held
-// in registers while the class visits that row, so LDS traffic per move is
-// the two table lookups.  Generator tables are uniform across the wavefront
-// and read through the scalar cache.
+// in registers while the class visits that row, so LDS traffic per move is the
+// two table lookups.  Generator tables are uniform across the wavefront and
+// read through the scalar cache.
 // ---------------------------------------------------------------------------
 typedef const __attribute__((address_space(4))) uint32_t const_u32;
 
@@ -523,13 +574,13 @@ __device__ __forceinline__ void row_flip(uint32_t (&r)[NW], uint32_t bo, uint32_
     }
 }
 
-template <int NW, bool PLAIN>
-__device__ void rows_task(const AnnealArgs &A, const GroupArgs &G, int64_t unit0, uint8_t *smem)
+template <int NW>
+__device__ void rows_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
+                          uint32_t seed_hi, uint8_t *smem)
 {
-    const PlanDev *pl = G.plan;
     const int lane = threadIdx.x;
     const int d = (int)uni(pl->d), nq = (int)uni(pl->nq), M = (int)uni(pl->M), nblk = (int)uni(pl->nblk);
-    const int nranks = (int)uni(pl->nranks), n_sweeps = (int)uni(pl->n_sweeps), ntypes = (int)uni(pl->ntypes);
+    const int nranks = (int)uni(pl->nranks), ntypes = (int)uni(pl->ntypes);
     const uint32_t kneg = uni(pl->kneg);
     const int rows = d + 2;
     const int Mpad = 4 * nblk;
@@ -539,31 +590,22 @@ __device__ void rows_task(const AnnealArgs &A, const GroupArgs &G, int64_t unit0
     const uint8_t *lut_s = smem + lo.lut;
     int2 *et_s = reinterpret_cast<int2 *>(__builtin_assume_aligned(smem + lo.et, 8));
     uint32_t *rw = reinterpret_cast<uint32_t *>(smem + lo.rows) + lane;   // this lane's column
+    const uint32_t uid = J.uid, cc = J.cc;
+    const bool use_x = !J.resume && (J.lp == 1 || J.lp == 2), use_z = !J.resume && (J.lp == 2 || J.lp == 3);
 
-    const int nc = 4 * G.n_rep;
-    const int64_t unit = unit0 + lane;
-    const bool active = unit < G.n_units;
-    const int64_t u_abs = G.unit_offset + (active ? unit : 0);
-    const int64_t s = u_abs / nc;
-    const int cc = (int)(u_abs - s * nc);
-    const int r = cc >> 2, lp = cc & 3;
-    const uint32_t uid = G.uid[s];
-    const uint8_t *ref = G.refs + ((size_t)s * G.n_rep + r) * nq;
-    const bool use_x = (lp == 1 || lp == 2), use_z = (lp == 2 || lp == 3);
-
-    // pack R_r * L_P' into rows; E_0 on the way
+    // pack the state into rows; E of the state on the way
     int32_t E = 0;
     for (int Y = 0; Y < rows; ++Y) {
         const int y = Y - 1;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             uint32_t word = 0;
-            if (y >= 0 && y < d) {
+            if (J.active && y >= 0 && y < d) {
                 for (int j = 0; j < 16; ++j) {
                     const int x = 16 * w + j - 1;
                     if (x >= 0 && x < d) {
                         const int q = y * d + x;
-                        uint32_t v = ref[q] & 3u;
+                        uint32_t v = J.src[q] & 3u;
                         if (use_x) v ^= pl->lx[q];
                         if (use_z) v ^= pl->lz[q];
                         word |= v << (2 * j);
@@ -575,9 +617,14 @@ __device__ void rows_task(const AnnealArgs &A, const GroupArgs &G, int64_t unit0
         }
     }
     int32_t Emin = E, stop = 0;
+    if (J.resume && J.active) {
+        E = J.efin[J.ci];
+        Emin = J.emin[J.ci];
+        stop = J.stop[J.ci];
+    }
     wave_lds_fence();
 
-    for (int t = 0; t < n_sweeps; ++t) {
+    for (int t = t_begin; t < t_end; ++t) {
         for (int i = lane; i < nranks; i += kWave) et_s[i].y = (int)pl->thr[(size_t)t * nranks + i];
         wave_lds_fence();
         for (int k = 0; k < 4; ++k) {
@@ -593,8 +640,8 @@ __device__ void rows_task(const AnnealArgs &A, const GroupArgs &G, int64_t unit0
 #pragma unroll
             for (int w = 0; w < NW; ++w) rA[w] = rB[w] = fA[w] = fB[w] = 0;
             for (int b = 0; b < nblk; ++b) {
-                const uint4 rnd = philox4x32_10(make_uint4(uid, (uint32_t)cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
-                                                A.seed_lo, A.seed_hi);
+                const uint4 rnd = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
+                                                seed_lo, seed_hi);
                 const uint32_t uw[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
                 const uint32_t fdv[4] = {tab[4 * b], tab[4 * b + 1], tab[4 * b + 2], tab[4 * b + 3]};
 #pragma unroll
@@ -643,12 +690,12 @@ __device__ void rows_task(const AnnealArgs &A, const GroupArgs &G, int64_t unit0
             if (E < Emin) { Emin = E; stop = 4 * t + k + 1; }
         }
     }
-    if (active) {
-        G.emin[u_abs] = Emin;
-        G.stop[u_abs] = stop;
-        G.efin[u_abs] = E;
-        if (G.final) {
-            uint8_t *dst = G.final + (size_t)u_abs * nq;
+    if (J.active) {
+        J.emin[J.ci] = Emin;
+        J.stop[J.ci] = stop;
+        J.efin[J.ci] = E;
+        if (J.states) {
+            uint8_t *dst = J.states + (size_t)J.ci * nq;
             for (int q = 0; q < nq; ++q) {
                 const int y = q / d, x = q - y * d;
                 const uint32_t word = rw[((y + 1) * NW + (x + 1) / 16) * kWave];
@@ -671,40 +718,6 @@ __device__ void load_rows_tables(const PlanDev *pl, uint8_t *smem)
     wave_lds_fence();
 }
 
-template <bool PLAIN>
-__device__ __forceinline__ void rows_kernel_body(const AnnealArgs &A)
-{
-    extern __shared__ __align__(16) uint8_t smem[];
-    const PlanDev *loaded = nullptr;
-    for (int iter = 0;; ++iter) {
-        uint32_t task = 0;
-        if (PLAIN) {
-            if (iter > 0) break;
-            task = blockIdx.x;
-        } else {
-            if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
-            task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
-        }
-        if (task >= A.n_tasks) break;
-        int gi = 0;
-        while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
-        const GroupArgs &G = A.g[gi];
-        const int64_t unit0 = ((int64_t)task - G.task_begin) * kWave;
-        if (G.plan != loaded) {
-            wave_lds_fence();
-            load_rows_tables(G.plan, smem);
-            loaded = G.plan;
-        }
-        if (G.row_words == 1)
-            rows_task<1, PLAIN>(A, G, unit0, smem);
-        else
-            rows_task<2, PLAIN>(A, G, unit0, smem);
-    }
-}
-
-__global__ __launch_bounds__(kWave) void k_anneal_rows(AnnealArgs A) { rows_kernel_body<false>(A); }
-__global__ __launch_bounds__(kWave) void k_anneal_rows_plain(AnnealArgs A) { rows_kernel_body<true>(A); }
-
 __device__ void load_plan_tables(const PlanDev *pl, uint8_t *smem)
 {
     const int lane = threadIdx.x;
@@ -720,13 +733,17 @@ __device__ void load_plan_tables(const PlanDev *pl, uint8_t *smem)
     wave_lds_fence();
 }
 
-// MODE 0: persistent annealing (atomic task queue); 1: persistent replay of
-// the best chains; 2: plain form (one task per workgroup, no queue).
-template <int MODE>
-__device__ __forceinline__ void anneal_kernel_body(const AnnealArgs &A)
+// ---------------------------------------------------------------------------
+// Batch kernels.  MODE 0: persistent wavefronts pulling tasks from an atomic
+// queue over every group of the launch; MODE 2: plain form, one task per
+// workgroup.  ROWS selects the packed-row core; otherwise the byte-state core
+// with LOGG = log2(lanes per chain), the same for every group of the launch;
+// REPLAY (byte-state only) re-runs each syndrome's best chain.
+// ---------------------------------------------------------------------------
+template <int MODE, bool ROWS, int LOGG, bool REPLAY>
+__device__ __forceinline__ void batch_kernel_body(const AnnealArgs &A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    constexpr bool REPLAY = MODE == 1;
     const PlanDev *loaded = nullptr;
     for (int iter = 0;; ++iter) {
         uint32_t task = 0;
@@ -741,27 +758,116 @@ __device__ __forceinline__ void anneal_kernel_body(const AnnealArgs &A)
         int gi = 0;
         while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
         const GroupArgs &G = A.g[gi];
-        const int64_t unit0 = ((int64_t)task - G.task_begin) << (6 - G.log_lanes);
+        constexpr int lg = ROWS ? 0 : LOGG;
+        const int64_t unit0 = ((int64_t)task - G.task_begin) << (6 - lg);
         if (G.plan != loaded) {
             wave_lds_fence();
-            load_plan_tables(G.plan, smem);
+            if (ROWS) load_rows_tables(G.plan, smem);
+            else load_plan_tables(G.plan, smem);
             loaded = G.plan;
         }
-        switch (G.log_lanes) {
-        case 0: anneal_task<0, REPLAY>(A, G, unit0, smem); break;
-        case 1: anneal_task<1, REPLAY>(A, G, unit0, smem); break;
-        case 2: anneal_task<2, REPLAY>(A, G, unit0, smem); break;
-        case 3: anneal_task<3, REPLAY>(A, G, unit0, smem); break;
-        case 4: anneal_task<4, REPLAY>(A, G, unit0, smem); break;
-        case 5: anneal_task<5, REPLAY>(A, G, unit0, smem); break;
-        default: anneal_task<6, REPLAY>(A, G, unit0, smem); break;
+        const int n_sweeps = G.plan->n_sweeps;
+        if (ROWS) {
+            const ChainJob J = batch_job(G, unit0 + threadIdx.x, false);
+            if (G.row_words == 1) rows_core<1>(G.plan, J, 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
+            else rows_core<2>(G.plan, J, 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
+        } else {
+            const ChainJob J = batch_job(G, unit0 + (threadIdx.x >> lg), REPLAY);
+            bytes_core<lg, REPLAY>(G.plan, J, 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
         }
     }
 }
 
-__global__ __launch_bounds__(kWave) void k_anneal(AnnealArgs A) { anneal_kernel_body<0>(A); }
-__global__ __launch_bounds__(kWave) void k_replay(AnnealArgs A) { anneal_kernel_body<1>(A); }
-__global__ __launch_bounds__(kWave) void k_anneal_plain(AnnealArgs A) { anneal_kernel_body<2>(A); }
+template <int LOGG>
+__global__ __launch_bounds__(kWave) void k_anneal(AnnealArgs A) { batch_kernel_body<0, false, LOGG, false>(A); }
+template <int LOGG>
+__global__ __launch_bounds__(kWave) void k_replay(AnnealArgs A) { batch_kernel_body<0, false, LOGG, true>(A); }
+template <int LOGG>
+__global__ __launch_bounds__(kWave) void k_anneal_plain(AnnealArgs A) { batch_kernel_body<2, false, LOGG, false>(A); }
+__global__ __launch_bounds__(kWave) void k_anneal_rows(AnnealArgs A) { batch_kernel_body<0, true, 0, false>(A); }
+__global__ __launch_bounds__(kWave) void k_anneal_rows_plain(AnnealArgs A) { batch_kernel_body<2, true, 0, false>(A); }
+
+typedef void (*AnnealKernel)(AnnealArgs);
+static AnnealKernel bytes_kernel(int mode, int lg)
+{
+    // mode 0: persistent, 1: replay, 2: plain
+    static const AnnealKernel tab[3][7] = {
+        {k_anneal<0>, k_anneal<1>, k_anneal<2>, k_anneal<3>, k_anneal<4>, k_anneal<5>, k_anneal<6>},
+        {k_replay<0>, k_replay<1>, k_replay<2>, k_replay<3>, k_replay<4>, k_replay<5>, k_replay<6>},
+        {k_anneal_plain<0>, k_anneal_plain<1>, k_anneal_plain<2>, k_anneal_plain<3>, k_anneal_plain<4>,
+         k_anneal_plain<5>, k_anneal_plain<6>}};
+    return tab[mode][lg];
+}
+
+// ---------------------------------------------------------------------------
+// Serving kernels: one workgroup per task of the slice.  A task covers
+// consecutive chains of one resident request, all at the same sweep range.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ ChainJob serve_job(const ServeTask &T, int slot, bool replay)
+{
+    ChainJob j;
+    const int nc = 4 * T.n_rep;
+    const int nq = T.plan->nq;
+    j.active = slot < T.nchains;
+    int c = T.chain0 + (j.active ? slot : 0);
+    if (replay) c = *T.best;
+    j.cc = (uint32_t)c;
+    j.lp = c & 3;
+    j.uid = T.uid;
+    j.resume = !replay && T.t_begin > 0;
+    j.src = j.resume ? T.states + (size_t)c * nq : T.refs + (size_t)(c >> 2) * nq;
+    j.ci = c;
+    j.efin = T.e3;
+    j.emin = T.e3 + nc;
+    j.stop = T.e3 + 2 * nc;
+    j.states = replay ? nullptr : T.states;
+    j.target = replay ? T.e3[2 * nc + c] : -1;
+    j.snap = replay ? T.snap : nullptr;
+    return j;
+}
+
+template <bool ROWS, bool REPLAY>
+__device__ __forceinline__ void serve_kernel_body(const ServeTask *tasks, uint32_t seed_lo, uint32_t seed_hi)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const ServeTask &T = tasks[blockIdx.x];
+    const PlanDev *pl = T.plan;
+    if (ROWS) {
+        load_rows_tables(pl, smem);
+        const ChainJob J = serve_job(T, threadIdx.x, false);
+        if (T.row_words == 1) rows_core<1>(pl, J, T.t_begin, T.t_end, seed_lo, seed_hi, smem);
+        else rows_core<2>(pl, J, T.t_begin, T.t_end, seed_lo, seed_hi, smem);
+    } else {
+        load_plan_tables(pl, smem);
+        const int lg = T.log_lanes;
+        const ChainJob J = serve_job(T, threadIdx.x >> lg, REPLAY);
+        const int tb = REPLAY ? 0 : T.t_begin;
+        const int te = REPLAY ? pl->n_sweeps : T.t_end;
+        switch (lg) {
+        case 0: bytes_core<0, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
+        case 1: bytes_core<1, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
+        case 2: bytes_core<2, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
+        case 3: bytes_core<3, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
+        case 4: bytes_core<4, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
+        case 5: bytes_core<5, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
+        default: bytes_core<6, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_serve_rows(const ServeTask *tasks, uint32_t slo, uint32_t shi)
+{
+    serve_kernel_body<true, false>(tasks, slo, shi);
+}
+__global__ __launch_bounds__(kWave) void k_serve_bytes(const ServeTask *tasks, uint32_t slo, uint32_t shi)
+{
+    serve_kernel_body<false, false>(tasks, slo, shi);
+}
+__global__ __launch_bounds__(kWave) void k_serve_replay(const ServeTask *tasks, uint32_t slo, uint32_t shi)
+{
+    serve_kernel_body<false, true>(tasks, slo, shi);
+}
 
 __global__ void k_zero_u32(uint32_t *p, int n)
 {
@@ -830,6 +936,40 @@ __global__ __launch_bounds__(kWave) void k_reduce(ReduceArgs A)
     }
 }
 
+// Serving: per-coset reduction of a finished request (one wavefront each).
+// The class of replica r relative to replica 0 comes from the raw symplectic
+// bits the greedy kernel stored (bit 0: with L_Z, bit 1: with L_X).
+__global__ __launch_bounds__(kWave) void k_serve_reduce(const ServeFinish *fin)
+{
+    const ServeFinish &F = fin[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int nc = 4 * F.n_rep;
+    const int raw0 = F.qraw[0] & 3;
+    uint64_t best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+    for (int c = lane; c < nc; c += kWave) {
+        const int v = (F.qraw[c >> 2] & 3) ^ raw0;
+        const int cls = cls_mul(cls_from_bits(v & 1, v >> 1), c & 3);
+        const uint64_t key = ((uint64_t)(uint32_t)F.e3[nc + c] << 32) | (uint32_t)c;
+#pragma unroll
+        for (int P = 0; P < 4; ++P)
+            if (cls == P) best[P] = min(best[P], key);
+    }
+#pragma unroll
+    for (int P = 0; P < 4; ++P)
+#pragma unroll
+        for (int sh = 1; sh < kWave; sh <<= 1) best[P] = min(best[P], (uint64_t)__shfl_xor(best[P], sh, kWave));
+    int ps = 0;
+#pragma unroll
+    for (int P = 1; P < 4; ++P)
+        if ((best[P] >> 32) < (best[ps] >> 32)) ps = P;
+    if (lane == 0) {
+        F.result[0] = (int32_t)(best[ps] >> 32);
+        F.result[1] = ps;
+        F.result[2] = (int32_t)(best[ps] & 0xFFFFFFFFu);
+        for (int P = 0; P < 4; ++P) F.result[4 + P] = best[P] == ~0ull ? INT32_MAX : (int32_t)(best[P] >> 32);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch logic.
 // ---------------------------------------------------------------------------
@@ -863,6 +1003,7 @@ static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_
     A.n_syn = n_syn;
     A.n_rep = n_rep;
     A.mode = mode;
+    A.syn_stride = P.lat.nstab;
     A.seed_lo = (uint32_t)seed;
     A.seed_hi = (uint32_t)(seed >> 32);
     const int lds = greedy_lds(P, &A.max_nodes);
@@ -969,7 +1110,7 @@ enum class AnnealMode { Persistent, Replay, Plain };
 // otherwise the byte-state kernel with the plan's lanes per chain.  The replay
 // re-runs one chain per syndrome with the byte-state kernel, spreading a chain
 // over more lanes when that is needed to give every CU several wavefronts.
-static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::vector<int> &sel, bool rows,
+static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::vector<int> &sel, bool rows, int lanes,
                       AnnealMode mode, uint64_t seed, int64_t unit_offset, int64_t units_override,
                       uint32_t *d_counter, hipStream_t stream)
 {
@@ -981,27 +1122,17 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
     auto units_of = [&](int i) -> int64_t {
         return units_override >= 0 ? units_override : (replay ? groups[i].n_syn : groups[i].n_syn * 4 * groups[i].n_rep);
     };
-    int64_t total_units = 0;
-    for (int i : sel) total_units += units_of(i);
-    auto lanes_of = [&](int i) {
-        const Plan &P = groups[i].plan->P;
-        if (rows) return 1;
-        if (!replay) return P.lanes;
-        const int64_t want_waves = 8LL * device_cus();
-        int C = kWave / P.lanes;
-        while (C > 1 && total_units / C < want_waves) C >>= 1;
-        return kWave / C;
-    };
     // order groups by work per task (largest first) so the queue is LPT-like
     std::vector<int> order = sel;
     auto cost = [&](int i) {
         const Plan &P = groups[i].plan->P;
-        return (double)P.n_sweeps * P.lat.nstab * (kWave / lanes_of(i));
+        return (double)P.n_sweeps * P.lat.nstab;
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
     uint64_t tasks = 0;
     size_t lds = 0;
     int ng = 0;
+    const int lg = log2_int(lanes);
     for (int i : order) {
         const xzzx_group &g = groups[i];
         const Plan &P = g.plan->P;
@@ -1016,8 +1147,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         G.best_chain = ws[i].best_chain;
         G.recovery = g.d_recovery;
         G.n_rep = g.n_rep;
-        const int lanes = lanes_of(i);
-        G.log_lanes = log2_int(lanes);
+        G.log_lanes = lg;
         G.row_words = rows ? P.row_words : 0;
         G.unit_offset = unit_offset;
         const int64_t units = units_of(i);
@@ -1036,41 +1166,55 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         if (rows)
             hipLaunchKernelGGL(k_anneal_rows_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         else
-            hipLaunchKernelGGL(k_anneal_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
+            hipLaunchKernelGGL(bytes_kernel(2, lg), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         return check_hip(hipGetLastError(), "plain anneal launch");
     }
-    const void *kern = replay ? (const void *)k_replay : rows ? (const void *)k_anneal_rows : (const void *)k_anneal;
+    const AnnealKernel kern = rows ? k_anneal_rows : bytes_kernel(replay ? 1 : 0, lg);
     unsigned grid = 0;
-    int rc = anneal_grid(kern, lds, A.n_tasks, &grid);
+    int rc = anneal_grid((const void *)kern, lds, A.n_tasks, &grid);
     if (rc) return rc;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_counter, 1);
-    if (replay)
-        hipLaunchKernelGGL(k_replay, dim3(grid), dim3(kWave), lds, stream, A);
-    else if (rows)
-        hipLaunchKernelGGL(k_anneal_rows, dim3(grid), dim3(kWave), lds, stream, A);
-    else
-        hipLaunchKernelGGL(k_anneal, dim3(grid), dim3(kWave), lds, stream, A);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave), lds, stream, A);
     return check_hip(hipGetLastError(), "anneal launch");
 }
 
-// Annealing of every non-empty group: packed-row groups and byte-state groups
-// go to their own persistent launches (counters[0] and counters[2]); replay
-// uses counters[1].
+// Annealing of every non-empty group.  Packed-row groups share one persistent
+// launch; byte-state groups are launched per lanes-per-chain value.  The
+// replay re-runs one chain per syndrome with the byte-state kernel, spreading
+// a chain over more lanes when that is needed to give every CU several
+// wavefronts.  Each launch has its own queue counter (d_counters[0..8]).
 static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
                          uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
                          hipStream_t stream)
 {
-    std::vector<int> rows_sel, bytes_sel;
+    std::vector<int> rows_sel;
+    std::vector<int> bytes_sel[7];
+    int64_t total_syn = 0;
     for (int i = 0; i < n_groups; ++i) {
         if (groups[i].n_syn <= 0) continue;
-        if (mode != AnnealMode::Replay && groups[i].plan->P.use_rows) rows_sel.push_back(i);
-        else bytes_sel.push_back(i);
+        total_syn += groups[i].n_syn;
+        const Plan &P = groups[i].plan->P;
+        if (mode != AnnealMode::Replay && P.use_rows) rows_sel.push_back(i);
+        else bytes_sel[log2_int(P.lanes)].push_back(i);
     }
-    if (mode == AnnealMode::Replay)
-        return launch_set(groups, ws, bytes_sel, false, mode, seed, unit_offset, units_override, d_counters + 1, stream);
-    int rc = launch_set(groups, ws, rows_sel, true, mode, seed, unit_offset, units_override, d_counters, stream);
-    if (rc) return rc;
-    return launch_set(groups, ws, bytes_sel, false, mode, seed, unit_offset, units_override, d_counters + 2, stream);
+    if (mode == AnnealMode::Replay) {
+        // one chain per syndrome: enough wavefronts for 8 per CU
+        std::vector<int> all;
+        int C = kWave;
+        for (int l = 0; l < 7; ++l)
+            for (int i : bytes_sel[l]) {
+                all.push_back(i);
+                C = std::min(C, kWave / groups[i].plan->P.lanes);
+            }
+        const int64_t want = 8LL * device_cus();
+        while (C > 1 && total_syn / C < want) C >>= 1;
+        return launch_set(groups, ws, all, false, kWave / C, mode, seed, unit_offset, units_override, d_counters, stream);
+    }
+    int rc = launch_set(groups, ws, rows_sel, true, 1, mode, seed, unit_offset, units_override, d_counters, stream);
+    for (int l = 0; l < 7 && !rc; ++l)
+        rc = launch_set(groups, ws, bytes_sel[l], false, 1 << l, mode, seed, unit_offset, units_override,
+                        d_counters + 1 + l, stream);
+    return rc;
 }
 
 static int launch_reduce(const xzzx_group &g, const GroupWs &w, hipStream_t stream)
@@ -1143,7 +1287,56 @@ static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_se
         rc = launch_reduce(groups[i], ws[i], stream);
         if (rc) return rc;
     }
-    return launch_anneal(groups, ws.data(), n_groups, AnnealMode::Replay, anneal_seed, 0, -1, counter, stream);
+    return launch_anneal(groups, ws.data(), n_groups, AnnealMode::Replay, anneal_seed, 0, -1, counter + 8, stream);
+}
+
+
+// ---- serving launches (used by xzzx_server.cpp) ----
+int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const uint32_t *d_uid,
+                 const int32_t *d_slot_map, int n, int n_rep, uint8_t *refs_base, int64_t refs_stride,
+                 uint8_t *qraw_base, int64_t qraw_stride, uint64_t seed, int mode, hipStream_t stream)
+{
+    if (n <= 0) return XZZX_OK;
+    GreedyArgs A{};
+    A.plan = P.ddev;
+    A.syn = d_syn;
+    A.syn_stride = syn_stride;
+    A.uid = d_uid;
+    A.refs = refs_base;
+    A.qraw = qraw_base;
+    A.slot_map = d_slot_map;
+    A.refs_stride = refs_stride;
+    A.qraw_stride = qraw_stride;
+    A.n_syn = n;
+    A.n_rep = n_rep;
+    A.mode = mode;
+    A.seed_lo = (uint32_t)seed;
+    A.seed_hi = (uint32_t)(seed >> 32);
+    const int lds = greedy_lds(P, &A.max_nodes);
+    hipLaunchKernelGGL(k_greedy, dim3((unsigned)(n * n_rep)), dim3(kWave), lds, stream, A);
+    return check_hip(hipGetLastError(), "serving greedy launch");
+}
+
+int serve_slice(const ServeTask *d_rows, int n_rows, size_t lds_rows, const ServeTask *d_bytes, int n_bytes,
+                size_t lds_bytes, uint64_t seed, hipStream_t stream)
+{
+    if (n_rows > 0)
+        hipLaunchKernelGGL(k_serve_rows, dim3((unsigned)n_rows), dim3(kWave), lds_rows, stream, d_rows,
+                           (uint32_t)seed, (uint32_t)(seed >> 32));
+    if (n_bytes > 0)
+        hipLaunchKernelGGL(k_serve_bytes, dim3((unsigned)n_bytes), dim3(kWave), lds_bytes, stream, d_bytes,
+                           (uint32_t)seed, (uint32_t)(seed >> 32));
+    return check_hip(hipGetLastError(), "serving slice launch");
+}
+
+int serve_finish(const ServeFinish *d_fin, const ServeTask *d_replay, int n, size_t lds_replay, uint64_t seed,
+                 hipStream_t stream)
+{
+    if (n <= 0) return XZZX_OK;
+    hipLaunchKernelGGL(k_serve_reduce, dim3((unsigned)n), dim3(kWave), 0, stream, d_fin);
+    hipLaunchKernelGGL(k_serve_replay, dim3((unsigned)n), dim3(kWave), lds_replay, stream, d_replay,
+                       (uint32_t)seed, (uint32_t)(seed >> 32));
+    return check_hip(hipGetLastError(), "serving finish launch");
 }
 
 }  // namespace xzzx

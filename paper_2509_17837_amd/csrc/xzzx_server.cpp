@@ -1,0 +1,529 @@
+// Serving loop: continuous batching of single-syndrome decode requests.
+//
+// A scheduler thread owns one HIP stream (default priority) and repeats:
+//   1. admit queued requests into free device slots while the LDS budget
+//      allows (greedy references for all admissions of the slice, batched per
+//      plan, written straight into the slots);
+//   2. advance every resident request by sweeps_per_slice sweeps: one task per
+//      group of chains, all tasks of the slice in one launch per kernel family;
+//   3. finish requests whose schedule is complete (per-coset reduction and
+//      replay of the best chain on the device, results copied to pinned host
+//      memory);
+//   4. wait for the slice, then publish finished results with their latency.
+// Requests that arrive while a slice runs join at the next slice boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "xzzx_internal.h"
+
+using namespace xzzx;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Pending {
+    uint64_t ticket;
+    const xzzx_plan *plan;
+    std::vector<uint8_t> syn;
+    uint32_t uid;
+    int n_rep;
+    Clock::time_point submit;
+};
+
+struct Slot {
+    bool busy = false;
+    uint64_t ticket = 0;
+    const Plan *plan = nullptr;
+    uint32_t uid = 0;
+    int n_rep = 0;
+    int t = 0;             // sweeps done
+    bool started = false;  // first slice launched
+    size_t lds = 0;        // LDS its tasks take
+    Clock::time_point submit, admit;
+};
+
+struct Done {
+    int32_t e_best, cls, e_cls[4];
+    std::vector<uint8_t> recovery;
+    double latency_s, queue_s;
+};
+
+}  // namespace
+
+struct xzzx_server {
+    xzzx_server_cfg cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // device slot pool
+    uint8_t *d_pool = nullptr;
+    size_t slot_bytes = 0, off_refs = 0, off_states = 0, off_e3 = 0, off_qraw = 0, off_res = 0, off_rec = 0;
+    // staging (device + pinned host)
+    uint8_t *d_stage = nullptr, *h_stage = nullptr;
+    size_t stage_bytes = 0, st_syn = 0, st_uid = 0, st_map = 0, st_tasks = 0, st_fin = 0, st_out = 0;
+    size_t max_tasks = 0;
+    size_t lds_budget = 0, lds_used = 0;
+    int max_nstab = 0;
+    std::vector<Slot> slots;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> pending;
+    std::unordered_map<uint64_t, Done> done;
+    std::unordered_map<uint64_t, int> where;   // ticket -> 0 queued, 1 resident
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int error = XZZX_OK;
+    std::string error_msg;
+    // statistics
+    std::vector<double> latencies;
+    int64_t submitted = 0, completed = 0, rejected = 0, slices = 0;
+    double attempts_done = 0.0;
+    bool started = false;
+    Clock::time_point first_admit, last_done;
+
+    uint8_t *slot_ptr(int s) { return d_pool + (size_t)s * slot_bytes; }
+    void run();
+    int slice();
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t task_lds(const Plan &P, int *chains_per_task)
+{
+    if (P.use_rows) {
+        *chains_per_task = kWave;
+        return P.lds_bytes_rows();
+    }
+    *chains_per_task = kWave / P.lanes;
+    return P.lds_bytes_anneal(P.lanes);
+}
+
+size_t request_lds(const Plan &P, int n_rep)
+{
+    int C = 1;
+    const size_t per = task_lds(P, &C);
+    return per * (size_t)((4 * n_rep + C - 1) / C);
+}
+
+int check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return XZZX_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return XZZX_EDEVICE;
+}
+
+}  // namespace
+
+int xzzx_server::slice()
+{
+    // ---- 1. admission -----------------------------------------------------
+    std::vector<int> admitted;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        while (!pending.empty()) {
+            const Pending &p = pending.front();
+            const Plan &P = p.plan->P;
+            const size_t need = request_lds(P, p.n_rep);
+            if (lds_used + need > lds_budget && lds_used > 0) break;
+            int s = -1;
+            for (size_t i = 0; i < slots.size(); ++i)
+                if (!slots[i].busy) { s = (int)i; break; }
+            if (s < 0) break;
+            Slot &sl = slots[s];
+            sl.busy = true;
+            sl.ticket = p.ticket;
+            sl.plan = &P;
+            sl.uid = p.uid;
+            sl.n_rep = p.n_rep;
+            sl.t = 0;
+            sl.started = false;
+            sl.lds = need;
+            sl.submit = p.submit;
+            sl.admit = Clock::now();
+            lds_used += need;
+            where[p.ticket] = 1;
+            // stage the syndrome (index = position in `admitted`)
+            std::memcpy(h_stage + st_syn + admitted.size() * (size_t)max_nstab, p.syn.data(), p.syn.size());
+            reinterpret_cast<uint32_t *>(h_stage + st_uid)[admitted.size()] = p.uid;
+            reinterpret_cast<int32_t *>(h_stage + st_map)[admitted.size()] = s;
+            admitted.push_back(s);
+            if (!started) { started = true; first_admit = sl.admit; }
+            pending.pop_front();
+        }
+    }
+    int rc = XZZX_OK;
+    if (!admitted.empty()) {
+        const size_t n = admitted.size();
+        rc = check(hipMemcpyAsync(d_stage + st_syn, h_stage + st_syn, n * (size_t)max_nstab, hipMemcpyHostToDevice, stream), "stage syndromes");
+        if (!rc) rc = check(hipMemcpyAsync(d_stage + st_uid, h_stage + st_uid, n * 4, hipMemcpyHostToDevice, stream), "stage uids");
+        if (!rc) rc = check(hipMemcpyAsync(d_stage + st_map, h_stage + st_map, n * 4, hipMemcpyHostToDevice, stream), "stage slots");
+        // one greedy launch per (plan, n_rep) over consecutive staged entries
+        size_t i = 0;
+        while (!rc && i < n) {
+            size_t j = i + 1;
+            const Slot &a = slots[admitted[i]];
+            while (j < n && slots[admitted[j]].plan == a.plan && slots[admitted[j]].n_rep == a.n_rep) ++j;
+            rc = serve_greedy(*a.plan, d_stage + st_syn + i * (size_t)max_nstab, max_nstab,
+                              reinterpret_cast<const uint32_t *>(d_stage + st_uid) + i,
+                              reinterpret_cast<const int32_t *>(d_stage + st_map) + i, (int)(j - i), a.n_rep,
+                              d_pool + off_refs, (int64_t)slot_bytes, d_pool + off_qraw, (int64_t)slot_bytes,
+                              cfg.greedy_seed, cfg.greedy_mode, stream);
+            i = j;
+        }
+        if (rc) return rc;
+    }
+
+    // ---- 2. one slice of sweeps for every resident request -----------------
+    ServeTask *h_tasks = reinterpret_cast<ServeTask *>(h_stage + st_tasks);
+    std::vector<ServeTask> rows_t, bytes_t;
+    size_t lds_rows = 0, lds_bytes = 0;
+    std::vector<int> finished;
+    for (size_t s = 0; s < slots.size(); ++s) {
+        Slot &sl = slots[s];
+        if (!sl.busy) continue;
+        const Plan &P = *sl.plan;
+        const int t0 = sl.t, t1 = std::min(P.n_sweeps, t0 + cfg.sweeps_per_slice);
+        // a fresh request always gets a first task (it initialises E, E_min
+        // and the stored state even for an empty schedule)
+        if (t1 > t0 || !sl.started) {
+            sl.started = true;
+            int C = 1;
+            const size_t lds = task_lds(P, &C);
+            const int nc = 4 * sl.n_rep;
+            uint8_t *base = slot_ptr((int)s);
+            for (int c0 = 0; c0 < nc; c0 += C) {
+                ServeTask T{};
+                T.plan = P.ddev;
+                T.refs = base + off_refs;
+                T.states = base + off_states;
+                T.e3 = reinterpret_cast<int32_t *>(base + off_e3);
+                T.snap = nullptr;
+                T.best = nullptr;
+                T.uid = sl.uid;
+                T.n_rep = sl.n_rep;
+                T.chain0 = c0;
+                T.nchains = std::min(C, nc - c0);
+                T.t_begin = t0;
+                T.t_end = t1;
+                int lg = 0;
+                while ((1 << lg) < P.lanes) ++lg;
+                T.log_lanes = P.use_rows ? 0 : lg;
+                T.row_words = P.use_rows ? P.row_words : 0;
+                if (P.use_rows) { rows_t.push_back(T); lds_rows = std::max(lds_rows, lds); }
+                else { bytes_t.push_back(T); lds_bytes = std::max(lds_bytes, lds); }
+            }
+            sl.t = t1;
+        }
+        if (sl.t >= P.n_sweeps) finished.push_back((int)s);
+    }
+    const size_t nt = rows_t.size() + bytes_t.size();
+    if (nt > max_tasks) { set_error("serving task buffer overflow"); return XZZX_ERANGE; }
+    if (nt) {
+        std::copy(rows_t.begin(), rows_t.end(), h_tasks);
+        std::copy(bytes_t.begin(), bytes_t.end(), h_tasks + rows_t.size());
+        rc = check(hipMemcpyAsync(d_stage + st_tasks, h_tasks, nt * sizeof(ServeTask), hipMemcpyHostToDevice, stream),
+                   "stage tasks");
+        if (rc) return rc;
+        const ServeTask *d_tasks = reinterpret_cast<const ServeTask *>(d_stage + st_tasks);
+        rc = serve_slice(d_tasks, (int)rows_t.size(), lds_rows, d_tasks + rows_t.size(), (int)bytes_t.size(),
+                         lds_bytes, cfg.anneal_seed, stream);
+        if (rc) return rc;
+        ++slices;
+    }
+
+    // ---- 3. finish completed requests -------------------------------------
+    const size_t nf = finished.size();
+    if (nf) {
+        ServeFinish *h_fin = reinterpret_cast<ServeFinish *>(h_stage + st_fin);
+        ServeTask *h_rep = reinterpret_cast<ServeTask *>(h_stage + st_fin + align256(slots.size() * sizeof(ServeFinish)));
+        size_t lds_rep = 0;
+        for (size_t k = 0; k < nf; ++k) {
+            const int s = finished[k];
+            const Slot &sl = slots[s];
+            const Plan &P = *sl.plan;
+            uint8_t *base = slot_ptr(s);
+            ServeFinish F{};
+            F.e3 = reinterpret_cast<const int32_t *>(base + off_e3);
+            F.qraw = base + off_qraw;
+            F.result = reinterpret_cast<int32_t *>(base + off_res);
+            F.n_rep = sl.n_rep;
+            h_fin[k] = F;
+            // replay the best chain with every lane of a wavefront on it
+            ServeTask T{};
+            T.plan = P.ddev;
+            T.refs = base + off_refs;
+            T.states = base + off_states;
+            T.e3 = reinterpret_cast<int32_t *>(base + off_e3);
+            T.snap = base + off_rec;
+            T.best = reinterpret_cast<const int32_t *>(base + off_res) + 2;
+            T.uid = sl.uid;
+            T.n_rep = sl.n_rep;
+            T.chain0 = 0;
+            T.nchains = 1;
+            T.t_begin = 0;
+            T.t_end = P.n_sweeps;
+            T.log_lanes = 6;
+            T.row_words = 0;
+            h_rep[k] = T;
+            lds_rep = std::max(lds_rep, P.lds_bytes_anneal(kWave));
+        }
+        rc = check(hipMemcpyAsync(d_stage + st_fin, h_stage + st_fin,
+                                  align256(slots.size() * sizeof(ServeFinish)) + nf * sizeof(ServeTask),
+                                  hipMemcpyHostToDevice, stream), "stage finish");
+        if (rc) return rc;
+        rc = serve_finish(reinterpret_cast<const ServeFinish *>(d_stage + st_fin),
+                          reinterpret_cast<const ServeTask *>(d_stage + st_fin + align256(slots.size() * sizeof(ServeFinish))),
+                          (int)nf, lds_rep, cfg.anneal_seed, stream);
+        if (rc) return rc;
+        // results: [8 words][recovery max_qubits] per finished request
+        const size_t per = 32 + (size_t)cfg.max_qubits;
+        for (size_t k = 0; k < nf; ++k) {
+            uint8_t *base = slot_ptr(finished[k]);
+            rc = check(hipMemcpyAsync(h_stage + st_out + k * per, base + off_res, 32, hipMemcpyDeviceToHost, stream), "result");
+            if (!rc) rc = check(hipMemcpyAsync(h_stage + st_out + k * per + 32, base + off_rec, slots[finished[k]].plan->lat.nq,
+                                               hipMemcpyDeviceToHost, stream), "recovery");
+            if (rc) return rc;
+        }
+    }
+    rc = check(hipStreamSynchronize(stream), "slice");
+    if (rc) return rc;
+
+    // ---- 4. publish ---------------------------------------------------------
+    if (nf) {
+        const auto now = Clock::now();
+        const size_t per = 32 + (size_t)cfg.max_qubits;
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t k = 0; k < nf; ++k) {
+            Slot &sl = slots[finished[k]];
+            const int32_t *w = reinterpret_cast<const int32_t *>(h_stage + st_out + k * per);
+            Done dn;
+            dn.e_best = w[0];
+            dn.cls = w[1];
+            for (int P = 0; P < 4; ++P) dn.e_cls[P] = w[4 + P];
+            dn.recovery.assign(h_stage + st_out + k * per + 32, h_stage + st_out + k * per + 32 + sl.plan->lat.nq);
+            dn.latency_s = std::chrono::duration<double>(now - sl.submit).count();
+            dn.queue_s = std::chrono::duration<double>(sl.admit - sl.submit).count();
+            latencies.push_back(dn.latency_s);
+            attempts_done += 4.0 * sl.n_rep * sl.plan->n_sweeps * sl.plan->lat.nstab;
+            done[sl.ticket] = std::move(dn);
+            where.erase(sl.ticket);
+            lds_used -= sl.lds;
+            sl.busy = false;
+            ++completed;
+            last_done = now;
+        }
+        cv_done.notify_all();
+    }
+    return XZZX_OK;
+}
+
+void xzzx_server::run()
+{
+    (void)hipSetDevice(device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] {
+                if (stop || !pending.empty()) return true;
+                for (const Slot &s : slots)
+                    if (s.busy) return true;
+                return false;
+            });
+            bool any = !pending.empty();
+            for (const Slot &s : slots) any = any || s.busy;
+            if (stop && !any) return;
+        }
+        const int rc = slice();
+        if (rc) {
+            std::lock_guard<std::mutex> lk(mu);
+            error = rc;
+            error_msg = xzzx_last_error();
+            stop = true;
+            cv_done.notify_all();
+            return;
+        }
+    }
+}
+
+extern "C" {
+
+int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out)
+{
+    if (!cfg || !out) { set_error("NULL argument"); return XZZX_EINVAL; }
+    *out = nullptr;
+    if (cfg->max_slots < 1 || cfg->max_rep < 1 || cfg->max_qubits < 9 || cfg->max_qubits > 2047 ||
+        cfg->sweeps_per_slice < 1 || cfg->max_pending < 1 || cfg->lds_budget_bytes < 0 ||
+        (cfg->greedy_mode != XZZX_GREEDY_RANDOM && cfg->greedy_mode != XZZX_GREEDY_SAME &&
+         cfg->greedy_mode != XZZX_GREEDY_BOUNDARY)) {
+        set_error("bad server configuration");
+        return XZZX_EINVAL;
+    }
+    auto *S = new (std::nothrow) xzzx_server();
+    if (!S) { set_error("out of host memory"); return XZZX_ENOMEM; }
+    S->cfg = *cfg;
+    int rc = check(hipGetDevice(&S->device), "hipGetDevice");
+    int cus = 0, lds_cu = 0;
+    if (!rc) rc = check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device), "CU count");
+    if (!rc && hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, S->device) != hipSuccess)
+        lds_cu = 160 * 1024;
+    if (lds_cu <= 0) lds_cu = 160 * 1024;
+    S->lds_budget = cfg->lds_budget_bytes ? (size_t)cfg->lds_budget_bytes : (size_t)cus * (size_t)lds_cu;
+    const size_t nq = (size_t)cfg->max_qubits, R = (size_t)cfg->max_rep;
+    S->max_nstab = cfg->max_qubits;   // n_stabs < n_qubits for both layouts
+    S->off_refs = 0;
+    S->off_states = align256(R * nq);
+    S->off_e3 = S->off_states + align256(4 * R * nq);
+    S->off_qraw = S->off_e3 + align256(3 * 4 * R * 4);
+    S->off_res = S->off_qraw + align256(R);
+    S->off_rec = S->off_res + 256;
+    S->slot_bytes = S->off_rec + align256(nq);
+    const size_t ns = (size_t)cfg->max_slots;
+    S->max_tasks = ns * 4 * R;
+    S->st_syn = 0;
+    S->st_uid = align256(ns * (size_t)S->max_nstab);
+    S->st_map = S->st_uid + align256(ns * 4);
+    S->st_tasks = S->st_map + align256(ns * 4);
+    S->st_fin = S->st_tasks + align256(S->max_tasks * sizeof(ServeTask));
+    S->st_out = S->st_fin + align256(ns * sizeof(ServeFinish)) + align256(ns * sizeof(ServeTask));
+    S->stage_bytes = S->st_out + align256(ns * (32 + nq));
+    if (!rc) rc = check(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking), "stream");
+    if (!rc && hipMalloc(&S->d_pool, S->slot_bytes * ns) != hipSuccess) { S->d_pool = nullptr; set_error("slot pool allocation"); rc = XZZX_ENOMEM; }
+    if (!rc && hipMalloc(&S->d_stage, S->stage_bytes) != hipSuccess) { S->d_stage = nullptr; set_error("staging allocation"); rc = XZZX_ENOMEM; }
+    if (!rc && hipHostMalloc(&S->h_stage, S->stage_bytes, hipHostMallocDefault) != hipSuccess) { S->h_stage = nullptr; set_error("pinned staging"); rc = XZZX_ENOMEM; }
+    if (rc) {
+        if (S->h_stage) (void)hipHostFree(S->h_stage);
+        if (S->d_stage) (void)hipFree(S->d_stage);
+        if (S->d_pool) (void)hipFree(S->d_pool);
+        if (S->stream) (void)hipStreamDestroy(S->stream);
+        delete S;
+        return rc;
+    }
+    S->slots.resize(ns);
+    S->worker = std::thread([S] { S->run(); });
+    *out = S;
+    return XZZX_OK;
+}
+
+int xzzx_server_submit(xzzx_server *srv, const xzzx_request *req, uint64_t *ticket)
+{
+    if (!srv || !req || !ticket || !req->plan || !req->syndrome) { set_error("NULL argument"); return XZZX_EINVAL; }
+    const Plan &P = req->plan->P;
+    if (req->n_rep < 1 || req->n_rep > srv->cfg.max_rep || P.lat.nq > srv->cfg.max_qubits || P.device != srv->device) {
+        set_error("request does not fit the server's slots (n_rep, qubits or device)");
+        return XZZX_EINVAL;
+    }
+    if (request_lds(P, req->n_rep) > srv->lds_budget) { set_error("request needs more LDS than the budget"); return XZZX_EINVAL; }
+    Pending p;
+    p.plan = req->plan;
+    p.syn.assign(req->syndrome, req->syndrome + P.lat.nstab);
+    p.uid = req->uid;
+    p.n_rep = req->n_rep;
+    p.submit = Clock::now();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->error) { set_error(srv->error_msg); return srv->error; }
+    if ((int)srv->pending.size() >= srv->cfg.max_pending) {
+        ++srv->rejected;
+        set_error("server queue full");
+        return XZZX_EAGAIN;
+    }
+    p.ticket = srv->next_ticket++;
+    *ticket = p.ticket;
+    srv->where[p.ticket] = 0;
+    srv->pending.push_back(std::move(p));
+    ++srv->submitted;
+    srv->cv_work.notify_one();
+    return XZZX_OK;
+}
+
+int xzzx_server_poll(xzzx_server *srv, uint64_t ticket, xzzx_result *out)
+{
+    if (!srv || !out) { set_error("NULL argument"); return XZZX_EINVAL; }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->done.find(ticket);
+    if (it == srv->done.end()) {
+        if (srv->error) { set_error(srv->error_msg); return srv->error; }
+        if (srv->where.count(ticket)) return XZZX_ENOTREADY;
+        set_error("unknown ticket");
+        return XZZX_EINVAL;
+    }
+    const Done &d = it->second;
+    out->e_best = d.e_best;
+    out->cls = d.cls;
+    for (int P = 0; P < 4; ++P) out->e_cls[P] = d.e_cls[P];
+    if (out->recovery) std::memcpy(out->recovery, d.recovery.data(), d.recovery.size());
+    out->latency_s = d.latency_s;
+    out->queue_s = d.queue_s;
+    srv->done.erase(it);
+    return XZZX_OK;
+}
+
+int xzzx_server_drain(xzzx_server *srv)
+{
+    if (!srv) { set_error("NULL argument"); return XZZX_EINVAL; }
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_done.wait(lk, [&] { return srv->error != XZZX_OK || srv->where.empty(); });
+    if (srv->error) { set_error(srv->error_msg); return srv->error; }
+    return XZZX_OK;
+}
+
+int xzzx_server_stats(xzzx_server *srv, xzzx_serve_stats *out)
+{
+    if (!srv || !out) { set_error("NULL argument"); return XZZX_EINVAL; }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = xzzx_serve_stats{};
+    out->submitted = srv->submitted;
+    out->completed = srv->completed;
+    out->rejected = srv->rejected;
+    out->slices = srv->slices;
+    if (!srv->latencies.empty()) {
+        std::vector<double> v = srv->latencies;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) {
+            const size_t i = (size_t)std::min<double>((double)v.size() - 1, std::max(0.0, std::ceil(q * v.size()) - 1));
+            return v[i];
+        };
+        out->p50_latency_s = pct(0.50);
+        out->p99_latency_s = pct(0.99);
+        double sum = 0;
+        for (double x : v) sum += x;
+        out->mean_latency_s = sum / v.size();
+        out->busy_s = std::chrono::duration<double>(srv->last_done - srv->first_admit).count();
+        if (out->busy_s > 0) {
+            out->decodes_per_s = srv->completed / out->busy_s;
+            out->attempts_per_s = srv->attempts_done / out->busy_s;
+        }
+    }
+    return XZZX_OK;
+}
+
+void xzzx_server_destroy(xzzx_server *srv)
+{
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->cv_work.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    (void)hipStreamSynchronize(srv->stream);
+    if (srv->h_stage) (void)hipHostFree(srv->h_stage);
+    if (srv->d_stage) (void)hipFree(srv->d_stage);
+    if (srv->d_pool) (void)hipFree(srv->d_pool);
+    if (srv->stream) (void)hipStreamDestroy(srv->stream);
+    delete srv;
+}
+
+}  // extern "C"

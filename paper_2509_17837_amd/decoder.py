@@ -270,3 +270,68 @@ class Graph:
         if h is not None and h.value and X._lib is not None:
             X._lib.xzzx_graph_destroy(h)
             self.h = None
+
+
+class Server:
+    """Serving loop (continuous batching) of the C ABI: submit single-syndrome
+    requests, poll results, read latency/throughput statistics."""
+
+    def __init__(self, max_slots=256, max_rep=16, max_qubits=625, sweeps_per_slice=100, max_pending=1 << 20,
+                 greedy_seed=0, anneal_seed=0, greedy_mode=X.GREEDY_RANDOM, lds_budget_bytes=0):
+        cfg = X.ServerCfg(max_slots, max_rep, max_qubits, sweeps_per_slice, max_pending, greedy_mode,
+                          lds_budget_bytes, greedy_seed, anneal_seed)
+        h = C.c_void_p()
+        call("xzzx_server_create", C.byref(cfg), C.byref(h))
+        self.h = h
+        self._plans = {}
+
+    def submit(self, plan: Plan, syndrome: np.ndarray, uid: int, n_rep: int) -> int:
+        syn = np.ascontiguousarray(syndrome, np.uint8)
+        req = X.Request(plan.h, syn.ctypes.data_as(C.c_void_p), int(uid) & 0xFFFFFFFF, n_rep)
+        t = C.c_uint64()
+        call("xzzx_server_submit", self.h, C.byref(req), C.byref(t))
+        self._plans[t.value] = plan
+        return t.value
+
+    def try_submit(self, plan, syndrome, uid, n_rep):
+        """Like submit, but returns None when the queue is full (EAGAIN)."""
+        syn = np.ascontiguousarray(syndrome, np.uint8)
+        req = X.Request(plan.h, syn.ctypes.data_as(C.c_void_p), int(uid) & 0xFFFFFFFF, n_rep)
+        t = C.c_uint64()
+        rc = lib().xzzx_server_submit(self.h, C.byref(req), C.byref(t))
+        if rc == X.XZZX_EAGAIN:
+            return None
+        X.check("xzzx_server_submit", rc)
+        self._plans[t.value] = plan
+        return t.value
+
+    def poll(self, ticket: int):
+        """Result dict, or None while the request is queued or resident."""
+        plan = self._plans[ticket]
+        rec = np.zeros(plan.nq, np.uint8)
+        res = X.Result()
+        res.recovery = rec.ctypes.data_as(C.c_void_p)
+        rc = lib().xzzx_server_poll(self.h, C.c_uint64(ticket), C.byref(res))
+        if rc == X.XZZX_ENOTREADY:
+            return None
+        X.check("xzzx_server_poll", rc)
+        del self._plans[ticket]
+        return dict(e_best=res.e_best, cls=res.cls, e_cls=list(res.e_cls), recovery=rec,
+                    latency_s=res.latency_s, queue_s=res.queue_s)
+
+    def drain(self):
+        call("xzzx_server_drain", self.h)
+
+    def stats(self):
+        st = X.ServeStats()
+        call("xzzx_server_stats", self.h, C.byref(st))
+        return {k: getattr(st, k) for k, _ in X.ServeStats._fields_}
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and X._lib is not None:
+            X._lib.xzzx_server_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,142 @@
+"""Serving loop (continuous batching): a request decoded alone, in a mix of
+other requests of different distance and bias that arrive while it is on the
+device, and by the batch decoder all give identical results (bit for bit),
+which also match the oracle; admission respects the slot and queue limits."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2509_17837_amd import _lib as X
+from paper_2509_17837_amd import decoder as D
+from paper_2509_17837_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GS, AS = 0xC0FFEE, 0xBADC0DE
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm GPU visible")
+    X.lib()
+
+
+class Spec:
+    def __init__(self, d, p, eta, sweeps, n, stream, uid0):
+        self.d, self.p, self.eta, self.sweeps = d, p, eta, sweeps
+        self.lat = D.Lattice(X.ROTATED, d)
+        w, wg = D.weights(p, D.noise(p, eta))
+        beta = D.schedule(X.SCHED_GEOMETRIC, 0.05, 10.0, sweeps)
+        self.plan = D.Plan(self.lat, w, wg, beta)
+        self.olat = O.Lattice(O.ROTATED, d)
+        err = inputs.sample_errors(n, self.lat.nq, inputs.channel(p, eta), 77, stream=stream)
+        self.syn = np.stack([self.olat.syndrome(e) for e in err])
+        self.uid = inputs.sample_uids(n, uid0)
+
+    def batch(self, n_rep):
+        out = D.decode(self.plan, torch.from_numpy(self.syn).cuda(), torch.from_numpy(self.uid.view(np.int32)).cuda(),
+                       n_rep, GS, AS)
+        torch.cuda.synchronize()
+        return out
+
+
+def same(res, out, i):
+    return (res["e_best"] == out.e_best[i].item() and res["cls"] == out.cls[i].item() and
+            np.array_equal(res["recovery"], out.recovery[i].cpu().numpy()) and
+            res["e_cls"] == out.e_cls[i].cpu().tolist())
+
+
+def test_request_alone_and_in_mix():
+    R = 16
+    specs = [Spec(d, 0.12, eta, 300, 6, k, 1000 * k)
+             for k, (d, eta) in enumerate([(7, 1.0), (11, 10.0), (15, 1000.0), (19, 10.0), (25, 1.0), (11, 1000.0)])]
+    target = specs[1]
+    srv = D.Server(max_slots=32, max_rep=R, max_qubits=625, sweeps_per_slice=40, greedy_seed=GS, anneal_seed=AS)
+    # alone
+    t = srv.submit(target.plan, target.syn[0], target.uid[0], R)
+    srv.drain()
+    alone = srv.poll(t)
+    assert alone is not None
+    # in a mix: requests keep arriving while earlier ones are resident
+    tickets = []
+    rng = np.random.default_rng(1)
+    order = [(k, i) for k in range(len(specs)) for i in range(len(specs[k].uid))]
+    rng.shuffle(order)
+    for n, (k, i) in enumerate(order):
+        tickets.append((k, i, srv.submit(specs[k].plan, specs[k].syn[i], specs[k].uid[i], R)))
+        if n % 7 == 3:
+            time.sleep(0.002)
+    srv.drain()
+    results = {(k, i): srv.poll(tk) for k, i, tk in tickets}
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(order) + 1 and st["slices"] > 1
+    mixed = results[(1, 0)]
+    for key in ("e_best", "cls", "e_cls"):
+        assert alone[key] == mixed[key]
+    assert np.array_equal(alone["recovery"], mixed["recovery"])
+    # every served result equals the batch decoder's
+    for k, s in enumerate(specs):
+        out = s.batch(R)
+        for i in range(len(s.uid)):
+            assert same(results[(k, i)], out, i), f"spec {k} request {i}"
+    # and the oracle's, on a sample
+    for k, i in [(0, 2), (1, 0), (4, 5)]:
+        s = specs[k]
+        w, wg = O.weights(s.p, O.noise(s.p, s.eta))
+        beta = O.schedule(O.SCHED_GEOMETRIC, 0.05, 10.0, s.sweeps)
+        ref = s.olat.decode(w, wg, s.syn[i], int(s.uid[i]), R, beta, GS, AS)
+        r = results[(k, i)]
+        assert r["e_best"] == ref["e_best"] and r["cls"] == ref["cls"]
+        assert np.array_equal(r["recovery"], ref["recovery"])
+
+
+def test_admission_limits():
+    """Two slots and a tiny queue: submissions beyond the queue are refused
+    with EAGAIN, admitted work completes, and results still match."""
+    R = 4
+    s = Spec(9, 0.15, 10.0, 120, 12, 9, 500)
+    srv = D.Server(max_slots=2, max_rep=R, max_qubits=81, sweeps_per_slice=30, max_pending=3, greedy_seed=GS,
+                   anneal_seed=AS)
+    got, refused = {}, 0
+    for i in range(len(s.uid)):
+        while True:
+            t = srv.try_submit(s.plan, s.syn[i], s.uid[i], R)
+            if t is not None:
+                got[i] = t
+                break
+            refused += 1
+            time.sleep(0.001)
+    srv.drain()
+    res = {i: srv.poll(t) for i, t in got.items()}
+    st = srv.stats()
+    srv.close()
+    assert refused > 0 and st["rejected"] == refused
+    out = s.batch(R)
+    for i in range(len(s.uid)):
+        assert same(res[i], out, i)
+    assert st["p99_latency_s"] >= st["p50_latency_s"] > 0
+
+
+def test_byte_kernel_and_empty_schedule():
+    """Requests on the byte-state kernel (planar-free path via set_kernel) and
+    with an empty schedule are served like the batch decoder serves them."""
+    R = 2
+    a = Spec(7, 0.2, 10.0, 50, 3, 21, 40)
+    a.plan.set_kernel(X.KERNEL_BYTES)
+    b = Spec(5, 0.2, 10.0, 0, 3, 22, 80)
+    srv = D.Server(max_slots=8, max_rep=R, max_qubits=49, sweeps_per_slice=17, greedy_seed=GS, anneal_seed=AS)
+    tk = [(a, i, srv.submit(a.plan, a.syn[i], a.uid[i], R)) for i in range(3)]
+    tk += [(b, i, srv.submit(b.plan, b.syn[i], b.uid[i], R)) for i in range(3)]
+    srv.drain()
+    res = [(s, i, srv.poll(t)) for s, i, t in tk]
+    srv.close()
+    outs = {id(a): a.batch(R), id(b): b.batch(R)}
+    for s, i, r in res:
+        assert same(r, outs[id(s)], i)
+    with pytest.raises(X.XzzxError):
+        D.Server(max_slots=0)
