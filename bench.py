@@ -50,6 +50,14 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-syndromes", type=int, default=32)
     ap.add_argument("--eager", action="store_true", help="no hipGraph capture")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-knob autotuner")
+    ap.add_argument("--serve", action="store_true", help="serving-loop benchmark (Poisson arrivals)")
+    ap.add_argument("--rates", default="1e3,3e3,1e4,3e4,1e5")
+    ap.add_argument("--requests", type=int, default=2000, help="requests per arrival rate (--serve)")
+    ap.add_argument("--slice", type=int, default=100, help="sweeps per serving slice (--serve)")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="most lanes per chain the server may use (--serve; 0: library default, 1: plan kernels)")
+    ap.add_argument("--waves", type=int, default=0, help="wave budget per serving slice (--serve; 0: default)")
     return ap.parse_args()
 
 
@@ -66,6 +74,8 @@ def main():
     from paper_2509_17837_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    if args.serve:
+        return serve_bench(args)
     wl = inputs.WORKLOADS[args.workload]
     seeds = inputs.seeds(args.workload)
     sched_kind = inputs.SCHEDULE_KIND[wl["schedule"][0]]
@@ -85,6 +95,11 @@ def main():
         w, wg = D.weights(p, D.noise(p, eta))
         plans.append(D.Plan(lats[d], w, wg, beta))
     ng = len(plans)
+    tuned = {}
+    if not args.no_tune:
+        for (d, p, eta), plan in zip(specs, plans):
+            # probe at the launch's real size (all groups share one launch)
+            tuned[f"d{d}_p{p}_eta{eta:g}"] = plan.autotune(R, n_syn=B * ng, probe_sweeps=10)
 
     # ---- inputs for every step, resident in HBM before timing ------------
     syn_all, uid_all, err_all = [], [], []
@@ -184,6 +199,7 @@ def main():
             "syndromes_per_step": syndromes_step,
             "attempts_per_step": attempts_step,
             "graphs": graphs is not None,
+            "autotuned": tuned,
             "seeds": seeds,
         },
         "decodes_per_s": decodes,
@@ -281,6 +297,97 @@ def cpu_baseline(args, wl, specs, plans, syn0, uid0, outs, R, sweeps, gs, as_):
                   np.array_equal(outs[g].recovery[i].cpu().numpy(), r["recovery"]))
     out["bitexact_with_gpu"] = f"{ok}/{n}"
     return out
+
+
+def serve_bench(args):
+    """Serving loop under Poisson arrivals: requests of the serving workload
+    (d and eta drawn uniformly per request) are submitted at their arrival
+    times while earlier ones run; reports p50/p99 latency and throughput per
+    arrival rate."""
+    import torch
+
+    from paper_2509_17837_amd import _lib as X
+    from paper_2509_17837_amd import decoder as D
+    from paper_2509_17837_amd import inputs
+
+    name = "serving_d7_25"
+    wl = inputs.WORKLOADS[name]
+    seeds = inputs.seeds(name)
+    kind = inputs.SCHEDULE_KIND[wl["schedule"][0]]
+    beta = D.schedule(kind, wl["schedule"][1], wl["schedule"][2], wl["sweeps"])
+    R = wl["n_rep"]
+    specs = [(d, eta) for d in wl["d"] for eta in wl["eta"]]
+    plans, lats = [], {}
+    p = wl["p"][0]
+    for d, eta in specs:
+        if d not in lats:
+            lats[d] = D.Lattice(X.ROTATED, d)
+        w, wg = D.weights(p, D.noise(p, eta))
+        plan = D.Plan(lats[d], w, wg, beta)
+        plans.append(plan)
+    rates = [float(x) for x in args.rates.split(",")]
+    n = args.requests
+    # requests: spec index, syndrome, uid (seeded), sampled ahead of time
+    rng = np.random.default_rng([seeds["sample"], 11])
+    pick = rng.integers(0, len(specs), size=n)
+    reqs = []
+    for i in range(n):
+        d, eta = specs[pick[i]]
+        err = inputs.sample_errors(1, d * d, inputs.channel(p, eta), seeds["sample"], stream=100000 + i)[0]
+        reqs.append((int(pick[i]), err))
+    # syndromes through the library's own kernel (untimed setup)
+    syns = []
+    for k, err in reqs:
+        syns.append(D.syndrome(plans[k], torch.from_numpy(err[None]).cuda())[0].cpu().numpy())
+    torch.cuda.synchronize()
+    attempts_per_req = [4 * R * wl["sweeps"] * plans[k].nstab for k, _ in reqs]
+    out = []
+    for rate in rates:
+        arr = inputs.poisson_arrivals(rate, n, seeds["sample"] + int(rate))
+        srv = D.Server(max_slots=4096, max_rep=R, max_qubits=max(d * d for d in wl["d"]),
+                       sweeps_per_slice=args.slice, greedy_seed=seeds["greedy"], anneal_seed=seeds["anneal"],
+                       max_lanes_per_chain=args.lanes, max_waves=args.waves)
+        t0 = time.perf_counter()
+        tickets = []
+        for i, (k, _) in enumerate(reqs):
+            while True:
+                now = time.perf_counter() - t0
+                if now >= arr[i]:
+                    break
+                if arr[i] - now > 2e-4:
+                    time.sleep((arr[i] - now) * 0.5)
+            tickets.append(srv.submit(plans[k], syns[i], 7_000_000 + i, R))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        for t in tickets:
+            srv.poll(t)
+        srv.close()
+        out.append({
+            "rate_per_s": rate, "requests": n,
+            "p50_latency_ms": 1e3 * st["p50_latency_s"], "p99_latency_ms": 1e3 * st["p99_latency_s"],
+            "mean_latency_ms": 1e3 * st["mean_latency_s"],
+            "decodes_per_s": st["decodes_per_s"], "attempts_per_s": st["attempts_per_s"],
+            "offered_attempts_per_s": rate * float(np.mean(attempts_per_req)),
+            "slices": st["slices"], "wall_s": wall,
+        })
+        print(f"[serve] rate {rate:g}/s: p50 {out[-1]['p50_latency_ms']:.2f} ms, p99 "
+              f"{out[-1]['p99_latency_ms']:.2f} ms, {st['decodes_per_s']:.0f} decodes/s", file=sys.stderr, flush=True)
+    result = {
+        "metric": "decode latency p50/p99 (serving, continuous batching)",
+        "value": out[0]["p99_latency_ms"],
+        "unit": "ms (p99 at the lowest rate)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"single-syndrome requests, rotated XZZX d in {wl['d']}, eta in {wl['eta']}, "
+                               f"p={p}, {R} replicas, {wl['sweeps']} sweeps geometric 0.05->10, Poisson arrivals",
+                   "name": name, "sweeps_per_slice": args.slice, "max_lanes_per_chain": args.lanes,
+                   "max_waves": args.waves, "seeds": seeds},
+        "rates": out,
+    }
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":

@@ -174,6 +174,24 @@ int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain);
 enum { XZZX_KERNEL_AUTO = 0, XZZX_KERNEL_ROWS = 1, XZZX_KERNEL_BYTES = 2 };
 int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel);
 
+/* Autotuner of the result-invariant knobs (kernel family, lanes per chain).
+ * Builds a probe plan with the same lattice and weights and the first
+ * probe_sweeps sweeps of the schedule, decodes n_syn random syndromes with
+ * n_rep replicas once per candidate on `stream` (annealing stage timed with
+ * HIP events, best of 3), and applies the fastest candidate to `plan`.
+ * Candidates: the packed-row kernel where it applies, and the byte-state
+ * kernel with 1, 2, 4, ..., 64 lanes per chain where its LDS fits.
+ * times_ms[8] (may be NULL) receives the time of each candidate, index 0 for
+ * the packed-row kernel and 1 + log2(lanes) for the byte-state kernel (-1 if
+ * not tried).  Allocates and frees its own device buffers. */
+typedef struct {
+    int kernel;            /* chosen XZZX_KERNEL_ROWS or XZZX_KERNEL_BYTES */
+    int lanes_per_chain;   /* chosen lanes (byte-state kernel) */
+    float times_ms[8];
+} xzzx_tune_result;
+int xzzx_plan_autotune(xzzx_plan *plan, int n_rep, int n_syn, int probe_sweeps, void *stream,
+                       xzzx_tune_result *out);
+
 /* ---- device operations ---------------------------------------------------- */
 
 /* Syndrome (Eq. (2)) of n configurations d_cfg[n][n_qubits] -> d_syn[n][n_stabs]. */
@@ -247,7 +265,9 @@ void xzzx_graph_destroy(xzzx_graph *graph);
  * slices: at each slice boundary it admits queued requests (greedy references
  * computed on the device), advances every resident request by
  * sweeps_per_slice sweeps in one launch per kernel family (requests of
- * different distance and noise mix freely), and finishes requests whose
+ * different distance and noise mix freely; a request advances a number of
+ * sweeps inversely proportional to the sequential work of one of its sweeps,
+ * so the tasks of a slice carry equal work), and finishes requests whose
  * schedule is complete (reduction and recovery on the device).  Chain states
  * stay in device memory between slices; counter-based random numbers make a
  * resumed chain identical to an uninterrupted one, so a request's result is
@@ -257,19 +277,30 @@ void xzzx_graph_destroy(xzzx_graph *graph);
  * slots of max_rep replicas on at most max_qubits qubits are allocated at
  * creation: the HBM budget) and the LDS its tasks need, summed over resident
  * requests, stays within lds_budget_bytes (0 = the device's total LDS), so
- * every resident task of a slice runs concurrently. */
+ * every resident task of a slice runs concurrently.
+ *
+ * Lanes per chain: each slice picks the largest power of two up to
+ * max_lanes_per_chain for which the slice's wavefronts stay within max_waves
+ * and its LDS within the budget; a request then runs on the byte-state kernel
+ * with that many lanes per chain (capped by its colour-class size), which
+ * cuts its latency when the device is lightly loaded.  When even two lanes do
+ * not fit, every request runs on its plan's own kernel choice.  Results do
+ * not depend on this choice. */
 typedef struct xzzx_server xzzx_server;
 
 typedef struct {
     int max_slots;            /* resident requests (device slots) */
     int max_rep;              /* largest n_rep of a request */
     int max_qubits;           /* largest lattice (qubits) of a request */
-    int sweeps_per_slice;     /* sweeps a resident request advances per slice (>= 1) */
+    int sweeps_per_slice;     /* sweeps per slice of the largest resident lattice (>= 1);
+                                 smaller lattices advance proportionally more */
     int max_pending;          /* queued requests before submit returns EAGAIN */
     int greedy_mode;          /* XZZX_GREEDY_* */
     int64_t lds_budget_bytes; /* 0: the device's total LDS */
     uint64_t greedy_seed;
     uint64_t anneal_seed;
+    int max_lanes_per_chain;  /* 0: 16; 1: always the plan's own kernel; else a power of two <= 64 */
+    int max_waves;            /* wavefronts per slice before lanes per chain shrink; 0: 32 per CU */
 } xzzx_server_cfg;
 
 typedef struct {

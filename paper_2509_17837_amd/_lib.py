@@ -55,6 +55,10 @@ class Group(C.Structure):
     ]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("kernel", C.c_int), ("lanes_per_chain", C.c_int), ("times_ms", C.c_float * 8)]
+
+
 class ServerCfg(C.Structure):
     _fields_ = [
         ("max_slots", C.c_int),
@@ -66,6 +70,8 @@ class ServerCfg(C.Structure):
         ("lds_budget_bytes", C.c_int64),
         ("greedy_seed", C.c_uint64),
         ("anneal_seed", C.c_uint64),
+        ("max_lanes_per_chain", C.c_int),
+        ("max_waves", C.c_int),
     ]
 
 
@@ -136,6 +142,7 @@ def lib():
         "xzzx_plan_info": (I, [V, P(I), P(I), P(I), P(I), P(I), P(I)]),
         "xzzx_plan_set_lanes": (I, [V, I]),
         "xzzx_plan_set_kernel": (I, [V, I]),
+        "xzzx_plan_autotune": (I, [V, I, I, I, V, P(TuneResult)]),
         "xzzx_syndrome": (I, [V, V, I64, V, V]),
         "xzzx_greedy_init": (I, [V, V, V, I64, I, U64, I, V, V, V]),
         "xzzx_decode_workspace": (I, [P(Group), I, P(C.c_size_t)]),

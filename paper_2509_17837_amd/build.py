@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxzzx_sa.so")
-SOURCES = ["xzzx_host.cpp", "xzzx_kernels.hip", "xzzx_server.cpp"]
+SOURCES = ["xzzx_host.cpp", "xzzx_kernels.hip", "xzzx_server.cpp", "xzzx_tune.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

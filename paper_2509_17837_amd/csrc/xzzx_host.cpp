@@ -355,6 +355,10 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
         if (it == shapes.end()) { shapes.push_back(mask); it = shapes.end() - 1; }
         shape_of_face[f] = (int)(it - shapes.begin());
     }
+    // a null shape (no slot present, energy change 0) pads the packed-row
+    // generator lists to whole Philox blocks
+    const int null_shape = (int)shapes.size();
+    shapes.push_back(0);
     P.ntypes = (int)shapes.size();
     // move energy of every (shape, slot pattern); absent slots contribute 0,
     // whatever their (scratch) byte holds
@@ -390,8 +394,12 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     const int mpad = 4 * ((L.per_class + 3) / 4);
     std::vector<uint32_t> rowface(4 * mpad, 0);
     if (P.row_words) {
+        // padding entries: the null shape on the nibble at column d+1 of rows
+        // 0 and 1, which holds only padding bits (never a qubit)
+        const uint32_t pad = 0u | ((2u * (uint32_t)(L.d + 1)) << 8) | ((uint32_t)null_shape << 16);
         for (int k = 0; k < 4; ++k)
-            for (int m = 0; m < L.per_class; ++m) {
+            for (int m = 0; m < mpad; ++m) {
+                if (m >= L.per_class) { rowface[k * mpad + m] = pad; continue; }
                 const int f = L.by_class[k * L.per_class + m];
                 const uint32_t Y = (uint32_t)(L.fcy[f] + 1), X = (uint32_t)(L.fcx[f] + 1);
                 rowface[k * mpad + m] = Y | ((2u * X) << 8) | ((uint32_t)shape_of_face[f] << 16);

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     extern __shared__ __align__(16) uint8_t smem[];
     const PlanDev *pl = A.plan;
     const int lane = threadIdx.x;
-    const int nq = pl->nq, nstab = pl->nstab;
+    const int nq = pl->nq;
     const int64_t sr = blockIdx.x;
     const int64_t s = sr / A.n_rep;
     const uint32_t r = (uint32_t)(sr - s * A.n_rep);
@@ -574,12 +574,34 @@ __device__ __forceinline__ void row_flip(uint32_t (&r)[NW], uint32_t bo, uint32_
     }
 }
 
+// r ^= (mask << bo) & sel as one v_bitop3 per word (truth table 0x6A:
+// c ^ (a & b) with a = shifted mask, b = sel, c = r).
+__device__ __forceinline__ uint32_t xor_and(uint32_t r, uint32_t mask, uint32_t sel)
+{
+    return __builtin_amdgcn_bitop3_b32(mask, sel, r, 0x6A);
+}
+
+template <int NW>
+__device__ __forceinline__ void row_flip_sel(uint32_t (&r)[NW], uint32_t bo, uint32_t mask, uint32_t sel)
+{
+    if (NW == 1) {
+        r[0] = xor_and(r[0], mask << bo, sel);
+        return;
+    }
+    if (bo < 32) {
+        r[0] = xor_and(r[0], mask << bo, sel);
+        if (bo > 28) r[NW > 1 ? 1 : 0] = xor_and(r[NW > 1 ? 1 : 0], mask >> (32 - bo), sel);
+    } else {
+        r[NW > 1 ? 1 : 0] = xor_and(r[NW > 1 ? 1 : 0], mask << (bo - 32), sel);
+    }
+}
+
 template <int NW>
 __device__ void rows_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
                           uint32_t seed_hi, uint8_t *smem)
 {
     const int lane = threadIdx.x;
-    const int d = (int)uni(pl->d), nq = (int)uni(pl->nq), M = (int)uni(pl->M), nblk = (int)uni(pl->nblk);
+    const int d = (int)uni(pl->d), nq = (int)uni(pl->nq), nblk = (int)uni(pl->nblk);
     const int nranks = (int)uni(pl->nranks), ntypes = (int)uni(pl->ntypes);
     const uint32_t kneg = uni(pl->kneg);
     const int rows = d + 2;
@@ -646,8 +668,7 @@ __device__ void rows_core(const PlanDev *pl, const ChainJob &J, int t_begin, int
                 const uint32_t fdv[4] = {tab[4 * b], tab[4 * b + 1], tab[4 * b + 2], tab[4 * b + 3]};
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
-                    const int m = 4 * b + w;
-                    if (m >= M) break;
+                    // ranks >= M are null generators (padding bits, dE = 0)
                     const uint32_t fd = fdv[w];
                     const int Y = (int)(fd & 0xFFu);
                     const uint32_t bo = (fd >> 8) & 0xFFu;
@@ -671,11 +692,12 @@ __device__ void rows_core(const PlanDev *pl, const ChainJob &J, int t_begin, int
                     const uint32_t pat = row_nibble<NW>(rA, bo) | (row_nibble<NW>(rB, bo) << 4);
                     const uint32_t rank = lut_s[(shp << 8) | pat];
                     const int2 et = et_s[rank];
-                    if (rank < kneg || uw[w] < (uint32_t)et.y) {
-                        row_flip<NW>(fA, bo, 6u);   // X_left (2) | Z_up (1 << 2)
-                        row_flip<NW>(fB, bo, 9u);   // Z_down (1) | X_right (2 << 2)
-                        acc_de += et.x;
-                    }
+                    // branch-free acceptance: sel is all ones on accepting lanes
+                    const bool accept = (rank < kneg) | (uw[w] < (uint32_t)et.y);
+                    const uint32_t sel = accept ? 0xFFFFFFFFu : 0u;
+                    row_flip_sel<NW>(fA, bo, 6u, sel);   // X_left (2) | Z_up (1 << 2)
+                    row_flip_sel<NW>(fB, bo, 9u, sel);   // Z_down (1) | X_right (2 << 2)
+                    acc_de += (int32_t)((uint32_t)et.x & sel);
                 }
             }
             if (curY >= 0) {

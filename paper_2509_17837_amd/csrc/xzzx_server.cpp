@@ -4,8 +4,10 @@
 //   1. admit queued requests into free device slots while the LDS budget
 //      allows (greedy references for all admissions of the slice, batched per
 //      plan, written straight into the slots);
-//   2. advance every resident request by sweeps_per_slice sweeps: one task per
-//      group of chains, all tasks of the slice in one launch per kernel family;
+//   2. advance every resident request by its share of sweeps (balanced so
+//      that every task carries about the same sequential work), with as many
+//      lanes per chain as the load allows: one task per group of chains, all
+//      tasks of the slice in one launch per kernel family;
 //   3. finish requests whose schedule is complete (per-coset reduction and
 //      replay of the best chain on the device, results copied to pinned host
 //      memory);
@@ -73,6 +75,7 @@ struct xzzx_server {
     size_t stage_bytes = 0, st_syn = 0, st_uid = 0, st_map = 0, st_tasks = 0, st_fin = 0, st_out = 0;
     size_t max_tasks = 0;
     size_t lds_budget = 0, lds_used = 0;
+    int64_t wave_budget = 0;
     int max_nstab = 0;
     std::vector<Slot> slots;
     std::thread worker;
@@ -111,6 +114,24 @@ size_t task_lds(const Plan &P, int *chains_per_task)
     return P.lds_bytes_anneal(P.lanes);
 }
 
+// lanes per chain for a request when the slice offers g: no more than a
+// colour class has generators (a power of two, at least 1)
+int lanes_for(const Plan &P, int g)
+{
+    const int per_class = std::max(1, P.lat.nstab / 4);
+    int c = 1;
+    while (2 * c <= per_class && 2 * c <= g) c *= 2;
+    return c;
+}
+
+// sequential work of one sweep of one chain: generators per lane
+int64_t sweep_cost(const Plan &P, int g)
+{
+    if (g == 1) return P.lat.nstab;
+    const int gr = lanes_for(P, g);
+    return (P.lat.nstab + gr - 1) / gr;
+}
+
 size_t request_lds(const Plan &P, int n_rep)
 {
     int C = 1;
@@ -133,6 +154,9 @@ int xzzx_server::slice()
     std::vector<int> admitted;
     {
         std::lock_guard<std::mutex> lk(mu);
+        // admit in arrival order; stage grouped by (plan, n_rep) so that one
+        // greedy launch covers every admission of a plan
+        std::vector<std::pair<int, Pending>> adm;
         while (!pending.empty()) {
             const Pending &p = pending.front();
             const Plan &P = p.plan->P;
@@ -155,13 +179,20 @@ int xzzx_server::slice()
             sl.admit = Clock::now();
             lds_used += need;
             where[p.ticket] = 1;
-            // stage the syndrome (index = position in `admitted`)
+            if (!started) { started = true; first_admit = sl.admit; }
+            adm.emplace_back(s, std::move(pending.front()));
+            pending.pop_front();
+        }
+        std::stable_sort(adm.begin(), adm.end(), [](const auto &a, const auto &b) {
+            if (a.second.plan != b.second.plan) return std::less<const xzzx_plan *>()(a.second.plan, b.second.plan);
+            return a.second.n_rep < b.second.n_rep;
+        });
+        // stage the syndromes (index = position in `admitted`)
+        for (const auto &[s, p] : adm) {
             std::memcpy(h_stage + st_syn + admitted.size() * (size_t)max_nstab, p.syn.data(), p.syn.size());
             reinterpret_cast<uint32_t *>(h_stage + st_uid)[admitted.size()] = p.uid;
             reinterpret_cast<int32_t *>(h_stage + st_map)[admitted.size()] = s;
             admitted.push_back(s);
-            if (!started) { started = true; first_admit = sl.admit; }
-            pending.pop_front();
         }
     }
     int rc = XZZX_OK;
@@ -191,17 +222,45 @@ int xzzx_server::slice()
     std::vector<ServeTask> rows_t, bytes_t;
     size_t lds_rows = 0, lds_bytes = 0;
     std::vector<int> finished;
+    // lanes per chain for this slice: at light load every chain spreads over
+    // up to max_lanes_per_chain lanes of the byte-state kernel (lower latency
+    // per request); as resident work grows the count halves until the slice
+    // fits the wave and LDS budgets, down to each plan's own kernel choice.
+    // Every choice gives the same chain trajectories, so it may change from
+    // one slice to the next.
+    int G = 1;
+    for (int g = cfg.max_lanes_per_chain; g > 1; g >>= 1) {
+        int64_t waves = 0;
+        size_t lds_max = 0;
+        for (const Slot &sl : slots) {
+            if (!sl.busy) continue;
+            const int gr = lanes_for(*sl.plan, g);
+            waves += (4 * sl.n_rep * gr + kWave - 1) / kWave;
+            lds_max = std::max(lds_max, sl.plan->lds_bytes_anneal(gr));
+        }
+        if (waves <= wave_budget && (size_t)waves * lds_max <= lds_budget) { G = g; break; }
+    }
+    // work-balanced slice: a request advances sweeps in inverse proportion to
+    // the sequential work of one of its sweeps (generators per lane), so every
+    // task of the slice carries about the work of sweeps_per_slice sweeps of
+    // the costliest resident request
+    int64_t ref_cost = 1;
+    for (const Slot &sl : slots)
+        if (sl.busy) ref_cost = std::max(ref_cost, sweep_cost(*sl.plan, G));
     for (size_t s = 0; s < slots.size(); ++s) {
         Slot &sl = slots[s];
         if (!sl.busy) continue;
         const Plan &P = *sl.plan;
-        const int t0 = sl.t, t1 = std::min(P.n_sweeps, t0 + cfg.sweeps_per_slice);
+        const int64_t share = std::max<int64_t>(1, (int64_t)cfg.sweeps_per_slice * ref_cost / sweep_cost(P, G));
+        const int t0 = sl.t, t1 = (int)std::min<int64_t>(P.n_sweeps, t0 + share);
         // a fresh request always gets a first task (it initialises E, E_min
         // and the stored state even for an empty schedule)
         if (t1 > t0 || !sl.started) {
             sl.started = true;
-            int C = 1;
-            const size_t lds = task_lds(P, &C);
+            const bool rows = G == 1 && P.use_rows;
+            const int gr = G > 1 ? lanes_for(P, G) : (P.use_rows ? 1 : P.lanes);
+            const int C = kWave / gr;
+            const size_t lds = rows ? P.lds_bytes_rows() : P.lds_bytes_anneal(gr);
             const int nc = 4 * sl.n_rep;
             uint8_t *base = slot_ptr((int)s);
             for (int c0 = 0; c0 < nc; c0 += C) {
@@ -219,10 +278,10 @@ int xzzx_server::slice()
                 T.t_begin = t0;
                 T.t_end = t1;
                 int lg = 0;
-                while ((1 << lg) < P.lanes) ++lg;
-                T.log_lanes = P.use_rows ? 0 : lg;
-                T.row_words = P.use_rows ? P.row_words : 0;
-                if (P.use_rows) { rows_t.push_back(T); lds_rows = std::max(lds_rows, lds); }
+                while ((1 << lg) < gr) ++lg;
+                T.log_lanes = rows ? 0 : lg;
+                T.row_words = rows ? P.row_words : 0;
+                if (rows) { rows_t.push_back(T); lds_rows = std::max(lds_rows, lds); }
                 else { bytes_t.push_back(T); lds_bytes = std::max(lds_bytes, lds); }
             }
             sl.t = t1;
@@ -366,6 +425,8 @@ int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out)
     *out = nullptr;
     if (cfg->max_slots < 1 || cfg->max_rep < 1 || cfg->max_qubits < 9 || cfg->max_qubits > 2047 ||
         cfg->sweeps_per_slice < 1 || cfg->max_pending < 1 || cfg->lds_budget_bytes < 0 ||
+        cfg->max_lanes_per_chain < 0 || cfg->max_lanes_per_chain > kWave ||
+        (cfg->max_lanes_per_chain & (cfg->max_lanes_per_chain - 1)) != 0 || cfg->max_waves < 0 ||
         (cfg->greedy_mode != XZZX_GREEDY_RANDOM && cfg->greedy_mode != XZZX_GREEDY_SAME &&
          cfg->greedy_mode != XZZX_GREEDY_BOUNDARY)) {
         set_error("bad server configuration");
@@ -381,6 +442,8 @@ int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out)
         lds_cu = 160 * 1024;
     if (lds_cu <= 0) lds_cu = 160 * 1024;
     S->lds_budget = cfg->lds_budget_bytes ? (size_t)cfg->lds_budget_bytes : (size_t)cus * (size_t)lds_cu;
+    S->wave_budget = cfg->max_waves ? cfg->max_waves : 32 * (int64_t)cus;
+    if (!S->cfg.max_lanes_per_chain) S->cfg.max_lanes_per_chain = 16;
     const size_t nq = (size_t)cfg->max_qubits, R = (size_t)cfg->max_rep;
     S->max_nstab = cfg->max_qubits;   // n_stabs < n_qubits for both layouts
     S->off_refs = 0;

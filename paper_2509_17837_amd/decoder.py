@@ -127,6 +127,14 @@ class Plan:
     def set_kernel(self, kernel):
         call("xzzx_plan_set_kernel", self.h, int(kernel))
 
+    def autotune(self, n_rep, n_syn=256, probe_sweeps=50, stream=None):
+        """Pick the fastest result-invariant launch knobs for this plan."""
+        r = X.TuneResult()
+        call("xzzx_plan_autotune", self.h, n_rep, n_syn, probe_sweeps, _stream(stream), C.byref(r))
+        names = ["rows"] + [f"bytes{1 << i}" for i in range(7)]
+        return {"kernel": "rows" if r.kernel == X.KERNEL_ROWS else "bytes", "lanes_per_chain": r.lanes_per_chain,
+                "times_ms": {n: round(t, 3) for n, t in zip(names, r.times_ms) if t >= 0}}
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h is not None and h.value and X._lib is not None:
@@ -277,9 +285,10 @@ class Server:
     requests, poll results, read latency/throughput statistics."""
 
     def __init__(self, max_slots=256, max_rep=16, max_qubits=625, sweeps_per_slice=100, max_pending=1 << 20,
-                 greedy_seed=0, anneal_seed=0, greedy_mode=X.GREEDY_RANDOM, lds_budget_bytes=0):
+                 greedy_seed=0, anneal_seed=0, greedy_mode=X.GREEDY_RANDOM, lds_budget_bytes=0,
+                 max_lanes_per_chain=0, max_waves=0):
         cfg = X.ServerCfg(max_slots, max_rep, max_qubits, sweeps_per_slice, max_pending, greedy_mode,
-                          lds_budget_bytes, greedy_seed, anneal_seed)
+                          lds_budget_bytes, greedy_seed, anneal_seed, max_lanes_per_chain, max_waves)
         h = C.c_void_p()
         call("xzzx_server_create", C.byref(cfg), C.byref(h))
         self.h = h

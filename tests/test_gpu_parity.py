@@ -113,6 +113,17 @@ def test_row_and_byte_kernels_agree(d):
         gpu_plan(Problem(1, 5, 0.2, 10.0, 1, 1, 1)).set_kernel(X.KERNEL_ROWS)
 
 
+def test_autotuned_plan_matches_oracle():
+    """The autotuner only chooses among result-invariant launch knobs."""
+    for d, R in [(9, 8), (25, 4)]:
+        prob = Problem(0, d, 0.2, 10.0, 4, R, 25, seed=400 + d)
+        plan = gpu_plan(prob)
+        tuned = plan.autotune(R, n_syn=64, probe_sweeps=10)
+        print(f"[autotune] d={d}: {tuned}", flush=True)
+        assert tuned["times_ms"]
+        compare_decode(prob, run_decode(prob, plan), prob.oracle_decode())
+
+
 def test_plain_form_matches_persistent():
     prob = Problem(0, 7, 0.15, 10.0, 9, 4, 40, seed=77)
     ref = prob.oracle_decode()

@@ -50,12 +50,18 @@ def same(res, out, i):
             res["e_cls"] == out.e_cls[i].cpu().tolist())
 
 
-def test_request_alone_and_in_mix():
+@pytest.mark.parametrize("lanes,waves", [(0, 0), (1, 0), (64, 0), (16, 30)],
+                         ids=["adaptive", "plan-kernel", "up-to-64-lanes", "lanes-shift-with-load"])
+def test_request_alone_and_in_mix(lanes, waves):
+    """lanes/waves: the per-slice lanes-per-chain policy; with a small wave
+    budget the lane count of a resident request changes as others arrive and
+    leave, which must not change its result."""
     R = 16
     specs = [Spec(d, 0.12, eta, 300, 6, k, 1000 * k)
              for k, (d, eta) in enumerate([(7, 1.0), (11, 10.0), (15, 1000.0), (19, 10.0), (25, 1.0), (11, 1000.0)])]
     target = specs[1]
-    srv = D.Server(max_slots=32, max_rep=R, max_qubits=625, sweeps_per_slice=40, greedy_seed=GS, anneal_seed=AS)
+    srv = D.Server(max_slots=32, max_rep=R, max_qubits=625, sweeps_per_slice=40, greedy_seed=GS, anneal_seed=AS,
+                   max_lanes_per_chain=lanes, max_waves=waves)
     # alone
     t = srv.submit(target.plan, target.syn[0], target.uid[0], R)
     srv.drain()
@@ -140,3 +146,7 @@ def test_byte_kernel_and_empty_schedule():
         assert same(r, outs[id(s)], i)
     with pytest.raises(X.XzzxError):
         D.Server(max_slots=0)
+    with pytest.raises(X.XzzxError):
+        D.Server(max_lanes_per_chain=3)
+    with pytest.raises(X.XzzxError):
+        D.Server(max_lanes_per_chain=128)
