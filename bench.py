@@ -38,6 +38,28 @@ OPS_PER_ATTEMPT = 19
 ALU_PEAK_OPS = 256 * 128 * 2.4e9
 
 
+def measured_traffic(kernel, workload, batch):
+    """HBM bytes per launch of the annealing kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of known
+    size), or None when the summary is for another kernel source, kernel or
+    workload."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
+    src = os.path.join(ROOT, "paper_2509_17837_amd", "csrc", "xzzx_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if " = " in line:
+            k, v = line.split(" = ", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != sha or kv.get("workload") != f"{workload} batch {batch}":
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +200,7 @@ def main():
         fails = sum(1 for i in range(B) if lats[d].cls(err[i], rec[i]) != 0)
         ler[f"d{d}_p{p}_eta{eta:g}"] = fails / B
 
+    kernel_name = "k_anneal_rows" if all(pl.info()["kernel"] == X.KERNEL_ROWS for pl in plans) else "k_anneal"
     result = {
         "metric": "stabilizer-flip attempts/s",
         "value": value,
@@ -206,12 +229,13 @@ def main():
         "stage_ms": {"greedy": stage_ms[0], "anneal": stage_ms[1], "finish": stage_ms[2]},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_anneal_rows" if all(pl.info()["kernel"] == X.KERNEL_ROWS for pl in plans) else "k_anneal",
+            "kernel": kernel_name,
             "achieved": achieved_ops / 1e12,
             "peak": ALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (int32 lane-ops)",
             "frac": achieved_ops / ALU_PEAK_OPS,
-            "traffic": None,
+            "traffic": measured_traffic(kernel_name, args.workload, B),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "ops_per_attempt": OPS_PER_ATTEMPT,
             "anneal_ms_per_launch": stage_ms[1],
         },
