@@ -200,7 +200,13 @@ def main():
         fails = sum(1 for i in range(B) if lats[d].cls(err[i], rec[i]) != 0)
         ler[f"d{d}_p{p}_eta{eta:g}"] = fails / B
 
-    kernel_name = "k_anneal_rows" if all(pl.info()["kernel"] == X.KERNEL_ROWS for pl in plans) else "k_anneal"
+    kinds = {pl.info()["kernel"] for pl in plans}
+    if kinds == {X.KERNEL_ROWS} and len(set(wl["d"])) == 1 and (4 * R) % 64 == 0:
+        kernel_name = f"k_anneal_rows_d{wl['d'][0]}"   # packed rows specialised to d
+    elif kinds <= {X.KERNEL_ROWS, X.KERNEL_ROWS_GENERIC}:
+        kernel_name = "k_anneal_rows"
+    else:
+        kernel_name = "k_anneal"
     result = {
         "metric": "stabilizer-flip attempts/s",
         "value": value,

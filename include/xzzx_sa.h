@@ -166,12 +166,17 @@ int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sw
 int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain);
 
 /* Which annealing kernel a plan uses (results are identical):
- *   XZZX_KERNEL_ROWS: one chain per lane, 2-bit codes packed row by row in
- *     LDS and staged through registers (rotated lattices with d <= 29);
+ *   XZZX_KERNEL_ROWS: one chain per lane, 2-bit codes packed row by row
+ *     (rotated lattices with d <= 29); for d <= 13 a variant specialised to
+ *     the distance keeps every row in registers and its generator schedule
+ *     in the instruction stream;
+ *   XZZX_KERNEL_ROWS_GENERIC: the packed-row kernel without that
+ *     specialisation (rows in LDS, schedule read from the plan);
  *   XZZX_KERNEL_BYTES: byte-per-qubit states, lanes_per_chain lanes per chain;
  *   XZZX_KERNEL_AUTO: ROWS where it applies, else BYTES (the default).
- * EINVAL for ROWS on a lattice it does not cover. */
-enum { XZZX_KERNEL_AUTO = 0, XZZX_KERNEL_ROWS = 1, XZZX_KERNEL_BYTES = 2 };
+ * EINVAL for ROWS or ROWS_GENERIC on a lattice they do not cover.
+ * xzzx_plan_info reports ROWS only where the specialised variant runs. */
+enum { XZZX_KERNEL_AUTO = 0, XZZX_KERNEL_ROWS = 1, XZZX_KERNEL_BYTES = 2, XZZX_KERNEL_ROWS_GENERIC = 3 };
 int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel);
 
 /* Autotuner of the result-invariant knobs (kernel family, lanes per chain).

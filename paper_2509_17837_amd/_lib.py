@@ -19,7 +19,7 @@ SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
 FLAG_PLAIN = 1
 STAGE_GREEDY, STAGE_ANNEAL, STAGE_FINISH = 2, 4, 8
-KERNEL_AUTO, KERNEL_ROWS, KERNEL_BYTES = 0, 1, 2
+KERNEL_AUTO, KERNEL_ROWS, KERNEL_BYTES, KERNEL_ROWS_GENERIC = 0, 1, 2, 3
 
 _STATUS = {
     XZZX_EINVAL: "EINVAL", XZZX_ENOMEM: "ENOMEM", XZZX_EDEVICE: "EDEVICE",

@@ -203,6 +203,32 @@ size_t Plan::lds_bytes_rows() const
     return (off + 15) & ~size_t(15);
 }
 
+template <int D>
+static bool schedule_matches(const std::vector<uint32_t> &rowface, int mpad)
+{
+    constexpr RotSchedule<D> S{};
+    if (S.MP != mpad) return false;
+    for (int k = 0; k < 4; ++k)
+        for (int m = 0; m < mpad; ++m) {
+            const RotGen &g = S.g[k][m];
+            if (rowface[k * mpad + m] != (g.Y | ((uint32_t)g.bo << 8) | ((uint32_t)g.shp << 16))) return false;
+        }
+    return true;
+}
+
+static bool static_schedule_matches(int d, const std::vector<uint32_t> &rowface, int mpad)
+{
+    switch (d) {
+    case 3: return schedule_matches<3>(rowface, mpad);
+    case 5: return schedule_matches<5>(rowface, mpad);
+    case 7: return schedule_matches<7>(rowface, mpad);
+    case 9: return schedule_matches<9>(rowface, mpad);
+    case 11: return schedule_matches<11>(rowface, mpad);
+    case 13: return schedule_matches<13>(rowface, mpad);
+    default: return false;
+    }
+}
+
 // Packed-row layout (rotated lattice): the padded grid has columns and rows
 // -1..d; a row of 2-bit codes takes 2(d+2) bits, so 1 word for d <= 13 and 2
 // words for d <= 29.
@@ -346,15 +372,18 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     for (double b : P.beta)
         if (!(b >= 0.0) || !std::isfinite(b)) { set_error("beta must be finite and >= 0"); return XZZX_EINVAL; }
 
-    // shapes = which of the four slots exist
-    std::vector<int> shape_of_face(L.nstab), shapes;
+    // shapes = which of the four slots exist, numbered in descending mask
+    // order (the canonical numbering the specialised kernels assume)
+    std::vector<int> shape_of_face(L.nstab), mask_of_face(L.nstab), shapes;
     for (int f = 0; f < L.nstab; ++f) {
         int mask = 0;
         for (int s = 0; s < 4; ++s) if (L.fq[4 * f + s] >= 0) mask |= 1 << s;
-        auto it = std::find(shapes.begin(), shapes.end(), mask);
-        if (it == shapes.end()) { shapes.push_back(mask); it = shapes.end() - 1; }
-        shape_of_face[f] = (int)(it - shapes.begin());
+        mask_of_face[f] = mask;
+        if (std::find(shapes.begin(), shapes.end(), mask) == shapes.end()) shapes.push_back(mask);
     }
+    std::sort(shapes.begin(), shapes.end(), std::greater<int>());
+    for (int f = 0; f < L.nstab; ++f)
+        shape_of_face[f] = (int)(std::find(shapes.begin(), shapes.end(), mask_of_face[f]) - shapes.begin());
     // a null shape (no slot present, energy change 0) pads the packed-row
     // generator lists to whole Philox blocks
     const int null_shape = (int)shapes.size();
@@ -405,6 +434,13 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
                 rowface[k * mpad + m] = Y | ((2u * X) << 8) | ((uint32_t)shape_of_face[f] << 16);
             }
     }
+    // the specialised packed-row kernel applies when its compile-time
+    // schedule is exactly this plan's table
+    P.static_d = 0;
+    if (P.row_words == 1 && L.layout == XZZX_ROTATED && L.d >= kStaticMinD && L.d <= kStaticMaxD &&
+        nranks <= kStaticRanks && static_schedule_matches(L.d, rowface, mpad))
+        P.static_d = L.d;
+    P.static_ok = P.static_d ? 1 : 0;
     std::vector<Desc> desc(4 * L.per_class), fdesc(L.nstab);
     for (int f = 0; f < L.nstab; ++f) fdesc[f] = pack_desc(L, f, shape_of_face[f]);
     for (int k = 0; k < 4; ++k)
@@ -685,9 +721,11 @@ int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel)
     if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
     if (kernel == XZZX_KERNEL_AUTO) {
         plan->P.use_rows = plan->P.row_words ? 1 : 0;
-    } else if (kernel == XZZX_KERNEL_ROWS) {
+        plan->P.static_d = plan->P.static_ok ? plan->P.lat.d : 0;
+    } else if (kernel == XZZX_KERNEL_ROWS || kernel == XZZX_KERNEL_ROWS_GENERIC) {
         if (!plan->P.row_words) { set_error("the packed-row kernel needs a rotated lattice with d <= 29"); return XZZX_EINVAL; }
         plan->P.use_rows = 1;
+        plan->P.static_d = (kernel == XZZX_KERNEL_ROWS && plan->P.static_ok) ? plan->P.lat.d : 0;
     } else if (kernel == XZZX_KERNEL_BYTES) {
         plan->P.use_rows = 0;
     } else {
@@ -700,7 +738,8 @@ int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel)
 int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sweeps, int *n_dE,
                    int *lanes_per_chain, int *kernel)
 {
-    if (plan && kernel) *kernel = plan->P.use_rows ? XZZX_KERNEL_ROWS : XZZX_KERNEL_BYTES;
+    if (plan && kernel)
+        *kernel = !plan->P.use_rows ? XZZX_KERNEL_BYTES : plan->P.static_d ? XZZX_KERNEL_ROWS : XZZX_KERNEL_ROWS_GENERIC;
     if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
     if (n_qubits) *n_qubits = plan->P.lat.nq;
     if (n_stabs) *n_stabs = plan->P.lat.nstab;

@@ -27,6 +27,60 @@ struct Desc {
     uint32_t x, y;
 };
 
+// Canonical generator shapes (slot-presence masks, slot s = bit s) in
+// descending mask order; the plan numbers the shapes of a lattice in this
+// order and appends the null shape (no slot) last.  On the rotated lattice
+// these are: 15 bulk, 12 bottom edge, 10 left edge, 5 right edge, 3 top edge.
+constexpr int kRotShapeMasks[6] = {15, 12, 10, 5, 3, 0};
+
+// Compile-time generator schedule of the rotated lattice at distance D for
+// the packed-row kernel specialised to D (one 32-bit word per row, so
+// D <= 13): for colour class k and rank m, the row Y = j + 1 of cell (i, j),
+// the bit offset 2(i + 1) of its nibble and its canonical shape.  Ranks run
+// row-major over (j, i), as in the plan; each class is padded to a multiple
+// of four with null generators on the padding nibble of rows 0 and 1.
+struct RotGen {
+    uint8_t Y, bo, shp;
+};
+
+template <int D>
+struct RotSchedule {
+    static constexpr int M = (D * D - 1) / 4;
+    static constexpr int MP = (M + 3) / 4 * 4;
+    RotGen g[4][MP];
+    constexpr RotSchedule() : g{}
+    {
+        int cnt[4] = {0, 0, 0, 0};
+        for (int j = -1; j < D; ++j)
+            for (int i = -1; i < D; ++i) {
+                const bool col_in = i >= 0 && i <= D - 2, row_in = j >= 0 && j <= D - 2;
+                bool gen = false;
+                if (col_in && row_in) gen = true;
+                else if (col_in && j == -1) gen = (i % 2) == 1;
+                else if (col_in && j == D - 1) gen = (i % 2) == 0;
+                else if (row_in && i == -1) gen = (j % 2) == 0;
+                else if (row_in && i == D - 1) gen = (j % 2) == 1;
+                if (!gen) continue;
+                int mask = 0;
+                if (i >= 0 && j >= 0) mask |= 1;                  // X on (i, j)
+                if (i <= D - 2 && j >= 0) mask |= 2;              // Z on (i+1, j)
+                if (i >= 0 && j <= D - 2) mask |= 4;              // Z on (i, j+1)
+                if (i <= D - 2 && j <= D - 2) mask |= 8;          // X on (i+1, j+1)
+                int shp = 0;
+                while (kRotShapeMasks[shp] != mask) ++shp;
+                const int k = ((i + 1) & 1) | (((j + 1) & 1) << 1);
+                g[k][cnt[k]++] = RotGen{(uint8_t)(j + 1), (uint8_t)(2 * (i + 1)), (uint8_t)shp};
+            }
+        for (int k = 0; k < 4; ++k)
+            for (int m = cnt[k]; m < MP; ++m) g[k][m] = RotGen{0, (uint8_t)(2 * (D + 1)), 5};
+    }
+};
+
+// Distances with a specialised packed-row kernel, and the largest number of
+// distinct move energies its static tables hold.
+constexpr int kStaticMinD = 3, kStaticMaxD = 13;
+constexpr int kStaticRanks = 128;
+
 // Host-side lattice: geometry shared by every plan built on it.
 struct Lattice {
     int layout = 0, d = 0, nq = 0, nstab = 0, per_class = 0;
@@ -74,6 +128,9 @@ struct Plan {
     int lanes_default = 1, lanes = 1;
     int row_words = 0;             // 0: the packed-row kernel does not apply to this lattice
     int use_rows = 0;              // 1: annealing runs on the packed-row kernel
+    int static_d = 0;              // d if the packed-row kernel specialised to d applies, else 0
+    int static_ok = 0;             // the plan's tables match the specialised schedule
+    int nranks() const { return (int)dE.size(); }
     int device = 0;
     void *dmem = nullptr;          // device allocation holding every table
     size_t dbytes = 0;

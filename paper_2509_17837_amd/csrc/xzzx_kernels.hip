@@ -16,6 +16,8 @@
 //   k_reduce    Eqs. (18)-(21): per-coset minima, P*, best chain.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -728,6 +730,221 @@ __device__ void rows_core(const PlanDev *pl, const ChainJob &J, int t_begin, int
     wave_lds_fence();
 }
 
+// ---------------------------------------------------------------------------
+// Packed-row core specialised to distance D (rotated lattice, D <= 13).
+// Same chains as rows_core, bit for bit; what changes is where things live.
+// Every row of the chain's padded grid stays in a register for the whole run,
+// and the generator schedule (row, nibble offset, shape of every rank of every
+// class) is a compile-time table, so the sweep is straight-line code: no
+// descriptor loads, no row loads or stores, no per-move scalar work, and the
+// null generators that pad a class to whole Philox blocks cost nothing.  The
+// move-energy lookup maps (shape, pattern) to the byte offset of a 16-byte
+// (dE, threshold, always-accept mask) entry in static LDS; the four generators
+// of a Philox block are disjoint, so their patterns are read before any flips.
+// ---------------------------------------------------------------------------
+__device__ void load_static_tables(const PlanDev *pl, uint16_t *lut_s, uint4 *et_s)
+{
+    const int lane = threadIdx.x;
+    for (int i = lane; i < 256 * 6; i += kWave) lut_s[i] = (uint16_t)(16u * pl->lut[i]);
+    for (int i = lane; i < pl->nranks; i += kWave) {
+        const int32_t de = pl->dE[i];
+        et_s[i] = make_uint4((uint32_t)de, 0u, de <= 0 ? 0xFFFFFFFFu : 0u, 0u);
+    }
+    wave_lds_fence();
+}
+
+// Philox4x32-10 of the counter (uid, cc, c2, b) with uid, c2, b and the key
+// uniform across the wavefront and cc the lane's chain.  Tracing which words
+// depend on the lane: the two products of round 0 are uniform; round 1
+// multiplies one lane word and one uniform word; round 2 likewise; from round
+// 3 on every word depends on the lane.  The lane products of rounds 1-2 do
+// not involve b, so PhiloxHead computes them once per (sweep, class) and
+// philox_block adds the b-dependent uniform products on the scalar unit.
+constexpr uint32_t kPhM0 = 0xD2511F53u, kPhM1 = 0xCD9E8D57u, kPhW0 = 0x9E3779B9u, kPhW1 = 0xBB67AE85u;
+
+struct PhiloxHead {
+    uint32_t hi0, y1;   // uniform: high word of M0*uid (round 0), low word of M1*c2
+    uint32_t w2, z2x;   // lane: round-1 outputs w and (z without the b-dependent part)
+    uint32_t a3, y3;    // lane: high and low words of M1*z2 (round 2)
+};
+
+__device__ __forceinline__ PhiloxHead philox_head(uint32_t uid, uint32_t cc, uint32_t c2, uint32_t k0, uint32_t k1)
+{
+    PhiloxHead h;
+    const uint64_t p0 = (uint64_t)uid * kPhM0;            // uniform
+    const uint64_t p1 = (uint64_t)c2 * kPhM1;             // uniform
+    h.hi0 = (uint32_t)(p0 >> 32);
+    h.y1 = (uint32_t)p1;
+    const uint32_t w1 = (uint32_t)p0;
+    const uint32_t x1 = (uint32_t)(p1 >> 32) ^ k0 ^ cc;   // lane
+    const uint64_t q = (uint64_t)x1 * kPhM0;              // round 1, lane
+    h.z2x = (uint32_t)(q >> 32) ^ w1 ^ (k1 + kPhW1);
+    h.w2 = (uint32_t)q;
+    const uint64_t r = (uint64_t)h.z2x * kPhM1;           // round 2, lane
+    h.a3 = (uint32_t)(r >> 32);
+    h.y3 = (uint32_t)r;
+    return h;
+}
+
+__device__ __forceinline__ uint4 philox_block(const PhiloxHead &h, uint32_t b, uint32_t k0, uint32_t k1)
+{
+    uint32_t z1 = h.hi0 ^ b ^ k1;                         // round 0 output z (uniform)
+    // computed per block on the scalar unit rather than hoisted out of the
+    // sweep loop into vector registers
+    asm volatile("" : "+s"(z1));
+    const uint64_t p1 = (uint64_t)z1 * kPhM1;             // round 1, uniform
+    const uint32_t x2 = (uint32_t)(p1 >> 32) ^ h.y1 ^ (k0 + kPhW0);
+    const uint32_t y2 = (uint32_t)p1;
+    const uint64_t p0 = (uint64_t)x2 * kPhM0;             // round 2, uniform
+    uint4 c = make_uint4(h.a3 ^ (y2 ^ (k0 + 2u * kPhW0)), h.y3,
+                         h.w2 ^ ((uint32_t)(p0 >> 32) ^ (k1 + 2u * kPhW1)), (uint32_t)p0);
+    k0 += 3u * kPhW0;
+    k1 += 3u * kPhW1;
+#pragma unroll
+    for (int i = 3; i < 10; ++i) {
+        const uint64_t q0 = (uint64_t)c.x * kPhM0;
+        const uint64_t q1 = (uint64_t)c.z * kPhM1;
+        c = make_uint4(xor3_key((uint32_t)(q1 >> 32), c.y, k0), (uint32_t)q1,
+                       xor3_key((uint32_t)(q0 >> 32), c.w, k1), (uint32_t)q0);
+        k0 += kPhW0;
+        k1 += kPhW1;
+    }
+    return c;
+}
+
+// All ones where u < thr (unsigned), from the borrow of u - thr: bit 31 of
+// (~u & thr) | (~(u ^ thr) & (u - thr)), one v_bitop3 (truth table 0x8E).
+__device__ __forceinline__ uint32_t lt_mask(uint32_t u, uint32_t thr)
+{
+    return (uint32_t)((int32_t)__builtin_amdgcn_bitop3_b32(u, thr, u - thr, 0x8E) >> 31);
+}
+
+// Pattern of the generator at nibble offset BO of rows (ra, rb), times two:
+// bits 1-4 from ra, bits 5-8 from rb.
+template <int BO>
+__device__ __forceinline__ uint32_t pattern_x2(uint32_t ra, uint32_t rb)
+{
+    const uint32_t a = BO >= 1 ? ra >> (BO - 1) : ra << 1;
+    const uint32_t b = BO >= 5 ? rb >> (BO - 5) : rb << (5 - BO);
+    return (b & 0x1E0u) | (a & 0x1Eu);
+}
+
+template <int D, int K, int B, int W>
+__device__ __forceinline__ void static_move(uint32_t (&r)[D + 2], uint32_t u, const uint16_t *lut_s, const uint4 *et_s,
+                                            int32_t &acc)
+{
+    constexpr RotSchedule<D> S{};
+    constexpr RotGen g = S.g[K][4 * B + W];
+    if constexpr (g.shp != 5) {
+        const uint32_t pat2 = pattern_x2<g.bo>(r[g.Y], r[g.Y + 1]);
+        const uint32_t off = *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(lut_s) +
+                                                                 512u * g.shp + pat2);
+        const uint4 e = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint8_t *>(et_s) + off);
+        // all ones on accepting lanes: u < threshold, or dE <= 0
+        const uint32_t sel = lt_mask(u, e.y) | e.z;
+        r[g.Y] = xor_and(r[g.Y], 6u << g.bo, sel);           // X_left | Z_up
+        r[g.Y + 1] = xor_and(r[g.Y + 1], 9u << g.bo, sel);   // Z_down | X_right
+        acc += (int32_t)(e.x & sel);
+    }
+}
+
+template <int D, int K, int B>
+__device__ __forceinline__ void static_block(uint32_t (&r)[D + 2], const PhiloxHead &h, uint32_t k0, uint32_t k1,
+                                             const uint16_t *lut_s, const uint4 *et_s, int32_t &acc)
+{
+    const uint4 u = philox_block(h, (uint32_t)B, k0, k1);
+    static_move<D, K, B, 0>(r, u.x, lut_s, et_s, acc);
+    static_move<D, K, B, 1>(r, u.y, lut_s, et_s, acc);
+    static_move<D, K, B, 2>(r, u.z, lut_s, et_s, acc);
+    static_move<D, K, B, 3>(r, u.w, lut_s, et_s, acc);
+}
+
+template <int D, int K, int... Bs>
+__device__ __forceinline__ void static_class(uint32_t (&r)[D + 2], const PhiloxHead &h, uint32_t k0, uint32_t k1,
+                                             const uint16_t *lut_s, const uint4 *et_s, int32_t &acc,
+                                             std::integer_sequence<int, Bs...>)
+{
+    (static_block<D, K, Bs>(r, h, k0, k1, lut_s, et_s, acc), ...);
+}
+
+template <int D>
+__device__ void rows_static_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
+                                 uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s)
+{
+    constexpr int NR = D + 2;
+    constexpr int NB = RotSchedule<D>::MP / 4;
+    using Blocks = std::make_integer_sequence<int, NB>;
+    const int lane = threadIdx.x;
+    const int nranks = (int)uni(pl->nranks);
+    int32_t W[4];
+    W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
+    // a task's 64 chains belong to one syndrome
+    const uint32_t uid = uni(J.uid), cc = J.cc;
+    const uint32_t k0 = uni(seed_lo), k1 = uni(seed_hi);
+    const bool use_x = !J.resume && (J.lp == 1 || J.lp == 2), use_z = !J.resume && (J.lp == 2 || J.lp == 3);
+
+    uint32_t r[NR];
+    int32_t E = 0;
+#pragma unroll
+    for (int Y = 0; Y < NR; ++Y) {
+        uint32_t word = 0;
+        if (Y >= 1 && Y <= D && J.active) {
+            // not unrolled: a fully unrolled row would keep every byte load in flight
+#pragma unroll 1
+            for (int x = 0; x < D; ++x) {
+                const int q = (Y - 1) * D + x;
+                uint32_t v = J.src[q] & 3u;
+                if (use_x) v ^= pl->lx[q];
+                if (use_z) v ^= pl->lz[q];
+                word |= v << (2 * (x + 1));
+                E += weight_of(W, v);
+            }
+        }
+        r[Y] = word;
+    }
+    int32_t Emin = E, stop = 0;
+    if (J.resume && J.active) {
+        E = J.efin[J.ci];
+        Emin = J.emin[J.ci];
+        stop = J.stop[J.ci];
+    }
+
+    for (int t = t_begin; t < t_end; ++t) {
+        wave_lds_fence();
+        for (int i = lane; i < nranks; i += kWave) et_s[i].y = pl->thr[(size_t)t * nranks + i];
+        wave_lds_fence();
+        const uint32_t c2 = 4u * (uint32_t)t;
+        int32_t acc = 0;
+        static_class<D, 0>(r, philox_head(uid, cc, c2, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
+        E += acc;
+        if (E < Emin) { Emin = E; stop = 4 * t + 1; }
+        acc = 0;
+        static_class<D, 1>(r, philox_head(uid, cc, c2 + 1u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
+        E += acc;
+        if (E < Emin) { Emin = E; stop = 4 * t + 2; }
+        acc = 0;
+        static_class<D, 2>(r, philox_head(uid, cc, c2 + 2u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
+        E += acc;
+        if (E < Emin) { Emin = E; stop = 4 * t + 3; }
+        acc = 0;
+        static_class<D, 3>(r, philox_head(uid, cc, c2 + 3u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
+        E += acc;
+        if (E < Emin) { Emin = E; stop = 4 * t + 4; }
+    }
+    if (J.active) {
+        J.emin[J.ci] = Emin;
+        J.stop[J.ci] = stop;
+        J.efin[J.ci] = E;
+        if (J.states) {
+            uint8_t *dst = J.states + (size_t)J.ci * (D * D);
+#pragma unroll
+            for (int Y = 1; Y <= D; ++Y)
+#pragma unroll 1
+                for (int x = 0; x < D; ++x) dst[(Y - 1) * D + x] = (uint8_t)((r[Y] >> (2 * (x + 1))) & 3u);
+        }
+    }
+}
+
 __device__ void load_rows_tables(const PlanDev *pl, uint8_t *smem)
 {
     const int lane = threadIdx.x;
@@ -800,6 +1017,50 @@ __device__ __forceinline__ void batch_kernel_body(const AnnealArgs &A)
     }
 }
 
+// Batch body of the specialised packed-row kernel (MODE as above).  Every
+// group of the launch has distance SD and tasks of 64 chains of one syndrome.
+template <int MODE, int SD>
+__device__ __forceinline__ void static_rows_body(const AnnealArgs &A)
+{
+    __shared__ uint16_t lut_s[256 * 6];
+    __shared__ uint4 et_s[kStaticRanks];
+    const PlanDev *loaded = nullptr;
+    for (int iter = 0;; ++iter) {
+        uint32_t task = 0;
+        if (MODE == 2) {
+            if (iter > 0) break;
+            task = blockIdx.x;
+        } else {
+            if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
+            task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
+        }
+        if (task >= A.n_tasks) break;
+        int gi = 0;
+        while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
+        const GroupArgs &G = A.g[gi];
+        const int64_t unit0 = ((int64_t)task - G.task_begin) << 6;
+        if (G.plan != loaded) {
+            wave_lds_fence();
+            load_static_tables(G.plan, lut_s, et_s);
+            loaded = G.plan;
+        }
+        const ChainJob J = batch_job(G, unit0 + threadIdx.x, false);
+        rows_static_core<SD>(G.plan, J, 0, G.plan->n_sweeps, A.seed_lo, A.seed_hi, lut_s, et_s);
+    }
+}
+
+// Occupancy target of the specialised kernels: eight wavefronts per SIMD (at
+// most 64 VGPRs) hides the LDS and multiply latencies best, even at the cost
+// of a few spilled registers at d = 11 (measured); d = 13 keeps six.
+constexpr int static_waves(int d) { return d <= 11 ? 8 : 6; }
+
+template <int D>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(static_waves(D), static_waves(D))))
+void k_anneal_rows_d(AnnealArgs A) { static_rows_body<0, D>(A); }
+template <int D>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(static_waves(D), static_waves(D))))
+void k_anneal_rows_d_plain(AnnealArgs A) { static_rows_body<2, D>(A); }
+
 template <int LOGG>
 __global__ __launch_bounds__(kWave) void k_anneal(AnnealArgs A) { batch_kernel_body<0, false, LOGG, false>(A); }
 template <int LOGG>
@@ -810,6 +1071,19 @@ __global__ __launch_bounds__(kWave) void k_anneal_rows(AnnealArgs A) { batch_ker
 __global__ __launch_bounds__(kWave) void k_anneal_rows_plain(AnnealArgs A) { batch_kernel_body<2, true, 0, false>(A); }
 
 typedef void (*AnnealKernel)(AnnealArgs);
+static AnnealKernel static_rows_kernel(int d, bool plain)
+{
+    switch (d) {
+    case 3: return plain ? k_anneal_rows_d_plain<3> : k_anneal_rows_d<3>;
+    case 5: return plain ? k_anneal_rows_d_plain<5> : k_anneal_rows_d<5>;
+    case 7: return plain ? k_anneal_rows_d_plain<7> : k_anneal_rows_d<7>;
+    case 9: return plain ? k_anneal_rows_d_plain<9> : k_anneal_rows_d<9>;
+    case 11: return plain ? k_anneal_rows_d_plain<11> : k_anneal_rows_d<11>;
+    case 13: return plain ? k_anneal_rows_d_plain<13> : k_anneal_rows_d<13>;
+    default: return nullptr;
+    }
+}
+
 static AnnealKernel bytes_kernel(int mode, int lg)
 {
     // mode 0: persistent, 1: replay, 2: plain
@@ -1134,7 +1408,7 @@ enum class AnnealMode { Persistent, Replay, Plain };
 // over more lanes when that is needed to give every CU several wavefronts.
 static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::vector<int> &sel, bool rows, int lanes,
                       AnnealMode mode, uint64_t seed, int64_t unit_offset, int64_t units_override,
-                      uint32_t *d_counter, hipStream_t stream)
+                      uint32_t *d_counter, hipStream_t stream, int static_d = 0)
 {
     const bool replay = mode == AnnealMode::Replay;
     AnnealArgs A{};
@@ -1177,7 +1451,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         G.task_begin = (int64_t)tasks;
         const int C = kWave / lanes;
         tasks += (uint64_t)((units + C - 1) / C);
-        lds = std::max(lds, rows ? P.lds_bytes_rows() : P.lds_bytes_anneal(lanes));
+        lds = std::max(lds, static_d ? (size_t)0 : rows ? P.lds_bytes_rows() : P.lds_bytes_anneal(lanes));
     }
     if (ng == 0 || tasks == 0) return XZZX_OK;
     if (tasks >= 0xFFFFFFF0ull) { set_error("too many anneal tasks in one launch"); return XZZX_ERANGE; }
@@ -1185,13 +1459,16 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
     A.n_tasks = (uint32_t)tasks;
     if (lds > 65536) { set_error("LDS demand above 64 KiB"); return XZZX_ERANGE; }
     if (mode == AnnealMode::Plain) {
-        if (rows)
+        if (static_d)
+            hipLaunchKernelGGL(static_rows_kernel(static_d, true), dim3((unsigned)tasks), dim3(kWave), 0, stream, A);
+        else if (rows)
             hipLaunchKernelGGL(k_anneal_rows_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         else
             hipLaunchKernelGGL(bytes_kernel(2, lg), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         return check_hip(hipGetLastError(), "plain anneal launch");
     }
-    const AnnealKernel kern = rows ? k_anneal_rows : bytes_kernel(replay ? 1 : 0, lg);
+    const AnnealKernel kern =
+        static_d ? static_rows_kernel(static_d, false) : rows ? k_anneal_rows : bytes_kernel(replay ? 1 : 0, lg);
     unsigned grid = 0;
     int rc = anneal_grid((const void *)kern, lds, A.n_tasks, &grid);
     if (rc) return rc;
@@ -1204,19 +1481,24 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
 // launch; byte-state groups are launched per lanes-per-chain value.  The
 // replay re-runs one chain per syndrome with the byte-state kernel, spreading
 // a chain over more lanes when that is needed to give every CU several
-// wavefronts.  Each launch has its own queue counter (d_counters[0..8]).
+// wavefronts.  Each launch has its own queue counter (d_counters[0..8], and
+// [16..21] for the kernels specialised to d = 3, 5, ..., 13).
 static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
                          uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
                          hipStream_t stream)
 {
     std::vector<int> rows_sel;
     std::vector<int> bytes_sel[7];
+    std::vector<int> static_sel[kStaticMaxD + 1];
     int64_t total_syn = 0;
     for (int i = 0; i < n_groups; ++i) {
         if (groups[i].n_syn <= 0) continue;
         total_syn += groups[i].n_syn;
         const Plan &P = groups[i].plan->P;
-        if (mode != AnnealMode::Replay && P.use_rows) rows_sel.push_back(i);
+        // the specialised kernel needs every 64-chain task inside one syndrome
+        const bool whole = (4 * groups[i].n_rep) % kWave == 0 && unit_offset % kWave == 0;
+        if (mode != AnnealMode::Replay && P.use_rows && P.static_d && whole) static_sel[P.static_d].push_back(i);
+        else if (mode != AnnealMode::Replay && P.use_rows) rows_sel.push_back(i);
         else bytes_sel[log2_int(P.lanes)].push_back(i);
     }
     if (mode == AnnealMode::Replay) {
@@ -1233,6 +1515,9 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         return launch_set(groups, ws, all, false, kWave / C, mode, seed, unit_offset, units_override, d_counters, stream);
     }
     int rc = launch_set(groups, ws, rows_sel, true, 1, mode, seed, unit_offset, units_override, d_counters, stream);
+    for (int d = kStaticMinD; d <= kStaticMaxD && !rc; d += 2)
+        rc = launch_set(groups, ws, static_sel[d], true, 1, mode, seed, unit_offset, units_override,
+                        d_counters + 16 + (d - kStaticMinD) / 2, stream, d);
     for (int l = 0; l < 7 && !rc; ++l)
         rc = launch_set(groups, ws, bytes_sel[l], false, 1 << l, mode, seed, unit_offset, units_override,
                         d_counters + 1 + l, stream);

@@ -132,7 +132,8 @@ class Plan:
         r = X.TuneResult()
         call("xzzx_plan_autotune", self.h, n_rep, n_syn, probe_sweeps, _stream(stream), C.byref(r))
         names = ["rows"] + [f"bytes{1 << i}" for i in range(7)]
-        return {"kernel": "rows" if r.kernel == X.KERNEL_ROWS else "bytes", "lanes_per_chain": r.lanes_per_chain,
+        kind = {X.KERNEL_ROWS: "rows", X.KERNEL_ROWS_GENERIC: "rows_generic"}.get(r.kernel, "bytes")
+        return {"kernel": kind, "lanes_per_chain": r.lanes_per_chain,
                 "times_ms": {n: round(t, 3) for n, t in zip(names, r.times_ms) if t >= 0}}
 
     def __del__(self):

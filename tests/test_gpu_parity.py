@@ -113,6 +113,35 @@ def test_row_and_byte_kernels_agree(d):
         gpu_plan(Problem(1, 5, 0.2, 10.0, 1, 1, 1)).set_kernel(X.KERNEL_ROWS)
 
 
+@pytest.mark.parametrize("d", [3, 5, 7, 9, 11, 13])
+def test_specialised_row_kernel(d):
+    """The packed-row kernel specialised to d (registers for rows, compile-time
+    schedule) runs when every 64-chain task lies in one syndrome; its chains,
+    final states and results equal the generic packed-row kernel's, the
+    byte-state kernel's and the oracle's, in the persistent and plain forms."""
+    R = 16 if d > 9 else 32
+    prob = Problem(0, d, 0.2, 10.0, 3, R, 24, seed=700 + d)
+    ref = prob.oracle_decode()
+    plan = gpu_plan(prob)
+    assert plan.info()["kernel"] == X.KERNEL_ROWS
+    compare_decode(prob, run_decode(prob, plan), ref)
+    compare_decode(prob, run_decode(prob, plan, flags=X.FLAG_PLAIN), ref)
+    plan.set_kernel(X.KERNEL_ROWS_GENERIC)
+    assert plan.info()["kernel"] == X.KERNEL_ROWS_GENERIC
+    compare_decode(prob, run_decode(prob, plan), ref)
+    plan.set_kernel(X.KERNEL_BYTES)
+    compare_decode(prob, run_decode(prob, plan), ref)
+    plan.set_kernel(X.KERNEL_AUTO)
+    assert plan.info()["kernel"] == X.KERNEL_ROWS
+
+
+def test_specialised_kernel_not_applicable():
+    """d = 15 has no specialised variant; the planar layout has no packed-row
+    kernel at all."""
+    assert gpu_plan(Problem(0, 15, 0.2, 10.0, 1, 1, 1)).info()["kernel"] == X.KERNEL_ROWS_GENERIC
+    assert gpu_plan(Problem(1, 5, 0.2, 10.0, 1, 1, 1)).info()["kernel"] == X.KERNEL_BYTES
+
+
 def test_autotuned_plan_matches_oracle():
     """The autotuner only chooses among result-invariant launch knobs."""
     for d, R in [(9, 8), (25, 4)]:
@@ -134,9 +163,12 @@ def test_plain_form_matches_persistent():
         compare_decode(prob, run_decode(prob, plan, flags=0), ref)
 
 
-def test_mixed_distances_one_launch():
-    """Uneven distances in one persistent launch (groups of d = 5..21)."""
-    probs = [Problem(0, d, 0.18, 10.0, n, 4, 30, seed=200 + d) for d, n in [(5, 7), (9, 5), (13, 3), (17, 2), (21, 2)]]
+@pytest.mark.parametrize("R", [4, 16])
+def test_mixed_distances_one_launch(R):
+    """Uneven distances in one persistent launch (groups of d = 5..21).  With
+    R = 16 the groups of d <= 13 run on the specialised packed-row kernels and
+    the others on the generic one, all in one decode call."""
+    probs = [Problem(0, d, 0.18, 10.0, n, R, 30, seed=200 + d) for d, n in [(5, 7), (9, 5), (13, 3), (17, 2), (21, 2)]]
     groups, outs = [], []
     for prob in probs:
         plan = gpu_plan(prob)
@@ -163,6 +195,10 @@ def test_edge_cases():
     # very cold: only dE <= 0 moves
     prob = Problem(0, 7, 0.2, 10.0, 4, 2, 9, seed=7, beta=np.full(9, 1e6))
     compare_decode(prob, run_decode(prob), prob.oracle_decode())
+    # the same extremes on the specialised packed-row kernel
+    for beta in (np.zeros(7), np.full(7, 1e6)):
+        prob = Problem(0, 7, 0.2, 10.0, 2, 16, 7, seed=17, beta=beta)
+        compare_decode(prob, run_decode(prob), prob.oracle_decode())
     # single chain group tail: n_syn * 4R not a multiple of the chains per wave
     prob = Problem(0, 11, 0.2, 100.0, 3, 3, 20, seed=8)
     compare_decode(prob, run_decode(prob), prob.oracle_decode())
