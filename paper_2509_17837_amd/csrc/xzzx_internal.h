@@ -80,6 +80,9 @@ struct RotSchedule {
 // distinct move energies its static tables hold.
 constexpr int kStaticMinD = 3, kStaticMaxD = 13;
 constexpr int kStaticRanks = 128;
+// sweeps between the specialised kernel's state checkpoints (the replay of a
+// syndrome's best chain starts from the last one before its E_min phase)
+constexpr int kCheckpointEvery = 256;
 
 // Host-side lattice: geometry shared by every plan built on it.
 struct Lattice {

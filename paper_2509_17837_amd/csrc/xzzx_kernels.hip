@@ -345,6 +345,12 @@ struct ChainJob {
     int32_t lp;            // coset logical applied at start (0..3)
     int32_t target;        // replay: phase whose state is stored (-1 = none)
     bool active, resume;
+    // checkpoints of the specialised packed-row kernel (word-major rows of
+    // rows 1..d, plane stride cp_stride chains)
+    uint32_t *cp_out;      // anneal: checkpoint planes to write (nullable), base of checkpoint 0
+    const uint32_t *cp_in; // replay: packed rows to start from instead of src (nullable)
+    int64_t cp_stride;     // chains per word plane
+    int32_t t0;            // first sweep to run (replay from a checkpoint)
 };
 
 struct GroupArgs {
@@ -361,6 +367,9 @@ struct GroupArgs {
     int n_rep;
     int log_lanes;
     int row_words;                // packed-row kernel: words per row (1 or 2)
+    uint32_t *cp_rows;            // specialised packed-row kernel: checkpoints [n_cp][d][n_chains]
+    int64_t n_chains;             // chains of the whole group
+    int cp_every;                 // sweeps between checkpoints (0 = none)
 };
 
 struct AnnealArgs {
@@ -402,6 +411,19 @@ __device__ __forceinline__ ChainJob batch_job(const GroupArgs &G, int64_t unit, 
     j.stop = G.stop;
     j.efin = G.efin;
     j.states = replay ? nullptr : G.final;
+    j.cp_out = replay ? nullptr : G.cp_rows;
+    j.cp_in = nullptr;
+    j.cp_stride = G.n_chains;
+    j.t0 = 0;
+    if (replay && G.cp_rows && j.target > 0) {
+        // start from the last checkpoint at or before the sweep of the target phase
+        const int t_target = (j.target - 1) >> 2;
+        const int n_cp = t_target / G.cp_every;
+        if (n_cp > 0) {
+            j.cp_in = G.cp_rows + (int64_t)(n_cp - 1) * G.plan->d * G.n_chains + ci;
+            j.t0 = n_cp * G.cp_every;
+        }
+    }
     return j;
 }
 
@@ -443,11 +465,19 @@ __device__ void bytes_core(const PlanDev *pl, const ChainJob &J, int t_begin, in
     // initial state, interleaved: qubit q of slot c at q*C + c
     const bool use_x = (J.lp == 1 || J.lp == 2), use_z = (J.lp == 2 || J.lp == 3);
     int32_t part = 0;
+    const int dd = pl->d;
     for (int q = gl; q < nq; q += (1 << LOGG)) {
-        uint32_t v = J.active ? (J.src[q] & 3u) : 0u;
-        if (!J.resume) {
-            if (use_x) v ^= pl->lx[q];
-            if (use_z) v ^= pl->lz[q];
+        uint32_t v;
+        if (J.cp_in) {
+            // checkpoint rows (rotated lattice): row y of qubit q, 2 bits at column x + 1
+            const int y = q / dd, x = q - y * dd;
+            v = J.active ? (J.cp_in[(int64_t)y * J.cp_stride] >> (2 * (x + 1))) & 3u : 0u;
+        } else {
+            v = J.active ? (J.src[q] & 3u) : 0u;
+            if (!J.resume) {
+                if (use_x) v ^= pl->lx[q];
+                if (use_z) v ^= pl->lz[q];
+            }
         }
         st[(q << LOGC) + c] = (uint8_t)v;
         part += weight_of(W, v);
@@ -869,7 +899,7 @@ __device__ __forceinline__ void static_class(uint32_t (&r)[D + 2], const PhiloxH
 
 template <int D>
 __device__ void rows_static_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
-                                 uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s)
+                                 uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s, int cp_interval)
 {
     constexpr int NR = D + 2;
     constexpr int NB = RotSchedule<D>::MP / 4;
@@ -882,6 +912,9 @@ __device__ void rows_static_core(const PlanDev *pl, const ChainJob &J, int t_beg
     const uint32_t uid = uni(J.uid), cc = J.cc;
     const uint32_t k0 = uni(seed_lo), k1 = uni(seed_hi);
     const bool use_x = !J.resume && (J.lp == 1 || J.lp == 2), use_z = !J.resume && (J.lp == 2 || J.lp == 3);
+    // lane 0 is always active and a task's chains are consecutive: chain of lane l = ci0 + l
+    const int64_t ci0 = (int64_t)(((uint64_t)uni((uint32_t)((uint64_t)J.ci >> 32)) << 32) | uni((uint32_t)J.ci));
+    const int cp_every = J.cp_out ? cp_interval : 0;
 
     uint32_t r[NR];
     int32_t E = 0;
@@ -909,27 +942,38 @@ __device__ void rows_static_core(const PlanDev *pl, const ChainJob &J, int t_beg
         stop = J.stop[J.ci];
     }
 
-    for (int t = t_begin; t < t_end; ++t) {
-        wave_lds_fence();
-        for (int i = lane; i < nranks; i += kWave) et_s[i].y = pl->thr[(size_t)t * nranks + i];
-        wave_lds_fence();
-        const uint32_t c2 = 4u * (uint32_t)t;
-        int32_t acc = 0;
-        static_class<D, 0>(r, philox_head(uid, cc, c2, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
-        E += acc;
-        if (E < Emin) { Emin = E; stop = 4 * t + 1; }
-        acc = 0;
-        static_class<D, 1>(r, philox_head(uid, cc, c2 + 1u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
-        E += acc;
-        if (E < Emin) { Emin = E; stop = 4 * t + 2; }
-        acc = 0;
-        static_class<D, 2>(r, philox_head(uid, cc, c2 + 2u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
-        E += acc;
-        if (E < Emin) { Emin = E; stop = 4 * t + 3; }
-        acc = 0;
-        static_class<D, 3>(r, philox_head(uid, cc, c2 + 3u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
-        E += acc;
-        if (E < Emin) { Emin = E; stop = 4 * t + 4; }
+    for (int t = t_begin; t < t_end;) {
+        // sweeps up to the next checkpoint, then the checkpoint (the state at
+        // the start of sweep t, every cp_every sweeps)
+        int t_stop = t_end;
+        if (cp_every) t_stop = min(t_end, (t / cp_every + 1) * cp_every);
+        for (; t < t_stop; ++t) {
+            wave_lds_fence();
+            for (int i = lane; i < nranks; i += kWave) et_s[i].y = pl->thr[(size_t)t * nranks + i];
+            wave_lds_fence();
+            const uint32_t c2 = 4u * (uint32_t)t;
+            int32_t acc = 0;
+            static_class<D, 0>(r, philox_head(uid, cc, c2, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
+            E += acc;
+            if (E < Emin) { Emin = E; stop = 4 * t + 1; }
+            acc = 0;
+            static_class<D, 1>(r, philox_head(uid, cc, c2 + 1u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
+            E += acc;
+            if (E < Emin) { Emin = E; stop = 4 * t + 2; }
+            acc = 0;
+            static_class<D, 2>(r, philox_head(uid, cc, c2 + 2u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
+            E += acc;
+            if (E < Emin) { Emin = E; stop = 4 * t + 3; }
+            acc = 0;
+            static_class<D, 3>(r, philox_head(uid, cc, c2 + 3u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
+            E += acc;
+            if (E < Emin) { Emin = E; stop = 4 * t + 4; }
+        }
+        if (cp_every && t < t_end && J.active) {
+            uint32_t *cp = J.cp_out + (int64_t)(t / cp_every - 1) * D * J.cp_stride + ci0 + lane;
+#pragma unroll
+            for (int Y = 1; Y <= D; ++Y) cp[(Y - 1) * J.cp_stride] = r[Y];
+        }
     }
     if (J.active) {
         J.emin[J.ci] = Emin;
@@ -1012,7 +1056,8 @@ __device__ __forceinline__ void batch_kernel_body(const AnnealArgs &A)
             else rows_core<2>(G.plan, J, 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
         } else {
             const ChainJob J = batch_job(G, unit0 + (threadIdx.x >> lg), REPLAY);
-            bytes_core<lg, REPLAY>(G.plan, J, 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
+            // a replay from a checkpoint runs one chain per wavefront (uniform t0)
+            bytes_core<lg, REPLAY>(G.plan, J, REPLAY ? J.t0 : 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
         }
     }
 }
@@ -1045,7 +1090,7 @@ __device__ __forceinline__ void static_rows_body(const AnnealArgs &A)
             loaded = G.plan;
         }
         const ChainJob J = batch_job(G, unit0 + threadIdx.x, false);
-        rows_static_core<SD>(G.plan, J, 0, G.plan->n_sweeps, A.seed_lo, A.seed_hi, lut_s, et_s);
+        rows_static_core<SD>(G.plan, J, 0, G.plan->n_sweeps, A.seed_lo, A.seed_hi, lut_s, et_s, G.cp_every);
     }
 }
 
@@ -1120,6 +1165,10 @@ __device__ __forceinline__ ChainJob serve_job(const ServeTask &T, int slot, bool
     j.states = replay ? nullptr : T.states;
     j.target = replay ? T.e3[2 * nc + c] : -1;
     j.snap = replay ? T.snap : nullptr;
+    j.cp_out = nullptr;
+    j.cp_in = nullptr;
+    j.cp_stride = 0;
+    j.t0 = 0;
     return j;
 }
 
@@ -1320,7 +1369,24 @@ static int launch_qcls(const uint8_t *d_qraw, int64_t n_syn, int n_rep, uint8_t 
 struct GroupWs {
     uint8_t *refs, *qraw, *qcls;
     int32_t *emin, *stop, *efin, *best_chain;
+    uint32_t *cp_rows;     // checkpoints of groups on the specialised packed-row kernel
 };
+
+// A group runs on the packed-row kernel specialised to its distance when the
+// plan allows it and every 64-chain task lies inside one syndrome.
+static bool uses_static(const xzzx_group &g, int64_t unit_offset)
+{
+    const Plan &P = g.plan->P;
+    return P.use_rows && P.static_d && (4 * g.n_rep) % kWave == 0 && unit_offset % kWave == 0;
+}
+
+// Checkpoints a specialised group keeps: the states at the start of sweeps
+// kCheckpointEvery, 2 kCheckpointEvery, ... before the last sweep.
+static int checkpoints_of(const xzzx_group &g)
+{
+    if (!uses_static(g, 0) || g.plan->P.n_sweeps <= 0) return 0;
+    return (g.plan->P.n_sweeps - 1) / kCheckpointEvery;
+}
 
 static size_t group_ws_bytes(const xzzx_group &g, bool decode)
 {
@@ -1334,6 +1400,7 @@ static size_t group_ws_bytes(const xzzx_group &g, bool decode)
     if (!g.d_chain_stop) b += align256(nc * 4);
     if (!g.d_chain_e) b += align256(nc * 4);
     if (!g.d_best_chain) b += align256(ns * 4);
+    b += align256((size_t)checkpoints_of(g) * P.lat.d * nc * 4);
     return b;
 }
 
@@ -1350,6 +1417,8 @@ static GroupWs carve_group(const xzzx_group &g, bool decode, uint8_t *&p)
     w.stop = g.d_chain_stop ? g.d_chain_stop : reinterpret_cast<int32_t *>(take(nc * 4));
     w.efin = g.d_chain_e ? g.d_chain_e : reinterpret_cast<int32_t *>(take(nc * 4));
     w.best_chain = g.d_best_chain ? g.d_best_chain : reinterpret_cast<int32_t *>(take(ns * 4));
+    const int ncp = checkpoints_of(g);
+    w.cp_rows = ncp ? reinterpret_cast<uint32_t *>(take((size_t)ncp * P.lat.d * nc * 4)) : nullptr;
     return w;
 }
 
@@ -1445,6 +1514,11 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         G.n_rep = g.n_rep;
         G.log_lanes = lg;
         G.row_words = rows ? P.row_words : 0;
+        // checkpoints: written by the specialised kernel, read by the replay
+        const bool cp = checkpoints_of(g) > 0 && (static_d || replay);
+        G.cp_rows = cp ? ws[i].cp_rows : nullptr;
+        G.cp_every = cp ? kCheckpointEvery : 0;
+        G.n_chains = g.n_syn * 4 * g.n_rep;
         G.unit_offset = unit_offset;
         const int64_t units = units_of(i);
         G.n_units = units;
@@ -1490,14 +1564,14 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
     std::vector<int> rows_sel;
     std::vector<int> bytes_sel[7];
     std::vector<int> static_sel[kStaticMaxD + 1];
+    std::vector<int> replay_cp;   // replays starting from checkpoints: one chain per wavefront
     int64_t total_syn = 0;
     for (int i = 0; i < n_groups; ++i) {
         if (groups[i].n_syn <= 0) continue;
         total_syn += groups[i].n_syn;
         const Plan &P = groups[i].plan->P;
-        // the specialised kernel needs every 64-chain task inside one syndrome
-        const bool whole = (4 * groups[i].n_rep) % kWave == 0 && unit_offset % kWave == 0;
-        if (mode != AnnealMode::Replay && P.use_rows && P.static_d && whole) static_sel[P.static_d].push_back(i);
+        if (mode != AnnealMode::Replay && uses_static(groups[i], unit_offset)) static_sel[P.static_d].push_back(i);
+        else if (mode == AnnealMode::Replay && checkpoints_of(groups[i]) > 0) replay_cp.push_back(i);
         else if (mode != AnnealMode::Replay && P.use_rows) rows_sel.push_back(i);
         else bytes_sel[log2_int(P.lanes)].push_back(i);
     }
@@ -1512,7 +1586,12 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
             }
         const int64_t want = 8LL * device_cus();
         while (C > 1 && total_syn / C < want) C >>= 1;
-        return launch_set(groups, ws, all, false, kWave / C, mode, seed, unit_offset, units_override, d_counters, stream);
+        int rc = launch_set(groups, ws, all, false, kWave / C, mode, seed, unit_offset, units_override, d_counters,
+                            stream);
+        if (!rc)
+            rc = launch_set(groups, ws, replay_cp, false, kWave, mode, seed, unit_offset, units_override,
+                            d_counters + 2, stream);
+        return rc;
     }
     int rc = launch_set(groups, ws, rows_sel, true, 1, mode, seed, unit_offset, units_override, d_counters, stream);
     for (int d = kStaticMinD; d <= kStaticMaxD && !rc; d += 2)

@@ -135,6 +135,18 @@ def test_specialised_row_kernel(d):
     assert plan.info()["kernel"] == X.KERNEL_ROWS
 
 
+@pytest.mark.parametrize("sweeps", [256, 257, 700])
+def test_replay_from_checkpoints(sweeps):
+    """Groups on the specialised kernel keep a state checkpoint every 256
+    sweeps; each syndrome's recovery is replayed from the last checkpoint
+    before its E_min phase (256 sweeps: none; 257: one, at the start of the
+    last sweep; 700: two)."""
+    prob = Problem(0, 7, 0.2, 10.0, 4, 16, sweeps, seed=800 + sweeps)
+    plan = gpu_plan(prob)
+    assert plan.info()["kernel"] == X.KERNEL_ROWS
+    compare_decode(prob, run_decode(prob, plan), prob.oracle_decode())
+
+
 def test_specialised_kernel_not_applicable():
     """d = 15 has no specialised variant; the planar layout has no packed-row
     kernel at all."""
