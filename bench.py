@@ -75,7 +75,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-knob autotuner")
     ap.add_argument("--serve", action="store_true", help="serving-loop benchmark (Poisson arrivals)")
     ap.add_argument("--rates", default="1e3,3e3,1e4,3e4,1e5")
-    ap.add_argument("--requests", type=int, default=2000, help="requests per arrival rate (--serve)")
+    ap.add_argument("--requests", type=int, default=20000, help="most requests per arrival rate (--serve)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="arrival window per rate (--serve): min(--requests, rate x this) requests")
     ap.add_argument("--slice", type=int, default=100, help="sweeps per serving slice (--serve)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="most lanes per chain the server may use (--serve; 0: library default, 1: plan kernels)")
@@ -356,7 +358,7 @@ def serve_bench(args):
         plan = D.Plan(lats[d], w, wg, beta)
         plans.append(plan)
     rates = [float(x) for x in args.rates.split(",")]
-    n = args.requests
+    n = max(int(args.requests), 1)
     # requests: spec index, syndrome, uid (seeded), sampled ahead of time
     rng = np.random.default_rng([seeds["sample"], 11])
     pick = rng.integers(0, len(specs), size=n)
@@ -373,13 +375,14 @@ def serve_bench(args):
     attempts_per_req = [4 * R * wl["sweeps"] * plans[k].nstab for k, _ in reqs]
     out = []
     for rate in rates:
-        arr = inputs.poisson_arrivals(rate, n, seeds["sample"] + int(rate))
+        n_rate = max(1, min(n, int(rate * args.serve_seconds)))
+        arr = inputs.poisson_arrivals(rate, n_rate, seeds["sample"] + int(rate))
         srv = D.Server(max_slots=4096, max_rep=R, max_qubits=max(d * d for d in wl["d"]),
                        sweeps_per_slice=args.slice, greedy_seed=seeds["greedy"], anneal_seed=seeds["anneal"],
                        max_lanes_per_chain=args.lanes, max_waves=args.waves)
         t0 = time.perf_counter()
         tickets = []
-        for i, (k, _) in enumerate(reqs):
+        for i, (k, _) in enumerate(reqs[:n_rate]):
             while True:
                 now = time.perf_counter() - t0
                 if now >= arr[i]:
@@ -394,11 +397,11 @@ def serve_bench(args):
             srv.poll(t)
         srv.close()
         out.append({
-            "rate_per_s": rate, "requests": n,
+            "rate_per_s": rate, "requests": n_rate,
             "p50_latency_ms": 1e3 * st["p50_latency_s"], "p99_latency_ms": 1e3 * st["p99_latency_s"],
             "mean_latency_ms": 1e3 * st["mean_latency_s"],
             "decodes_per_s": st["decodes_per_s"], "attempts_per_s": st["attempts_per_s"],
-            "offered_attempts_per_s": rate * float(np.mean(attempts_per_req)),
+            "offered_attempts_per_s": rate * float(np.mean(attempts_per_req[:n_rate])),
             "slices": st["slices"], "wall_s": wall,
         })
         print(f"[serve] rate {rate:g}/s: p50 {out[-1]['p50_latency_ms']:.2f} ms, p99 "

@@ -13,7 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxzzx_sa.so")
-SOURCES = ["xzzx_host.cpp", "xzzx_kernels.hip", "xzzx_server.cpp", "xzzx_tune.cpp"]
+SOURCES = ["xzzx_static_g.hip", "xzzx_static_f.hip", "xzzx_static_e.hip", "xzzx_static_d.hip",
+           "xzzx_static_c.hip", "xzzx_static_b.hip", "xzzx_static_a.hip",
+           "xzzx_kernels.hip", "xzzx_host.cpp", "xzzx_server.cpp", "xzzx_tune.cpp"]   # longest first
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -33,13 +35,30 @@ def hipcc() -> str:
     return exe
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source to an object in parallel (the specialised kernels
+    are large), then link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include")]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [hipcc(), *compile_flags, *inc, "-c", "-x", "hip", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    n = jobs or min(len(srcs), max(1, os.cpu_count() or 1), 8)
+    with ThreadPoolExecutor(n) as ex:
+        objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp]
-    for s in srcs:
-        cmd += ["-x", "hip", s]
-    cmd += ["-lpthread"]
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

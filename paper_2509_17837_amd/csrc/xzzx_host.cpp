@@ -225,6 +225,14 @@ static bool static_schedule_matches(int d, const std::vector<uint32_t> &rowface,
     case 9: return schedule_matches<9>(rowface, mpad);
     case 11: return schedule_matches<11>(rowface, mpad);
     case 13: return schedule_matches<13>(rowface, mpad);
+    case 15: return schedule_matches<15>(rowface, mpad);
+    case 17: return schedule_matches<17>(rowface, mpad);
+    case 19: return schedule_matches<19>(rowface, mpad);
+    case 21: return schedule_matches<21>(rowface, mpad);
+    case 23: return schedule_matches<23>(rowface, mpad);
+    case 25: return schedule_matches<25>(rowface, mpad);
+    case 27: return schedule_matches<27>(rowface, mpad);
+    case 29: return schedule_matches<29>(rowface, mpad);
     default: return false;
     }
 }
@@ -437,7 +445,7 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     // the specialised packed-row kernel applies when its compile-time
     // schedule is exactly this plan's table
     P.static_d = 0;
-    if (P.row_words == 1 && L.layout == XZZX_ROTATED && L.d >= kStaticMinD && L.d <= kStaticMaxD &&
+    if (P.row_words && L.layout == XZZX_ROTATED && L.d >= kStaticMinD && L.d <= kStaticMaxD &&
         nranks <= kStaticRanks && static_schedule_matches(L.d, rowface, mpad))
         P.static_d = L.d;
     P.static_ok = P.static_d ? 1 : 0;

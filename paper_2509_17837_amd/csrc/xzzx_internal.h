@@ -34,8 +34,8 @@ struct Desc {
 constexpr int kRotShapeMasks[6] = {15, 12, 10, 5, 3, 0};
 
 // Compile-time generator schedule of the rotated lattice at distance D for
-// the packed-row kernel specialised to D (one 32-bit word per row, so
-// D <= 13): for colour class k and rank m, the row Y = j + 1 of cell (i, j),
+// the packed-row kernel specialised to D (one 32-bit word per row for
+// D <= 13, two for D <= 29): for colour class k and rank m, the row Y = j + 1 of cell (i, j),
 // the bit offset 2(i + 1) of its nibble and its canonical shape.  Ranks run
 // row-major over (j, i), as in the plan; each class is padded to a multiple
 // of four with null generators on the padding nibble of rows 0 and 1.
@@ -78,7 +78,7 @@ struct RotSchedule {
 
 // Distances with a specialised packed-row kernel, and the largest number of
 // distinct move energies its static tables hold.
-constexpr int kStaticMinD = 3, kStaticMaxD = 13;
+constexpr int kStaticMinD = 3, kStaticMaxD = 29;
 constexpr int kStaticRanks = 128;
 // sweeps between the specialised kernel's state checkpoints (the replay of a
 // syndrome's best chain starts from the last one before its E_min phase)
@@ -161,20 +161,33 @@ struct ServeTask {
     int32_t row_words;       // packed-row core: words per row
 };
 
-// Serving-loop finish entry: per-coset reduction of one finished request.
+// Serving-loop finish entry: per-coset reduction of one finished request,
+// and where its result and recovery are gathered for the copy to the host.
 struct ServeFinish {
     const int32_t *e3;       // request chain words [3][4 n_rep]
     const uint8_t *qraw;     // request raw symplectic bits [n_rep]
     int32_t *result;         // [8]: E_best, P*, best chain, unused, E_P[4]
+    const uint8_t *recovery; // the request's recovery [nq] (written by the replay)
+    uint8_t *out;            // gathered [32-byte result][nq recovery]
     int32_t n_rep;
-    int32_t pad;
+    int32_t nq;
+};
+
+// One launch of a serving slice: tasks of one kernel family.
+//   kind 0: packed-row kernel; 1: byte-state kernel; 2: packed-row kernel
+//   specialised to distance d.
+struct ServeLaunch {
+    const ServeTask *tasks;
+    int32_t n;
+    int32_t kind;
+    int32_t d;
+    size_t lds;
 };
 
 int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const uint32_t *d_uid,
                  const int32_t *d_slot_map, int n, int n_rep, uint8_t *refs_base, int64_t refs_stride,
                  uint8_t *qraw_base, int64_t qraw_stride, uint64_t seed, int mode, hipStream_t stream);
-int serve_slice(const ServeTask *d_rows, int n_rows, size_t lds_rows, const ServeTask *d_bytes, int n_bytes,
-                size_t lds_bytes, uint64_t seed, hipStream_t stream);
+int serve_slice(const ServeLaunch *launches, int n_launches, uint64_t seed, hipStream_t stream);
 int serve_finish(const ServeFinish *d_fin, const ServeTask *d_replay, int n, size_t lds_replay, uint64_t seed,
                  hipStream_t stream);
 

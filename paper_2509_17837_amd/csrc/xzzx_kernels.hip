@@ -22,57 +22,9 @@
 #include <cstring>
 #include <vector>
 
-#include "xzzx_internal.h"
+#include "xzzx_device.h"
 
 namespace xzzx {
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
-// by the Philox multipliers, high/low halves crossed with the other words and
-// the round key; the key advances by the two Weyl increments.
-// ---------------------------------------------------------------------------
-// Three-input XOR as one gfx950 v_bitop3_b32 (truth table 0x96 = odd parity).
-__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t key)
-{
-    return __builtin_amdgcn_bitop3_b32(a, b, key, 0x96);
-}
-
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int i = 0; i < 10; ++i) {
-        const uint64_t p0 = (uint64_t)c.x * 0xD2511F53u;
-        const uint64_t p1 = (uint64_t)c.z * 0xCD9E8D57u;
-        c = make_uint4(xor3_key((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
-                       xor3_key((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c;
-}
-
-__device__ __forceinline__ void wave_lds_fence()
-{
-    // Orders this wavefront's LDS traffic across a phase boundary: all lanes
-    // see the stores of the previous phase before any load of the next one.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int32_t weight_of(const int32_t W[4], uint32_t code)
-{
-    return code == 0 ? 0 : code == 1 ? W[1] : code == 2 ? W[2] : W[3];
-}
-
-// Sum over the G lanes of one chain (lanes c*G .. c*G+G-1 of the wavefront).
-template <int LOGG>
-__device__ __forceinline__ int32_t chain_sum(int32_t v)
-{
-#pragma unroll
-    for (int s = 1; s < (1 << LOGG); s <<= 1) v += __shfl_xor(v, s, kWave);
-    return v;
-}
 
 // ---------------------------------------------------------------------------
 // Syndrome, Eq. (2): s_f = 1 iff the configuration anticommutes with G_f.
@@ -322,790 +274,6 @@ __global__ void k_qcls(const uint8_t *qraw, int64_t n_syn, int n_rep, uint8_t *q
     }
 }
 
-// ---------------------------------------------------------------------------
-// Annealing (Algs. 2-3).
-//
-// Both annealing kernels run a chain from a per-lane ChainJob: start at the
-// replica reference R_r times the coset's logical L_P' (or resume from a
-// saved state with its E, E_min and phase of the minimum), run sweeps
-// [t_begin, t_end) of the plan's schedule, then store E, E_min, the phase of
-// E_min and optionally the state.  Replay jobs stop at the phase of the
-// chain's minimum and store that state (the recovery).  A task is a set of
-// chains sharing a plan and a sweep range; the batch launch builds its tasks
-// from syndrome groups, the serving loop from its resident requests.
-// ---------------------------------------------------------------------------
-struct ChainJob {
-    const uint8_t *src;    // start: reference R_r; resume: saved state
-    int32_t *emin, *stop, *efin;   // result word arrays (wave-uniform bases), entry ci
-    uint8_t *states;       // end-of-range states (wave-uniform base, stride nq), entry ci; nullable
-    uint8_t *snap;         // replay: destination of the state at `target`
-    int64_t ci;            // this chain's entry in the result arrays
-    uint32_t uid;          // syndrome id (RNG counter word 0)
-    uint32_t cc;           // chain index in its syndrome (RNG counter word 1)
-    int32_t lp;            // coset logical applied at start (0..3)
-    int32_t target;        // replay: phase whose state is stored (-1 = none)
-    bool active, resume;
-    // checkpoints of the specialised packed-row kernel (word-major rows of
-    // rows 1..d, plane stride cp_stride chains)
-    uint32_t *cp_out;      // anneal: checkpoint planes to write (nullable), base of checkpoint 0
-    const uint32_t *cp_in; // replay: packed rows to start from instead of src (nullable)
-    int64_t cp_stride;     // chains per word plane
-    int32_t t0;            // first sweep to run (replay from a checkpoint)
-};
-
-struct GroupArgs {
-    const PlanDev *plan;
-    const uint32_t *uid;
-    const uint8_t *refs;          // [n_syn][n_rep][nq]
-    int32_t *emin, *stop, *efin;  // [n_syn][4 n_rep]
-    uint8_t *final;               // optional [n_syn][4 n_rep][nq]
-    const int32_t *best_chain;    // replay: [n_syn]
-    uint8_t *recovery;            // replay: [n_syn][nq]
-    int64_t unit_offset;          // first unit (chain or syndrome) of this launch
-    int64_t n_units;              // units handled by this launch
-    int64_t task_begin;           // first task index of this group
-    int n_rep;
-    int log_lanes;
-    int row_words;                // packed-row kernel: words per row (1 or 2)
-    uint32_t *cp_rows;            // specialised packed-row kernel: checkpoints [n_cp][d][n_chains]
-    int64_t n_chains;             // chains of the whole group
-    int cp_every;                 // sweeps between checkpoints (0 = none)
-};
-
-struct AnnealArgs {
-    GroupArgs g[kMaxGroups];
-    int n_groups;
-    uint32_t n_tasks;
-    uint32_t *counter;
-    uint32_t seed_lo, seed_hi;
-};
-
-// Batch job of the chain (or, in replay, syndrome) `unit` of group G.
-__device__ __forceinline__ ChainJob batch_job(const GroupArgs &G, int64_t unit, bool replay)
-{
-    ChainJob j;
-    const int nc = 4 * G.n_rep;
-    j.active = unit < G.n_units;
-    const int64_t u_abs = G.unit_offset + (j.active ? unit : 0);
-    int64_t s, ci;
-    if (replay) {
-        s = u_abs;
-        j.cc = (uint32_t)G.best_chain[s];
-        ci = s * nc + j.cc;
-        j.target = G.stop[ci];
-        j.snap = G.recovery + (size_t)s * G.plan->nq;
-    } else {
-        s = u_abs / nc;
-        ci = u_abs;
-        j.cc = (uint32_t)(u_abs - s * nc);
-        j.target = -1;
-        j.snap = nullptr;
-    }
-    const int r = (int)(j.cc >> 2);
-    j.lp = (int)(j.cc & 3);
-    j.uid = G.uid[s];
-    j.src = G.refs + ((size_t)s * G.n_rep + r) * G.plan->nq;
-    j.resume = false;
-    j.ci = ci;
-    j.emin = G.emin;
-    j.stop = G.stop;
-    j.efin = G.efin;
-    j.states = replay ? nullptr : G.final;
-    j.cp_out = replay ? nullptr : G.cp_rows;
-    j.cp_in = nullptr;
-    j.cp_stride = G.n_chains;
-    j.t0 = 0;
-    if (replay && G.cp_rows && j.target > 0) {
-        // start from the last checkpoint at or before the sweep of the target phase
-        const int t_target = (j.target - 1) >> 2;
-        const int n_cp = t_target / G.cp_every;
-        if (n_cp > 0) {
-            j.cp_in = G.cp_rows + (int64_t)(n_cp - 1) * G.plan->d * G.n_chains + ci;
-            j.t0 = n_cp * G.cp_every;
-        }
-    }
-    return j;
-}
-
-struct LdsLayout {
-    uint32_t desc, lut, et, state;
-};
-
-__device__ __forceinline__ LdsLayout lds_layout(int M, int ntypes, int nranks)
-{
-    LdsLayout o;
-    o.desc = 0;
-    o.lut = 8u * 4u * (uint32_t)M;
-    o.et = (o.lut + 256u * (uint32_t)ntypes + 7u) & ~7u;
-    o.state = (o.et + 8u * (uint32_t)nranks + 15u) & ~15u;
-    return o;
-}
-
-// Byte-state core: C = 64/G chains per wavefront, chain c on lanes c*G..c*G+G-1;
-// the G lanes of a chain split the generators of each colour class.
-template <int LOGG, bool REPLAY>
-__device__ void bytes_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
-                           uint32_t seed_hi, uint8_t *smem)
-{
-    constexpr int LOGC = 6 - LOGG;
-    const int lane = threadIdx.x;
-    const int c = lane >> LOGG;          // chain slot in this wavefront
-    const int gl = lane & ((1 << LOGG) - 1);
-    const int nq = pl->nq, M = pl->M, nblk = pl->nblk, nranks = pl->nranks;
-    const uint32_t kneg = (uint32_t)pl->kneg;
-    int32_t W[4];
-    W[0] = pl->W[0]; W[1] = pl->W[1]; W[2] = pl->W[2]; W[3] = pl->W[3];
-    const LdsLayout lo = lds_layout(M, pl->ntypes, nranks);
-    const uint2 *desc_s = reinterpret_cast<const uint2 *>(smem + lo.desc);
-    const uint8_t *lut_s = smem + lo.lut;
-    int2 *et_s = reinterpret_cast<int2 *>(smem + lo.et);
-    uint8_t *st = smem + lo.state;
-    const uint32_t uid = J.uid, cc = J.cc;
-
-    // initial state, interleaved: qubit q of slot c at q*C + c
-    const bool use_x = (J.lp == 1 || J.lp == 2), use_z = (J.lp == 2 || J.lp == 3);
-    int32_t part = 0;
-    const int dd = pl->d;
-    for (int q = gl; q < nq; q += (1 << LOGG)) {
-        uint32_t v;
-        if (J.cp_in) {
-            // checkpoint rows (rotated lattice): row y of qubit q, 2 bits at column x + 1
-            const int y = q / dd, x = q - y * dd;
-            v = J.active ? (J.cp_in[(int64_t)y * J.cp_stride] >> (2 * (x + 1))) & 3u : 0u;
-        } else {
-            v = J.active ? (J.src[q] & 3u) : 0u;
-            if (!J.resume) {
-                if (use_x) v ^= pl->lx[q];
-                if (use_z) v ^= pl->lz[q];
-            }
-        }
-        st[(q << LOGC) + c] = (uint8_t)v;
-        part += weight_of(W, v);
-    }
-    if (gl == 0) st[(nq << LOGC) + c] = 0;
-    int32_t E = chain_sum<LOGG>(part);
-    int32_t Emin = E, stop = 0;
-    if (J.resume && J.active) {
-        E = J.efin[J.ci];
-        Emin = J.emin[J.ci];
-        stop = J.stop[J.ci];
-    }
-    wave_lds_fence();
-
-    auto save_state = [&](uint8_t *dst) {
-        for (int q = gl; q < nq; q += (1 << LOGG)) dst[q] = st[(q << LOGC) + c];
-    };
-    int32_t last_phase = 4 * t_end;
-    if (REPLAY) {
-        if (J.active && J.target == 0) save_state(J.snap);
-        int32_t tmax = J.active ? J.target : 0;
-#pragma unroll
-        for (int sh = 1; sh < kWave; sh <<= 1) tmax = max(tmax, __shfl_xor(tmax, sh, kWave));
-        last_phase = tmax;
-    }
-
-    for (int t = t_begin; t < t_end && 4 * t < last_phase; ++t) {
-        for (int i = lane; i < nranks; i += kWave) et_s[i].y = (int)pl->thr[(size_t)t * nranks + i];
-        wave_lds_fence();
-        for (int k = 0; k < 4; ++k) {
-            const uint2 *dk = desc_s + k * M;
-            int32_t acc_de = 0;
-            for (int b = gl; b < nblk; b += (1 << LOGG)) {
-                const uint4 rnd = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
-                                                seed_lo, seed_hi);
-                const uint32_t uw[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    const int m = 4 * b + w;
-                    if (m >= M) break;
-                    const uint2 d = dk[m];
-                    const uint32_t a0 = ((d.x & 0xFFFFu) << LOGC) + c;
-                    const uint32_t a1 = ((d.x >> 16) << LOGC) + c;
-                    const uint32_t a2 = ((d.y & 0xFFFFu) << LOGC) + c;
-                    const uint32_t a3 = (((d.y >> 16) & 0x7FFu) << LOGC) + c;
-                    const uint32_t c0 = st[a0], c1 = st[a1], c2 = st[a2], c3 = st[a3];
-                    const uint32_t pat = c0 | (c1 << 2) | (c2 << 4) | (c3 << 6);
-                    const uint32_t rank = lut_s[((d.y >> 27) << 8) | pat];
-                    const int2 et = et_s[rank];
-                    if (rank < kneg || uw[w] < (uint32_t)et.y) {
-                        st[a0] = (uint8_t)(c0 ^ 2u);
-                        st[a1] = (uint8_t)(c1 ^ 1u);
-                        st[a2] = (uint8_t)(c2 ^ 1u);
-                        st[a3] = (uint8_t)(c3 ^ 2u);
-                        acc_de += et.x;
-                    }
-                }
-            }
-            wave_lds_fence();
-            E += chain_sum<LOGG>(acc_de);
-            const int32_t phase = 4 * t + k + 1;
-            if (E < Emin) { Emin = E; stop = phase; }
-            if (REPLAY && J.active && phase == J.target) save_state(J.snap);
-        }
-    }
-    if (!REPLAY && J.active) {
-        if (gl == 0) {
-            J.emin[J.ci] = Emin;
-            J.stop[J.ci] = stop;
-            J.efin[J.ci] = E;
-        }
-        if (J.states) save_state(J.states + (size_t)J.ci * nq);
-    }
-    wave_lds_fence();
-}
-
-// ---------------------------------------------------------------------------
-// Packed-row core (rotated lattices, d <= 29): one chain per lane.  The padded
-// grid (columns and rows -1..d) is stored as 2-bit codes, each lattice row in
-// NW 32-bit words; word w of row Y of the chain in lane l sits at
-// rows_s[(Y*NW + w)*64 + l], so a wavefront's row accesses are 64 consecutive
-// dwords.  The generators of a colour class are visited in rank order; a
-// generator at cell (i,j) covers the 4-bit nibble at bit 2(i+1) of rows j+1
-// (slots X_left, Z_up) and j+2 (slots Z_down, X_right).  The two rows are held
-// in registers while the class visits that row, so LDS traffic per move is the
-// two table lookups.  Generator tables are uniform across the wavefront and
-// read through the scalar cache.
-// ---------------------------------------------------------------------------
-typedef const __attribute__((address_space(4))) uint32_t const_u32;
-
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-struct RowsLds {
-    uint32_t lut, et, rows;
-};
-
-__device__ __forceinline__ RowsLds rows_layout(int ntypes, int nranks)
-{
-    RowsLds o;
-    o.lut = 0;
-    o.et = (256u * (uint32_t)ntypes + 7u) & ~7u;
-    o.rows = (o.et + 8u * (uint32_t)nranks + 15u) & ~15u;
-    return o;
-}
-
-template <int NW>
-__device__ __forceinline__ uint32_t row_nibble(const uint32_t (&r)[NW], uint32_t bo)
-{
-    if (NW == 1) return __builtin_amdgcn_ubfe(r[0], bo, 4);
-    if (bo < 32) return __builtin_amdgcn_alignbit(r[NW > 1 ? 1 : 0], r[0], bo) & 0xFu;
-    return __builtin_amdgcn_ubfe(r[NW > 1 ? 1 : 0], bo - 32, 4);
-}
-
-template <int NW>
-__device__ __forceinline__ void row_flip(uint32_t (&r)[NW], uint32_t bo, uint32_t mask)
-{
-    if (NW == 1) {
-        r[0] ^= mask << bo;
-        return;
-    }
-    if (bo < 32) {
-        r[0] ^= mask << bo;
-        if (bo > 28) r[NW > 1 ? 1 : 0] ^= mask >> (32 - bo);
-    } else {
-        r[NW > 1 ? 1 : 0] ^= mask << (bo - 32);
-    }
-}
-
-// r ^= (mask << bo) & sel as one v_bitop3 per word (truth table 0x6A:
-// c ^ (a & b) with a = shifted mask, b = sel, c = r).
-__device__ __forceinline__ uint32_t xor_and(uint32_t r, uint32_t mask, uint32_t sel)
-{
-    return __builtin_amdgcn_bitop3_b32(mask, sel, r, 0x6A);
-}
-
-template <int NW>
-__device__ __forceinline__ void row_flip_sel(uint32_t (&r)[NW], uint32_t bo, uint32_t mask, uint32_t sel)
-{
-    if (NW == 1) {
-        r[0] = xor_and(r[0], mask << bo, sel);
-        return;
-    }
-    if (bo < 32) {
-        r[0] = xor_and(r[0], mask << bo, sel);
-        if (bo > 28) r[NW > 1 ? 1 : 0] = xor_and(r[NW > 1 ? 1 : 0], mask >> (32 - bo), sel);
-    } else {
-        r[NW > 1 ? 1 : 0] = xor_and(r[NW > 1 ? 1 : 0], mask << (bo - 32), sel);
-    }
-}
-
-template <int NW>
-__device__ void rows_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
-                          uint32_t seed_hi, uint8_t *smem)
-{
-    const int lane = threadIdx.x;
-    const int d = (int)uni(pl->d), nq = (int)uni(pl->nq), nblk = (int)uni(pl->nblk);
-    const int nranks = (int)uni(pl->nranks), ntypes = (int)uni(pl->ntypes);
-    const uint32_t kneg = uni(pl->kneg);
-    const int rows = d + 2;
-    const int Mpad = 4 * nblk;
-    int32_t W[4];
-    W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
-    const RowsLds lo = rows_layout(ntypes, nranks);
-    const uint8_t *lut_s = smem + lo.lut;
-    int2 *et_s = reinterpret_cast<int2 *>(__builtin_assume_aligned(smem + lo.et, 8));
-    uint32_t *rw = reinterpret_cast<uint32_t *>(smem + lo.rows) + lane;   // this lane's column
-    const uint32_t uid = J.uid, cc = J.cc;
-    const bool use_x = !J.resume && (J.lp == 1 || J.lp == 2), use_z = !J.resume && (J.lp == 2 || J.lp == 3);
-
-    // pack the state into rows; E of the state on the way
-    int32_t E = 0;
-    for (int Y = 0; Y < rows; ++Y) {
-        const int y = Y - 1;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            uint32_t word = 0;
-            if (J.active && y >= 0 && y < d) {
-                for (int j = 0; j < 16; ++j) {
-                    const int x = 16 * w + j - 1;
-                    if (x >= 0 && x < d) {
-                        const int q = y * d + x;
-                        uint32_t v = J.src[q] & 3u;
-                        if (use_x) v ^= pl->lx[q];
-                        if (use_z) v ^= pl->lz[q];
-                        word |= v << (2 * j);
-                        E += weight_of(W, v);
-                    }
-                }
-            }
-            rw[(Y * NW + w) * kWave] = word;
-        }
-    }
-    int32_t Emin = E, stop = 0;
-    if (J.resume && J.active) {
-        E = J.efin[J.ci];
-        Emin = J.emin[J.ci];
-        stop = J.stop[J.ci];
-    }
-    wave_lds_fence();
-
-    for (int t = t_begin; t < t_end; ++t) {
-        for (int i = lane; i < nranks; i += kWave) et_s[i].y = (int)pl->thr[(size_t)t * nranks + i];
-        wave_lds_fence();
-        for (int k = 0; k < 4; ++k) {
-            // descriptors of class k; the table is padded to a multiple of 4
-            const_u32 *tab = (const_u32 *)(uintptr_t)(pl->rowface + k * Mpad);
-            int32_t acc_de = 0;
-            int curY = -1;
-            // rA/rB: the two rows of the current row pair; fA/fB: accumulated
-            // flips.  Generators of one class in one row touch disjoint bits,
-            // so patterns are read from rA/rB and flips are merged at the end
-            // of the row, which keeps the moves of a row independent.
-            uint32_t rA[NW], rB[NW], fA[NW], fB[NW];
-#pragma unroll
-            for (int w = 0; w < NW; ++w) rA[w] = rB[w] = fA[w] = fB[w] = 0;
-            for (int b = 0; b < nblk; ++b) {
-                const uint4 rnd = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
-                                                seed_lo, seed_hi);
-                const uint32_t uw[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
-                const uint32_t fdv[4] = {tab[4 * b], tab[4 * b + 1], tab[4 * b + 2], tab[4 * b + 3]};
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    // ranks >= M are null generators (padding bits, dE = 0)
-                    const uint32_t fd = fdv[w];
-                    const int Y = (int)(fd & 0xFFu);
-                    const uint32_t bo = (fd >> 8) & 0xFFu;
-                    const uint32_t shp = fd >> 16;
-                    if (Y != curY) {
-                        if (curY >= 0) {
-#pragma unroll
-                            for (int v = 0; v < NW; ++v) {
-                                rw[(curY * NW + v) * kWave] = rA[v] ^ fA[v];
-                                rw[((curY + 1) * NW + v) * kWave] = rB[v] ^ fB[v];
-                            }
-                        }
-#pragma unroll
-                        for (int v = 0; v < NW; ++v) {
-                            rA[v] = rw[(Y * NW + v) * kWave];
-                            rB[v] = rw[((Y + 1) * NW + v) * kWave];
-                            fA[v] = fB[v] = 0;
-                        }
-                        curY = Y;
-                    }
-                    const uint32_t pat = row_nibble<NW>(rA, bo) | (row_nibble<NW>(rB, bo) << 4);
-                    const uint32_t rank = lut_s[(shp << 8) | pat];
-                    const int2 et = et_s[rank];
-                    // branch-free acceptance: sel is all ones on accepting lanes
-                    const bool accept = (rank < kneg) | (uw[w] < (uint32_t)et.y);
-                    const uint32_t sel = accept ? 0xFFFFFFFFu : 0u;
-                    row_flip_sel<NW>(fA, bo, 6u, sel);   // X_left (2) | Z_up (1 << 2)
-                    row_flip_sel<NW>(fB, bo, 9u, sel);   // Z_down (1) | X_right (2 << 2)
-                    acc_de += (int32_t)((uint32_t)et.x & sel);
-                }
-            }
-            if (curY >= 0) {
-#pragma unroll
-                for (int v = 0; v < NW; ++v) {
-                    rw[(curY * NW + v) * kWave] = rA[v] ^ fA[v];
-                    rw[((curY + 1) * NW + v) * kWave] = rB[v] ^ fB[v];
-                }
-            }
-            wave_lds_fence();
-            E += acc_de;
-            if (E < Emin) { Emin = E; stop = 4 * t + k + 1; }
-        }
-    }
-    if (J.active) {
-        J.emin[J.ci] = Emin;
-        J.stop[J.ci] = stop;
-        J.efin[J.ci] = E;
-        if (J.states) {
-            uint8_t *dst = J.states + (size_t)J.ci * nq;
-            for (int q = 0; q < nq; ++q) {
-                const int y = q / d, x = q - y * d;
-                const uint32_t word = rw[((y + 1) * NW + (x + 1) / 16) * kWave];
-                dst[q] = (uint8_t)((word >> (2 * ((x + 1) % 16))) & 3u);
-            }
-        }
-    }
-    wave_lds_fence();
-}
-
-// ---------------------------------------------------------------------------
-// Packed-row core specialised to distance D (rotated lattice, D <= 13).
-// Same chains as rows_core, bit for bit; what changes is where things live.
-// Every row of the chain's padded grid stays in a register for the whole run,
-// and the generator schedule (row, nibble offset, shape of every rank of every
-// class) is a compile-time table, so the sweep is straight-line code: no
-// descriptor loads, no row loads or stores, no per-move scalar work, and the
-// null generators that pad a class to whole Philox blocks cost nothing.  The
-// move-energy lookup maps (shape, pattern) to the byte offset of a 16-byte
-// (dE, threshold, always-accept mask) entry in static LDS; the four generators
-// of a Philox block are disjoint, so their patterns are read before any flips.
-// ---------------------------------------------------------------------------
-__device__ void load_static_tables(const PlanDev *pl, uint16_t *lut_s, uint4 *et_s)
-{
-    const int lane = threadIdx.x;
-    for (int i = lane; i < 256 * 6; i += kWave) lut_s[i] = (uint16_t)(16u * pl->lut[i]);
-    for (int i = lane; i < pl->nranks; i += kWave) {
-        const int32_t de = pl->dE[i];
-        et_s[i] = make_uint4((uint32_t)de, 0u, de <= 0 ? 0xFFFFFFFFu : 0u, 0u);
-    }
-    wave_lds_fence();
-}
-
-// Philox4x32-10 of the counter (uid, cc, c2, b) with uid, c2, b and the key
-// uniform across the wavefront and cc the lane's chain.  Tracing which words
-// depend on the lane: the two products of round 0 are uniform; round 1
-// multiplies one lane word and one uniform word; round 2 likewise; from round
-// 3 on every word depends on the lane.  The lane products of rounds 1-2 do
-// not involve b, so PhiloxHead computes them once per (sweep, class) and
-// philox_block adds the b-dependent uniform products on the scalar unit.
-constexpr uint32_t kPhM0 = 0xD2511F53u, kPhM1 = 0xCD9E8D57u, kPhW0 = 0x9E3779B9u, kPhW1 = 0xBB67AE85u;
-
-struct PhiloxHead {
-    uint32_t hi0, y1;   // uniform: high word of M0*uid (round 0), low word of M1*c2
-    uint32_t w2, z2x;   // lane: round-1 outputs w and (z without the b-dependent part)
-    uint32_t a3, y3;    // lane: high and low words of M1*z2 (round 2)
-};
-
-__device__ __forceinline__ PhiloxHead philox_head(uint32_t uid, uint32_t cc, uint32_t c2, uint32_t k0, uint32_t k1)
-{
-    PhiloxHead h;
-    const uint64_t p0 = (uint64_t)uid * kPhM0;            // uniform
-    const uint64_t p1 = (uint64_t)c2 * kPhM1;             // uniform
-    h.hi0 = (uint32_t)(p0 >> 32);
-    h.y1 = (uint32_t)p1;
-    const uint32_t w1 = (uint32_t)p0;
-    const uint32_t x1 = (uint32_t)(p1 >> 32) ^ k0 ^ cc;   // lane
-    const uint64_t q = (uint64_t)x1 * kPhM0;              // round 1, lane
-    h.z2x = (uint32_t)(q >> 32) ^ w1 ^ (k1 + kPhW1);
-    h.w2 = (uint32_t)q;
-    const uint64_t r = (uint64_t)h.z2x * kPhM1;           // round 2, lane
-    h.a3 = (uint32_t)(r >> 32);
-    h.y3 = (uint32_t)r;
-    return h;
-}
-
-__device__ __forceinline__ uint4 philox_block(const PhiloxHead &h, uint32_t b, uint32_t k0, uint32_t k1)
-{
-    uint32_t z1 = h.hi0 ^ b ^ k1;                         // round 0 output z (uniform)
-    // computed per block on the scalar unit rather than hoisted out of the
-    // sweep loop into vector registers
-    asm volatile("" : "+s"(z1));
-    const uint64_t p1 = (uint64_t)z1 * kPhM1;             // round 1, uniform
-    const uint32_t x2 = (uint32_t)(p1 >> 32) ^ h.y1 ^ (k0 + kPhW0);
-    const uint32_t y2 = (uint32_t)p1;
-    const uint64_t p0 = (uint64_t)x2 * kPhM0;             // round 2, uniform
-    uint4 c = make_uint4(h.a3 ^ (y2 ^ (k0 + 2u * kPhW0)), h.y3,
-                         h.w2 ^ ((uint32_t)(p0 >> 32) ^ (k1 + 2u * kPhW1)), (uint32_t)p0);
-    k0 += 3u * kPhW0;
-    k1 += 3u * kPhW1;
-#pragma unroll
-    for (int i = 3; i < 10; ++i) {
-        const uint64_t q0 = (uint64_t)c.x * kPhM0;
-        const uint64_t q1 = (uint64_t)c.z * kPhM1;
-        c = make_uint4(xor3_key((uint32_t)(q1 >> 32), c.y, k0), (uint32_t)q1,
-                       xor3_key((uint32_t)(q0 >> 32), c.w, k1), (uint32_t)q0);
-        k0 += kPhW0;
-        k1 += kPhW1;
-    }
-    return c;
-}
-
-// All ones where u < thr (unsigned), from the borrow of u - thr: bit 31 of
-// (~u & thr) | (~(u ^ thr) & (u - thr)), one v_bitop3 (truth table 0x8E).
-__device__ __forceinline__ uint32_t lt_mask(uint32_t u, uint32_t thr)
-{
-    return (uint32_t)((int32_t)__builtin_amdgcn_bitop3_b32(u, thr, u - thr, 0x8E) >> 31);
-}
-
-// Pattern of the generator at nibble offset BO of rows (ra, rb), times two:
-// bits 1-4 from ra, bits 5-8 from rb.
-template <int BO>
-__device__ __forceinline__ uint32_t pattern_x2(uint32_t ra, uint32_t rb)
-{
-    const uint32_t a = BO >= 1 ? ra >> (BO - 1) : ra << 1;
-    const uint32_t b = BO >= 5 ? rb >> (BO - 5) : rb << (5 - BO);
-    return (b & 0x1E0u) | (a & 0x1Eu);
-}
-
-template <int D, int K, int B, int W>
-__device__ __forceinline__ void static_move(uint32_t (&r)[D + 2], uint32_t u, const uint16_t *lut_s, const uint4 *et_s,
-                                            int32_t &acc)
-{
-    constexpr RotSchedule<D> S{};
-    constexpr RotGen g = S.g[K][4 * B + W];
-    if constexpr (g.shp != 5) {
-        const uint32_t pat2 = pattern_x2<g.bo>(r[g.Y], r[g.Y + 1]);
-        const uint32_t off = *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(lut_s) +
-                                                                 512u * g.shp + pat2);
-        const uint4 e = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint8_t *>(et_s) + off);
-        // all ones on accepting lanes: u < threshold, or dE <= 0
-        const uint32_t sel = lt_mask(u, e.y) | e.z;
-        r[g.Y] = xor_and(r[g.Y], 6u << g.bo, sel);           // X_left | Z_up
-        r[g.Y + 1] = xor_and(r[g.Y + 1], 9u << g.bo, sel);   // Z_down | X_right
-        acc += (int32_t)(e.x & sel);
-    }
-}
-
-template <int D, int K, int B>
-__device__ __forceinline__ void static_block(uint32_t (&r)[D + 2], const PhiloxHead &h, uint32_t k0, uint32_t k1,
-                                             const uint16_t *lut_s, const uint4 *et_s, int32_t &acc)
-{
-    const uint4 u = philox_block(h, (uint32_t)B, k0, k1);
-    static_move<D, K, B, 0>(r, u.x, lut_s, et_s, acc);
-    static_move<D, K, B, 1>(r, u.y, lut_s, et_s, acc);
-    static_move<D, K, B, 2>(r, u.z, lut_s, et_s, acc);
-    static_move<D, K, B, 3>(r, u.w, lut_s, et_s, acc);
-}
-
-template <int D, int K, int... Bs>
-__device__ __forceinline__ void static_class(uint32_t (&r)[D + 2], const PhiloxHead &h, uint32_t k0, uint32_t k1,
-                                             const uint16_t *lut_s, const uint4 *et_s, int32_t &acc,
-                                             std::integer_sequence<int, Bs...>)
-{
-    (static_block<D, K, Bs>(r, h, k0, k1, lut_s, et_s, acc), ...);
-}
-
-template <int D>
-__device__ void rows_static_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
-                                 uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s, int cp_interval)
-{
-    constexpr int NR = D + 2;
-    constexpr int NB = RotSchedule<D>::MP / 4;
-    using Blocks = std::make_integer_sequence<int, NB>;
-    const int lane = threadIdx.x;
-    const int nranks = (int)uni(pl->nranks);
-    int32_t W[4];
-    W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
-    // a task's 64 chains belong to one syndrome
-    const uint32_t uid = uni(J.uid), cc = J.cc;
-    const uint32_t k0 = uni(seed_lo), k1 = uni(seed_hi);
-    const bool use_x = !J.resume && (J.lp == 1 || J.lp == 2), use_z = !J.resume && (J.lp == 2 || J.lp == 3);
-    // lane 0 is always active and a task's chains are consecutive: chain of lane l = ci0 + l
-    const int64_t ci0 = (int64_t)(((uint64_t)uni((uint32_t)((uint64_t)J.ci >> 32)) << 32) | uni((uint32_t)J.ci));
-    const int cp_every = J.cp_out ? cp_interval : 0;
-
-    uint32_t r[NR];
-    int32_t E = 0;
-#pragma unroll
-    for (int Y = 0; Y < NR; ++Y) {
-        uint32_t word = 0;
-        if (Y >= 1 && Y <= D && J.active) {
-            // not unrolled: a fully unrolled row would keep every byte load in flight
-#pragma unroll 1
-            for (int x = 0; x < D; ++x) {
-                const int q = (Y - 1) * D + x;
-                uint32_t v = J.src[q] & 3u;
-                if (use_x) v ^= pl->lx[q];
-                if (use_z) v ^= pl->lz[q];
-                word |= v << (2 * (x + 1));
-                E += weight_of(W, v);
-            }
-        }
-        r[Y] = word;
-    }
-    int32_t Emin = E, stop = 0;
-    if (J.resume && J.active) {
-        E = J.efin[J.ci];
-        Emin = J.emin[J.ci];
-        stop = J.stop[J.ci];
-    }
-
-    for (int t = t_begin; t < t_end;) {
-        // sweeps up to the next checkpoint, then the checkpoint (the state at
-        // the start of sweep t, every cp_every sweeps)
-        int t_stop = t_end;
-        if (cp_every) t_stop = min(t_end, (t / cp_every + 1) * cp_every);
-        for (; t < t_stop; ++t) {
-            wave_lds_fence();
-            for (int i = lane; i < nranks; i += kWave) et_s[i].y = pl->thr[(size_t)t * nranks + i];
-            wave_lds_fence();
-            const uint32_t c2 = 4u * (uint32_t)t;
-            int32_t acc = 0;
-            static_class<D, 0>(r, philox_head(uid, cc, c2, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
-            E += acc;
-            if (E < Emin) { Emin = E; stop = 4 * t + 1; }
-            acc = 0;
-            static_class<D, 1>(r, philox_head(uid, cc, c2 + 1u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
-            E += acc;
-            if (E < Emin) { Emin = E; stop = 4 * t + 2; }
-            acc = 0;
-            static_class<D, 2>(r, philox_head(uid, cc, c2 + 2u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
-            E += acc;
-            if (E < Emin) { Emin = E; stop = 4 * t + 3; }
-            acc = 0;
-            static_class<D, 3>(r, philox_head(uid, cc, c2 + 3u, k0, k1), k0, k1, lut_s, et_s, acc, Blocks{});
-            E += acc;
-            if (E < Emin) { Emin = E; stop = 4 * t + 4; }
-        }
-        if (cp_every && t < t_end && J.active) {
-            uint32_t *cp = J.cp_out + (int64_t)(t / cp_every - 1) * D * J.cp_stride + ci0 + lane;
-#pragma unroll
-            for (int Y = 1; Y <= D; ++Y) cp[(Y - 1) * J.cp_stride] = r[Y];
-        }
-    }
-    if (J.active) {
-        J.emin[J.ci] = Emin;
-        J.stop[J.ci] = stop;
-        J.efin[J.ci] = E;
-        if (J.states) {
-            uint8_t *dst = J.states + (size_t)J.ci * (D * D);
-#pragma unroll
-            for (int Y = 1; Y <= D; ++Y)
-#pragma unroll 1
-                for (int x = 0; x < D; ++x) dst[(Y - 1) * D + x] = (uint8_t)((r[Y] >> (2 * (x + 1))) & 3u);
-        }
-    }
-}
-
-__device__ void load_rows_tables(const PlanDev *pl, uint8_t *smem)
-{
-    const int lane = threadIdx.x;
-    const RowsLds lo = rows_layout(pl->ntypes, pl->nranks);
-    const uint32_t *lut_g = reinterpret_cast<const uint32_t *>(pl->lut);
-    uint32_t *lut_s = reinterpret_cast<uint32_t *>(smem + lo.lut);
-    for (int i = lane; i < 64 * pl->ntypes; i += kWave) lut_s[i] = lut_g[i];
-    int2 *et_s = reinterpret_cast<int2 *>(smem + lo.et);
-    for (int i = lane; i < pl->nranks; i += kWave) et_s[i] = make_int2(pl->dE[i], 0);
-    wave_lds_fence();
-}
-
-__device__ void load_plan_tables(const PlanDev *pl, uint8_t *smem)
-{
-    const int lane = threadIdx.x;
-    const LdsLayout lo = lds_layout(pl->M, pl->ntypes, pl->nranks);
-    uint2 *desc_s = reinterpret_cast<uint2 *>(smem + lo.desc);
-    const uint2 *desc_g = reinterpret_cast<const uint2 *>(pl->desc);
-    for (int i = lane; i < 4 * pl->M; i += kWave) desc_s[i] = desc_g[i];
-    const uint32_t *lut_g = reinterpret_cast<const uint32_t *>(pl->lut);
-    uint32_t *lut_s = reinterpret_cast<uint32_t *>(smem + lo.lut);
-    for (int i = lane; i < 64 * pl->ntypes; i += kWave) lut_s[i] = lut_g[i];
-    int2 *et_s = reinterpret_cast<int2 *>(smem + lo.et);
-    for (int i = lane; i < pl->nranks; i += kWave) et_s[i] = make_int2(pl->dE[i], 0);
-    wave_lds_fence();
-}
-
-// ---------------------------------------------------------------------------
-// Batch kernels.  MODE 0: persistent wavefronts pulling tasks from an atomic
-// queue over every group of the launch; MODE 2: plain form, one task per
-// workgroup.  ROWS selects the packed-row core; otherwise the byte-state core
-// with LOGG = log2(lanes per chain), the same for every group of the launch;
-// REPLAY (byte-state only) re-runs each syndrome's best chain.
-// ---------------------------------------------------------------------------
-template <int MODE, bool ROWS, int LOGG, bool REPLAY>
-__device__ __forceinline__ void batch_kernel_body(const AnnealArgs &A)
-{
-    extern __shared__ __align__(16) uint8_t smem[];
-    const PlanDev *loaded = nullptr;
-    for (int iter = 0;; ++iter) {
-        uint32_t task = 0;
-        if (MODE == 2) {
-            if (iter > 0) break;
-            task = blockIdx.x;
-        } else {
-            if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
-            task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
-        }
-        if (task >= A.n_tasks) break;
-        int gi = 0;
-        while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
-        const GroupArgs &G = A.g[gi];
-        constexpr int lg = ROWS ? 0 : LOGG;
-        const int64_t unit0 = ((int64_t)task - G.task_begin) << (6 - lg);
-        if (G.plan != loaded) {
-            wave_lds_fence();
-            if (ROWS) load_rows_tables(G.plan, smem);
-            else load_plan_tables(G.plan, smem);
-            loaded = G.plan;
-        }
-        const int n_sweeps = G.plan->n_sweeps;
-        if (ROWS) {
-            const ChainJob J = batch_job(G, unit0 + threadIdx.x, false);
-            if (G.row_words == 1) rows_core<1>(G.plan, J, 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
-            else rows_core<2>(G.plan, J, 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
-        } else {
-            const ChainJob J = batch_job(G, unit0 + (threadIdx.x >> lg), REPLAY);
-            // a replay from a checkpoint runs one chain per wavefront (uniform t0)
-            bytes_core<lg, REPLAY>(G.plan, J, REPLAY ? J.t0 : 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
-        }
-    }
-}
-
-// Batch body of the specialised packed-row kernel (MODE as above).  Every
-// group of the launch has distance SD and tasks of 64 chains of one syndrome.
-template <int MODE, int SD>
-__device__ __forceinline__ void static_rows_body(const AnnealArgs &A)
-{
-    __shared__ uint16_t lut_s[256 * 6];
-    __shared__ uint4 et_s[kStaticRanks];
-    const PlanDev *loaded = nullptr;
-    for (int iter = 0;; ++iter) {
-        uint32_t task = 0;
-        if (MODE == 2) {
-            if (iter > 0) break;
-            task = blockIdx.x;
-        } else {
-            if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
-            task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
-        }
-        if (task >= A.n_tasks) break;
-        int gi = 0;
-        while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
-        const GroupArgs &G = A.g[gi];
-        const int64_t unit0 = ((int64_t)task - G.task_begin) << 6;
-        if (G.plan != loaded) {
-            wave_lds_fence();
-            load_static_tables(G.plan, lut_s, et_s);
-            loaded = G.plan;
-        }
-        const ChainJob J = batch_job(G, unit0 + threadIdx.x, false);
-        rows_static_core<SD>(G.plan, J, 0, G.plan->n_sweeps, A.seed_lo, A.seed_hi, lut_s, et_s, G.cp_every);
-    }
-}
-
-// Occupancy target of the specialised kernels: eight wavefronts per SIMD (at
-// most 64 VGPRs) hides the LDS and multiply latencies best, even at the cost
-// of a few spilled registers at d = 11 (measured); d = 13 keeps six.
-constexpr int static_waves(int d) { return d <= 11 ? 8 : 6; }
-
-template <int D>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(static_waves(D), static_waves(D))))
-void k_anneal_rows_d(AnnealArgs A) { static_rows_body<0, D>(A); }
-template <int D>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(static_waves(D), static_waves(D))))
-void k_anneal_rows_d_plain(AnnealArgs A) { static_rows_body<2, D>(A); }
-
 template <int LOGG>
 __global__ __launch_bounds__(kWave) void k_anneal(AnnealArgs A) { batch_kernel_body<0, false, LOGG, false>(A); }
 template <int LOGG>
@@ -1115,18 +283,22 @@ __global__ __launch_bounds__(kWave) void k_anneal_plain(AnnealArgs A) { batch_ke
 __global__ __launch_bounds__(kWave) void k_anneal_rows(AnnealArgs A) { batch_kernel_body<0, true, 0, false>(A); }
 __global__ __launch_bounds__(kWave) void k_anneal_rows_plain(AnnealArgs A) { batch_kernel_body<2, true, 0, false>(A); }
 
-typedef void (*AnnealKernel)(AnnealArgs);
 static AnnealKernel static_rows_kernel(int d, bool plain)
 {
-    switch (d) {
-    case 3: return plain ? k_anneal_rows_d_plain<3> : k_anneal_rows_d<3>;
-    case 5: return plain ? k_anneal_rows_d_plain<5> : k_anneal_rows_d<5>;
-    case 7: return plain ? k_anneal_rows_d_plain<7> : k_anneal_rows_d<7>;
-    case 9: return plain ? k_anneal_rows_d_plain<9> : k_anneal_rows_d<9>;
-    case 11: return plain ? k_anneal_rows_d_plain<11> : k_anneal_rows_d<11>;
-    case 13: return plain ? k_anneal_rows_d_plain<13> : k_anneal_rows_d<13>;
-    default: return nullptr;
-    }
+#define XZZX_TRY_PART(P) \
+    if (AnnealKernel k = static_rows_kernel_##P(d, plain)) return k;
+    XZZX_STATIC_PARTS(XZZX_TRY_PART)
+#undef XZZX_TRY_PART
+    return nullptr;
+}
+
+static ServeKernel static_serve_kernel(int d)
+{
+#define XZZX_TRY_PART(P) \
+    if (ServeKernel k = static_serve_kernel_##P(d)) return k;
+    XZZX_STATIC_PARTS(XZZX_TRY_PART)
+#undef XZZX_TRY_PART
+    return nullptr;
 }
 
 static AnnealKernel bytes_kernel(int mode, int lg)
@@ -1138,67 +310,6 @@ static AnnealKernel bytes_kernel(int mode, int lg)
         {k_anneal_plain<0>, k_anneal_plain<1>, k_anneal_plain<2>, k_anneal_plain<3>, k_anneal_plain<4>,
          k_anneal_plain<5>, k_anneal_plain<6>}};
     return tab[mode][lg];
-}
-
-// ---------------------------------------------------------------------------
-// Serving kernels: one workgroup per task of the slice.  A task covers
-// consecutive chains of one resident request, all at the same sweep range.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ ChainJob serve_job(const ServeTask &T, int slot, bool replay)
-{
-    ChainJob j;
-    const int nc = 4 * T.n_rep;
-    const int nq = T.plan->nq;
-    j.active = slot < T.nchains;
-    int c = T.chain0 + (j.active ? slot : 0);
-    if (replay) c = *T.best;
-    j.cc = (uint32_t)c;
-    j.lp = c & 3;
-    j.uid = T.uid;
-    j.resume = !replay && T.t_begin > 0;
-    j.src = j.resume ? T.states + (size_t)c * nq : T.refs + (size_t)(c >> 2) * nq;
-    j.ci = c;
-    j.efin = T.e3;
-    j.emin = T.e3 + nc;
-    j.stop = T.e3 + 2 * nc;
-    j.states = replay ? nullptr : T.states;
-    j.target = replay ? T.e3[2 * nc + c] : -1;
-    j.snap = replay ? T.snap : nullptr;
-    j.cp_out = nullptr;
-    j.cp_in = nullptr;
-    j.cp_stride = 0;
-    j.t0 = 0;
-    return j;
-}
-
-template <bool ROWS, bool REPLAY>
-__device__ __forceinline__ void serve_kernel_body(const ServeTask *tasks, uint32_t seed_lo, uint32_t seed_hi)
-{
-    extern __shared__ __align__(16) uint8_t smem[];
-    const ServeTask &T = tasks[blockIdx.x];
-    const PlanDev *pl = T.plan;
-    if (ROWS) {
-        load_rows_tables(pl, smem);
-        const ChainJob J = serve_job(T, threadIdx.x, false);
-        if (T.row_words == 1) rows_core<1>(pl, J, T.t_begin, T.t_end, seed_lo, seed_hi, smem);
-        else rows_core<2>(pl, J, T.t_begin, T.t_end, seed_lo, seed_hi, smem);
-    } else {
-        load_plan_tables(pl, smem);
-        const int lg = T.log_lanes;
-        const ChainJob J = serve_job(T, threadIdx.x >> lg, REPLAY);
-        const int tb = REPLAY ? 0 : T.t_begin;
-        const int te = REPLAY ? pl->n_sweeps : T.t_end;
-        switch (lg) {
-        case 0: bytes_core<0, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
-        case 1: bytes_core<1, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
-        case 2: bytes_core<2, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
-        case 3: bytes_core<3, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
-        case 4: bytes_core<4, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
-        case 5: bytes_core<5, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
-        default: bytes_core<6, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;
-        }
-    }
 }
 
 __global__ __launch_bounds__(kWave) void k_serve_rows(const ServeTask *tasks, uint32_t slo, uint32_t shi)
@@ -1213,6 +324,8 @@ __global__ __launch_bounds__(kWave) void k_serve_replay(const ServeTask *tasks, 
 {
     serve_kernel_body<false, true>(tasks, slo, shi);
 }
+
+
 
 __global__ void k_zero_u32(uint32_t *p, int n)
 {
@@ -1284,6 +397,15 @@ __global__ __launch_bounds__(kWave) void k_reduce(ReduceArgs A)
 // Serving: per-coset reduction of a finished request (one wavefront each).
 // The class of replica r relative to replica 0 comes from the raw symplectic
 // bits the greedy kernel stored (bit 0: with L_Z, bit 1: with L_X).
+// Results and recoveries of the finished requests, packed for one copy to the host.
+__global__ __launch_bounds__(kWave) void k_serve_gather(const ServeFinish *fin)
+{
+    const ServeFinish &F = fin[blockIdx.x];
+    const int lane = threadIdx.x;
+    if (lane < 8) reinterpret_cast<int32_t *>(F.out)[lane] = F.result[lane];
+    for (int q = lane; q < F.nq; q += kWave) F.out[32 + q] = F.recovery[q];
+}
+
 __global__ __launch_bounds__(kWave) void k_serve_reduce(const ServeFinish *fin)
 {
     const ServeFinish &F = fin[blockIdx.x];
@@ -1400,7 +522,7 @@ static size_t group_ws_bytes(const xzzx_group &g, bool decode)
     if (!g.d_chain_stop) b += align256(nc * 4);
     if (!g.d_chain_e) b += align256(nc * 4);
     if (!g.d_best_chain) b += align256(ns * 4);
-    b += align256((size_t)checkpoints_of(g) * P.lat.d * nc * 4);
+    b += align256((size_t)checkpoints_of(g) * P.lat.d * P.row_words * nc * 4);
     return b;
 }
 
@@ -1418,7 +540,7 @@ static GroupWs carve_group(const xzzx_group &g, bool decode, uint8_t *&p)
     w.efin = g.d_chain_e ? g.d_chain_e : reinterpret_cast<int32_t *>(take(nc * 4));
     w.best_chain = g.d_best_chain ? g.d_best_chain : reinterpret_cast<int32_t *>(take(ns * 4));
     const int ncp = checkpoints_of(g);
-    w.cp_rows = ncp ? reinterpret_cast<uint32_t *>(take((size_t)ncp * P.lat.d * nc * 4)) : nullptr;
+    w.cp_rows = ncp ? reinterpret_cast<uint32_t *>(take((size_t)ncp * P.lat.d * P.row_words * nc * 4)) : nullptr;
     return w;
 }
 
@@ -1703,15 +825,22 @@ int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const 
     return check_hip(hipGetLastError(), "serving greedy launch");
 }
 
-int serve_slice(const ServeTask *d_rows, int n_rows, size_t lds_rows, const ServeTask *d_bytes, int n_bytes,
-                size_t lds_bytes, uint64_t seed, hipStream_t stream)
+int serve_slice(const ServeLaunch *launches, int n_launches, uint64_t seed, hipStream_t stream)
 {
-    if (n_rows > 0)
-        hipLaunchKernelGGL(k_serve_rows, dim3((unsigned)n_rows), dim3(kWave), lds_rows, stream, d_rows,
-                           (uint32_t)seed, (uint32_t)(seed >> 32));
-    if (n_bytes > 0)
-        hipLaunchKernelGGL(k_serve_bytes, dim3((unsigned)n_bytes), dim3(kWave), lds_bytes, stream, d_bytes,
-                           (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint32_t lo = (uint32_t)seed, hi = (uint32_t)(seed >> 32);
+    for (int i = 0; i < n_launches; ++i) {
+        const ServeLaunch &L = launches[i];
+        if (L.n <= 0) continue;
+        if (L.kind == 0) {
+            hipLaunchKernelGGL(k_serve_rows, dim3((unsigned)L.n), dim3(kWave), L.lds, stream, L.tasks, lo, hi);
+        } else if (L.kind == 1) {
+            hipLaunchKernelGGL(k_serve_bytes, dim3((unsigned)L.n), dim3(kWave), L.lds, stream, L.tasks, lo, hi);
+        } else {
+            const ServeKernel k = static_serve_kernel(L.d);
+            if (!k) { set_error("no specialised serving kernel for this distance"); return XZZX_EINVAL; }
+            hipLaunchKernelGGL(k, dim3((unsigned)L.n), dim3(kWave), 0, stream, L.tasks, lo, hi);
+        }
+    }
     return check_hip(hipGetLastError(), "serving slice launch");
 }
 
@@ -1722,6 +851,7 @@ int serve_finish(const ServeFinish *d_fin, const ServeTask *d_replay, int n, siz
     hipLaunchKernelGGL(k_serve_reduce, dim3((unsigned)n), dim3(kWave), 0, stream, d_fin);
     hipLaunchKernelGGL(k_serve_replay, dim3((unsigned)n), dim3(kWave), lds_replay, stream, d_replay,
                        (uint32_t)seed, (uint32_t)(seed >> 32));
+    hipLaunchKernelGGL(k_serve_gather, dim3((unsigned)n), dim3(kWave), 0, stream, d_fin);
     return check_hip(hipGetLastError(), "serving finish launch");
 }
 

@@ -96,6 +96,8 @@ struct xzzx_server {
     Clock::time_point first_admit, last_done;
 
     uint8_t *slot_ptr(int s) { return d_pool + (size_t)s * slot_bytes; }
+    // bytes per finished request in the result staging: 32-byte result, recovery, 16-byte aligned
+    size_t out_stride() const { return (32 + (size_t)cfg.max_qubits + 15) & ~size_t(15); }
     void run();
     int slice();
 };
@@ -219,7 +221,7 @@ int xzzx_server::slice()
 
     // ---- 2. one slice of sweeps for every resident request -----------------
     ServeTask *h_tasks = reinterpret_cast<ServeTask *>(h_stage + st_tasks);
-    std::vector<ServeTask> rows_t, bytes_t;
+    std::vector<ServeTask> rows_t, bytes_t, static_t[kStaticMaxD + 1];
     size_t lds_rows = 0, lds_bytes = 0;
     std::vector<int> finished;
     // lanes per chain for this slice: at light load every chain spreads over
@@ -281,24 +283,44 @@ int xzzx_server::slice()
                 while ((1 << lg) < gr) ++lg;
                 T.log_lanes = rows ? 0 : lg;
                 T.row_words = rows ? P.row_words : 0;
-                if (rows) { rows_t.push_back(T); lds_rows = std::max(lds_rows, lds); }
+                if (rows && P.static_d) static_t[P.static_d].push_back(T);
+                else if (rows) { rows_t.push_back(T); lds_rows = std::max(lds_rows, lds); }
                 else { bytes_t.push_back(T); lds_bytes = std::max(lds_bytes, lds); }
             }
             sl.t = t1;
         }
         if (sl.t >= P.n_sweeps) finished.push_back((int)s);
     }
-    const size_t nt = rows_t.size() + bytes_t.size();
+    // one launch per kernel family: generic packed rows, byte states, and
+    // the packed-row kernel specialised to each distance present
+    std::vector<ServeLaunch> launches;
+    size_t nt = 0;
+    auto add = [&](const std::vector<ServeTask> &v, int kind, int d, size_t lds) {
+        if (v.empty()) return;
+        ServeLaunch L{};
+        L.tasks = reinterpret_cast<const ServeTask *>(d_stage + st_tasks) + nt;
+        L.n = (int32_t)v.size();
+        L.kind = kind;
+        L.d = d;
+        L.lds = lds;
+        launches.push_back(L);
+        nt += v.size();
+    };
+    add(rows_t, 0, 0, lds_rows);
+    add(bytes_t, 1, 0, lds_bytes);
+    for (int d = kStaticMinD; d <= kStaticMaxD; d += 2) add(static_t[d], 2, d, 0);
     if (nt > max_tasks) { set_error("serving task buffer overflow"); return XZZX_ERANGE; }
     if (nt) {
-        std::copy(rows_t.begin(), rows_t.end(), h_tasks);
-        std::copy(bytes_t.begin(), bytes_t.end(), h_tasks + rows_t.size());
+        size_t at = 0;
+        for (const auto *v : {&rows_t, &bytes_t}) { std::copy(v->begin(), v->end(), h_tasks + at); at += v->size(); }
+        for (int d = kStaticMinD; d <= kStaticMaxD; d += 2) {
+            std::copy(static_t[d].begin(), static_t[d].end(), h_tasks + at);
+            at += static_t[d].size();
+        }
         rc = check(hipMemcpyAsync(d_stage + st_tasks, h_tasks, nt * sizeof(ServeTask), hipMemcpyHostToDevice, stream),
                    "stage tasks");
         if (rc) return rc;
-        const ServeTask *d_tasks = reinterpret_cast<const ServeTask *>(d_stage + st_tasks);
-        rc = serve_slice(d_tasks, (int)rows_t.size(), lds_rows, d_tasks + rows_t.size(), (int)bytes_t.size(),
-                         lds_bytes, cfg.anneal_seed, stream);
+        rc = serve_slice(launches.data(), (int)launches.size(), cfg.anneal_seed, stream);
         if (rc) return rc;
         ++slices;
     }
@@ -318,7 +340,10 @@ int xzzx_server::slice()
             F.e3 = reinterpret_cast<const int32_t *>(base + off_e3);
             F.qraw = base + off_qraw;
             F.result = reinterpret_cast<int32_t *>(base + off_res);
+            F.recovery = base + off_rec;
+            F.out = d_stage + st_out + k * out_stride();
             F.n_rep = sl.n_rep;
+            F.nq = P.lat.nq;
             h_fin[k] = F;
             // replay the best chain with every lane of a wavefront on it
             ServeTask T{};
@@ -347,15 +372,11 @@ int xzzx_server::slice()
                           reinterpret_cast<const ServeTask *>(d_stage + st_fin + align256(slots.size() * sizeof(ServeFinish))),
                           (int)nf, lds_rep, cfg.anneal_seed, stream);
         if (rc) return rc;
-        // results: [8 words][recovery max_qubits] per finished request
-        const size_t per = 32 + (size_t)cfg.max_qubits;
-        for (size_t k = 0; k < nf; ++k) {
-            uint8_t *base = slot_ptr(finished[k]);
-            rc = check(hipMemcpyAsync(h_stage + st_out + k * per, base + off_res, 32, hipMemcpyDeviceToHost, stream), "result");
-            if (!rc) rc = check(hipMemcpyAsync(h_stage + st_out + k * per + 32, base + off_rec, slots[finished[k]].plan->lat.nq,
-                                               hipMemcpyDeviceToHost, stream), "recovery");
-            if (rc) return rc;
-        }
+        // results, gathered on the device as [8 words][recovery max_qubits]
+        // per finished request: one copy to the host
+        rc = check(hipMemcpyAsync(h_stage + st_out, d_stage + st_out, nf * out_stride(), hipMemcpyDeviceToHost, stream),
+                   "results");
+        if (rc) return rc;
     }
     rc = check(hipStreamSynchronize(stream), "slice");
     if (rc) return rc;
@@ -363,7 +384,7 @@ int xzzx_server::slice()
     // ---- 4. publish ---------------------------------------------------------
     if (nf) {
         const auto now = Clock::now();
-        const size_t per = 32 + (size_t)cfg.max_qubits;
+        const size_t per = out_stride();
         std::lock_guard<std::mutex> lk(mu);
         for (size_t k = 0; k < nf; ++k) {
             Slot &sl = slots[finished[k]];
@@ -461,7 +482,7 @@ int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out)
     S->st_tasks = S->st_map + align256(ns * 4);
     S->st_fin = S->st_tasks + align256(S->max_tasks * sizeof(ServeTask));
     S->st_out = S->st_fin + align256(ns * sizeof(ServeFinish)) + align256(ns * sizeof(ServeTask));
-    S->stage_bytes = S->st_out + align256(ns * (32 + nq));
+    S->stage_bytes = S->st_out + align256(ns * S->out_stride());
     if (!rc) rc = check(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking), "stream");
     if (!rc && hipMalloc(&S->d_pool, S->slot_bytes * ns) != hipSuccess) { S->d_pool = nullptr; set_error("slot pool allocation"); rc = XZZX_ENOMEM; }
     if (!rc && hipMalloc(&S->d_stage, S->stage_bytes) != hipSuccess) { S->d_stage = nullptr; set_error("staging allocation"); rc = XZZX_ENOMEM; }

@@ -113,14 +113,14 @@ def test_row_and_byte_kernels_agree(d):
         gpu_plan(Problem(1, 5, 0.2, 10.0, 1, 1, 1)).set_kernel(X.KERNEL_ROWS)
 
 
-@pytest.mark.parametrize("d", [3, 5, 7, 9, 11, 13])
+@pytest.mark.parametrize("d", list(range(3, 30, 2)))
 def test_specialised_row_kernel(d):
     """The packed-row kernel specialised to d (registers for rows, compile-time
     schedule) runs when every 64-chain task lies in one syndrome; its chains,
     final states and results equal the generic packed-row kernel's, the
     byte-state kernel's and the oracle's, in the persistent and plain forms."""
     R = 16 if d > 9 else 32
-    prob = Problem(0, d, 0.2, 10.0, 3, R, 24, seed=700 + d)
+    prob = Problem(0, d, 0.2, 10.0, 3 if d <= 21 else 2, R, 24 if d <= 21 else 12, seed=700 + d)
     ref = prob.oracle_decode()
     plan = gpu_plan(prob)
     assert plan.info()["kernel"] == X.KERNEL_ROWS
@@ -135,22 +135,22 @@ def test_specialised_row_kernel(d):
     assert plan.info()["kernel"] == X.KERNEL_ROWS
 
 
-@pytest.mark.parametrize("sweeps", [256, 257, 700])
-def test_replay_from_checkpoints(sweeps):
+@pytest.mark.parametrize("d,sweeps", [(7, 256), (7, 257), (7, 700), (19, 300)])
+def test_replay_from_checkpoints(d, sweeps):
     """Groups on the specialised kernel keep a state checkpoint every 256
     sweeps; each syndrome's recovery is replayed from the last checkpoint
     before its E_min phase (256 sweeps: none; 257: one, at the start of the
-    last sweep; 700: two)."""
-    prob = Problem(0, 7, 0.2, 10.0, 4, 16, sweeps, seed=800 + sweeps)
+    last sweep; 700: two; d = 19 stores two words per row)."""
+    prob = Problem(0, d, 0.2, 10.0, 4 if d < 15 else 2, 16, sweeps, seed=800 + sweeps)
     plan = gpu_plan(prob)
     assert plan.info()["kernel"] == X.KERNEL_ROWS
     compare_decode(prob, run_decode(prob, plan), prob.oracle_decode())
 
 
 def test_specialised_kernel_not_applicable():
-    """d = 15 has no specialised variant; the planar layout has no packed-row
+    """d = 31 (rows of three words) and the planar layout have no packed-row
     kernel at all."""
-    assert gpu_plan(Problem(0, 15, 0.2, 10.0, 1, 1, 1)).info()["kernel"] == X.KERNEL_ROWS_GENERIC
+    assert gpu_plan(Problem(0, 31, 0.2, 10.0, 1, 1, 1)).info()["kernel"] == X.KERNEL_BYTES
     assert gpu_plan(Problem(1, 5, 0.2, 10.0, 1, 1, 1)).info()["kernel"] == X.KERNEL_BYTES
 
 
