@@ -38,6 +38,20 @@ OPS_PER_ATTEMPT = 19
 ALU_PEAK_OPS = 256 * 128 * 2.4e9
 
 
+def kernel_source_sha256():
+    """Digest of every device source (kernels, shared device header, internal
+    header), in name order."""
+    import glob
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_2509_17837_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel, workload, batch):
     """HBM bytes per launch of the annealing kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of known
@@ -46,7 +60,6 @@ def measured_traffic(kernel, workload, batch):
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
-    src = os.path.join(ROOT, "paper_2509_17837_amd", "csrc", "xzzx_kernels.hip")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -54,7 +67,7 @@ def measured_traffic(kernel, workload, batch):
         if " = " in line:
             k, v = line.split(" = ", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_sha256()
     if kv.get("kernel_source_sha256") != sha or kv.get("workload") != f"{workload} batch {batch}":
         return None
     return int(kv["traffic_bytes_per_launch"])

@@ -19,6 +19,7 @@
 #include <utility>
 
 #include <algorithm>
+#include <mutex>
 #include <cstring>
 #include <vector>
 
@@ -673,6 +674,67 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
     return check_hip(hipGetLastError(), "anneal launch");
 }
 
+// Side streams of the current device (default priority, created once) for
+// running independent launches of one call concurrently.
+constexpr int kSideStreams = 3;
+
+static int side_streams(hipStream_t out[kSideStreams])
+{
+    static std::mutex mu;
+    static hipStream_t streams[64][kSideStreams] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { set_error("hipGetDevice failed"); return XZZX_EDEVICE; }
+    std::lock_guard<std::mutex> lk(mu);
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (!streams[dev][i] && hipStreamCreateWithFlags(&streams[dev][i], hipStreamNonBlocking) != hipSuccess) {
+            streams[dev][i] = nullptr;
+            set_error("side stream creation failed");
+            return XZZX_EDEVICE;
+        }
+        out[i] = streams[dev][i];
+    }
+    return XZZX_OK;
+}
+
+// Runs launch(i, stream_i) for i < n: launch 0 on `stream`, the others on side
+// streams that wait for `stream`'s prior work; `stream` then waits for all.
+// Works under hipGraph capture (the events become graph dependencies).
+template <typename F>
+static int fork_join(hipStream_t stream, int n, F launch)
+{
+    hipStream_t side[kSideStreams];
+    int rc = side_streams(side);
+    if (rc) return rc;
+    hipEvent_t fork = nullptr;
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) { set_error("event creation failed"); return XZZX_EDEVICE; }
+    rc = check_hip(hipEventRecord(fork, stream), "fork record");
+    std::vector<hipEvent_t> joins;
+    bool waited[kSideStreams] = {false, false, false};
+    for (int i = 0; i < n && !rc; ++i) {
+        hipStream_t s = stream;
+        if (i > 0) {
+            const int k = (i - 1) % kSideStreams;
+            s = side[k];
+            if (!waited[k]) {
+                rc = check_hip(hipStreamWaitEvent(s, fork, 0), "fork wait");
+                waited[k] = true;
+            }
+        }
+        if (!rc) rc = launch(i, s);
+    }
+    for (int k = 0; k < kSideStreams && !rc; ++k) {
+        if (!waited[k]) continue;
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { set_error("event creation failed"); rc = XZZX_EDEVICE; break; }
+        joins.push_back(e);
+        rc = check_hip(hipEventRecord(e, side[k]), "join record");
+        if (!rc) rc = check_hip(hipStreamWaitEvent(stream, e, 0), "join wait");
+    }
+    (void)hipEventDestroy(fork);
+    for (hipEvent_t e : joins) (void)hipEventDestroy(e);
+    return rc;
+}
+
 // Annealing of every non-empty group.  Packed-row groups share one persistent
 // launch; byte-state groups are launched per lanes-per-chain value.  The
 // replay re-runs one chain per syndrome with the byte-state kernel, spreading
@@ -715,14 +777,36 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
                             d_counters + 2, stream);
         return rc;
     }
-    int rc = launch_set(groups, ws, rows_sel, true, 1, mode, seed, unit_offset, units_override, d_counters, stream);
-    for (int d = kStaticMinD; d <= kStaticMaxD && !rc; d += 2)
-        rc = launch_set(groups, ws, static_sel[d], true, 1, mode, seed, unit_offset, units_override,
-                        d_counters + 16 + (d - kStaticMinD) / 2, stream, d);
-    for (int l = 0; l < 7 && !rc; ++l)
-        rc = launch_set(groups, ws, bytes_sel[l], false, 1 << l, mode, seed, unit_offset, units_override,
-                        d_counters + 1 + l, stream);
-    return rc;
+    // the launches of one call (one per kernel family and distance) run
+    // concurrently: each alone may not fill the device (a mixed-distance batch
+    // with a few hundred syndromes per distance)
+    struct Set {
+        const std::vector<int> *sel;
+        bool rows;
+        int lanes;
+        uint32_t *counter;
+        int static_d;
+    };
+    std::vector<Set> sets;
+    if (!rows_sel.empty()) sets.push_back({&rows_sel, true, 1, d_counters, 0});
+    for (int d = kStaticMinD; d <= kStaticMaxD; d += 2)
+        if (!static_sel[d].empty())
+            sets.push_back({&static_sel[d], true, 1, d_counters + 16 + (d - kStaticMinD) / 2, d});
+    for (int l = 0; l < 7; ++l)
+        if (!bytes_sel[l].empty()) sets.push_back({&bytes_sel[l], false, 1 << l, d_counters + 1 + l, 0});
+    if (sets.size() <= 1 || mode == AnnealMode::Plain) {
+        int rc = XZZX_OK;
+        for (const Set &S : sets)
+            if (!rc)
+                rc = launch_set(groups, ws, *S.sel, S.rows, S.lanes, mode, seed, unit_offset, units_override, S.counter,
+                                stream, S.static_d);
+        return rc;
+    }
+    return fork_join(stream, (int)sets.size(), [&](int i, hipStream_t s) {
+        const Set &S = sets[i];
+        return launch_set(groups, ws, *S.sel, S.rows, S.lanes, mode, seed, unit_offset, units_override, S.counter, s,
+                          S.static_d);
+    });
 }
 
 static int launch_reduce(const xzzx_group &g, const GroupWs &w, hipStream_t stream)
