@@ -91,7 +91,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=20000, help="most requests per arrival rate (--serve)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="arrival window per rate (--serve): min(--requests, rate x this) requests")
-    ap.add_argument("--slice", type=int, default=100, help="sweeps per serving slice (--serve)")
+    ap.add_argument("--slice", type=int, default=400,
+                    help="sweeps per serving slice of the costliest resident request (--serve)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="most lanes per chain the server may use (--serve; 0: library default, 1: plan kernels)")
     ap.add_argument("--waves", type=int, default=0, help="wave budget per serving slice (--serve; 0: default)")

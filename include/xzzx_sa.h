@@ -304,7 +304,7 @@ typedef struct {
     int64_t lds_budget_bytes; /* 0: the device's total LDS */
     uint64_t greedy_seed;
     uint64_t anneal_seed;
-    int max_lanes_per_chain;  /* 0: 16; 1: always the plan's own kernel; else a power of two <= 64 */
+    int max_lanes_per_chain;  /* 0: 64; 1: always the plan's own kernel; else a power of two <= 64 */
     int max_waves;            /* wavefronts per slice before lanes per chain shrink; 0: 32 per CU */
 } xzzx_server_cfg;
 

@@ -912,20 +912,23 @@ int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const 
 int serve_slice(const ServeLaunch *launches, int n_launches, uint64_t seed, hipStream_t stream)
 {
     const uint32_t lo = (uint32_t)seed, hi = (uint32_t)(seed >> 32);
-    for (int i = 0; i < n_launches; ++i) {
+    auto one = [&](int i, hipStream_t s) -> int {
         const ServeLaunch &L = launches[i];
-        if (L.n <= 0) continue;
+        if (L.n <= 0) return XZZX_OK;
         if (L.kind == 0) {
-            hipLaunchKernelGGL(k_serve_rows, dim3((unsigned)L.n), dim3(kWave), L.lds, stream, L.tasks, lo, hi);
+            hipLaunchKernelGGL(k_serve_rows, dim3((unsigned)L.n), dim3(kWave), L.lds, s, L.tasks, lo, hi);
         } else if (L.kind == 1) {
-            hipLaunchKernelGGL(k_serve_bytes, dim3((unsigned)L.n), dim3(kWave), L.lds, stream, L.tasks, lo, hi);
+            hipLaunchKernelGGL(k_serve_bytes, dim3((unsigned)L.n), dim3(kWave), L.lds, s, L.tasks, lo, hi);
         } else {
             const ServeKernel k = static_serve_kernel(L.d);
             if (!k) { set_error("no specialised serving kernel for this distance"); return XZZX_EINVAL; }
-            hipLaunchKernelGGL(k, dim3((unsigned)L.n), dim3(kWave), 0, stream, L.tasks, lo, hi);
+            hipLaunchKernelGGL(k, dim3((unsigned)L.n), dim3(kWave), 0, s, L.tasks, lo, hi);
         }
-    }
-    return check_hip(hipGetLastError(), "serving slice launch");
+        return check_hip(hipGetLastError(), "serving slice launch");
+    };
+    // the kernels of one slice (one per family and distance) run concurrently
+    if (n_launches <= 1) return n_launches ? one(0, stream) : XZZX_OK;
+    return fork_join(stream, n_launches, one);
 }
 
 int serve_finish(const ServeFinish *d_fin, const ServeTask *d_replay, int n, size_t lds_replay, uint64_t seed,

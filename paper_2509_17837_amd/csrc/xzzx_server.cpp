@@ -464,7 +464,7 @@ int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out)
     if (lds_cu <= 0) lds_cu = 160 * 1024;
     S->lds_budget = cfg->lds_budget_bytes ? (size_t)cfg->lds_budget_bytes : (size_t)cus * (size_t)lds_cu;
     S->wave_budget = cfg->max_waves ? cfg->max_waves : 32 * (int64_t)cus;
-    if (!S->cfg.max_lanes_per_chain) S->cfg.max_lanes_per_chain = 16;
+    if (!S->cfg.max_lanes_per_chain) S->cfg.max_lanes_per_chain = kWave;
     const size_t nq = (size_t)cfg->max_qubits, R = (size_t)cfg->max_rep;
     S->max_nstab = cfg->max_qubits;   // n_stabs < n_qubits for both layouts
     S->off_refs = 0;
