@@ -1,19 +1,24 @@
-// gfx950 kernels of the XZZX simulated-annealing decoder and the device-side
-// entry points of the C ABI.
+// gfx950 kernels of the XZZX simulated-annealing decoder (those not
+// specialised to a distance) and the device-side entry points of the C ABI.
 //
-//   k_syndrome  Eq. (2): syndrome of a batch of configurations.
-//   k_greedy    Algs. 5-6: greedy matching per (syndrome, replica), both
-//               decoding-graph colours, paths XOR-ed into an LDS configuration.
-//   k_qcls      Alg. 7: class Q_r of each reference relative to replica 0.
-//   k_anneal    Algs. 2-3: the hot loop.  Persistent wavefronts pull tasks of
-//               C = 64/G chains from an atomic queue spanning every syndrome
-//               group of the launch (uneven distances allowed).  Each chain's
-//               byte-per-qubit state lives in LDS, interleaved across the C
-//               chains of the wavefront; the G lanes of a chain split the
-//               generators of one colour class (qubit-disjoint, so they update
-//               concurrently).  Replay mode re-runs the best chain of each
-//               syndrome up to the phase of its minimum and stores that state.
-//   k_reduce    Eqs. (18)-(21): per-coset minima, P*, best chain.
+//   k_syndrome     Eq. (2): syndrome of a batch of configurations.
+//   k_greedy       Algs. 5-6: greedy matching per (syndrome, replica), both
+//                  decoding-graph colours, paths XOR-ed into an LDS configuration.
+//   k_qcls         Alg. 7: class Q_r of each reference relative to replica 0.
+//   k_anneal<L>    Algs. 2-3 on byte-per-qubit states, 2^L lanes per chain
+//                  (any lattice); k_anneal_rows: the generic packed-row kernel
+//                  (rotated lattices, d <= 29).  Both are persistent: wavefronts
+//                  pull tasks from an atomic queue spanning every syndrome group
+//                  of the launch.  The packed-row kernels specialised to one
+//                  distance are in xzzx_device.h / xzzx_static_*.hip.
+//   k_replay<L>    re-runs each syndrome's best chain up to the phase of its
+//                  minimum (from a checkpoint where the specialised kernel left
+//                  one) and stores that state: the recovery.
+//   k_reduce       Eqs. (18)-(21): per-coset minima, P*, best chain.
+//   k_serve_*      the serving loop's slices, finish and result gather.
+//
+// The host half turns xzzx_group descriptions into launches: one persistent
+// launch per kernel family and distance, run concurrently on side streams.
 #include <hip/hip_runtime.h>
 
 #include <utility>

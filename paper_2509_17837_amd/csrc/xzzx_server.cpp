@@ -6,11 +6,12 @@
 //      plan, written straight into the slots);
 //   2. advance every resident request by its share of sweeps (balanced so
 //      that every task carries about the same sequential work), with as many
-//      lanes per chain as the load allows: one task per group of chains, all
-//      tasks of the slice in one launch per kernel family;
+//      lanes per chain as the load allows: one task per group of chains, one
+//      launch per kernel family and distance, the launches of a slice running
+//      concurrently;
 //   3. finish requests whose schedule is complete (per-coset reduction and
-//      replay of the best chain on the device, results copied to pinned host
-//      memory);
+//      replay of the best chain on the device; results gathered on the
+//      device and copied to pinned host memory in one transfer);
 //   4. wait for the slice, then publish finished results with their latency.
 // Requests that arrive while a slice runs join at the next slice boundary.
 #include <hip/hip_runtime.h>
