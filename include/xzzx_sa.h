@@ -167,11 +167,13 @@ int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain);
 
 /* Which annealing kernel a plan uses (results are identical):
  *   XZZX_KERNEL_ROWS: one chain per lane, 2-bit codes packed row by row
- *     (rotated lattices with d <= 29); for d <= 13 a variant specialised to
- *     the distance keeps every row in registers and its generator schedule
- *     in the instruction stream;
+ *     (rotated lattices with d <= 31); a variant specialised to the distance
+ *     keeps every row in registers and its generator schedule in the
+ *     instruction stream.  Batch groups whose 4 n_rep chains per syndrome
+ *     are not a multiple of 64 run the generic variant instead (d <= 29),
+ *     or the byte-state kernel (d = 31);
  *   XZZX_KERNEL_ROWS_GENERIC: the packed-row kernel without that
- *     specialisation (rows in LDS, schedule read from the plan);
+ *     specialisation (rows in LDS, schedule read from the plan; d <= 29);
  *   XZZX_KERNEL_BYTES: byte-per-qubit states, lanes_per_chain lanes per chain;
  *   XZZX_KERNEL_AUTO: ROWS where it applies, else BYTES (the default).
  * EINVAL for ROWS or ROWS_GENERIC on a lattice they do not cover.

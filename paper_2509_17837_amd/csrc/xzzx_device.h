@@ -85,8 +85,8 @@ struct ChainJob {
     int32_t lp;            // coset logical applied at start (0..3)
     int32_t target;        // replay: phase whose state is stored (-1 = none)
     bool active, resume;
-    // checkpoints of the specialised packed-row kernel (word-major rows of
-    // rows 1..d, plane stride cp_stride chains)
+    // checkpoints of the specialised packed-row kernel (word-major planes of
+    // lattice rows 0..d-1, plane stride cp_stride chains)
     uint32_t *cp_out;      // anneal: checkpoint planes to write (nullable), base of checkpoint 0
     const uint32_t *cp_in; // replay: packed rows to start from instead of src (nullable)
     int64_t cp_stride;     // chains per word plane
@@ -155,14 +155,14 @@ __device__ __forceinline__ ChainJob batch_job(const GroupArgs &G, int64_t unit, 
     j.cp_out = replay ? nullptr : G.cp_rows;
     j.cp_in = nullptr;
     j.cp_stride = G.n_chains;
-    j.cp_words = G.plan->row_words;
+    j.cp_words = G.plan->static_words;
     j.t0 = 0;
     if (replay && G.cp_rows && j.target > 0) {
         // start from the last checkpoint at or before the sweep of the target phase
         const int t_target = (j.target - 1) >> 2;
         const int n_cp = t_target / G.cp_every;
         if (n_cp > 0) {
-            j.cp_in = G.cp_rows + (int64_t)(n_cp - 1) * G.plan->d * G.plan->row_words * G.n_chains + ci;
+            j.cp_in = G.cp_rows + (int64_t)(n_cp - 1) * G.plan->d * G.plan->static_words * G.n_chains + ci;
             j.t0 = n_cp * G.cp_every;
         }
     }
@@ -211,10 +211,10 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
     for (int q = gl; q < nq; q += (1 << LOGG)) {
         uint32_t v;
         if (J.cp_in) {
-            // checkpoint rows (rotated lattice): row y of qubit q, 2 bits at padded column x + 1
-            const int y = q / dd, x = q - y * dd, X = x + 1;
-            const int64_t plane = (int64_t)y * J.cp_words + (X >> 4);
-            v = J.active ? (J.cp_in[plane * J.cp_stride] >> (2 * (X & 15))) & 3u : 0u;
+            // checkpoint rows (rotated lattice): qubit x of row y at bits 2x, 2x + 1
+            const int y = q / dd, x = q - y * dd;
+            const int64_t plane = (int64_t)y * J.cp_words + (x >> 4);
+            v = J.active ? (J.cp_in[plane * J.cp_stride] >> (2 * (x & 15))) & 3u : 0u;
         } else {
             v = J.active ? (J.src[q] & 3u) : 0u;
             if (!J.resume) {
@@ -592,17 +592,20 @@ __device__ __forceinline__ uint32_t lt_mask(uint32_t u, uint32_t thr)
     return (uint32_t)((int32_t)__builtin_amdgcn_bitop3_b32(u, thr, u - thr, 0x8E) >> 31);
 }
 
-// Words per padded row of the specialised kernel: one for d <= 13, two for d <= 29.
+// Rows of the specialised kernel: the d lattice rows only, qubit x of a row
+// at bits 2x, 2x + 1, and one spare column (x = d) at the right end that the
+// right-boundary generators may flip (its bits are never read as a qubit).
+// 2(d + 1) bits: one word for d <= 15, two for d <= 31.
 template <int D>
 struct StaticRows {
-    static constexpr int NW = 2 * (D + 2) <= 32 ? 1 : 2;
-    static constexpr int NR = D + 2;
-    static constexpr int N = NR * NW;   // registers per chain; word w of row Y at [Y * NW + w]
+    static constexpr int NW = 2 * (D + 1) <= 32 ? 1 : 2;
+    static constexpr int N = D * NW;   // registers per chain; word w of lattice row y at [y * NW + w]
 };
 
 // Bits [BO - S, BO - S + 31] of row word pair (hi:lo) of a row, for a shift
-// S in [0, 5]: the nibble at BO lands at bit S.  A nibble may straddle the
-// two words of a row (BO = 30).
+// S in [0, 5]: the nibble at BO lands at bit S.  BO = -2 is the nibble of
+// the left-boundary generators, whose missing column reads as zero.  A
+// nibble may straddle the two words of a row (BO = 30).
 template <int NW, int BO, int S>
 __device__ __forceinline__ uint32_t row_bits(const uint32_t *w)
 {
@@ -613,14 +616,6 @@ __device__ __forceinline__ uint32_t row_bits(const uint32_t *w)
     } else {
         return __builtin_amdgcn_alignbit(w[1], w[0], BO - S);
     }
-}
-
-// Pattern of the generator at nibble offset BO of rows Y, Y + 1, times two:
-// bits 1-4 from row Y, bits 5-8 from row Y + 1.
-template <int NW, int BO>
-__device__ __forceinline__ uint32_t pattern_x2(const uint32_t *ra, const uint32_t *rb)
-{
-    return (row_bits<NW, BO, 5>(rb) & 0x1E0u) | (row_bits<NW, BO, 1>(ra) & 0x1Eu);
 }
 
 // A 32-bit constant materialised in a scalar register where it is used.
@@ -634,11 +629,12 @@ __device__ __forceinline__ uint32_t sreg_const()
     return v;
 }
 
-// w ^= (MASK << BO) & sel over the words of one row (MASK: 4 bits)
+// w ^= (MASK << BO) & sel over the words of one row (MASK: 4 bits; for
+// BO = -2 the bits of the missing column drop out)
 template <int NW, int BO, uint32_t MASK>
 __device__ __forceinline__ void row_flip_static(uint32_t *w, uint32_t sel)
 {
-    constexpr uint64_t m = (uint64_t)MASK << BO;
+    constexpr uint64_t m = BO >= 0 ? (uint64_t)MASK << BO : (uint64_t)(MASK >> -BO);
     if constexpr (NW == 1) {
         w[0] = xor_and(w[0], (uint32_t)m, sel);
     } else {
@@ -655,15 +651,21 @@ __device__ __forceinline__ void static_move(uint32_t (&r)[StaticRows<D>::N], uin
     constexpr RotSchedule<D> S{};
     constexpr RotGen g = S.g[K][4 * B + W];
     if constexpr (g.shp != 5) {
-        uint32_t *ra = r + g.Y * NW, *rb = r + (g.Y + 1) * NW;
-        const uint32_t pat2 = pattern_x2<NW, g.bo>(ra, rb);
+        // cell (i, j): lattice rows j (slots 0, 1) and j + 1 (slots 2, 3),
+        // nibble of columns i, i + 1 at bit 2i; rows -1 and d do not exist
+        constexpr int ya = g.Y - 1, BO = g.bo - 2;
+        constexpr bool has_a = ya >= 0, has_b = ya + 1 < D;
+        uint32_t *ra = r + (has_a ? ya : 0) * NW, *rb = r + (has_b ? ya + 1 : 0) * NW;
+        uint32_t pat2 = 0;
+        if constexpr (has_a) pat2 |= row_bits<NW, BO, 1>(ra) & 0x1Eu;
+        if constexpr (has_b) pat2 |= row_bits<NW, BO, 5>(rb) & 0x1E0u;
         const uint32_t off = *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(lut_s) +
                                                                  512u * g.shp + pat2);
         const uint4 e = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint8_t *>(et_s) + off);
         // all ones on accepting lanes: u < threshold, or dE <= 0
         const uint32_t sel = lt_mask(u, e.y) | e.z;
-        row_flip_static<NW, g.bo, 6u>(ra, sel);   // X_left | Z_up
-        row_flip_static<NW, g.bo, 9u>(rb, sel);   // Z_down | X_right
+        if constexpr (has_a) row_flip_static<NW, BO, 6u>(ra, sel);   // X_left | Z_up
+        if constexpr (has_b) row_flip_static<NW, BO, 9u>(rb, sel);   // Z_down | X_right
         acc += (int32_t)(e.x & sel);
     }
 }
@@ -695,7 +697,6 @@ template <int D>
 __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
                                  uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s, int cp_interval)
 {
-    constexpr int NR = D + 2;
     constexpr int NW = StaticRows<D>::NW;
     constexpr int NB = RotSchedule<D>::MP / 4;
     using Blocks = std::make_integer_sequence<int, NB>;
@@ -714,24 +715,24 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
     uint32_t r[StaticRows<D>::N];
     int32_t E = 0;
 #pragma unroll
-    for (int Y = 0; Y < NR; ++Y) {
+    for (int y = 0; y < D; ++y) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             uint32_t word = 0;
-            if (Y >= 1 && Y <= D && J.active) {
-                // columns X = 16 w .. 16 w + 15 of the padded row (qubit x = X - 1);
-                // not unrolled: a fully unrolled row would keep every byte load in flight
+            if (J.active) {
+                // qubits x = 16 w .. 16 w + 15 of lattice row y; not unrolled:
+                // a fully unrolled row would keep every byte load in flight
 #pragma unroll 1
-                for (int x = max(0, 16 * w - 1); x < min(D, 16 * w + 15); ++x) {
-                    const int q = (Y - 1) * D + x;
+                for (int x = 16 * w; x < min(D, 16 * w + 16); ++x) {
+                    const int q = y * D + x;
                     uint32_t v = J.src[q] & 3u;
                     if (use_x) v ^= pl->lx[q];
                     if (use_z) v ^= pl->lz[q];
-                    word |= v << (2 * (x + 1 - 16 * w));
+                    word |= v << (2 * (x - 16 * w));
                     E += weight_of(W, v);
                 }
             }
-            r[Y * NW + w] = word;
+            r[y * NW + w] = word;
         }
     }
     int32_t Emin = E, stop = 0;
@@ -771,7 +772,7 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
         if (cp_every && t < t_end && J.active) {
             uint32_t *cp = J.cp_out + (int64_t)(t / cp_every - 1) * (D * NW) * J.cp_stride + ci0 + lane;
 #pragma unroll
-            for (int i = 0; i < D * NW; ++i) cp[i * J.cp_stride] = r[NW + i];   // rows 1..D
+            for (int i = 0; i < D * NW; ++i) cp[i * J.cp_stride] = r[i];
         }
     }
     if (J.active) {
@@ -781,12 +782,12 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
         if (J.states) {
             uint8_t *dst = J.states + (size_t)J.ci * (D * D);
 #pragma unroll
-            for (int Y = 1; Y <= D; ++Y)
+            for (int y = 0; y < D; ++y)
 #pragma unroll
                 for (int w = 0; w < NW; ++w)
 #pragma unroll 1
-                    for (int x = max(0, 16 * w - 1); x < min(D, 16 * w + 15); ++x)
-                        dst[(Y - 1) * D + x] = (uint8_t)((r[Y * NW + w] >> (2 * (x + 1 - 16 * w))) & 3u);
+                    for (int x = 16 * w; x < min(D, 16 * w + 16); ++x)
+                        dst[y * D + x] = (uint8_t)((r[y * NW + w] >> (2 * (x - 16 * w))) & 3u);
         }
     }
 }
@@ -899,9 +900,9 @@ __device__ __forceinline__ void static_rows_body(const AnnealArgs &A)
 // Occupancy target of the specialised kernels (VGPR budget 512 / waves):
 // eight wavefronts per SIMD hides the LDS and multiply latencies best
 // (measured at d = 11: eight waves with a few spills beat seven without);
-// with two words per row the state alone takes 2 (d + 2) registers, so
+// with two words per row (d >= 17) the state alone takes 2d registers, so
 // larger lattices run fewer wavefronts.
-constexpr int static_waves(int d) { return d <= 13 ? 8 : d <= 15 ? 6 : d <= 21 ? 5 : 4; }
+constexpr int static_waves(int d) { return d <= 15 ? 8 : d <= 21 ? 5 : 4; }
 
 template <int D>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(static_waves(D), static_waves(D))))
@@ -992,7 +993,7 @@ typedef void (*ServeKernel)(const ServeTask *, uint32_t, uint32_t);
 
 // The specialised kernels live in several translation units (compiled in
 // parallel); each returns its kernels for the distances it holds, else NULL.
-#define XZZX_STATIC_PARTS(X) X(a) X(b) X(c) X(d) X(e) X(f) X(g)
+#define XZZX_STATIC_PARTS(X) X(a) X(b) X(c) X(d) X(e) X(f) X(g) X(h)
 #define XZZX_DECLARE_PART(P) \
     AnnealKernel static_rows_kernel_##P(int d, bool plain); \
     ServeKernel static_serve_kernel_##P(int d);

@@ -233,6 +233,7 @@ static bool static_schedule_matches(int d, const std::vector<uint32_t> &rowface,
     case 25: return schedule_matches<25>(rowface, mpad);
     case 27: return schedule_matches<27>(rowface, mpad);
     case 29: return schedule_matches<29>(rowface, mpad);
+    case 31: return schedule_matches<31>(rowface, mpad);
     default: return false;
     }
 }
@@ -430,7 +431,7 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     // multiple of 4 entries so a block of four is read at once
     const int mpad = 4 * ((L.per_class + 3) / 4);
     std::vector<uint32_t> rowface(4 * mpad, 0);
-    if (P.row_words) {
+    if (L.layout == XZZX_ROTATED && L.d <= kStaticMaxD) {
         // padding entries: the null shape on the nibble at column d+1 of rows
         // 0 and 1, which holds only padding bits (never a qubit)
         const uint32_t pad = 0u | ((2u * (uint32_t)(L.d + 1)) << 8) | ((uint32_t)null_shape << 16);
@@ -445,10 +446,12 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     // the specialised packed-row kernel applies when its compile-time
     // schedule is exactly this plan's table
     P.static_d = 0;
-    if (P.row_words && L.layout == XZZX_ROTATED && L.d >= kStaticMinD && L.d <= kStaticMaxD &&
+    if (L.layout == XZZX_ROTATED && L.d >= kStaticMinD && L.d <= kStaticMaxD &&
         nranks <= kStaticRanks && static_schedule_matches(L.d, rowface, mpad))
         P.static_d = L.d;
     P.static_ok = P.static_d ? 1 : 0;
+    // its rows hold the d qubits and one spare column: 2(d + 1) bits
+    P.static_words = P.static_ok ? (2 * (L.d + 1) + 31) / 32 : 0;
     std::vector<Desc> desc(4 * L.per_class), fdesc(L.nstab);
     for (int f = 0; f < L.nstab; ++f) fdesc[f] = pack_desc(L, f, shape_of_face[f]);
     for (int k = 0; k < 4; ++k)
@@ -516,7 +519,8 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     h.d = L.d;
     h.row_words = P.row_words;
     h.rows = L.d + 2;
-    P.use_rows = P.row_words ? 1 : 0;
+    h.static_words = P.static_words;
+    P.use_rows = (P.row_words || P.static_ok) ? 1 : 0;
     h.rowface = reinterpret_cast<const uint32_t *>(base + o_rowface);
     std::memcpy(h.W, w, sizeof(h.W));
     h.desc = reinterpret_cast<const Desc *>(base + o_desc);
@@ -728,12 +732,19 @@ int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel)
 {
     if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
     if (kernel == XZZX_KERNEL_AUTO) {
-        plan->P.use_rows = plan->P.row_words ? 1 : 0;
+        plan->P.use_rows = (plan->P.row_words || plan->P.static_ok) ? 1 : 0;
         plan->P.static_d = plan->P.static_ok ? plan->P.lat.d : 0;
-    } else if (kernel == XZZX_KERNEL_ROWS || kernel == XZZX_KERNEL_ROWS_GENERIC) {
-        if (!plan->P.row_words) { set_error("the packed-row kernel needs a rotated lattice with d <= 29"); return XZZX_EINVAL; }
+    } else if (kernel == XZZX_KERNEL_ROWS) {
+        if (!plan->P.row_words && !plan->P.static_ok) {
+            set_error("the packed-row kernel needs a rotated lattice with d <= 31");
+            return XZZX_EINVAL;
+        }
         plan->P.use_rows = 1;
-        plan->P.static_d = (kernel == XZZX_KERNEL_ROWS && plan->P.static_ok) ? plan->P.lat.d : 0;
+        plan->P.static_d = plan->P.static_ok ? plan->P.lat.d : 0;
+    } else if (kernel == XZZX_KERNEL_ROWS_GENERIC) {
+        if (!plan->P.row_words) { set_error("the generic packed-row kernel needs a rotated lattice with d <= 29"); return XZZX_EINVAL; }
+        plan->P.use_rows = 1;
+        plan->P.static_d = 0;
     } else if (kernel == XZZX_KERNEL_BYTES) {
         plan->P.use_rows = 0;
     } else {
@@ -765,7 +776,7 @@ int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain)
     if (plan->P.lds_bytes_anneal(g) > 65536) { set_error("chains per wavefront do not fit in LDS"); return XZZX_ERANGE; }
     plan->P.lanes = g;
     plan->P.hdev.lanes = g;
-    plan->P.use_rows = (lanes_per_chain == 0 && plan->P.row_words) ? 1 : 0;
+    plan->P.use_rows = (lanes_per_chain == 0 && (plan->P.row_words || plan->P.static_ok)) ? 1 : 0;
     if (hipMemcpy(&plan->P.ddev->lanes, &g, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
         set_error("plan update failed");
         return XZZX_EDEVICE;

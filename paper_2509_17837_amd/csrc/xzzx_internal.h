@@ -34,11 +34,13 @@ struct Desc {
 constexpr int kRotShapeMasks[6] = {15, 12, 10, 5, 3, 0};
 
 // Compile-time generator schedule of the rotated lattice at distance D for
-// the packed-row kernel specialised to D (one 32-bit word per row for
-// D <= 13, two for D <= 29): for colour class k and rank m, the row Y = j + 1 of cell (i, j),
-// the bit offset 2(i + 1) of its nibble and its canonical shape.  Ranks run
-// row-major over (j, i), as in the plan; each class is padded to a multiple
-// of four with null generators on the padding nibble of rows 0 and 1.
+// the packed-row kernel specialised to D: for colour class k and rank m, the
+// row Y = j + 1 of cell (i, j) and the bit offset 2(i + 1) of its nibble in
+// the padded grid of the generic packed-row kernel (rows and columns -1..D),
+// and its canonical shape.  This is the plan's own table, against which the
+// host checks it.  Ranks run row-major over (j, i), as in the plan; each
+// class is padded to a multiple of four with null generators on the padding
+// nibble of rows 0 and 1.
 struct RotGen {
     uint8_t Y, bo, shp;
 };
@@ -78,11 +80,14 @@ struct RotSchedule {
 
 // Distances with a specialised packed-row kernel, and the largest number of
 // distinct move energies its static tables hold.
-constexpr int kStaticMinD = 3, kStaticMaxD = 29;
+constexpr int kStaticMinD = 3, kStaticMaxD = 31;
 constexpr int kStaticRanks = 128;
-// sweeps between the specialised kernel's state checkpoints (the replay of a
-// syndrome's best chain starts from the last one before its E_min phase)
+// The specialised kernel's state checkpoints (the replay of a syndrome's
+// best chain starts from the last one before its E_min phase): every
+// kCheckpointEvery sweeps, or sparser so that a chain keeps at most
+// kMaxCheckpoints of them.
 constexpr int kCheckpointEvery = 256;
+constexpr int kMaxCheckpoints = 8;
 
 // Host-side lattice: geometry shared by every plan built on it.
 struct Lattice {
@@ -104,6 +109,7 @@ struct PlanDev {
     int layout, d;
     int row_words;                 // packed-row kernel: 32-bit words per lattice row (0 = unavailable)
     int rows;                      // rows of the padded grid (d + 2)
+    int static_words;              // specialised kernel: words per unpadded row (0 = unavailable)
     int32_t W[4];
     const uint32_t *rowface;       // [4][4*nblk] row | bit offset << 8 | shape << 16 (packed-row kernel)
     const Desc *desc;              // [4][M] by (class, rank)
@@ -133,6 +139,7 @@ struct Plan {
     int use_rows = 0;              // 1: annealing runs on the packed-row kernel
     int static_d = 0;              // d if the packed-row kernel specialised to d applies, else 0
     int static_ok = 0;             // the plan's tables match the specialised schedule
+    int static_words = 0;          // words per row of the specialised kernel's rows (2(d+1) bits)
     int nranks() const { return (int)dE.size(); }
     int device = 0;
     void *dmem = nullptr;          // device allocation holding every table

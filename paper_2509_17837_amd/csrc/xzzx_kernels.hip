@@ -10,7 +10,8 @@
 //                  (rotated lattices, d <= 29).  Both are persistent: wavefronts
 //                  pull tasks from an atomic queue spanning every syndrome group
 //                  of the launch.  The packed-row kernels specialised to one
-//                  distance are in xzzx_device.h / xzzx_static_*.hip.
+//                  distance (every odd d <= 31) are in xzzx_device.h /
+//                  xzzx_static_*.hip.
 //   k_replay<L>    re-runs each syndrome's best chain up to the phase of its
 //                  minimum (from a checkpoint where the specialised kernel left
 //                  one) and stores that state: the recovery.
@@ -508,12 +509,20 @@ static bool uses_static(const xzzx_group &g, int64_t unit_offset)
     return P.use_rows && P.static_d && (4 * g.n_rep) % kWave == 0 && unit_offset % kWave == 0;
 }
 
+// Sweeps between the checkpoints of a plan: kCheckpointEvery, or the least
+// interval that leaves at most kMaxCheckpoints before the last sweep.
+static int checkpoint_interval(const Plan &P)
+{
+    const int spread = (P.n_sweeps - 1 + kMaxCheckpoints - 1) / kMaxCheckpoints;
+    return std::max(kCheckpointEvery, spread);
+}
+
 // Checkpoints a specialised group keeps: the states at the start of sweeps
-// kCheckpointEvery, 2 kCheckpointEvery, ... before the last sweep.
+// c, 2c, ... before the last sweep, for c = checkpoint_interval.
 static int checkpoints_of(const xzzx_group &g)
 {
     if (!uses_static(g, 0) || g.plan->P.n_sweeps <= 0) return 0;
-    return (g.plan->P.n_sweeps - 1) / kCheckpointEvery;
+    return (g.plan->P.n_sweeps - 1) / checkpoint_interval(g.plan->P);
 }
 
 static size_t group_ws_bytes(const xzzx_group &g, bool decode)
@@ -528,7 +537,7 @@ static size_t group_ws_bytes(const xzzx_group &g, bool decode)
     if (!g.d_chain_stop) b += align256(nc * 4);
     if (!g.d_chain_e) b += align256(nc * 4);
     if (!g.d_best_chain) b += align256(ns * 4);
-    b += align256((size_t)checkpoints_of(g) * P.lat.d * P.row_words * nc * 4);
+    b += align256((size_t)checkpoints_of(g) * P.lat.d * P.static_words * nc * 4);
     return b;
 }
 
@@ -546,7 +555,7 @@ static GroupWs carve_group(const xzzx_group &g, bool decode, uint8_t *&p)
     w.efin = g.d_chain_e ? g.d_chain_e : reinterpret_cast<int32_t *>(take(nc * 4));
     w.best_chain = g.d_best_chain ? g.d_best_chain : reinterpret_cast<int32_t *>(take(ns * 4));
     const int ncp = checkpoints_of(g);
-    w.cp_rows = ncp ? reinterpret_cast<uint32_t *>(take((size_t)ncp * P.lat.d * P.row_words * nc * 4)) : nullptr;
+    w.cp_rows = ncp ? reinterpret_cast<uint32_t *>(take((size_t)ncp * P.lat.d * P.static_words * nc * 4)) : nullptr;
     return w;
 }
 
@@ -645,7 +654,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         // checkpoints: written by the specialised kernel, read by the replay
         const bool cp = checkpoints_of(g) > 0 && (static_d || replay);
         G.cp_rows = cp ? ws[i].cp_rows : nullptr;
-        G.cp_every = cp ? kCheckpointEvery : 0;
+        G.cp_every = cp ? checkpoint_interval(P) : 0;
         G.n_chains = g.n_syn * 4 * g.n_rep;
         G.unit_offset = unit_offset;
         const int64_t units = units_of(i);
@@ -761,7 +770,7 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         const Plan &P = groups[i].plan->P;
         if (mode != AnnealMode::Replay && uses_static(groups[i], unit_offset)) static_sel[P.static_d].push_back(i);
         else if (mode == AnnealMode::Replay && checkpoints_of(groups[i]) > 0) replay_cp.push_back(i);
-        else if (mode != AnnealMode::Replay && P.use_rows) rows_sel.push_back(i);
+        else if (mode != AnnealMode::Replay && P.use_rows && P.row_words) rows_sel.push_back(i);
         else bytes_sel[log2_int(P.lanes)].push_back(i);
     }
     if (mode == AnnealMode::Replay) {

@@ -76,7 +76,7 @@ extern "C" int xzzx_plan_autotune(xzzx_plan *plan, int n_rep, int n_syn, int pro
     if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) { set_error("events"); rc = XZZX_EDEVICE; }
     for (int cand = 0; cand < 8 && !rc; ++cand) {
         if (cand == 0) {
-            if (!P.row_words) continue;
+            if (!P.row_words && !P.static_ok) continue;
             probe->P.use_rows = 1;
         } else {
             const int lanes = 1 << (cand - 1);

@@ -113,12 +113,13 @@ def test_row_and_byte_kernels_agree(d):
         gpu_plan(Problem(1, 5, 0.2, 10.0, 1, 1, 1)).set_kernel(X.KERNEL_ROWS)
 
 
-@pytest.mark.parametrize("d", list(range(3, 30, 2)))
+@pytest.mark.parametrize("d", list(range(3, 32, 2)))
 def test_specialised_row_kernel(d):
     """The packed-row kernel specialised to d (registers for rows, compile-time
     schedule) runs when every 64-chain task lies in one syndrome; its chains,
-    final states and results equal the generic packed-row kernel's, the
-    byte-state kernel's and the oracle's, in the persistent and plain forms."""
+    final states and results equal the generic packed-row kernel's (d <= 29),
+    the byte-state kernel's and the oracle's, in the persistent and plain
+    forms.  Rows take one word up to d = 15 and two words up to d = 31."""
     R = 16 if d > 9 else 32
     prob = Problem(0, d, 0.2, 10.0, 3 if d <= 21 else 2, R, 24 if d <= 21 else 12, seed=700 + d)
     ref = prob.oracle_decode()
@@ -126,32 +127,40 @@ def test_specialised_row_kernel(d):
     assert plan.info()["kernel"] == X.KERNEL_ROWS
     compare_decode(prob, run_decode(prob, plan), ref)
     compare_decode(prob, run_decode(prob, plan, flags=X.FLAG_PLAIN), ref)
-    plan.set_kernel(X.KERNEL_ROWS_GENERIC)
-    assert plan.info()["kernel"] == X.KERNEL_ROWS_GENERIC
-    compare_decode(prob, run_decode(prob, plan), ref)
+    if d <= 29:
+        plan.set_kernel(X.KERNEL_ROWS_GENERIC)
+        assert plan.info()["kernel"] == X.KERNEL_ROWS_GENERIC
+        compare_decode(prob, run_decode(prob, plan), ref)
+    else:
+        with pytest.raises(X.XzzxError):
+            plan.set_kernel(X.KERNEL_ROWS_GENERIC)
     plan.set_kernel(X.KERNEL_BYTES)
     compare_decode(prob, run_decode(prob, plan), ref)
     plan.set_kernel(X.KERNEL_AUTO)
     assert plan.info()["kernel"] == X.KERNEL_ROWS
 
 
-@pytest.mark.parametrize("d,sweeps", [(7, 256), (7, 257), (7, 700), (19, 300)])
+@pytest.mark.parametrize("d,sweeps", [(7, 256), (7, 257), (7, 700), (7, 2100), (15, 300), (19, 300), (31, 300)])
 def test_replay_from_checkpoints(d, sweeps):
     """Groups on the specialised kernel keep a state checkpoint every 256
-    sweeps; each syndrome's recovery is replayed from the last checkpoint
-    before its E_min phase (256 sweeps: none; 257: one, at the start of the
-    last sweep; 700: two; d = 19 stores two words per row)."""
-    prob = Problem(0, d, 0.2, 10.0, 4 if d < 15 else 2, 16, sweeps, seed=800 + sweeps)
+    sweeps, or at most eight evenly spaced; each syndrome's recovery is
+    replayed from the last checkpoint before its E_min phase (256 sweeps:
+    none; 257: one, at the start of the last sweep; 700: two; 2100: seven,
+    263 sweeps apart; d = 15 stores one word per row, d = 19 and d = 31
+    two)."""
+    prob = Problem(0, d, 0.2, 10.0, 4 if d < 15 else 2, 16, sweeps, seed=800 + sweeps + d)
     plan = gpu_plan(prob)
     assert plan.info()["kernel"] == X.KERNEL_ROWS
     compare_decode(prob, run_decode(prob, plan), prob.oracle_decode())
 
 
 def test_specialised_kernel_not_applicable():
-    """d = 31 (rows of three words) and the planar layout have no packed-row
-    kernel at all."""
-    assert gpu_plan(Problem(0, 31, 0.2, 10.0, 1, 1, 1)).info()["kernel"] == X.KERNEL_BYTES
+    """The planar layout has no packed-row kernel at all; at d = 31 a replica
+    count that splits 64-chain tasks over syndromes runs on the byte-state
+    kernel (there is no generic packed-row kernel at d = 31)."""
     assert gpu_plan(Problem(1, 5, 0.2, 10.0, 1, 1, 1)).info()["kernel"] == X.KERNEL_BYTES
+    prob = Problem(0, 31, 0.2, 10.0, 3, 5, 6, seed=931)
+    compare_decode(prob, run_decode(prob, gpu_plan(prob)), prob.oracle_decode())
 
 
 def test_autotuned_plan_matches_oracle():
