@@ -52,12 +52,28 @@ __device__ __forceinline__ int32_t weight_of(const int32_t W[4], uint32_t code)
     return code == 0 ? 0 : code == 1 ? W[1] : code == 2 ? W[2] : W[3];
 }
 
-// Sum over the G lanes of one chain (lanes c*G .. c*G+G-1 of the wavefront).
+// Sum over the G = 2^LOGG lanes of one chain (lanes c*G .. c*G+G-1 of the
+// wavefront), left in every one of them.  Each step doubles the group over
+// which every lane holds the sum: DPP quad permutations (pairs, quads), the
+// half-row and row mirrors (8 and 16 lanes: the mirrored lane lies in the
+// other half), then the row swaps across 16 and 32 lanes.  All VALU, no LDS
+// round trip (a shuffle would go through ds_bpermute), which matters on the
+// latency-bound serving path where a chain spans the whole wavefront.
 template <int LOGG>
 __device__ __forceinline__ int32_t chain_sum(int32_t v)
 {
-#pragma unroll
-    for (int s = 1; s < (1 << LOGG); s <<= 1) v += __shfl_xor(v, s, kWave);
+    if constexpr (LOGG >= 1) v += __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    if constexpr (LOGG >= 2) v += __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    if constexpr (LOGG >= 3) v += __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    if constexpr (LOGG >= 4) v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);  // row_mirror
+    if constexpr (LOGG >= 5) {
+        const auto p = __builtin_amdgcn_permlane16_swap((uint32_t)v, (uint32_t)v, false, false);
+        v = (int32_t)(p[0] + p[1]);
+    }
+    if constexpr (LOGG >= 6) {
+        const auto p = __builtin_amdgcn_permlane32_swap((uint32_t)v, (uint32_t)v, false, false);
+        v = (int32_t)(p[0] + p[1]);
+    }
     return v;
 }
 
@@ -92,6 +108,14 @@ struct ChainJob {
     int64_t cp_stride;     // chains per word plane
     int32_t cp_words;      // words per row of the checkpoint planes
     int32_t t0;            // first sweep to run (replay from a checkpoint)
+    // serving: the state at the start of this sweep range is stored to
+    // cp_start (nullable); if E_min improves within the range (or the range
+    // starts at sweep 0), cp_meta[ci] (nullable) is set to cp_commit, which
+    // names that stored state and its sweep for a later replay
+    uint8_t *cp_start;
+    int32_t *cp_meta;
+    int32_t cp_commit;
+    bool raw;              // replay: src holds the chain's own state (logical already applied)
 };
 
 struct GroupArgs {
@@ -157,6 +181,10 @@ __device__ __forceinline__ ChainJob batch_job(const GroupArgs &G, int64_t unit, 
     j.cp_stride = G.n_chains;
     j.cp_words = G.plan->static_words;
     j.t0 = 0;
+    j.cp_start = nullptr;
+    j.cp_meta = nullptr;
+    j.cp_commit = -1;
+    j.raw = false;
     if (replay && G.cp_rows && j.target > 0) {
         // start from the last checkpoint at or before the sweep of the target phase
         const int t_target = (j.target - 1) >> 2;
@@ -217,10 +245,11 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
             v = J.active ? (J.cp_in[plane * J.cp_stride] >> (2 * (x & 15))) & 3u : 0u;
         } else {
             v = J.active ? (J.src[q] & 3u) : 0u;
-            if (!J.resume) {
+            if (!J.resume && !J.raw) {
                 if (use_x) v ^= pl->lx[q];
                 if (use_z) v ^= pl->lz[q];
             }
+            if (J.cp_start) J.cp_start[q] = (uint8_t)v;
         }
         st[(q << LOGC) + c] = (uint8_t)v;
         part += weight_of(W, v);
@@ -247,9 +276,24 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
         last_phase = tmax;
     }
 
+    // the thresholds of sweep t + 1 are fetched from HBM while sweep t runs
+    constexpr int kThrPerLane = (kMaxRanks + kWave - 1) / kWave;
+    uint32_t thr_next[kThrPerLane];
+    auto fetch_thr = [&](int t) {
+#pragma unroll
+        for (int j = 0; j < kThrPerLane; ++j) {
+            const int i = lane + j * kWave;
+            thr_next[j] = (t < t_end && i < nranks) ? pl->thr[(size_t)t * nranks + i] : 0u;
+        }
+    };
+    fetch_thr(t_begin);
+
     for (int t = t_begin; t < t_end && 4 * t < last_phase; ++t) {
-        for (int i = lane; i < nranks; i += kWave) et_s[i].y = (int)pl->thr[(size_t)t * nranks + i];
+#pragma unroll
+        for (int j = 0; j < kThrPerLane; ++j)
+            if (lane + j * kWave < nranks) et_s[lane + j * kWave].y = (int)thr_next[j];
         wave_lds_fence();
+        fetch_thr(t + 1);
         for (int k = 0; k < 4; ++k) {
             const uint2 *dk = desc_s + k * M;
             int32_t acc_de = 0;
@@ -257,24 +301,37 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
                 const uint4 rnd = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
                                                 seed_lo, seed_hi);
                 const uint32_t uw[4] = {rnd.x, rnd.y, rnd.z, rnd.w};
+                // The four moves of a block act on disjoint qubits (one colour
+                // class), so all their loads are issued before any store; the
+                // block's tail beyond M repeats the class's last move, which is
+                // never applied.
+                uint2 dw[4];
+                uint32_t pat[4], rank[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) dw[w] = dk[min(4 * b + w, M - 1)];
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
-                    const int m = 4 * b + w;
-                    if (m >= M) break;
-                    const uint2 d = dk[m];
-                    const uint32_t a0 = ((d.x & 0xFFFFu) << LOGC) + c;
-                    const uint32_t a1 = ((d.x >> 16) << LOGC) + c;
-                    const uint32_t a2 = ((d.y & 0xFFFFu) << LOGC) + c;
-                    const uint32_t a3 = (((d.y >> 16) & 0x7FFu) << LOGC) + c;
-                    const uint32_t c0 = st[a0], c1 = st[a1], c2 = st[a2], c3 = st[a3];
-                    const uint32_t pat = c0 | (c1 << 2) | (c2 << 4) | (c3 << 6);
-                    const uint32_t rank = lut_s[((d.y >> 27) << 8) | pat];
-                    const int2 et = et_s[rank];
-                    if (rank < kneg || uw[w] < (uint32_t)et.y) {
-                        st[a0] = (uint8_t)(c0 ^ 2u);
-                        st[a1] = (uint8_t)(c1 ^ 1u);
-                        st[a2] = (uint8_t)(c2 ^ 1u);
-                        st[a3] = (uint8_t)(c3 ^ 2u);
+                    const uint2 d = dw[w];
+                    const uint32_t c0 = st[((d.x & 0xFFFFu) << LOGC) + c];
+                    const uint32_t c1 = st[((d.x >> 16) << LOGC) + c];
+                    const uint32_t c2 = st[((d.y & 0xFFFFu) << LOGC) + c];
+                    const uint32_t c3 = st[(((d.y >> 16) & 0x7FFu) << LOGC) + c];
+                    pat[w] = c0 | (c1 << 2) | (c2 << 4) | (c3 << 6);
+                }
+#pragma unroll
+                for (int w = 0; w < 4; ++w) rank[w] = lut_s[((dw[w].y >> 27) << 8) | pat[w]];
+                int2 ets[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) ets[w] = et_s[rank[w]];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int2 et = ets[w];
+                    if (4 * b + w < M && (rank[w] < kneg || uw[w] < (uint32_t)et.y)) {
+                        const uint2 d = dw[w];
+                        st[((d.x & 0xFFFFu) << LOGC) + c] = (uint8_t)((pat[w] & 3u) ^ 2u);
+                        st[((d.x >> 16) << LOGC) + c] = (uint8_t)(((pat[w] >> 2) & 3u) ^ 1u);
+                        st[((d.y & 0xFFFFu) << LOGC) + c] = (uint8_t)(((pat[w] >> 4) & 3u) ^ 1u);
+                        st[(((d.y >> 16) & 0x7FFu) << LOGC) + c] = (uint8_t)((pat[w] >> 6) ^ 2u);
                         acc_de += et.x;
                     }
                 }
@@ -291,6 +348,7 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
             J.emin[J.ci] = Emin;
             J.stop[J.ci] = stop;
             J.efin[J.ci] = E;
+            if (J.cp_meta && (t_begin == 0 || stop > 4 * t_begin)) J.cp_meta[J.ci] = J.cp_commit;
         }
         if (J.states) save_state(J.states + (size_t)J.ci * nq);
     }
@@ -405,6 +463,7 @@ __device__ inline void rows_core(const PlanDev *pl, const ChainJob &J, int t_beg
                         uint32_t v = J.src[q] & 3u;
                         if (use_x) v ^= pl->lx[q];
                         if (use_z) v ^= pl->lz[q];
+                        if (J.cp_start) J.cp_start[q] = (uint8_t)v;
                         word |= v << (2 * j);
                         E += weight_of(W, v);
                     }
@@ -491,6 +550,7 @@ __device__ inline void rows_core(const PlanDev *pl, const ChainJob &J, int t_beg
         J.emin[J.ci] = Emin;
         J.stop[J.ci] = stop;
         J.efin[J.ci] = E;
+        if (J.cp_meta && (t_begin == 0 || stop > 4 * t_begin)) J.cp_meta[J.ci] = J.cp_commit;
         if (J.states) {
             uint8_t *dst = J.states + (size_t)J.ci * nq;
             for (int q = 0; q < nq; ++q) {
@@ -728,6 +788,7 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
                     uint32_t v = J.src[q] & 3u;
                     if (use_x) v ^= pl->lx[q];
                     if (use_z) v ^= pl->lz[q];
+                    if (J.cp_start) J.cp_start[q] = (uint8_t)v;
                     word |= v << (2 * (x - 16 * w));
                     E += weight_of(W, v);
                 }
@@ -779,6 +840,7 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
         J.emin[J.ci] = Emin;
         J.stop[J.ci] = stop;
         J.efin[J.ci] = E;
+        if (J.cp_meta && (t_begin == 0 || stop > 4 * t_begin)) J.cp_meta[J.ci] = J.cp_commit;
         if (J.states) {
             uint8_t *dst = J.states + (size_t)J.ci * (D * D);
 #pragma unroll
@@ -941,6 +1003,32 @@ __device__ __forceinline__ ChainJob serve_job(const ServeTask &T, int slot, bool
     j.cp_stride = 0;
     j.cp_words = 0;
     j.t0 = 0;
+    // start states kept at sweep-range boundaries: buffer b of chain c at
+    // cp + (b nc + c) nq; cpm[c] = (sweep << 1) | b of the one a replay of
+    // the chain's E_min phase starts from, -1 for the references at sweep 0
+    j.cp_start = nullptr;
+    j.cp_meta = nullptr;
+    j.cp_commit = -1;
+    j.raw = false;
+    if (T.cpm) {
+        if (replay) {
+            const int32_t meta = T.cpm[c];
+            if (meta >= 0) {
+                j.src = T.cp + ((size_t)(meta & 1) * nc + c) * nq;
+                j.raw = true;
+                j.t0 = meta >> 1;
+            }
+        } else if (j.active) {
+            j.cp_meta = T.cpm;
+            if (T.t_begin > 0) {
+                // the buffer not named by the chain's current entry
+                const int32_t meta = T.cpm[c];
+                const int b = meta >= 0 ? 1 - (meta & 1) : 0;
+                j.cp_start = T.cp + ((size_t)b * nc + c) * nq;
+                j.cp_commit = (T.t_begin << 1) | b;
+            }
+        }
+    }
     return j;
 }
 
@@ -959,7 +1047,7 @@ __device__ __forceinline__ void serve_kernel_body(const ServeTask *tasks, uint32
         load_plan_tables(pl, smem);
         const int lg = T.log_lanes;
         const ChainJob J = serve_job(T, threadIdx.x >> lg, REPLAY);
-        const int tb = REPLAY ? 0 : T.t_begin;
+        const int tb = REPLAY ? J.t0 : T.t_begin;
         const int te = REPLAY ? pl->n_sweeps : T.t_end;
         switch (lg) {
         case 0: bytes_core<0, REPLAY>(pl, J, tb, te, seed_lo, seed_hi, smem); break;

@@ -166,6 +166,8 @@ struct ServeTask {
     int32_t t_begin, t_end;  // sweep range; t_begin == 0 starts from the references
     int32_t log_lanes;       // byte-state core: lanes per chain
     int32_t row_words;       // packed-row core: words per row
+    uint8_t *cp;             // chain states at range starts [2][4 n_rep][nq] (nullable)
+    int32_t *cpm;            // per chain: (sweep << 1) | buffer of the replay start, -1: references
 };
 
 // Serving-loop finish entry: per-coset reduction of one finished request,
