@@ -96,6 +96,9 @@ def parse():
     ap.add_argument("--lanes", type=int, default=0,
                     help="most lanes per chain the server may use (--serve; 0: library default, 1: plan kernels)")
     ap.add_argument("--waves", type=int, default=0, help="wave budget per serving slice (--serve; 0: default)")
+    ap.add_argument("--by-distance", action="store_true",
+                    help="annealing rate of the default kernel for each odd d in --distances")
+    ap.add_argument("--distances", default="11,13,15,17,21,25,29,31")
     return ap.parse_args()
 
 
@@ -114,6 +117,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     if args.serve:
         return serve_bench(args)
+    if args.by_distance:
+        return distance_bench(args)
     wl = inputs.WORKLOADS[args.workload]
     seeds = inputs.seeds(args.workload)
     sched_kind = inputs.SCHEDULE_KIND[wl["schedule"][0]]
@@ -343,6 +348,52 @@ def cpu_baseline(args, wl, specs, plans, syn0, uid0, outs, R, sweeps, gs, as_):
                   np.array_equal(outs[g].recovery[i].cpu().numpy(), r["recovery"]))
     out["bitexact_with_gpu"] = f"{ok}/{n}"
     return out
+
+
+def distance_bench(args):
+    """Annealing-stage rate by lattice distance: rotated lattice, p = 0.15,
+    eta = 10, 16 replicas (one 64-chain task per syndrome), 200 sweeps
+    geometric 0.05->10, enough syndromes for several tasks per wavefront
+    slot; the greedy stage runs once, untimed."""
+    import torch
+
+    from paper_2509_17837_amd import _lib as X
+    from paper_2509_17837_amd import decoder as D
+    from paper_2509_17837_amd import inputs
+
+    p, eta, R, sweeps = 0.15, 10.0, 16, 200
+    beta = D.schedule(inputs.SCHEDULE_KIND["geometric"], 0.05, 10.0, sweeps)
+    kernels = {X.KERNEL_ROWS: "rows", X.KERNEL_ROWS_GENERIC: "rows_generic", X.KERNEL_BYTES: "bytes"}
+    rows = []
+    for d in [int(x) for x in args.distances.split(",")]:
+        lat = D.Lattice(X.ROTATED, d)
+        w, wg = D.weights(p, D.noise(p, eta))
+        plan = D.Plan(lat, w, wg, beta)
+        n_syn = 32768 if d <= 21 else 16384
+        err = inputs.sample_errors(n_syn, lat.nq, inputs.channel(p, eta), 1100 + d)
+        syn = D.syndrome(plan, torch.from_numpy(np.ascontiguousarray(err)).cuda())
+        uid = torch.from_numpy(inputs.sample_uids(n_syn).view(np.int32)).cuda()
+        g, _ = D.make_group(plan, R, uid, syn=syn)
+        ws = D.decode_groups([g], 1, 2, flags=X.STAGE_GREEDY)
+        times = []
+        for _ in range(args.warmup + args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            D.decode_groups([g], 1, 2, flags=X.STAGE_ANNEAL, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times[args.warmup:]))
+        attempts = n_syn * 4 * R * sweeps * lat.nstab
+        rows.append({"d": d, "syndromes": n_syn, "anneal_ms": ms, "attempts_per_s": attempts / ms * 1e3,
+                     "kernel": kernels.get(plan.info()["kernel"], "?")})
+        print(f"[by-distance] d={d}: {ms:.2f} ms, {attempts / ms * 1e3:.4g} attempts/s ({rows[-1]['kernel']})",
+              file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "stabilizer-flip attempts/s by distance (annealing stage)", "unit": "attempts/s",
+                      "n_gpus": 1, "dtype": "int32", "data": "synthetic",
+                      "config": {"workload": f"rotated XZZX, p={p}, eta={eta}, {R} replicas, {sweeps} sweeps "
+                                             f"geometric 0.05->10"},
+                      "distances": rows}), flush=True)
 
 
 def serve_bench(args):

@@ -115,6 +115,12 @@ struct ChainJob {
     uint8_t *cp_start;
     int32_t *cp_meta;
     int32_t cp_commit;
+    // the byte-state core also stores states inside the range: buffer b of
+    // the chain at cp_base + b cp_bstride; cp_meta0 = the chain's entry at
+    // the range start (-1: the references at sweep 0)
+    uint8_t *cp_base;
+    int64_t cp_bstride;
+    int32_t cp_meta0;
     bool raw;              // replay: src holds the chain's own state (logical already applied)
 };
 
@@ -184,6 +190,9 @@ __device__ __forceinline__ ChainJob batch_job(const GroupArgs &G, int64_t unit, 
     j.cp_start = nullptr;
     j.cp_meta = nullptr;
     j.cp_commit = -1;
+    j.cp_base = nullptr;
+    j.cp_bstride = 0;
+    j.cp_meta0 = -1;
     j.raw = false;
     if (replay && G.cp_rows && j.target > 0) {
         // start from the last checkpoint at or before the sweep of the target phase
@@ -288,7 +297,25 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
     };
     fetch_thr(t_begin);
 
+    // serving: the state at the start of every kServeCheckpointEvery sweeps
+    // is kept in the chain's scratch buffer (sb); when E_min has improved
+    // since that start, the entry is committed to it and the other buffer
+    // becomes the scratch.  A sub-range starting at sweep 0 commits the
+    // references (-1) and needs no stored state.
+    const bool keep = !REPLAY && J.cp_meta != nullptr;
+    int32_t meta = J.cp_meta0;
+    int sb = meta >= 0 ? 1 - (meta & 1) : 0;
+    int sub = t_begin;
+
     for (int t = t_begin; t < t_end && 4 * t < last_phase; ++t) {
+        if (keep && t > sub && (t - t_begin) % kServeCheckpointEvery == 0) {
+            if (stop > 4 * sub) {
+                meta = sub == 0 ? -1 : ((sub << 1) | sb);
+                if (sub > 0) sb ^= 1;
+            }
+            save_state(J.cp_base + sb * J.cp_bstride);
+            sub = t;
+        }
 #pragma unroll
         for (int j = 0; j < kThrPerLane; ++j)
             if (lane + j * kWave < nranks) et_s[lane + j * kWave].y = (int)thr_next[j];
@@ -348,7 +375,10 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
             J.emin[J.ci] = Emin;
             J.stop[J.ci] = stop;
             J.efin[J.ci] = E;
-            if (J.cp_meta && (t_begin == 0 || stop > 4 * t_begin)) J.cp_meta[J.ci] = J.cp_commit;
+            if (keep) {
+                if (stop > 4 * sub) meta = sub == 0 ? -1 : ((sub << 1) | sb);
+                J.cp_meta[J.ci] = meta;
+            }
         }
         if (J.states) save_state(J.states + (size_t)J.ci * nq);
     }
@@ -1009,6 +1039,9 @@ __device__ __forceinline__ ChainJob serve_job(const ServeTask &T, int slot, bool
     j.cp_start = nullptr;
     j.cp_meta = nullptr;
     j.cp_commit = -1;
+    j.cp_base = nullptr;
+    j.cp_bstride = 0;
+    j.cp_meta0 = -1;
     j.raw = false;
     if (T.cpm) {
         if (replay) {
@@ -1020,11 +1053,13 @@ __device__ __forceinline__ ChainJob serve_job(const ServeTask &T, int slot, bool
             }
         } else if (j.active) {
             j.cp_meta = T.cpm;
+            j.cp_base = T.cp + (size_t)c * nq;
+            j.cp_bstride = (int64_t)nc * nq;
             if (T.t_begin > 0) {
-                // the buffer not named by the chain's current entry
-                const int32_t meta = T.cpm[c];
-                const int b = meta >= 0 ? 1 - (meta & 1) : 0;
-                j.cp_start = T.cp + ((size_t)b * nc + c) * nq;
+                // the start state goes to the buffer not named by the chain's entry
+                j.cp_meta0 = T.cpm[c];
+                const int b = j.cp_meta0 >= 0 ? 1 - (j.cp_meta0 & 1) : 0;
+                j.cp_start = j.cp_base + b * j.cp_bstride;
                 j.cp_commit = (T.t_begin << 1) | b;
             }
         }

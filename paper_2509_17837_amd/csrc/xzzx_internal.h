@@ -88,6 +88,10 @@ constexpr int kStaticRanks = 128;
 // kMaxCheckpoints of them.
 constexpr int kCheckpointEvery = 256;
 constexpr int kMaxCheckpoints = 8;
+// sweeps between the states the serving loop's byte-state kernel keeps for
+// the best chain's replay (the packed-row kernels keep the state at the start
+// of each slice only)
+constexpr int kServeCheckpointEvery = 64;
 
 // Host-side lattice: geometry shared by every plan built on it.
 struct Lattice {

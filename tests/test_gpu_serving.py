@@ -150,3 +150,27 @@ def test_byte_kernel_and_empty_schedule():
         D.Server(max_lanes_per_chain=3)
     with pytest.raises(X.XzzxError):
         D.Server(max_lanes_per_chain=128)
+
+
+@pytest.mark.parametrize("slice_sweeps", [1000, 100])
+def test_replay_from_states_kept_while_serving(slice_sweeps):
+    """The byte-state serving kernel keeps each chain's state every 64 sweeps
+    inside a slice (1000: the whole 300-sweep schedule in one slice; 100:
+    slice starts and one kept state per slice), and the best chain's replay
+    starts from the last kept state before its E_min phase; recoveries equal
+    the batch decoder's and the oracle's."""
+    R = 16
+    s = Spec(11, 0.12, 10.0, 300, 4, 31, 9000)
+    srv = D.Server(max_slots=8, max_rep=R, max_qubits=121, sweeps_per_slice=slice_sweeps, greedy_seed=GS,
+                   anneal_seed=AS, max_lanes_per_chain=64)
+    tk = [srv.submit(s.plan, s.syn[i], s.uid[i], R) for i in range(4)]
+    srv.drain()
+    res = [srv.poll(t) for t in tk]
+    srv.close()
+    out = s.batch(R)
+    for i, r in enumerate(res):
+        assert same(r, out, i), f"request {i}"
+    w, wg = O.weights(s.p, O.noise(s.p, s.eta))
+    beta = O.schedule(O.SCHED_GEOMETRIC, 0.05, 10.0, s.sweeps)
+    ref = s.olat.decode(w, wg, s.syn[0], int(s.uid[0]), R, beta, GS, AS)
+    assert res[0]["e_best"] == ref["e_best"] and np.array_equal(res[0]["recovery"], ref["recovery"])
