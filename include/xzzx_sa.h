@@ -289,8 +289,9 @@ void xzzx_graph_destroy(xzzx_graph *graph);
  * Lanes per chain: each slice picks the largest power of two up to
  * max_lanes_per_chain for which the slice's wavefronts stay within max_waves
  * and its LDS within the budget; a request then runs on the byte-state kernel
- * with that many lanes per chain (capped by its colour-class size), which
- * cuts its latency when the device is lightly loaded.  When even two lanes do
+ * with that many lanes per chain, or fewer where fewer already give each lane
+ * at most one block of four generators of a colour class, which cuts its
+ * latency when the device is lightly loaded.  When even two lanes do
  * not fit, every request runs on its plan's own kernel choice.  Results do
  * not depend on this choice. */
 typedef struct xzzx_server xzzx_server;

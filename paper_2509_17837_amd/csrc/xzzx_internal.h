@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -201,6 +202,9 @@ int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const 
                  const int32_t *d_slot_map, int n, int n_rep, uint8_t *refs_base, int64_t refs_stride,
                  uint8_t *qraw_base, int64_t qraw_stride, uint64_t seed, int mode, hipStream_t stream);
 int serve_slice(const ServeLaunch *launches, int n_launches, uint64_t seed, hipStream_t stream);
+// launch(i, s) for i < n: the first on `stream`, the others on side streams
+// that wait for `stream`'s prior work; `stream` then waits for them all
+int run_concurrently(hipStream_t stream, int n, const std::function<int(int, hipStream_t)> &launch);
 int serve_finish(const ServeFinish *d_fin, const ServeTask *d_replay, int n, size_t lds_replay, uint64_t seed,
                  hipStream_t stream);
 

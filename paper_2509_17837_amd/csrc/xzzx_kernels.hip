@@ -25,6 +25,7 @@
 #include <utility>
 
 #include <algorithm>
+#include <functional>
 #include <mutex>
 #include <cstring>
 #include <vector>
@@ -152,7 +153,8 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     int32_t *D = reinterpret_cast<int32_t *>(smem + 4 * nwords);
     int32_t *best = D + A.max_nodes + 1;
     int32_t *pairs = best + A.max_nodes + 1;
-    uint8_t *freef = reinterpret_cast<uint8_t *>(pairs + A.max_nodes + 1);
+    int32_t *dbD = pairs + A.max_nodes + 1;   // boundary distance of each defect
+    uint8_t *freef = reinterpret_cast<uint8_t *>(dbD + A.max_nodes + 1);
     __shared__ int s_count;
 
     for (int i = lane; i < nwords; i += kWave) cfgw[i] = 0;
@@ -180,32 +182,44 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
         }
         const int na = nd + (nd & 1);   // odd count: the virtual boundary joins as node nd
         for (int i = lane; i < na; i += kWave) freef[i] = 1;
+        for (int i = lane; i < nd; i += kWave) dbD[i] = db[D[i]];
         if (lane == 0) s_count = 0;
         __syncthreads();
         int nfree = na;
         const bool randomized = A.mode == XZZX_GREEDY_RANDOM;
-        // every round matches at least the least free pair, so na/2 rounds suffice
+        // every round matches at least the least free pair, so na/2 rounds
+        // suffice.  Free defects only leave, so a defect whose least partner
+        // is still free keeps it; only the others search again.
         for (int round = 0; nfree > 0 && round <= na / 2; ++round) {
             for (int i = lane; i < na; i += kWave) {
                 if (!freef[i]) continue;
+                if (round > 0 && best[i] >= 0 && freef[best[i]]) continue;
+                // least (w, key, id) over free partners j; the interior
+                // distances of four partners are loaded before any is used
+                const bool iv = i == nd;   // the virtual boundary node
+                const int32_t dbi = iv ? 0 : dbD[i];
+                const int32_t *drow = dint + (size_t)(iv ? 0 : D[i]) * n;
                 uint32_t bw = 0xFFFFFFFFu, bk = 0xFFFFFFFFu, bid = 0xFFFFFFFFu;
                 int bj = -1;
-                for (int j = 0; j < na; ++j) {
-                    if (j == i || !freef[j]) continue;
-                    const int lo = min(i, j), hi = max(i, j);
-                    uint32_t w;
-                    if (hi == nd) {
-                        w = (uint32_t)db[D[lo]];
-                    } else {
-                        const int u = D[lo], v = D[hi];
-                        w = (uint32_t)min(dint[(size_t)u * n + v], db[u] + db[v]);
+                for (int j0 = 0; j0 < na; j0 += 4) {
+                    int32_t dv[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) dv[k] = drow[j0 + k < nd ? D[j0 + k] : 0];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int j = j0 + k;
+                        if (j >= na || j == i || !freef[j]) continue;
+                        // a pair with the virtual node weighs the real defect's boundary distance
+                        const uint32_t w = iv ? (uint32_t)dbD[j]
+                                         : j == nd ? (uint32_t)dbi
+                                                   : (uint32_t)min(dv[k], dbi + dbD[j]);
+                        const uint32_t id = (uint32_t)(min(i, j) * na + max(i, j));
+                        if (w > bw) continue;
+                        const uint32_t key = randomized
+                            ? philox4x32_10(make_uint4(uid, r, 0x100u + (uint32_t)g, id), A.seed_lo, A.seed_hi).x
+                            : 0u;
+                        if (w < bw || key < bk || (key == bk && id < bid)) { bw = w; bk = key; bid = id; bj = j; }
                     }
-                    const uint32_t id = (uint32_t)(lo * na + hi);
-                    if (w > bw) continue;
-                    const uint32_t key = randomized
-                        ? philox4x32_10(make_uint4(uid, r, 0x100u + (uint32_t)g, id), A.seed_lo, A.seed_hi).x
-                        : 0u;
-                    if (w < bw || key < bk || (key == bk && id < bid)) { bw = w; bk = key; bid = id; bj = j; }
                 }
                 best[i] = bj;
             }
@@ -460,7 +474,7 @@ static int greedy_lds(const Plan &P, int *max_nodes)
 {
     const int mn = std::max(P.hdev.ncol[0], P.hdev.ncol[1]);
     *max_nodes = mn;
-    return 4 * ((P.lat.nq + 3) / 4) + 3 * 4 * (mn + 1) + (mn + 1) + 16;
+    return 4 * ((P.lat.nq + 3) / 4) + 4 * 4 * (mn + 1) + (mn + 1) + 16;
 }
 
 static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_uid, int64_t n_syn,
@@ -943,6 +957,12 @@ int serve_slice(const ServeLaunch *launches, int n_launches, uint64_t seed, hipS
     // the kernels of one slice (one per family and distance) run concurrently
     if (n_launches <= 1) return n_launches ? one(0, stream) : XZZX_OK;
     return fork_join(stream, n_launches, one);
+}
+
+int run_concurrently(hipStream_t stream, int n, const std::function<int(int, hipStream_t)> &launch)
+{
+    if (n <= 1) return n ? launch(0, stream) : XZZX_OK;
+    return fork_join(stream, n, launch);
 }
 
 int serve_finish(const ServeFinish *d_fin, const ServeTask *d_replay, int n, size_t lds_replay, uint64_t seed,

@@ -118,22 +118,32 @@ size_t task_lds(const Plan &P, int *chains_per_task)
     return P.lds_bytes_anneal(P.lanes);
 }
 
-// lanes per chain for a request when the slice offers g: no more than a
-// colour class has generators (a power of two, at least 1)
+// Philox blocks (four generators each) of a colour class: the byte-state
+// kernel gives each lane of a chain whole blocks
+int class_blocks(const Plan &P)
+{
+    return (std::max(1, P.lat.nstab / 4) + 3) / 4;
+}
+
+// lanes per chain for a request when the slice offers g: the least power of
+// two that gives every lane at most one block, capped at g (more lanes would
+// sit idle)
 int lanes_for(const Plan &P, int g)
 {
-    const int per_class = std::max(1, P.lat.nstab / 4);
+    const int nblk = class_blocks(P);
     int c = 1;
-    while (2 * c <= per_class && 2 * c <= g) c *= 2;
+    while (c < nblk && 2 * c <= g) c *= 2;
     return c;
 }
 
-// sequential work of one sweep of one chain: generators per lane
+// sequential work of one sweep of one chain: attempts on the packed-row
+// kernels (g = 1); blocks per lane on the byte-state kernel, whose sweep
+// latency is set by the blocks each lane runs in turn
 int64_t sweep_cost(const Plan &P, int g)
 {
     if (g == 1) return P.lat.nstab;
     const int gr = lanes_for(P, g);
-    return (P.lat.nstab + gr - 1) / gr;
+    return (class_blocks(P) + gr - 1) / gr;
 }
 
 size_t request_lds(const Plan &P, int n_rep)
@@ -205,19 +215,26 @@ int xzzx_server::slice()
         rc = check(hipMemcpyAsync(d_stage + st_syn, h_stage + st_syn, n * (size_t)max_nstab, hipMemcpyHostToDevice, stream), "stage syndromes");
         if (!rc) rc = check(hipMemcpyAsync(d_stage + st_uid, h_stage + st_uid, n * 4, hipMemcpyHostToDevice, stream), "stage uids");
         if (!rc) rc = check(hipMemcpyAsync(d_stage + st_map, h_stage + st_map, n * 4, hipMemcpyHostToDevice, stream), "stage slots");
-        // one greedy launch per (plan, n_rep) over consecutive staged entries
-        size_t i = 0;
-        while (!rc && i < n) {
+        // one greedy launch per (plan, n_rep) over consecutive staged entries;
+        // the launches of different plans run concurrently
+        std::vector<std::pair<size_t, size_t>> runs;
+        for (size_t i = 0; i < n;) {
             size_t j = i + 1;
             const Slot &a = slots[admitted[i]];
             while (j < n && slots[admitted[j]].plan == a.plan && slots[admitted[j]].n_rep == a.n_rep) ++j;
-            rc = serve_greedy(*a.plan, d_stage + st_syn + i * (size_t)max_nstab, max_nstab,
-                              reinterpret_cast<const uint32_t *>(d_stage + st_uid) + i,
-                              reinterpret_cast<const int32_t *>(d_stage + st_map) + i, (int)(j - i), a.n_rep,
-                              d_pool + off_refs, (int64_t)slot_bytes, d_pool + off_qraw, (int64_t)slot_bytes,
-                              cfg.greedy_seed, cfg.greedy_mode, stream);
+            runs.emplace_back(i, j);
             i = j;
         }
+        if (!rc)
+            rc = run_concurrently(stream, (int)runs.size(), [&](int r, hipStream_t s) {
+                const size_t i = runs[r].first, j = runs[r].second;
+                const Slot &a = slots[admitted[i]];
+                return serve_greedy(*a.plan, d_stage + st_syn + i * (size_t)max_nstab, max_nstab,
+                                    reinterpret_cast<const uint32_t *>(d_stage + st_uid) + i,
+                                    reinterpret_cast<const int32_t *>(d_stage + st_map) + i, (int)(j - i), a.n_rep,
+                                    d_pool + off_refs, (int64_t)slot_bytes, d_pool + off_qraw, (int64_t)slot_bytes,
+                                    cfg.greedy_seed, cfg.greedy_mode, s);
+            });
         if (rc) return rc;
     }
 
