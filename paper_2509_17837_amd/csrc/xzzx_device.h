@@ -108,21 +108,39 @@ struct ChainJob {
     int64_t cp_stride;     // chains per word plane
     int32_t cp_words;      // words per row of the checkpoint planes
     int32_t t0;            // first sweep to run (replay from a checkpoint)
-    // serving: the state at the start of this sweep range is stored to
-    // cp_start (nullable); if E_min improves within the range (or the range
-    // starts at sweep 0), cp_meta[ci] (nullable) is set to cp_commit, which
-    // names that stored state and its sweep for a later replay
-    uint8_t *cp_start;
+    // serving: the state at the start of this sweep range has been stored
+    // (k_serve_stash) in the buffer the chain's entry cp_meta[ci] does not
+    // name; if E_min improves within the range (or the range starts at sweep
+    // 0), the entry is set to name it (see commit_range_start); nullable
     int32_t *cp_meta;
-    int32_t cp_commit;
-    // the byte-state core also stores states inside the range: buffer b of
-    // the chain at cp_base + b cp_bstride; cp_meta0 = the chain's entry at
-    // the range start (-1: the references at sweep 0)
+    // buffer b of chain ci at cp_base + b cp_bstride + ci nq (wave-uniform
+    // cp_base: nothing per lane stays live through a sweep loop for it);
+    // cp_meta0 = the chain's entry at the range start (-1: the references)
     uint8_t *cp_base;
     int64_t cp_bstride;
     int32_t cp_meta0;
     bool raw;              // replay: src holds the chain's own state (logical already applied)
 };
+
+// Serving replay entries (one per chain): (sweep << 1) | b names the state
+// kept in the chain's buffer b at the start of that sweep; -1 names the
+// references at sweep 0.  A sweep range starting at t > 0 keeps its start
+// state in the buffer the entry does not name.
+__device__ __forceinline__ int range_start_buffer(int32_t entry) { return entry >= 0 ? 1 - (entry & 1) : 0; }
+
+// End of a sweep range [t_begin, ...) of a packed-row core: if E_min improved
+// inside the range (stop past its first phase), the entry names the range's
+// start state; a range from sweep 0 names the references.  The entry is
+// re-read here rather than kept live through the sweep loop (only this chain
+// writes it).  (A copy loop anywhere in these kernels -- stashing the start
+// state here or before the sweeps -- was measured to cost the sweep loop up to
+// 18 registers and spills at d = 9-11, so the stash is a kernel of its own.)
+__device__ __forceinline__ void commit_range_start(const ChainJob &J, int t_begin, int32_t stop)
+{
+    int32_t *entry = J.cp_meta + J.ci;
+    if (t_begin == 0) *entry = -1;
+    else if (stop > 4 * t_begin) *entry = (t_begin << 1) | range_start_buffer(*entry);
+}
 
 struct GroupArgs {
     const PlanDev *plan;
@@ -187,9 +205,7 @@ __device__ __forceinline__ ChainJob batch_job(const GroupArgs &G, int64_t unit, 
     j.cp_stride = G.n_chains;
     j.cp_words = G.plan->static_words;
     j.t0 = 0;
-    j.cp_start = nullptr;
     j.cp_meta = nullptr;
-    j.cp_commit = -1;
     j.cp_base = nullptr;
     j.cp_bstride = 0;
     j.cp_meta0 = -1;
@@ -258,7 +274,6 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
                 if (use_x) v ^= pl->lx[q];
                 if (use_z) v ^= pl->lz[q];
             }
-            if (J.cp_start) J.cp_start[q] = (uint8_t)v;
         }
         st[(q << LOGC) + c] = (uint8_t)v;
         part += weight_of(W, v);
@@ -313,7 +328,7 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
                 meta = sub == 0 ? -1 : ((sub << 1) | sb);
                 if (sub > 0) sb ^= 1;
             }
-            save_state(J.cp_base + sb * J.cp_bstride);
+            save_state(J.cp_base + sb * J.cp_bstride + J.ci * nq);
             sub = t;
         }
 #pragma unroll
@@ -493,7 +508,6 @@ __device__ inline void rows_core(const PlanDev *pl, const ChainJob &J, int t_beg
                         uint32_t v = J.src[q] & 3u;
                         if (use_x) v ^= pl->lx[q];
                         if (use_z) v ^= pl->lz[q];
-                        if (J.cp_start) J.cp_start[q] = (uint8_t)v;
                         word |= v << (2 * j);
                         E += weight_of(W, v);
                     }
@@ -580,7 +594,7 @@ __device__ inline void rows_core(const PlanDev *pl, const ChainJob &J, int t_beg
         J.emin[J.ci] = Emin;
         J.stop[J.ci] = stop;
         J.efin[J.ci] = E;
-        if (J.cp_meta && (t_begin == 0 || stop > 4 * t_begin)) J.cp_meta[J.ci] = J.cp_commit;
+        if (J.cp_meta) commit_range_start(J, t_begin, stop);
         if (J.states) {
             uint8_t *dst = J.states + (size_t)J.ci * nq;
             for (int q = 0; q < nq; ++q) {
@@ -818,7 +832,6 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
                     uint32_t v = J.src[q] & 3u;
                     if (use_x) v ^= pl->lx[q];
                     if (use_z) v ^= pl->lz[q];
-                    if (J.cp_start) J.cp_start[q] = (uint8_t)v;
                     word |= v << (2 * (x - 16 * w));
                     E += weight_of(W, v);
                 }
@@ -870,7 +883,7 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
         J.emin[J.ci] = Emin;
         J.stop[J.ci] = stop;
         J.efin[J.ci] = E;
-        if (J.cp_meta && (t_begin == 0 || stop > 4 * t_begin)) J.cp_meta[J.ci] = J.cp_commit;
+        if (J.cp_meta) commit_range_start(J, t_begin, stop);
         if (J.states) {
             uint8_t *dst = J.states + (size_t)J.ci * (D * D);
 #pragma unroll
@@ -1036,9 +1049,7 @@ __device__ __forceinline__ ChainJob serve_job(const ServeTask &T, int slot, bool
     // start states kept at sweep-range boundaries: buffer b of chain c at
     // cp + (b nc + c) nq; cpm[c] = (sweep << 1) | b of the one a replay of
     // the chain's E_min phase starts from, -1 for the references at sweep 0
-    j.cp_start = nullptr;
     j.cp_meta = nullptr;
-    j.cp_commit = -1;
     j.cp_base = nullptr;
     j.cp_bstride = 0;
     j.cp_meta0 = -1;
@@ -1053,15 +1064,9 @@ __device__ __forceinline__ ChainJob serve_job(const ServeTask &T, int slot, bool
             }
         } else if (j.active) {
             j.cp_meta = T.cpm;
-            j.cp_base = T.cp + (size_t)c * nq;
+            j.cp_base = T.cp;
             j.cp_bstride = (int64_t)nc * nq;
-            if (T.t_begin > 0) {
-                // the start state goes to the buffer not named by the chain's entry
-                j.cp_meta0 = T.cpm[c];
-                const int b = j.cp_meta0 >= 0 ? 1 - (j.cp_meta0 & 1) : 0;
-                j.cp_start = j.cp_base + b * j.cp_bstride;
-                j.cp_commit = (T.t_begin << 1) | b;
-            }
+            if (T.t_begin > 0) j.cp_meta0 = T.cpm[c];
         }
     }
     return j;
@@ -1096,31 +1101,50 @@ __device__ __forceinline__ void serve_kernel_body(const ServeTask *tasks, uint32
     }
 }
 
-// Serving slice on the specialised packed-row kernel: one task (64 chains of
-// one request, one sweep range) per workgroup; chain states resume from and
-// return to the request's slot.
+// Serving slices on the specialised packed-row kernels: one task (64 chains
+// of one request, one sweep range) per workgroup; chain states resume from
+// and return to the request's slot.  The distances of one register class
+// share a kernel that branches on the task's distance (wave-uniform), so a
+// slice issues one launch per class rather than one per distance, and every
+// task of a slice can run at once however few queues the device gives the
+// process.  Classes: see serve_class_max.
+
 template <int D>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(static_waves(D), static_waves(D))))
-void k_serve_rows_d(const ServeTask *tasks, uint32_t slo, uint32_t shi)
+__device__ __forceinline__ void serve_static_task(const ServeTask &T, uint32_t slo, uint32_t shi, uint16_t *lut_s,
+                                                  uint4 *et_s)
+{
+    load_static_tables(T.plan, lut_s, et_s);
+    const ChainJob J = serve_job(T, threadIdx.x, false);
+    rows_static_core<D>(T.plan, J, T.t_begin, T.t_end, slo, shi, lut_s, et_s, 0);
+}
+
+template <int DMAX, int... Ds>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(static_waves(DMAX), static_waves(DMAX))))
+void k_serve_rows_class(const ServeTask *tasks, uint32_t slo, uint32_t shi)
 {
     __shared__ uint16_t lut_s[256 * 6];
     __shared__ uint4 et_s[kStaticRanks];
     const ServeTask &T = tasks[blockIdx.x];
-    load_static_tables(T.plan, lut_s, et_s);
-    const ChainJob J = serve_job(T, threadIdx.x, false);
-    rows_static_core<D>(T.plan, J, T.t_begin, T.t_end, slo, shi, lut_s, et_s, 0);
+    const int d = (int)uni(T.plan->d);
+    ((d == Ds ? serve_static_task<Ds>(T, slo, shi, lut_s, et_s) : (void)0), ...);
 }
 
 typedef void (*AnnealKernel)(AnnealArgs);
 typedef void (*ServeKernel)(const ServeTask *, uint32_t, uint32_t);
 
 // The specialised kernels live in several translation units (compiled in
-// parallel); each returns its kernels for the distances it holds, else NULL.
+// parallel): the annealing kernels by distance (each part returns its kernels
+// for the distances it holds, else NULL), the serving kernels by class (each
+// part returns the kernel of its class).
 #define XZZX_STATIC_PARTS(X) X(a) X(b) X(c) X(d) X(e) X(f) X(g) X(h)
-#define XZZX_DECLARE_PART(P) \
-    AnnealKernel static_rows_kernel_##P(int d, bool plain); \
-    ServeKernel static_serve_kernel_##P(int d);
+#define XZZX_DECLARE_PART(P) AnnealKernel static_rows_kernel_##P(int d, bool plain);
 XZZX_STATIC_PARTS(XZZX_DECLARE_PART)
 #undef XZZX_DECLARE_PART
+ServeKernel serve_class_kernel_9();
+ServeKernel serve_class_kernel_15();
+ServeKernel serve_class_kernel_21();
+ServeKernel serve_class_kernel_25();
+ServeKernel serve_class_kernel_29();
+ServeKernel serve_class_kernel_31();
 
 }  // namespace xzzx

@@ -83,6 +83,9 @@ struct RotSchedule {
 // distinct move energies its static tables hold.
 constexpr int kStaticMinD = 3, kStaticMaxD = 31;
 constexpr int kStaticRanks = 128;
+// static LDS of a specialised kernel's workgroup: the u16 (shape, pattern)
+// lookup of six shapes and the 16-byte move-energy entries
+constexpr size_t kStaticLdsBytes = 2 * 256 * 6 + 16 * kStaticRanks;
 // The specialised kernel's state checkpoints (the replay of a syndrome's
 // best chain starts from the last one before its E_min phase): every
 // kCheckpointEvery sweeps, or sparser so that a chain keeps at most
@@ -93,6 +96,16 @@ constexpr int kMaxCheckpoints = 8;
 // the best chain's replay (the packed-row kernels keep the state at the start
 // of each slice only)
 constexpr int kServeCheckpointEvery = 64;
+// Register classes of the specialised serving kernels, named by their largest
+// distance: d <= 15 but 9 (one word per row, eight wavefronts per SIMD), 17-21,
+// 23-25, 27-29 and 31 (the largest kept apart to bound compile time).  d = 9
+// has a class of its own: its sweep takes more registers than the others of
+// the first class, and merged with them the kernel spills.  A serving slice
+// makes one launch per class present.
+constexpr int serve_class_max(int d)
+{
+    return d == 9 ? 9 : d <= 15 ? 15 : d <= 21 ? 21 : d <= 25 ? 25 : d <= 29 ? 29 : 31;
+}
 
 // Host-side lattice: geometry shared by every plan built on it.
 struct Lattice {
@@ -190,6 +203,8 @@ struct ServeFinish {
 // One launch of a serving slice: tasks of one kernel family.
 //   kind 0: packed-row kernel; 1: byte-state kernel; 2: packed-row kernel
 //   specialised to distance d.
+// One launch of a serving slice; the launches of a slice cover consecutive
+// ranges of one device task array, starting at launches[0].tasks.
 struct ServeLaunch {
     const ServeTask *tasks;
     int32_t n;

@@ -313,13 +313,18 @@ static AnnealKernel static_rows_kernel(int d, bool plain)
     return nullptr;
 }
 
+// serving kernel of the specialised class holding d (NULL outside [3, 31])
 static ServeKernel static_serve_kernel(int d)
 {
-#define XZZX_TRY_PART(P) \
-    if (ServeKernel k = static_serve_kernel_##P(d)) return k;
-    XZZX_STATIC_PARTS(XZZX_TRY_PART)
-#undef XZZX_TRY_PART
-    return nullptr;
+    if (d < kStaticMinD || d > kStaticMaxD) return nullptr;
+    switch (serve_class_max(d)) {
+    case 9: return serve_class_kernel_9();
+    case 15: return serve_class_kernel_15();
+    case 21: return serve_class_kernel_21();
+    case 25: return serve_class_kernel_25();
+    case 29: return serve_class_kernel_29();
+    default: return serve_class_kernel_31();
+    }
 }
 
 static AnnealKernel bytes_kernel(int mode, int lg)
@@ -344,6 +349,25 @@ __global__ __launch_bounds__(kWave) void k_serve_bytes(const ServeTask *tasks, u
 __global__ __launch_bounds__(kWave) void k_serve_replay(const ServeTask *tasks, uint32_t slo, uint32_t shi)
 {
     serve_kernel_body<false, true>(tasks, slo, shi);
+}
+
+// Before a slice: every task resuming at t_begin > 0 copies the stored state
+// of each of its chains into the chain's buffer that its replay entry does
+// not name (the range's start state, for a later replay).  One workgroup per
+// task, bytes of the task's chains spread over the lanes.
+__global__ __launch_bounds__(256) void k_serve_stash(const ServeTask *tasks)
+{
+    const ServeTask &T = tasks[blockIdx.x];
+    if (T.t_begin == 0 || !T.cpm) return;
+    const int nq = T.plan->nq;
+    const int64_t nc = 4 * (int64_t)T.n_rep;
+    const int64_t total = (int64_t)T.nchains * nq;
+    for (int64_t i = threadIdx.x; i < total; i += blockDim.x) {
+        const int64_t k = i / nq;
+        const int64_t c = T.chain0 + k, q = i - k * nq;
+        const int64_t b = range_start_buffer(T.cpm[c]);
+        T.cp[(b * nc + c) * nq + q] = T.states[c * nq + q];
+    }
 }
 
 
@@ -940,6 +964,14 @@ int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const 
 int serve_slice(const ServeLaunch *launches, int n_launches, uint64_t seed, hipStream_t stream)
 {
     const uint32_t lo = (uint32_t)seed, hi = (uint32_t)(seed >> 32);
+    // the launches' tasks are consecutive: stash the start states of them all
+    int n_tasks = 0;
+    for (int i = 0; i < n_launches; ++i) n_tasks += launches[i].n;
+    if (n_tasks > 0) {
+        hipLaunchKernelGGL(k_serve_stash, dim3((unsigned)n_tasks), dim3(256), 0, stream, launches[0].tasks);
+        const int rc = check_hip(hipGetLastError(), "serving stash launch");
+        if (rc) return rc;
+    }
     auto one = [&](int i, hipStream_t s) -> int {
         const ServeLaunch &L = launches[i];
         if (L.n <= 0) return XZZX_OK;

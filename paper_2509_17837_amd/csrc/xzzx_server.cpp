@@ -112,7 +112,8 @@ size_t task_lds(const Plan &P, int *chains_per_task)
 {
     if (P.use_rows) {
         *chains_per_task = kWave;
-        return P.lds_bytes_rows();
+        // the specialised kernels keep rows in registers: LDS holds only their tables
+        return P.static_d ? kStaticLdsBytes : P.lds_bytes_rows();
     }
     *chains_per_task = kWave / P.lanes;
     return P.lds_bytes_anneal(P.lanes);
@@ -304,7 +305,7 @@ int xzzx_server::slice()
                 while ((1 << lg) < gr) ++lg;
                 T.log_lanes = rows ? 0 : lg;
                 T.row_words = rows ? P.row_words : 0;
-                if (rows && P.static_d) static_t[P.static_d].push_back(T);
+                if (rows && P.static_d) static_t[serve_class_max(P.static_d)].push_back(T);
                 else if (rows) { rows_t.push_back(T); lds_rows = std::max(lds_rows, lds); }
                 else { bytes_t.push_back(T); lds_bytes = std::max(lds_bytes, lds); }
             }
@@ -313,7 +314,8 @@ int xzzx_server::slice()
         if (sl.t >= P.n_sweeps) finished.push_back((int)s);
     }
     // one launch per kernel family: generic packed rows, byte states, and
-    // the packed-row kernel specialised to each distance present
+    // the specialised packed-row kernel of each register class present
+    // (largest lattices first)
     std::vector<ServeLaunch> launches;
     size_t nt = 0;
     auto add = [&](const std::vector<ServeTask> &v, int kind, int d, size_t lds) {
@@ -329,14 +331,15 @@ int xzzx_server::slice()
     };
     add(rows_t, 0, 0, lds_rows);
     add(bytes_t, 1, 0, lds_bytes);
-    for (int d = kStaticMinD; d <= kStaticMaxD; d += 2) add(static_t[d], 2, d, 0);
+    static constexpr int kClasses[] = {31, 29, 25, 21, 15, 9};
+    for (int c : kClasses) add(static_t[c], 2, c, 0);
     if (nt > max_tasks) { set_error("serving task buffer overflow"); return XZZX_ERANGE; }
     if (nt) {
         size_t at = 0;
         for (const auto *v : {&rows_t, &bytes_t}) { std::copy(v->begin(), v->end(), h_tasks + at); at += v->size(); }
-        for (int d = kStaticMinD; d <= kStaticMaxD; d += 2) {
-            std::copy(static_t[d].begin(), static_t[d].end(), h_tasks + at);
-            at += static_t[d].size();
+        for (int c : kClasses) {
+            std::copy(static_t[c].begin(), static_t[c].end(), h_tasks + at);
+            at += static_t[c].size();
         }
         rc = check(hipMemcpyAsync(d_stage + st_tasks, h_tasks, nt * sizeof(ServeTask), hipMemcpyHostToDevice, stream),
                    "stage tasks");

@@ -18,17 +18,4 @@ AnnealKernel static_rows_kernel_a(int d, bool plain)
     }
 }
 
-ServeKernel static_serve_kernel_a(int d)
-{
-    switch (d) {
-    case 3: return k_serve_rows_d<3>;
-    case 5: return k_serve_rows_d<5>;
-    case 7: return k_serve_rows_d<7>;
-    case 9: return k_serve_rows_d<9>;
-    case 11: return k_serve_rows_d<11>;
-    case 13: return k_serve_rows_d<13>;
-    default: return nullptr;
-    }
-}
-
 }  // namespace xzzx

@@ -14,13 +14,4 @@ AnnealKernel static_rows_kernel_b(int d, bool plain)
     }
 }
 
-ServeKernel static_serve_kernel_b(int d)
-{
-    switch (d) {
-    case 15: return k_serve_rows_d<15>;
-    case 17: return k_serve_rows_d<17>;
-    default: return nullptr;
-    }
-}
-
 }  // namespace xzzx

@@ -14,13 +14,4 @@ AnnealKernel static_rows_kernel_c(int d, bool plain)
     }
 }
 
-ServeKernel static_serve_kernel_c(int d)
-{
-    switch (d) {
-    case 19: return k_serve_rows_d<19>;
-    case 21: return k_serve_rows_d<21>;
-    default: return nullptr;
-    }
-}
-
 }  // namespace xzzx

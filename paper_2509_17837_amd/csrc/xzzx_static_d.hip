@@ -13,12 +13,4 @@ AnnealKernel static_rows_kernel_d(int d, bool plain)
     }
 }
 
-ServeKernel static_serve_kernel_d(int d)
-{
-    switch (d) {
-    case 23: return k_serve_rows_d<23>;
-    default: return nullptr;
-    }
-}
-
 }  // namespace xzzx

@@ -13,12 +13,4 @@ AnnealKernel static_rows_kernel_e(int d, bool plain)
     }
 }
 
-ServeKernel static_serve_kernel_e(int d)
-{
-    switch (d) {
-    case 25: return k_serve_rows_d<25>;
-    default: return nullptr;
-    }
-}
-
 }  // namespace xzzx

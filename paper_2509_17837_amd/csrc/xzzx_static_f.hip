@@ -13,12 +13,4 @@ AnnealKernel static_rows_kernel_f(int d, bool plain)
     }
 }
 
-ServeKernel static_serve_kernel_f(int d)
-{
-    switch (d) {
-    case 27: return k_serve_rows_d<27>;
-    default: return nullptr;
-    }
-}
-
 }  // namespace xzzx

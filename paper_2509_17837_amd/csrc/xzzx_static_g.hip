@@ -13,12 +13,4 @@ AnnealKernel static_rows_kernel_g(int d, bool plain)
     }
 }
 
-ServeKernel static_serve_kernel_g(int d)
-{
-    switch (d) {
-    case 29: return k_serve_rows_d<29>;
-    default: return nullptr;
-    }
-}
-
 }  // namespace xzzx

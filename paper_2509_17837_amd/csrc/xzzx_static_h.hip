@@ -13,12 +13,4 @@ AnnealKernel static_rows_kernel_h(int d, bool plain)
     }
 }
 
-ServeKernel static_serve_kernel_h(int d)
-{
-    switch (d) {
-    case 31: return k_serve_rows_d<31>;
-    default: return nullptr;
-    }
-}
-
 }  // namespace xzzx
