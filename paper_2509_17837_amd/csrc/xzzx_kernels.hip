@@ -70,6 +70,12 @@ __global__ void k_syndrome(const PlanDev *__restrict__ pl, const uint8_t *__rest
 // canonical tight-edge walk (smallest edge id) and are XOR-ed into the
 // configuration with LDS atomics (paths may overlap).
 // ---------------------------------------------------------------------------
+// partners at the least weight a greedy scan lists before keying them, and
+// partners whose interior distances a scan loads at once (the table is in
+// HBM or L2: the loads of a batch overlap)
+constexpr int kGreedyTies = 8;
+constexpr int kGreedyBatch = 4;
+
 struct GreedyArgs {
     const PlanDev *plan;
     const uint8_t *syn;
@@ -94,20 +100,32 @@ __device__ __forceinline__ void xor_edge(uint32_t *cfgw, int eid)
     atomicXor(&cfgw[q >> 2], code << (8 * (q & 3)));
 }
 
+// Canonical walks.  Each step reads the node's four adjacency entries (in
+// edge-id order) and their far ends' distances at once, then takes the first
+// tight edge; the distance of the next node is known (dx - weight), so a step
+// costs two dependent rounds of loads rather than one per entry tried.
 __device__ void walk_interior(const PlanDev *pl, int g, int u, int v, uint32_t *cfgw)
 {
     const int n = pl->ncol[g];
     const int32_t *du = pl->dint[g] + (size_t)u * n;
     const int4 *adj = pl->adj[g];
     int x = v;
+    int32_t dx = du[x];
     for (int step = 0; step < n && x != u; ++step) {
-        const int32_t dx = du[x];
+        int4 e[4];
+        int32_t de[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) e[s] = adj[4 * x + s];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) de[s] = (e[s].x >= 0 && e[s].y >= 0) ? du[e[s].y] : -1;
         int nxt = -1;
-        for (int s = 0; s < 4; ++s) {
-            const int4 e = adj[4 * x + s];
-            if (e.x < 0 || e.y < 0) continue;
-            if (du[e.y] + e.z == dx) { xor_edge(cfgw, e.x); nxt = e.y; break; }
-        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (nxt < 0 && e[s].x >= 0 && e[s].y >= 0 && de[s] + e[s].z == dx) {
+                xor_edge(cfgw, e[s].x);
+                nxt = e[s].y;
+                dx = de[s];
+            }
         if (nxt < 0) return;
         x = nxt;
     }
@@ -119,21 +137,29 @@ __device__ void walk_boundary(const PlanDev *pl, int g, int u, uint32_t *cfgw)
     const int32_t *db = pl->db[g];
     const int4 *adj = pl->adj[g];
     int x = u;
+    int32_t dx = db[x];
     for (int step = 0; step <= n; ++step) {
-        const int32_t dx = db[x];
+        int4 e[4];
+        int32_t de[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) e[s] = adj[4 * x + s];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) de[s] = (e[s].x >= 0 && e[s].y >= 0) ? db[e[s].y] : -1;
+        // the first tight entry in edge-id order: a boundary half-edge ends the walk
         int nxt = -1;
+        bool done = false;
+#pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int4 e = adj[4 * x + s];
-            if (e.x < 0) continue;
-            if (e.y < 0) {
-                if (e.z == dx) { xor_edge(cfgw, e.x); return; }
-            } else if (db[e.y] + e.z == dx) {
-                xor_edge(cfgw, e.x);
-                nxt = e.y;
-                break;
+            if (done || nxt >= 0 || e[s].x < 0) continue;
+            if (e[s].y < 0) {
+                if (e[s].z == dx) { xor_edge(cfgw, e[s].x); done = true; }
+            } else if (de[s] + e[s].z == dx) {
+                xor_edge(cfgw, e[s].x);
+                nxt = e[s].y;
+                dx = de[s];
             }
         }
-        if (nxt < 0) return;
+        if (done || nxt < 0) return;
         x = nxt;
     }
 }
@@ -154,7 +180,8 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     int32_t *best = D + A.max_nodes + 1;
     int32_t *pairs = best + A.max_nodes + 1;
     int32_t *dbD = pairs + A.max_nodes + 1;   // boundary distance of each defect
-    uint8_t *freef = reinterpret_cast<uint8_t *>(dbD + A.max_nodes + 1);
+    int16_t *cands = reinterpret_cast<int16_t *>(dbD + A.max_nodes + 1);   // [64][kGreedyTies]
+    uint8_t *freef = reinterpret_cast<uint8_t *>(cands + kWave * kGreedyTies);
     __shared__ int s_count;
 
     for (int i = lane; i < nwords; i += kWave) cfgw[i] = 0;
@@ -194,31 +221,59 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
             for (int i = lane; i < na; i += kWave) {
                 if (!freef[i]) continue;
                 if (round > 0 && best[i] >= 0 && freef[best[i]]) continue;
-                // least (w, key, id) over free partners j; the interior
-                // distances of four partners are loaded before any is used
+                // least (w, key, id) over free partners j, in two passes: the
+                // least weight and the partners at it (in ascending j, so
+                // ascending pair id), then keys for those partners only -- a
+                // single scan that drew a key on every tie so far made the
+                // wavefront draw one for nearly every partner.  The interior
+                // distances of a batch of partners are loaded before any is used.
                 const bool iv = i == nd;   // the virtual boundary node
                 const int32_t dbi = iv ? 0 : dbD[i];
                 const int32_t *drow = dint + (size_t)(iv ? 0 : D[i]) * n;
-                uint32_t bw = 0xFFFFFFFFu, bk = 0xFFFFFFFFu, bid = 0xFFFFFFFFu;
-                int bj = -1;
-                for (int j0 = 0; j0 < na; j0 += 4) {
-                    int32_t dv[4];
+                int16_t *cand = cands + lane * kGreedyTies;
+                auto weight = [&](int j, int32_t dj) -> uint32_t {
+                    // a pair with the virtual node weighs the real defect's boundary distance
+                    return iv ? (uint32_t)dbD[j] : j == nd ? (uint32_t)dbi : (uint32_t)min(dj, dbi + dbD[j]);
+                };
+                uint32_t bw = 0xFFFFFFFFu;
+                int nt = 0;   // partners at weight bw
+                for (int j0 = 0; j0 < na; j0 += kGreedyBatch) {
+                    int32_t dv[kGreedyBatch];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) dv[k] = drow[j0 + k < nd ? D[j0 + k] : 0];
+                    for (int k = 0; k < kGreedyBatch; ++k) dv[k] = drow[j0 + k < nd ? D[j0 + k] : 0];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
+                    for (int k = 0; k < kGreedyBatch; ++k) {
                         const int j = j0 + k;
                         if (j >= na || j == i || !freef[j]) continue;
-                        // a pair with the virtual node weighs the real defect's boundary distance
-                        const uint32_t w = iv ? (uint32_t)dbD[j]
-                                         : j == nd ? (uint32_t)dbi
-                                                   : (uint32_t)min(dv[k], dbi + dbD[j]);
-                        const uint32_t id = (uint32_t)(min(i, j) * na + max(i, j));
+                        const uint32_t w = weight(j, dv[k]);
                         if (w > bw) continue;
-                        const uint32_t key = randomized
-                            ? philox4x32_10(make_uint4(uid, r, 0x100u + (uint32_t)g, id), A.seed_lo, A.seed_hi).x
-                            : 0u;
-                        if (w < bw || key < bk || (key == bk && id < bid)) { bw = w; bk = key; bid = id; bj = j; }
+                        if (w < bw) { bw = w; nt = 0; }
+                        if (nt < kGreedyTies) cand[nt] = (int16_t)j;
+                        ++nt;
+                    }
+                }
+                int bj = nt > 0 ? cand[0] : -1;
+                if (randomized && nt > 1) {
+                    auto pair_id = [&](int j) { return (uint32_t)(min(i, j) * na + max(i, j)); };
+                    auto pair_key = [&](uint32_t id) {
+                        return philox4x32_10(make_uint4(uid, r, 0x100u + (uint32_t)g, id), A.seed_lo, A.seed_hi).x;
+                    };
+                    uint32_t bid = pair_id(bj), bk = pair_key(bid);
+                    if (nt <= kGreedyTies) {
+                        for (int t = 1; t < nt; ++t) {
+                            const int j = cand[t];
+                            const uint32_t id = pair_id(j), key = pair_key(id);
+                            if (key < bk) { bk = key; bid = id; bj = j; }   // ids ascend: ties keep the first
+                        }
+                    } else {
+                        // more ties than the list holds: scan again
+                        for (int j = bj + 1; j < na; ++j) {
+                            if (j == i || !freef[j]) continue;
+                            const int32_t dj = (!iv && j < nd) ? drow[D[j]] : 0;
+                            if (weight(j, dj) != bw) continue;
+                            const uint32_t id = pair_id(j), key = pair_key(id);
+                            if (key < bk) { bk = key; bid = id; bj = j; }
+                        }
                     }
                 }
                 best[i] = bj;
@@ -498,7 +553,7 @@ static int greedy_lds(const Plan &P, int *max_nodes)
 {
     const int mn = std::max(P.hdev.ncol[0], P.hdev.ncol[1]);
     *max_nodes = mn;
-    return 4 * ((P.lat.nq + 3) / 4) + 4 * 4 * (mn + 1) + (mn + 1) + 16;
+    return 4 * ((P.lat.nq + 3) / 4) + 4 * 4 * (mn + 1) + 2 * kWave * kGreedyTies + (mn + 1) + 16;
 }
 
 static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_uid, int64_t n_syn,
