@@ -38,15 +38,23 @@ OPS_PER_ATTEMPT = 19
 ALU_PEAK_OPS = 256 * 128 * 2.4e9
 
 
-def kernel_source_sha256():
-    """Digest of every device source (kernels, shared device header, internal
-    header), in name order."""
+def kernel_source_sha256(kernel=""):
+    """Digest of the sources a kernel is built from, in name order.  The
+    annealing kernels specialised to a distance (k_anneal_rows_d<D>) come
+    from the headers and the xzzx_static_*.hip units alone; any other kernel
+    is digested with every device source."""
     import glob
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_2509_17837_amd", "csrc")
+    inc = os.path.join(ROOT, "include")
+    files = glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(inc, "*.h"))
+    if kernel.startswith("k_anneal_rows_d"):
+        files += glob.glob(os.path.join(csrc, "xzzx_static_*.hip"))
+    else:
+        files += glob.glob(os.path.join(csrc, "*.hip"))
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+    for f in sorted(files, key=os.path.basename):
         h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
     return h.hexdigest()
@@ -67,7 +75,7 @@ def measured_traffic(kernel, workload, batch):
         if " = " in line:
             k, v = line.split(" = ", 1)
             kv[k.strip()] = v.strip()
-    sha = kernel_source_sha256()
+    sha = kernel_source_sha256(kernel)
     if kv.get("kernel_source_sha256") != sha or kv.get("workload") != f"{workload} batch {batch}":
         return None
     return int(kv["traffic_bytes_per_launch"])
