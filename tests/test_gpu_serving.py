@@ -174,3 +174,23 @@ def test_replay_from_states_kept_while_serving(slice_sweeps):
     beta = O.schedule(O.SCHED_GEOMETRIC, 0.05, 10.0, s.sweeps)
     ref = s.olat.decode(w, wg, s.syn[0], int(s.uid[0]), R, beta, GS, AS)
     assert res[0]["e_best"] == ref["e_best"] and np.array_equal(res[0]["recovery"], ref["recovery"])
+
+
+def test_every_specialised_serving_class():
+    """With one lane per chain every request runs on the specialised
+    packed-row serving kernels, one launch per register class; distances
+    from every class (d = 3..15 but 9, 9, 17-21, 23-25, 27-29, 31) are served
+    together and each result equals the batch decoder's."""
+    R = 16
+    specs = [Spec(d, 0.12, 10.0, 40, 2, 40 + d, 20000 + 100 * d) for d in (5, 9, 13, 17, 21, 23, 27, 29, 31)]
+    srv = D.Server(max_slots=32, max_rep=R, max_qubits=961, sweeps_per_slice=15, greedy_seed=GS, anneal_seed=AS,
+                   max_lanes_per_chain=1)
+    tk = [(s, i, srv.submit(s.plan, s.syn[i], s.uid[i], R)) for s in specs for i in range(2)]
+    srv.drain()
+    res = [(s, i, srv.poll(t)) for s, i, t in tk]
+    st = srv.stats()
+    srv.close()
+    assert st["slices"] > 1
+    outs = {id(s): s.batch(R) for s in specs}
+    for s, i, r in res:
+        assert same(r, outs[id(s)], i), f"d={s.d} request {i}"
