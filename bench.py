@@ -104,6 +104,7 @@ def parse():
     ap.add_argument("--lanes", type=int, default=0,
                     help="most lanes per chain the server may use (--serve; 0: library default, 1: plan kernels)")
     ap.add_argument("--waves", type=int, default=0, help="wave budget per serving slice (--serve; 0: default)")
+    ap.add_argument("--slots", type=int, default=8192, help="resident requests at most (--serve)")
     ap.add_argument("--by-distance", action="store_true",
                     help="annealing rate of the default kernel for each odd d in --distances")
     ap.add_argument("--distances", default="11,13,15,17,21,25,29,31")
@@ -450,7 +451,7 @@ def serve_bench(args):
     for rate in rates:
         n_rate = max(1, min(n, int(rate * args.serve_seconds)))
         arr = inputs.poisson_arrivals(rate, n_rate, seeds["sample"] + int(rate))
-        srv = D.Server(max_slots=4096, max_rep=R, max_qubits=max(d * d for d in wl["d"]),
+        srv = D.Server(max_slots=args.slots, max_rep=R, max_qubits=max(d * d for d in wl["d"]),
                        sweeps_per_slice=args.slice, greedy_seed=seeds["greedy"], anneal_seed=seeds["anneal"],
                        max_lanes_per_chain=args.lanes, max_waves=args.waves)
         t0 = time.perf_counter()
@@ -489,7 +490,8 @@ def serve_bench(args):
         "data": "synthetic",
         "config": {"workload": f"single-syndrome requests, rotated XZZX d in {wl['d']}, eta in {wl['eta']}, "
                                f"p={p}, {R} replicas, {wl['sweeps']} sweeps geometric 0.05->10, Poisson arrivals",
-                   "name": name, "sweeps_per_slice": args.slice, "max_lanes_per_chain": args.lanes,
+                   "name": name, "sweeps_per_slice": args.slice, "max_slots": args.slots,
+                   "max_lanes_per_chain": args.lanes,
                    "max_waves": args.waves, "seeds": seeds},
         "rates": out,
     }

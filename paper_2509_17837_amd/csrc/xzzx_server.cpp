@@ -80,6 +80,9 @@ struct xzzx_server {
     int64_t wave_budget = 0;
     int max_nstab = 0;
     std::vector<Slot> slots;
+    // free slot indices (a stack) and the resident ones (unordered; position
+    // of each in resident_pos), so no step scans every slot
+    std::vector<int> free_slots, resident, resident_pos;
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -177,10 +180,11 @@ int xzzx_server::slice()
             const Plan &P = p.plan->P;
             const size_t need = request_lds(P, p.n_rep);
             if (lds_used + need > lds_budget && lds_used > 0) break;
-            int s = -1;
-            for (size_t i = 0; i < slots.size(); ++i)
-                if (!slots[i].busy) { s = (int)i; break; }
-            if (s < 0) break;
+            if (free_slots.empty()) break;
+            const int s = free_slots.back();
+            free_slots.pop_back();
+            resident_pos[s] = (int)resident.size();
+            resident.push_back(s);
             Slot &sl = slots[s];
             sl.busy = true;
             sl.ticket = p.ticket;
@@ -254,8 +258,8 @@ int xzzx_server::slice()
     for (int g = cfg.max_lanes_per_chain; g > 1; g >>= 1) {
         int64_t waves = 0;
         size_t lds_max = 0;
-        for (const Slot &sl : slots) {
-            if (!sl.busy) continue;
+        for (int s : resident) {
+            const Slot &sl = slots[s];
             const int gr = lanes_for(*sl.plan, g);
             waves += (4 * sl.n_rep * gr + kWave - 1) / kWave;
             lds_max = std::max(lds_max, sl.plan->lds_bytes_anneal(gr));
@@ -267,11 +271,9 @@ int xzzx_server::slice()
     // task of the slice carries about the work of sweeps_per_slice sweeps of
     // the costliest resident request
     int64_t ref_cost = 1;
-    for (const Slot &sl : slots)
-        if (sl.busy) ref_cost = std::max(ref_cost, sweep_cost(*sl.plan, G));
-    for (size_t s = 0; s < slots.size(); ++s) {
+    for (int s : resident) ref_cost = std::max(ref_cost, sweep_cost(*slots[s].plan, G));
+    for (int s : resident) {
         Slot &sl = slots[s];
-        if (!sl.busy) continue;
         const Plan &P = *sl.plan;
         const int64_t share = std::max<int64_t>(1, (int64_t)cfg.sweeps_per_slice * ref_cost / sweep_cost(P, G));
         const int t0 = sl.t, t1 = (int)std::min<int64_t>(P.n_sweeps, t0 + share);
@@ -284,7 +286,7 @@ int xzzx_server::slice()
             const int C = kWave / gr;
             const size_t lds = rows ? P.lds_bytes_rows() : P.lds_bytes_anneal(gr);
             const int nc = 4 * sl.n_rep;
-            uint8_t *base = slot_ptr((int)s);
+            uint8_t *base = slot_ptr(s);
             for (int c0 = 0; c0 < nc; c0 += C) {
                 ServeTask T{};
                 T.plan = P.ddev;
@@ -311,7 +313,7 @@ int xzzx_server::slice()
             }
             sl.t = t1;
         }
-        if (sl.t >= P.n_sweeps) finished.push_back((int)s);
+        if (sl.t >= P.n_sweeps) finished.push_back(s);
     }
     // one launch per kernel family: generic packed rows, byte states, and
     // the specialised packed-row kernel of each register class present
@@ -429,6 +431,12 @@ int xzzx_server::slice()
             where.erase(sl.ticket);
             lds_used -= sl.lds;
             sl.busy = false;
+            // swap-remove from the resident list, back to the free stack
+            const int s = finished[k], at = resident_pos[s], last = resident.back();
+            resident[at] = last;
+            resident_pos[last] = at;
+            resident.pop_back();
+            free_slots.push_back(s);
             ++completed;
             last_done = now;
         }
@@ -443,15 +451,8 @@ void xzzx_server::run()
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] {
-                if (stop || !pending.empty()) return true;
-                for (const Slot &s : slots)
-                    if (s.busy) return true;
-                return false;
-            });
-            bool any = !pending.empty();
-            for (const Slot &s : slots) any = any || s.busy;
-            if (stop && !any) return;
+            cv_work.wait(lk, [&] { return stop || !pending.empty() || !resident.empty(); });
+            if (stop && pending.empty() && resident.empty()) return;
         }
         const int rc = slice();
         if (rc) {
@@ -525,6 +526,9 @@ int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out)
         return rc;
     }
     S->slots.resize(ns);
+    S->resident_pos.assign(ns, -1);
+    S->resident.reserve(ns);
+    for (int i = ns - 1; i >= 0; --i) S->free_slots.push_back(i);
     S->worker = std::thread([S] { S->run(); });
     *out = S;
     return XZZX_OK;
