@@ -108,38 +108,51 @@ struct ChainJob {
     int64_t cp_stride;     // chains per word plane
     int32_t cp_words;      // words per row of the checkpoint planes
     int32_t t0;            // first sweep to run (replay from a checkpoint)
-    // serving: the state at the start of this sweep range has been stored
-    // (k_serve_stash) in the buffer the chain's entry cp_meta[ci] does not
-    // name; if E_min improves within the range (or the range starts at sweep
-    // 0), the entry is set to name it (see commit_range_start); nullable
-    int32_t *cp_meta;
-    // buffer b of chain ci at cp_base + b cp_bstride + ci nq (wave-uniform
-    // cp_base: nothing per lane stays live through a sweep loop for it);
-    // cp_meta0 = the chain's entry at the range start (-1: the references)
-    uint8_t *cp_base;
+    // serving: states kept for the replay of the chain's E_min phase (see
+    // kept_entry); all wave-uniform bases, so nothing per lane stays live
+    // through a sweep loop for them; nullable
+    int32_t *cp_meta;      // the chains' entries
+    uint8_t *cp_base;      // byte states: buffer b of chain ci at cp_base + b cp_bstride + ci nq
     int64_t cp_bstride;
-    int32_t cp_meta0;
+    uint32_t *cp_packed;   // packed rows: buffer b of chain ci at cp_packed + (b nc + ci) cp_pwords
+    int64_t cp_nc;
+    int32_t cp_pwords;
+    int32_t cp_meta0;      // the chain's entry at the range start (-1: the references)
     bool raw;              // replay: src holds the chain's own state (logical already applied)
 };
 
-// Serving replay entries (one per chain): (sweep << 1) | b names the state
-// kept in the chain's buffer b at the start of that sweep; -1 names the
-// references at sweep 0.  A sweep range starting at t > 0 keeps its start
-// state in the buffer the entry does not name.
-__device__ __forceinline__ int range_start_buffer(int32_t entry) { return entry >= 0 ? 1 - (entry & 1) : 0; }
+// Serving keeps, per chain, two buffers of byte states and two of packed
+// rows (the specialised kernel's layout), and one entry naming the state a
+// replay of the chain's E_min phase starts from: -1 for the references at
+// sweep 0, else (sweep << 2) | (packed << 1) | b.  Kept states go to buffer
+// kept_scratch(entry) -- the one the entry does not name -- of either kind:
+// the start state of a sweep range (bytes, by k_serve_stash), and inside a
+// range the state every kServeCheckpointEvery sweeps (bytes from the
+// byte-state kernel, packed rows from the specialised one).  When E_min has
+// improved since the last kept state, the entry is made to name it.
+__device__ __forceinline__ int kept_scratch(int32_t entry) { return entry >= 0 ? 1 - (entry & 1) : 0; }
+__device__ __forceinline__ int32_t kept_entry(int sweep, bool packed, int b)
+{
+    return sweep == 0 ? -1 : ((sweep << 2) | ((packed ? 1 : 0) << 1) | b);
+}
 
-// End of a sweep range [t_begin, ...) of a packed-row core: if E_min improved
-// inside the range (stop past its first phase), the entry names the range's
-// start state; a range from sweep 0 names the references.  The entry is
-// re-read here rather than kept live through the sweep loop (only this chain
-// writes it).  (A copy loop anywhere in these kernels -- stashing the start
-// state here or before the sweeps -- was measured to cost the sweep loop up to
-// 18 registers and spills at d = 9-11, so the stash is a kernel of its own.)
-__device__ __forceinline__ void commit_range_start(const ChainJob &J, int t_begin, int32_t stop)
+// Commit of a packed-row core's last kept state (at sweep sub; packed rows
+// unless it is the range start) if E_min improved after it (stop past sweep
+// sub's first phase).  The entry is re-read here rather than kept live
+// through the sweep loop (only this chain writes it); a range from sweep 0
+// sets it to -1 first.  Returns the entry.  (Copying the range's start
+// state inside these kernels, before the sweeps or after them, was measured
+// to cost the sweep loop up to 18 registers and spills at d = 9-11, so
+// k_serve_stash does it before a slice.)
+__device__ __forceinline__ int32_t commit_kept_state(const ChainJob &J, int sub, bool packed, int32_t stop)
 {
     int32_t *entry = J.cp_meta + J.ci;
-    if (t_begin == 0) *entry = -1;
-    else if (stop > 4 * t_begin) *entry = (t_begin << 1) | range_start_buffer(*entry);
+    int32_t e = *entry;
+    if (stop > 4 * sub) {
+        e = kept_entry(sub, packed, kept_scratch(e));
+        *entry = e;
+    }
+    return e;
 }
 
 struct GroupArgs {
@@ -208,6 +221,9 @@ __device__ __forceinline__ ChainJob batch_job(const GroupArgs &G, int64_t unit, 
     j.cp_meta = nullptr;
     j.cp_base = nullptr;
     j.cp_bstride = 0;
+    j.cp_packed = nullptr;
+    j.cp_nc = 0;
+    j.cp_pwords = 0;
     j.cp_meta0 = -1;
     j.raw = false;
     if (replay && G.cp_rows && j.target > 0) {
@@ -319,16 +335,16 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
     // references (-1) and needs no stored state.
     const bool keep = !REPLAY && J.cp_meta != nullptr;
     int32_t meta = J.cp_meta0;
-    int sb = meta >= 0 ? 1 - (meta & 1) : 0;
+    int sb = kept_scratch(meta);
     int sub = t_begin;
 
     for (int t = t_begin; t < t_end && 4 * t < last_phase; ++t) {
         if (keep && t > sub && (t - t_begin) % kServeCheckpointEvery == 0) {
             if (stop > 4 * sub) {
-                meta = sub == 0 ? -1 : ((sub << 1) | sb);
+                meta = kept_entry(sub, false, sb);
                 if (sub > 0) sb ^= 1;
             }
-            save_state(J.cp_base + sb * J.cp_bstride + J.ci * nq);
+            if (J.active) save_state(J.cp_base + sb * J.cp_bstride + J.ci * nq);
             sub = t;
         }
 #pragma unroll
@@ -391,7 +407,7 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
             J.stop[J.ci] = stop;
             J.efin[J.ci] = E;
             if (keep) {
-                if (stop > 4 * sub) meta = sub == 0 ? -1 : ((sub << 1) | sb);
+                if (stop > 4 * sub) meta = kept_entry(sub, false, sb);
                 J.cp_meta[J.ci] = meta;
             }
         }
@@ -493,6 +509,8 @@ __device__ inline void rows_core(const PlanDev *pl, const ChainJob &J, int t_beg
     const uint32_t uid = J.uid, cc = J.cc;
     const bool use_x = !J.resume && (J.lp == 1 || J.lp == 2), use_z = !J.resume && (J.lp == 2 || J.lp == 3);
 
+    // serving: a fresh request's replay entries start at the references
+    if (J.cp_meta && t_begin == 0 && J.active) J.cp_meta[J.ci] = -1;
     // pack the state into rows; E of the state on the way
     int32_t E = 0;
     for (int Y = 0; Y < rows; ++Y) {
@@ -594,7 +612,7 @@ __device__ inline void rows_core(const PlanDev *pl, const ChainJob &J, int t_beg
         J.emin[J.ci] = Emin;
         J.stop[J.ci] = stop;
         J.efin[J.ci] = E;
-        if (J.cp_meta) commit_range_start(J, t_begin, stop);
+        if (J.cp_meta) commit_kept_state(J, t_begin, false, stop);
         if (J.states) {
             uint8_t *dst = J.states + (size_t)J.ci * nq;
             for (int q = 0; q < nq; ++q) {
@@ -797,6 +815,20 @@ __device__ __forceinline__ void static_class(uint32_t (&r)[StaticRows<D>::N], co
     (static_block<D, K, Bs>(r, h, k0, k1, lut_s, et_s, acc), ...);
 }
 
+// One byte per qubit, row-major, from the specialised kernel's rows.
+template <int D>
+__device__ __forceinline__ void static_unpack(const uint32_t (&r)[StaticRows<D>::N], uint8_t *dst)
+{
+    constexpr int NW = StaticRows<D>::NW;
+#pragma unroll
+    for (int y = 0; y < D; ++y)
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+#pragma unroll 1
+            for (int x = 16 * w; x < min(D, 16 * w + 16); ++x)
+                dst[y * D + x] = (uint8_t)((r[y * NW + w] >> (2 * (x - 16 * w))) & 3u);
+}
+
 template <int D>
 __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
                                  uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s, int cp_interval)
@@ -846,11 +878,17 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
         stop = J.stop[J.ci];
     }
 
+    // serving: the state is also kept every kServeCheckpointEvery sweeps of
+    // the range, for the replay (sub: sweep of the state kept last)
+    const bool keep = J.cp_meta != nullptr;
+    if (keep && t_begin == 0 && J.active) J.cp_meta[J.ci] = -1;
+    int sub = t_begin;
     for (int t = t_begin; t < t_end;) {
         // sweeps up to the next checkpoint, then the checkpoint (the state at
         // the start of sweep t, every cp_every sweeps)
         int t_stop = t_end;
         if (cp_every) t_stop = min(t_end, (t / cp_every + 1) * cp_every);
+        if (keep) t_stop = min(t_end, t_begin + ((t - t_begin) / kServeCheckpointEvery + 1) * kServeCheckpointEvery);
         for (; t < t_stop; ++t) {
             wave_lds_fence();
             for (int i = lane; i < nranks; i += kWave) et_s[i].y = pl->thr[(size_t)t * nranks + i];
@@ -878,22 +916,22 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
 #pragma unroll
             for (int i = 0; i < D * NW; ++i) cp[i * J.cp_stride] = r[i];
         }
+        if (keep && t < t_end) {
+            if (J.active) {
+                const int32_t e = commit_kept_state(J, sub, sub != t_begin, stop);
+                uint32_t *dst = J.cp_packed + (kept_scratch(e) * J.cp_nc + J.ci) * J.cp_pwords;
+#pragma unroll
+                for (int i = 0; i < D * NW; ++i) dst[i] = r[i];
+            }
+            sub = t;
+        }
     }
     if (J.active) {
         J.emin[J.ci] = Emin;
         J.stop[J.ci] = stop;
         J.efin[J.ci] = E;
-        if (J.cp_meta) commit_range_start(J, t_begin, stop);
-        if (J.states) {
-            uint8_t *dst = J.states + (size_t)J.ci * (D * D);
-#pragma unroll
-            for (int y = 0; y < D; ++y)
-#pragma unroll
-                for (int w = 0; w < NW; ++w)
-#pragma unroll 1
-                    for (int x = 16 * w; x < min(D, 16 * w + 16); ++x)
-                        dst[y * D + x] = (uint8_t)((r[y * NW + w] >> (2 * (x - 16 * w))) & 3u);
-        }
+        if (keep) commit_kept_state(J, sub, sub != t_begin, stop);
+        if (J.states) static_unpack<D>(r, J.states + (size_t)J.ci * (D * D));
     }
 }
 
@@ -1052,20 +1090,35 @@ __device__ __forceinline__ ChainJob serve_job(const ServeTask &T, int slot, bool
     j.cp_meta = nullptr;
     j.cp_base = nullptr;
     j.cp_bstride = 0;
+    j.cp_packed = nullptr;
+    j.cp_nc = 0;
+    j.cp_pwords = 0;
     j.cp_meta0 = -1;
     j.raw = false;
     if (T.cpm) {
         if (replay) {
             const int32_t meta = T.cpm[c];
             if (meta >= 0) {
-                j.src = T.cp + ((size_t)(meta & 1) * nc + c) * nq;
-                j.raw = true;
-                j.t0 = meta >> 1;
+                const int b = meta & 1;
+                if (meta & 2) {   // packed rows of the specialised kernel
+                    j.cp_in = T.cpk + ((size_t)b * nc + c) * T.cpk_words;
+                    j.cp_stride = 1;
+                    j.cp_words = T.plan->static_words;
+                } else {
+                    j.src = T.cp + ((size_t)b * nc + c) * nq;
+                    j.raw = true;
+                }
+                j.t0 = meta >> 2;
             }
-        } else if (j.active) {
+        } else {
+            // set on every lane (the kernels branch on it wave-uniformly);
+            // only active lanes write
             j.cp_meta = T.cpm;
             j.cp_base = T.cp;
             j.cp_bstride = (int64_t)nc * nq;
+            j.cp_packed = T.cpk;
+            j.cp_nc = nc;
+            j.cp_pwords = T.cpk_words;
             if (T.t_begin > 0) j.cp_meta0 = T.cpm[c];
         }
     }
@@ -1118,8 +1171,15 @@ __device__ __forceinline__ void serve_static_task(const ServeTask &T, uint32_t s
     rows_static_core<D>(T.plan, J, T.t_begin, T.t_end, slo, shi, lut_s, et_s, 0);
 }
 
+// Occupancy of a serving class kernel: one wavefront per SIMD fewer than the
+// annealing kernels of its distances where the several distances of a class,
+// in one kernel, need more registers than any of them alone (measured: the
+// merged kernels of d <= 15 and 17-21 spilled at the annealing kernels'
+// occupancy).
+constexpr int serve_class_waves(int dmax) { return dmax == 15 ? 7 : dmax == 21 ? 4 : static_waves(dmax); }
+
 template <int DMAX, int... Ds>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(static_waves(DMAX), static_waves(DMAX))))
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(serve_class_waves(DMAX), serve_class_waves(DMAX))))
 void k_serve_rows_class(const ServeTask *tasks, uint32_t slo, uint32_t shi)
 {
     __shared__ uint16_t lut_s[256 * 6];

@@ -184,8 +184,10 @@ struct ServeTask {
     int32_t t_begin, t_end;  // sweep range; t_begin == 0 starts from the references
     int32_t log_lanes;       // byte-state core: lanes per chain
     int32_t row_words;       // packed-row core: words per row
-    uint8_t *cp;             // chain states at range starts [2][4 n_rep][nq] (nullable)
-    int32_t *cpm;            // per chain: (sweep << 1) | buffer of the replay start, -1: references
+    uint8_t *cp;             // kept byte states [2][4 n_rep][nq] (nullable)
+    uint32_t *cpk;           // kept packed rows [2][4 n_rep][cpk_words]
+    int32_t *cpm;            // per chain: entry naming the replay start (see kept_entry)
+    int32_t cpk_words;       // words per chain of a packed-rows buffer
 };
 
 // Serving-loop finish entry: per-coset reduction of one finished request,

@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256) void k_serve_stash(const ServeTask *tasks)
     for (int64_t i = threadIdx.x; i < total; i += blockDim.x) {
         const int64_t k = i / nq;
         const int64_t c = T.chain0 + k, q = i - k * nq;
-        const int64_t b = range_start_buffer(T.cpm[c]);
+        const int64_t b = kept_scratch(T.cpm[c]);
         T.cp[(b * nc + c) * nq + q] = T.states[c * nq + q];
     }
 }

@@ -71,7 +71,8 @@ struct xzzx_server {
     // device slot pool
     uint8_t *d_pool = nullptr;
     size_t slot_bytes = 0, off_refs = 0, off_states = 0, off_e3 = 0, off_qraw = 0, off_res = 0, off_rec = 0;
-    size_t off_cp = 0, off_cpm = 0;   // replay start states [2][4R][nq] and their entries [4R]
+    size_t off_cp = 0, off_cpk = 0, off_cpm = 0;   // kept states: bytes [2][4R][nq], packed rows [2][4R][cpk_words], entries [4R]
+    int cpk_words = 0;
     // staging (device + pinned host)
     uint8_t *d_stage = nullptr, *h_stage = nullptr;
     size_t stage_bytes = 0, st_syn = 0, st_uid = 0, st_map = 0, st_tasks = 0, st_fin = 0, st_out = 0;
@@ -296,6 +297,8 @@ int xzzx_server::slice()
                 T.snap = nullptr;
                 T.best = nullptr;
                 T.cp = base + off_cp;
+                T.cpk = reinterpret_cast<uint32_t *>(base + off_cpk);
+                T.cpk_words = cpk_words;
                 T.cpm = reinterpret_cast<int32_t *>(base + off_cpm);
                 T.uid = sl.uid;
                 T.n_rep = sl.n_rep;
@@ -381,6 +384,8 @@ int xzzx_server::slice()
             T.best = reinterpret_cast<const int32_t *>(base + off_res) + 2;
             // from the start state of the sweep range in which the chain's E_min was reached
             T.cp = base + off_cp;
+            T.cpk = reinterpret_cast<uint32_t *>(base + off_cpk);
+            T.cpk_words = cpk_words;
             T.cpm = reinterpret_cast<int32_t *>(base + off_cpm);
             T.uid = sl.uid;
             T.n_rep = sl.n_rep;
@@ -502,7 +507,12 @@ int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out)
     S->off_res = S->off_qraw + align256(R);
     S->off_rec = S->off_res + 256;
     S->off_cp = S->off_rec + align256(nq);
-    S->off_cpm = S->off_cp + align256(2 * 4 * R * nq);
+    // packed rows of the largest rotated lattice that fits max_qubits
+    int dmax = 1;
+    while ((size_t)(dmax + 1) * (dmax + 1) <= nq) ++dmax;
+    S->cpk_words = dmax * ((2 * (dmax + 1) + 31) / 32);
+    S->off_cpk = S->off_cp + align256(2 * 4 * R * nq);
+    S->off_cpm = S->off_cpk + align256(2 * 4 * R * (size_t)S->cpk_words * 4);
     S->slot_bytes = S->off_cpm + align256(4 * R * 4);
     const size_t ns = (size_t)cfg->max_slots;
     S->max_tasks = ns * 4 * R;
