@@ -765,29 +765,49 @@ __device__ __forceinline__ void row_flip_static(uint32_t *w, uint32_t sel)
     }
 }
 
+// Generator W of Philox block B of colour class K: cell (i, j) covers
+// lattice rows j (slots 0, 1) and j + 1 (slots 2, 3), nibble of columns
+// i, i + 1 at bit 2i; rows -1 and d do not exist.
 template <int D, int K, int B, int W>
-__device__ __forceinline__ void static_move(uint32_t (&r)[StaticRows<D>::N], uint32_t u, const uint16_t *lut_s,
-                                            const uint4 *et_s, int32_t &acc)
+struct StaticGen {
+    static constexpr RotGen g = RotSchedule<D>{}.g[K][4 * B + W];
+    static constexpr bool real = g.shp != 5;
+    static constexpr int ya = g.Y - 1, BO = g.bo - 2;
+    static constexpr bool has_a = ya >= 0, has_b = ya + 1 < D;
+};
+
+// The move's energy-table entry, looked up from its 8-bit slot pattern.
+template <int D, int K, int B, int W>
+__device__ __forceinline__ uint4 static_lookup(const uint32_t (&r)[StaticRows<D>::N], const uint16_t *lut_s,
+                                               const uint4 *et_s)
 {
+    using G = StaticGen<D, K, B, W>;
     constexpr int NW = StaticRows<D>::NW;
-    constexpr RotSchedule<D> S{};
-    constexpr RotGen g = S.g[K][4 * B + W];
-    if constexpr (g.shp != 5) {
-        // cell (i, j): lattice rows j (slots 0, 1) and j + 1 (slots 2, 3),
-        // nibble of columns i, i + 1 at bit 2i; rows -1 and d do not exist
-        constexpr int ya = g.Y - 1, BO = g.bo - 2;
-        constexpr bool has_a = ya >= 0, has_b = ya + 1 < D;
-        uint32_t *ra = r + (has_a ? ya : 0) * NW, *rb = r + (has_b ? ya + 1 : 0) * NW;
+    if constexpr (!G::real) {
+        return make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        const uint32_t *ra = r + (G::has_a ? G::ya : 0) * NW, *rb = r + (G::has_b ? G::ya + 1 : 0) * NW;
         uint32_t pat2 = 0;
-        if constexpr (has_a) pat2 |= row_bits<NW, BO, 1>(ra) & 0x1Eu;
-        if constexpr (has_b) pat2 |= row_bits<NW, BO, 5>(rb) & 0x1E0u;
+        if constexpr (G::has_a) pat2 |= row_bits<NW, G::BO, 1>(ra) & 0x1Eu;
+        if constexpr (G::has_b) pat2 |= row_bits<NW, G::BO, 5>(rb) & 0x1E0u;
         const uint32_t off = *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(lut_s) +
-                                                                 512u * g.shp + pat2);
-        const uint4 e = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint8_t *>(et_s) + off);
+                                                                 512u * G::g.shp + pat2);
+        return *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint8_t *>(et_s) + off);
+    }
+}
+
+// Acceptance of the move with draw u and entry e, its flips and energy.
+template <int D, int K, int B, int W>
+__device__ __forceinline__ void static_apply(uint32_t (&r)[StaticRows<D>::N], uint32_t u, const uint4 &e, int32_t &acc)
+{
+    using G = StaticGen<D, K, B, W>;
+    constexpr int NW = StaticRows<D>::NW;
+    if constexpr (G::real) {
+        uint32_t *ra = r + (G::has_a ? G::ya : 0) * NW, *rb = r + (G::has_b ? G::ya + 1 : 0) * NW;
         // all ones on accepting lanes: u < threshold, or dE <= 0
         const uint32_t sel = lt_mask(u, e.y) | e.z;
-        if constexpr (has_a) row_flip_static<NW, BO, 6u>(ra, sel);   // X_left | Z_up
-        if constexpr (has_b) row_flip_static<NW, BO, 9u>(rb, sel);   // Z_down | X_right
+        if constexpr (G::has_a) row_flip_static<NW, G::BO, 6u>(ra, sel);   // X_left | Z_up
+        if constexpr (G::has_b) row_flip_static<NW, G::BO, 9u>(rb, sel);   // Z_down | X_right
         acc += (int32_t)(e.x & sel);
     }
 }
@@ -797,10 +817,39 @@ __device__ __forceinline__ void static_block(uint32_t (&r)[StaticRows<D>::N], co
                                              const uint16_t *lut_s, const uint4 *et_s, int32_t &acc)
 {
     const uint4 u = philox_block(h, (uint32_t)B, k0, k1);
-    static_move<D, K, B, 0>(r, u.x, lut_s, et_s, acc);
-    static_move<D, K, B, 1>(r, u.y, lut_s, et_s, acc);
-    static_move<D, K, B, 2>(r, u.z, lut_s, et_s, acc);
-    static_move<D, K, B, 3>(r, u.w, lut_s, et_s, acc);
+    // The four generators of a block belong to one colour class and act on
+    // disjoint qubits: a flip of one leaves the others' slot bits as they
+    // were, so all four look up their entries from the rows before any flip
+    // and their LDS reads overlap (looked up one after another, each move's
+    // pattern waited for the previous move's flips of the same row words).
+    // Moves looked up together per group (measured per distance): four,
+    // but pairs at d = 15, where four entries in flight spill, and one at a
+    // time at d = 13, which ran fastest so.
+    constexpr int OV = D == 13 ? 1 : D == 15 ? 2 : 4;
+    if constexpr (OV == 1) {
+        static_apply<D, K, B, 0>(r, u.x, static_lookup<D, K, B, 0>(r, lut_s, et_s), acc);
+        static_apply<D, K, B, 1>(r, u.y, static_lookup<D, K, B, 1>(r, lut_s, et_s), acc);
+        static_apply<D, K, B, 2>(r, u.z, static_lookup<D, K, B, 2>(r, lut_s, et_s), acc);
+        static_apply<D, K, B, 3>(r, u.w, static_lookup<D, K, B, 3>(r, lut_s, et_s), acc);
+    } else if constexpr (OV == 2) {
+        const uint4 e0 = static_lookup<D, K, B, 0>(r, lut_s, et_s);
+        const uint4 e1 = static_lookup<D, K, B, 1>(r, lut_s, et_s);
+        static_apply<D, K, B, 0>(r, u.x, e0, acc);
+        static_apply<D, K, B, 1>(r, u.y, e1, acc);
+        const uint4 e2 = static_lookup<D, K, B, 2>(r, lut_s, et_s);
+        const uint4 e3 = static_lookup<D, K, B, 3>(r, lut_s, et_s);
+        static_apply<D, K, B, 2>(r, u.z, e2, acc);
+        static_apply<D, K, B, 3>(r, u.w, e3, acc);
+    } else {
+        const uint4 e0 = static_lookup<D, K, B, 0>(r, lut_s, et_s);
+        const uint4 e1 = static_lookup<D, K, B, 1>(r, lut_s, et_s);
+        const uint4 e2 = static_lookup<D, K, B, 2>(r, lut_s, et_s);
+        const uint4 e3 = static_lookup<D, K, B, 3>(r, lut_s, et_s);
+        static_apply<D, K, B, 0>(r, u.x, e0, acc);
+        static_apply<D, K, B, 1>(r, u.y, e1, acc);
+        static_apply<D, K, B, 2>(r, u.z, e2, acc);
+        static_apply<D, K, B, 3>(r, u.w, e3, acc);
+    }
     // the energy change is summed block by block: left free, the compiler
     // reassociates the whole class's sum into a tree at the end of the class
     // and keeps every move's term live in a register until then
