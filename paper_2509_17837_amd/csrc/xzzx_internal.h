@@ -90,8 +90,8 @@ constexpr size_t kStaticLdsBytes = 2 * 256 * 6 + 16 * kStaticRanks;
 // best chain starts from the last one before its E_min phase): every
 // kCheckpointEvery sweeps, or sparser so that a chain keeps at most
 // kMaxCheckpoints of them.
-constexpr int kCheckpointEvery = 256;
-constexpr int kMaxCheckpoints = 8;
+constexpr int kCheckpointEvery = 64;
+constexpr int kMaxCheckpoints = 32;
 // sweeps between the states the serving loop's byte-state kernel keeps for
 // the best chain's replay (the packed-row kernels keep the state at the start
 // of each slice only)

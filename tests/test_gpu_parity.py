@@ -140,13 +140,13 @@ def test_specialised_row_kernel(d):
     assert plan.info()["kernel"] == X.KERNEL_ROWS
 
 
-@pytest.mark.parametrize("d,sweeps", [(7, 256), (7, 257), (7, 700), (7, 2100), (15, 300), (19, 300), (31, 300)])
+@pytest.mark.parametrize("d,sweeps", [(7, 64), (7, 65), (7, 300), (7, 2100), (15, 300), (19, 300), (31, 300)])
 def test_replay_from_checkpoints(d, sweeps):
-    """Groups on the specialised kernel keep a state checkpoint every 256
-    sweeps, or at most eight evenly spaced; each syndrome's recovery is
-    replayed from the last checkpoint before its E_min phase (256 sweeps:
-    none; 257: one, at the start of the last sweep; 700: two; 2100: seven,
-    263 sweeps apart; d = 15 stores one word per row, d = 19 and d = 31
+    """Groups on the specialised kernel keep a state checkpoint every 64
+    sweeps, or at most 32 evenly spaced; each syndrome's recovery is
+    replayed from the last checkpoint before its E_min phase (64 sweeps:
+    none; 65: one, at the start of the last sweep; 300: four; 2100: 31,
+    66 sweeps apart; d = 15 stores one word per row, d = 19 and d = 31
     two)."""
     prob = Problem(0, d, 0.2, 10.0, 4 if d < 15 else 2, 16, sweeps, seed=800 + sweeps + d)
     plan = gpu_plan(prob)
