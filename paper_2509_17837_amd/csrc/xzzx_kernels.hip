@@ -59,7 +59,8 @@ __global__ void k_syndrome(const PlanDev *__restrict__ pl, const uint8_t *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Greedy matching (Algs. 5-6) -- one wavefront per (syndrome, replica).
+// Greedy matching (Algs. 5-6) -- one wavefront per (syndrome, replica), one
+// colour per half wavefront or the colours in turn (see k_greedy).
 //
 // The sequential rule "take the free pair of least (weight, key, pair id)"
 // is evaluated as repeated mutual-best elimination: every free defect finds
@@ -164,6 +165,12 @@ __device__ void walk_boundary(const PlanDev *pl, int g, int u, uint32_t *cfgw)
     }
 }
 
+// SPLIT: the two decoding-graph colours are independent matchings, so each
+// half of the wavefront (32 lanes) runs one, and both XOR their paths into the
+// shared configuration -- twice the lanes at work where a colour has no more
+// than a few dozen defects.  Otherwise the whole wavefront runs the colours one
+// after the other.
+template <bool SPLIT>
 __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -175,139 +182,144 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     const uint32_t r = (uint32_t)(sr - s * A.n_rep);
     const uint32_t uid = A.uid[s];
     const int nwords = (nq + 3) / 4;
+    constexpr int kHalf = SPLIT ? kWave / 2 : kWave;   // lanes per colour
+    const int hl = lane % kHalf;
+    const int stride = A.max_nodes + 1;
     uint32_t *cfgw = reinterpret_cast<uint32_t *>(smem);
-    int32_t *D = reinterpret_cast<int32_t *>(smem + 4 * nwords);
-    int32_t *best = D + A.max_nodes + 1;
-    int32_t *pairs = best + A.max_nodes + 1;
-    int32_t *dbD = pairs + A.max_nodes + 1;   // boundary distance of each defect
-    int16_t *cands = reinterpret_cast<int16_t *>(dbD + A.max_nodes + 1);   // [64][kGreedyTies]
-    uint8_t *freef = reinterpret_cast<uint8_t *>(cands + kWave * kGreedyTies);
-    __shared__ int s_count;
+    int16_t *cands = reinterpret_cast<int16_t *>(reinterpret_cast<int32_t *>(smem + 4 * nwords) + 8 * stride);
+    __shared__ int s_count[2];
 
     for (int i = lane; i < nwords; i += kWave) cfgw[i] = 0;
+    if (lane == 0) { s_count[0] = 0; s_count[1] = 0; }
     const uint8_t *sy = A.syn + s * A.syn_stride;
-    for (int g = 0; g < 2; ++g) {
+    const int n_both = max(pl->ncol[0], pl->ncol[1]);
+    for (int gg = 0; gg < (SPLIT ? 1 : 2); ++gg) {
+        const int g = SPLIT ? lane / kHalf : gg;
+        int32_t *D = reinterpret_cast<int32_t *>(smem + 4 * nwords) + g * 4 * stride;
+        int32_t *best = D + stride;
+        int32_t *pairs = best + stride;
+        int32_t *dbD = pairs + stride;   // boundary distance of each defect
+        uint8_t *freef = reinterpret_cast<uint8_t *>(cands + kWave * kGreedyTies) + g * stride;
         const int n = pl->ncol[g];
         const int32_t *cf = pl->col_face[g];
         const int32_t *dint = pl->dint[g];
         const int32_t *db = pl->db[g];
         // defects of this colour, ascending node index
         int nd = 0;
-        for (int base = 0; base < n; base += kWave) {
-            const int v = base + lane;
+        for (int base = 0; base < (SPLIT ? n_both : n); base += kHalf) {
+            const int v = base + hl;
             const bool flag = v < n && sy[cf[v]];
-            const uint64_t mask = __ballot(flag);
-            const int pos = nd + __popcll(mask & ((1ull << lane) - 1ull));
+            const uint64_t mask = SPLIT ? ((__ballot(flag) >> (g * kHalf)) & 0xFFFFFFFFull) : __ballot(flag);
+            const int pos = nd + __popcll(mask & ((1ull << hl) - 1ull));
             if (flag) D[pos] = v;
             nd += __popcll(mask);
         }
         __syncthreads();
         if (A.mode == XZZX_GREEDY_BOUNDARY) {
-            for (int i = lane; i < nd; i += kWave) walk_boundary(pl, g, D[i], cfgw);
+            for (int i = hl; i < nd; i += kHalf) walk_boundary(pl, g, D[i], cfgw);
+        } else {
+            const int na = nd + (nd & 1);   // odd count: the virtual boundary joins as node nd
+            for (int i = hl; i < na; i += kHalf) freef[i] = 1;
+            for (int i = hl; i < nd; i += kHalf) dbD[i] = db[D[i]];
             __syncthreads();
-            continue;
-        }
-        const int na = nd + (nd & 1);   // odd count: the virtual boundary joins as node nd
-        for (int i = lane; i < na; i += kWave) freef[i] = 1;
-        for (int i = lane; i < nd; i += kWave) dbD[i] = db[D[i]];
-        if (lane == 0) s_count = 0;
-        __syncthreads();
-        int nfree = na;
-        const bool randomized = A.mode == XZZX_GREEDY_RANDOM;
-        // every round matches at least the least free pair, so na/2 rounds
-        // suffice.  Free defects only leave, so a defect whose least partner
-        // is still free keeps it; only the others search again.
-        for (int round = 0; nfree > 0 && round <= na / 2; ++round) {
-            for (int i = lane; i < na; i += kWave) {
-                if (!freef[i]) continue;
-                if (round > 0 && best[i] >= 0 && freef[best[i]]) continue;
-                // least (w, key, id) over free partners j, in two passes: the
-                // least weight and the partners at it (in ascending j, so
-                // ascending pair id), then keys for those partners only -- a
-                // single scan that drew a key on every tie so far made the
-                // wavefront draw one for nearly every partner.  The interior
-                // distances of a batch of partners are loaded before any is used.
-                const bool iv = i == nd;   // the virtual boundary node
-                const int32_t dbi = iv ? 0 : dbD[i];
-                const int32_t *drow = dint + (size_t)(iv ? 0 : D[i]) * n;
-                int16_t *cand = cands + lane * kGreedyTies;
-                auto weight = [&](int j, int32_t dj) -> uint32_t {
-                    // a pair with the virtual node weighs the real defect's boundary distance
-                    return iv ? (uint32_t)dbD[j] : j == nd ? (uint32_t)dbi : (uint32_t)min(dj, dbi + dbD[j]);
-                };
-                uint32_t bw = 0xFFFFFFFFu;
-                int nt = 0;   // partners at weight bw
-                for (int j0 = 0; j0 < na; j0 += kGreedyBatch) {
-                    int32_t dv[kGreedyBatch];
-#pragma unroll
-                    for (int k = 0; k < kGreedyBatch; ++k) dv[k] = drow[j0 + k < nd ? D[j0 + k] : 0];
-#pragma unroll
-                    for (int k = 0; k < kGreedyBatch; ++k) {
-                        const int j = j0 + k;
-                        if (j >= na || j == i || !freef[j]) continue;
-                        const uint32_t w = weight(j, dv[k]);
-                        if (w > bw) continue;
-                        if (w < bw) { bw = w; nt = 0; }
-                        if (nt < kGreedyTies) cand[nt] = (int16_t)j;
-                        ++nt;
-                    }
-                }
-                int bj = nt > 0 ? cand[0] : -1;
-                if (randomized && nt > 1) {
-                    auto pair_id = [&](int j) { return (uint32_t)(min(i, j) * na + max(i, j)); };
-                    auto pair_key = [&](uint32_t id) {
-                        return philox4x32_10(make_uint4(uid, r, 0x100u + (uint32_t)g, id), A.seed_lo, A.seed_hi).x;
+            int nfree = na;
+            const bool randomized = A.mode == XZZX_GREEDY_RANDOM;
+            // every round matches at least the least free pair, so na/2 rounds
+            // suffice (rounds continue while either half has work).  Free
+            // defects only leave, so a defect whose least partner is still free
+            // keeps it; only the others search again.
+            for (int round = 0; __ballot(nfree > 0 && round <= na / 2) != 0; ++round) {
+                for (int i = hl; i < na; i += kHalf) {
+                    if (!freef[i]) continue;
+                    if (round > 0 && best[i] >= 0 && freef[best[i]]) continue;
+                    // least (w, key, id) over free partners j, in two passes: the
+                    // least weight and the partners at it (in ascending j, so
+                    // ascending pair id), then keys for those partners only -- a
+                    // single scan that drew a key on every tie so far made the
+                    // wavefront draw one for nearly every partner.  The interior
+                    // distances of a batch of partners are loaded before any is used.
+                    const bool iv = i == nd;   // the virtual boundary node
+                    const int32_t dbi = iv ? 0 : dbD[i];
+                    const int32_t *drow = dint + (size_t)(iv ? 0 : D[i]) * n;
+                    int16_t *cand = cands + lane * kGreedyTies;
+                    auto weight = [&](int j, int32_t dj) -> uint32_t {
+                        // a pair with the virtual node weighs the real defect's boundary distance
+                        return iv ? (uint32_t)dbD[j] : j == nd ? (uint32_t)dbi : (uint32_t)min(dj, dbi + dbD[j]);
                     };
-                    uint32_t bid = pair_id(bj), bk = pair_key(bid);
-                    if (nt <= kGreedyTies) {
-                        for (int t = 1; t < nt; ++t) {
-                            const int j = cand[t];
-                            const uint32_t id = pair_id(j), key = pair_key(id);
-                            if (key < bk) { bk = key; bid = id; bj = j; }   // ids ascend: ties keep the first
-                        }
-                    } else {
-                        // more ties than the list holds: scan again
-                        for (int j = bj + 1; j < na; ++j) {
-                            if (j == i || !freef[j]) continue;
-                            const int32_t dj = (!iv && j < nd) ? drow[D[j]] : 0;
-                            if (weight(j, dj) != bw) continue;
-                            const uint32_t id = pair_id(j), key = pair_key(id);
-                            if (key < bk) { bk = key; bid = id; bj = j; }
+                    uint32_t bw = 0xFFFFFFFFu;
+                    int nt = 0;   // partners at weight bw
+                    for (int j0 = 0; j0 < na; j0 += kGreedyBatch) {
+                        int32_t dv[kGreedyBatch];
+#pragma unroll
+                        for (int k = 0; k < kGreedyBatch; ++k) dv[k] = drow[j0 + k < nd ? D[j0 + k] : 0];
+#pragma unroll
+                        for (int k = 0; k < kGreedyBatch; ++k) {
+                            const int j = j0 + k;
+                            if (j >= na || j == i || !freef[j]) continue;
+                            const uint32_t w = weight(j, dv[k]);
+                            if (w > bw) continue;
+                            if (w < bw) { bw = w; nt = 0; }
+                            if (nt < kGreedyTies) cand[nt] = (int16_t)j;
+                            ++nt;
                         }
                     }
+                    int bj = nt > 0 ? cand[0] : -1;
+                    if (randomized && nt > 1) {
+                        auto pair_id = [&](int j) { return (uint32_t)(min(i, j) * na + max(i, j)); };
+                        auto pair_key = [&](uint32_t id) {
+                            return philox4x32_10(make_uint4(uid, r, 0x100u + (uint32_t)g, id), A.seed_lo, A.seed_hi).x;
+                        };
+                        uint32_t bid = pair_id(bj), bk = pair_key(bid);
+                        if (nt <= kGreedyTies) {
+                            for (int t = 1; t < nt; ++t) {
+                                const int j = cand[t];
+                                const uint32_t id = pair_id(j), key = pair_key(id);
+                                if (key < bk) { bk = key; bid = id; bj = j; }   // ids ascend: ties keep the first
+                            }
+                        } else {
+                            // more ties than the list holds: scan again
+                            for (int j = bj + 1; j < na; ++j) {
+                                if (j == i || !freef[j]) continue;
+                                const int32_t dj = (!iv && j < nd) ? drow[D[j]] : 0;
+                                if (weight(j, dj) != bw) continue;
+                                const uint32_t id = pair_id(j), key = pair_key(id);
+                                if (key < bk) { bk = key; bid = id; bj = j; }
+                            }
+                        }
+                    }
+                    best[i] = bj;
                 }
-                best[i] = bj;
-            }
-            __syncthreads();
-            for (int i = lane; i < na; i += kWave) {
-                if (!freef[i]) continue;
-                const int j = best[i];
-                if (j > i && best[j] == i) {
-                    const int p = atomicAdd(&s_count, 1);
-                    pairs[p] = i | (j << 16);
+                __syncthreads();
+                for (int i = hl; i < na; i += kHalf) {
+                    if (!freef[i]) continue;
+                    const int j = best[i];
+                    if (j > i && best[j] == i) {
+                        const int p = atomicAdd(&s_count[g], 1);
+                        pairs[p] = i | (j << 16);
+                    }
                 }
+                __syncthreads();
+                const int np = s_count[g];
+                for (int p = hl; p < np; p += kHalf) {
+                    freef[pairs[p] & 0xFFFF] = 0;
+                    freef[pairs[p] >> 16] = 0;
+                }
+                __syncthreads();
+                nfree = na - 2 * np;
             }
-            __syncthreads();
-            const int np = s_count;
-            for (int p = lane; p < np; p += kWave) {
-                freef[pairs[p] & 0xFFFF] = 0;
-                freef[pairs[p] >> 16] = 0;
-            }
-            __syncthreads();
-            nfree = na - 2 * np;
-        }
-        const int np = s_count;
-        for (int p = lane; p < np; p += kWave) {
-            const int i = pairs[p] & 0xFFFF, j = pairs[p] >> 16;
-            if (j == nd) {
-                walk_boundary(pl, g, D[i], cfgw);
-            } else {
-                const int u = D[i], v = D[j];
-                if (dint[(size_t)u * n + v] <= db[u] + db[v]) {
-                    walk_interior(pl, g, u, v, cfgw);
+            const int np = s_count[g];
+            for (int p = hl; p < np; p += kHalf) {
+                const int i = pairs[p] & 0xFFFF, j = pairs[p] >> 16;
+                if (j == nd) {
+                    walk_boundary(pl, g, D[i], cfgw);
                 } else {
-                    walk_boundary(pl, g, u, cfgw);
-                    walk_boundary(pl, g, v, cfgw);
+                    const int u = D[i], v = D[j];
+                    if (dint[(size_t)u * n + v] <= db[u] + db[v]) {
+                        walk_interior(pl, g, u, v, cfgw);
+                    } else {
+                        walk_boundary(pl, g, u, cfgw);
+                        walk_boundary(pl, g, v, cfgw);
+                    }
                 }
             }
         }
@@ -549,11 +561,17 @@ static int check_hip(hipError_t e, const char *what)
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// One colour per half wavefront where a colour has at most 128 nodes (rotated
+// d <= 15: few enough defects that 32 lanes take them in one or two turns);
+// the whole wavefront per colour on larger lattices.
+static bool greedy_split(const Plan &P) { return std::max(P.hdev.ncol[0], P.hdev.ncol[1]) <= 128; }
+
 static int greedy_lds(const Plan &P, int *max_nodes)
 {
     const int mn = std::max(P.hdev.ncol[0], P.hdev.ncol[1]);
     *max_nodes = mn;
-    return 4 * ((P.lat.nq + 3) / 4) + 4 * 4 * (mn + 1) + 2 * kWave * kGreedyTies + (mn + 1) + 16;
+    // per colour (one per half wavefront): D, best, pairs, dbD and the free flags
+    return 4 * ((P.lat.nq + 3) / 4) + 2 * 4 * 4 * (mn + 1) + 2 * kWave * kGreedyTies + 2 * (mn + 1) + 16;
 }
 
 static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_uid, int64_t n_syn,
@@ -576,7 +594,8 @@ static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_
     const int lds = greedy_lds(P, &A.max_nodes);
     const int64_t blocks = n_syn * n_rep;
     if (blocks > 0x7FFFFFFF) { set_error("too many (syndrome, replica) pairs"); return XZZX_ERANGE; }
-    hipLaunchKernelGGL(k_greedy, dim3((unsigned)blocks), dim3(kWave), lds, stream, A);
+    hipLaunchKernelGGL(greedy_split(P) ? k_greedy<true> : k_greedy<false>, dim3((unsigned)blocks), dim3(kWave), lds,
+                       stream, A);
     return check_hip(hipGetLastError(), "k_greedy launch");
 }
 
@@ -1012,7 +1031,8 @@ int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const 
     A.seed_lo = (uint32_t)seed;
     A.seed_hi = (uint32_t)(seed >> 32);
     const int lds = greedy_lds(P, &A.max_nodes);
-    hipLaunchKernelGGL(k_greedy, dim3((unsigned)(n * n_rep)), dim3(kWave), lds, stream, A);
+    hipLaunchKernelGGL(greedy_split(P) ? k_greedy<true> : k_greedy<false>, dim3((unsigned)(n * n_rep)), dim3(kWave),
+                       lds, stream, A);
     return check_hip(hipGetLastError(), "serving greedy launch");
 }
 

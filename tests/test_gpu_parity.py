@@ -45,10 +45,15 @@ def test_syndrome_kernel():
         assert np.array_equal(got, prob.olat.syndrome(cfg))
 
 
-@pytest.mark.parametrize("layout,d,p,eta", [(0, 3, 0.15, 10.0), (0, 11, 0.25, 100.0), (0, 21, 0.18, 10.0),
-                                            (0, 31, 0.2, 10.0), (1, 7, 0.1, 1.0)])
+@pytest.mark.parametrize("layout,d,p,eta", [(0, 3, 0.15, 10.0), (0, 11, 0.25, 100.0), (0, 15, 0.3, 1.0),
+                                            (0, 17, 0.2, 10.0), (0, 21, 0.18, 10.0), (0, 31, 0.2, 10.0),
+                                            (1, 7, 0.1, 1.0)])
 @pytest.mark.parametrize("mode", [X.GREEDY_RANDOM, X.GREEDY_SAME, X.GREEDY_BOUNDARY])
 def test_greedy_kernel(layout, d, p, eta, mode):
+    """References of the GPU greedy kernel equal the oracle's byte for byte.
+    Up to 128 nodes per colour (rotated d <= 15) each half wavefront matches
+    one colour (d = 15 at p = 0.3: several defects per lane); beyond, the
+    colours take the whole wavefront in turn."""
     n_syn, R = (12, 5) if d < 31 else (3, 4)
     prob = Problem(layout, d, p, eta, n_syn, R, 0, seed=d + 3)
     plan = gpu_plan(prob)
