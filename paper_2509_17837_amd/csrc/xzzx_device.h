@@ -822,10 +822,10 @@ __device__ __forceinline__ void static_block(uint32_t (&r)[StaticRows<D>::N], co
     // were, so all four look up their entries from the rows before any flip
     // and their LDS reads overlap (looked up one after another, each move's
     // pattern waited for the previous move's flips of the same row words).
-    // Moves looked up together per group (measured per distance): four,
-    // but pairs at d = 15, where four entries in flight spill, and one at a
-    // time at d = 13, which ran fastest so.
-    constexpr int OV = D == 13 ? 1 : D == 15 ? 2 : 4;
+    // Moves looked up together per group (measured per distance): four, but
+    // one at a time at d = 15, where four entries in flight spill (and pairs
+    // measured slower).
+    constexpr int OV = D == 15 ? 1 : 4;
     if constexpr (OV == 1) {
         static_apply<D, K, B, 0>(r, u.x, static_lookup<D, K, B, 0>(r, lut_s, et_s), acc);
         static_apply<D, K, B, 1>(r, u.y, static_lookup<D, K, B, 1>(r, lut_s, et_s), acc);
