@@ -186,7 +186,10 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     const int hl = lane % kHalf;
     const int stride = A.max_nodes + 1;
     uint32_t *cfgw = reinterpret_cast<uint32_t *>(smem);
-    int16_t *cands = reinterpret_cast<int16_t *>(reinterpret_cast<int32_t *>(smem + 4 * nwords) + 8 * stride);
+    // per colour: D, best, pairs, dbD and the free flags (the colours in turn
+    // share one set)
+    constexpr int kSets = SPLIT ? 2 : 1;
+    int16_t *cands = reinterpret_cast<int16_t *>(reinterpret_cast<int32_t *>(smem + 4 * nwords) + kSets * 4 * stride);
     __shared__ int s_count[2];
 
     for (int i = lane; i < nwords; i += kWave) cfgw[i] = 0;
@@ -195,11 +198,12 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     const int n_both = max(pl->ncol[0], pl->ncol[1]);
     for (int gg = 0; gg < (SPLIT ? 1 : 2); ++gg) {
         const int g = SPLIT ? lane / kHalf : gg;
-        int32_t *D = reinterpret_cast<int32_t *>(smem + 4 * nwords) + g * 4 * stride;
+        const int set = SPLIT ? g : 0;
+        int32_t *D = reinterpret_cast<int32_t *>(smem + 4 * nwords) + set * 4 * stride;
         int32_t *best = D + stride;
         int32_t *pairs = best + stride;
         int32_t *dbD = pairs + stride;   // boundary distance of each defect
-        uint8_t *freef = reinterpret_cast<uint8_t *>(cands + kWave * kGreedyTies) + g * stride;
+        uint8_t *freef = reinterpret_cast<uint8_t *>(cands + kWave * kGreedyTies) + set * stride;
         const int n = pl->ncol[g];
         const int32_t *cf = pl->col_face[g];
         const int32_t *dint = pl->dint[g];
@@ -570,8 +574,10 @@ static int greedy_lds(const Plan &P, int *max_nodes)
 {
     const int mn = std::max(P.hdev.ncol[0], P.hdev.ncol[1]);
     *max_nodes = mn;
-    // per colour (one per half wavefront): D, best, pairs, dbD and the free flags
-    return 4 * ((P.lat.nq + 3) / 4) + 2 * 4 * 4 * (mn + 1) + 2 * kWave * kGreedyTies + 2 * (mn + 1) + 16;
+    // D, best, pairs, dbD and the free flags: one set per colour when the
+    // halves of the wavefront match the colours at once, else one
+    const int sets = greedy_split(P) ? 2 : 1;
+    return 4 * ((P.lat.nq + 3) / 4) + sets * 4 * 4 * (mn + 1) + 2 * kWave * kGreedyTies + sets * (mn + 1) + 16;
 }
 
 static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_uid, int64_t n_syn,
