@@ -108,6 +108,14 @@ def parse():
     ap.add_argument("--by-distance", action="store_true",
                     help="annealing rate of the default kernel for each odd d in --distances")
     ap.add_argument("--distances", default="11,13,15,17,21,25,29,31")
+    ap.add_argument("--paper-trends", action="store_true",
+                    help="logical error rates of the paper's set-up against N_SA and N_beta (planar, 1:eta:1)")
+    ap.add_argument("--trend-d", type=int, default=9)
+    ap.add_argument("--trend-p", type=float, default=0.15)
+    ap.add_argument("--trend-etas", default="1,5,10")
+    ap.add_argument("--trend-samples", type=int, default=20000)
+    ap.add_argument("--trend-nsa", default="1,2,3,5,10,20,50,100")
+    ap.add_argument("--trend-nbeta", default="0,5,10,20,50,100")
     return ap.parse_args()
 
 
@@ -128,6 +136,8 @@ def main():
         return serve_bench(args)
     if args.by_distance:
         return distance_bench(args)
+    if args.paper_trends:
+        return trends_bench(args)
     wl = inputs.WORKLOADS[args.workload]
     seeds = inputs.seeds(args.workload)
     sched_kind = inputs.SCHEDULE_KIND[wl["schedule"][0]]
@@ -139,12 +149,13 @@ def main():
 
     # ---- plans: one group per (d, p, eta) --------------------------------
     specs = [(d, p, eta) for d in wl["d"] for p in wl["p"] for eta in wl["eta"]]
+    layout, conv = inputs.layout_of(wl), inputs.convention_of(wl)
     plans, lats = [], {}
     beta = D.schedule(sched_kind, wl["schedule"][1], wl["schedule"][2], sweeps)
     for d, p, eta in specs:
         if d not in lats:
-            lats[d] = D.Lattice(X.ROTATED, d)
-        w, wg = D.weights(p, D.noise(p, eta))
+            lats[d] = D.Lattice(layout, d)
+        w, wg = D.weights(p, D.noise(p, eta, conv))
         plans.append(D.Plan(lats[d], w, wg, beta))
     ng = len(plans)
     tuned = {}
@@ -158,7 +169,8 @@ def main():
     for k in range(steps + warm):
         row_s, row_u, row_e = [], [], []
         for gi, ((d, p, eta), plan) in enumerate(zip(specs, plans)):
-            err = inputs.sample_errors(B, plan.nq, inputs.channel(p, eta), seeds["sample"], stream=k * 64 + gi)
+            err = inputs.sample_errors(B, plan.nq, inputs.channel(p, eta, conv), seeds["sample"],
+                                       stream=k * 64 + gi)
             e_dev = torch.from_numpy(err).to(dev)
             row_s.append(D.syndrome(plan, e_dev))
             row_u.append(torch.from_numpy(inputs.sample_uids(B, (k * ng + gi) * B).view(np.int32)).to(dev))
@@ -251,7 +263,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": f"rotated XZZX d={','.join(str(d) for d in wl['d'])}, eta={wl['eta']}, p={wl['p']}, "
+            "workload": f"{wl.get('layout', 'rotated')} XZZX d={','.join(str(d) for d in wl['d'])}, "
+                        f"{'p_x:p_y:p_z = 1:eta:1' if conv else 'p_y = p eta/(eta+1)'}, eta={wl['eta']}, p={wl['p']}, "
                         f"{R} replicas ({4 * R} chains)/syndrome, {sweeps} sweeps {wl['schedule'][0]} "
                         f"{wl['schedule'][1]}->{wl['schedule'][2]}",
             "name": args.workload,
@@ -320,14 +333,17 @@ def cpu_baseline(args, wl, specs, plans, syn0, uid0, outs, R, sweeps, gs, as_):
     ng = len(specs)
     sched = wl["schedule"]
     obeta = O.schedule({"linear": 0, "geometric": 1, "paper_log": 2}[sched[0]], sched[1], sched[2], sweeps)
-    owts = [O.weights(p, O.noise(p, eta)) for (_, p, eta) in specs]
+    from paper_2509_17837_amd import inputs
+
+    layout, conv = inputs.layout_of(wl), inputs.convention_of(wl)
+    owts = [O.weights(p, O.noise(p, eta, conv)) for (_, p, eta) in specs]
     syn = [s.cpu().numpy() for s in syn0]
     uid = [u.cpu().numpy().view(np.uint32) for u in uid0]
 
     def one(job):
         g, i = job
         d = specs[g][0]
-        lat = O.Lattice(O.ROTATED, d)
+        lat = O.Lattice(layout, d)
         return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, gs, as_)
 
     # size the sample from one timed syndrome
@@ -403,6 +419,101 @@ def distance_bench(args):
                       "config": {"workload": f"rotated XZZX, p={p}, eta={eta}, {R} replicas, {sweeps} sweeps "
                                              f"geometric 0.05->10"},
                       "distances": rows}), flush=True)
+
+
+def logical_failures(lat, err, rec):
+    """Rows i where err[i] * rec[i] is a non-trivial logical operator, i.e.
+    anticommutes with L_X or L_Z (both have the syndrome of err[i])."""
+    lx, lz = lat.logicals()
+    e = np.bitwise_xor(err, rec).astype(np.int64)
+    ex, ez = (e >> 1) & 1, e & 1
+
+    def symp(L):
+        L = L.astype(np.int64)
+        return (ex @ (L & 1) + ez @ ((L >> 1) & 1)) & 1
+
+    return (symp(lx) | symp(lz)).astype(bool)
+
+
+def trends_bench(args):
+    """Logical error rates of the paper's own set-up (Sec. V): planar layout,
+    p_x:p_y:p_z = 1:eta:1, log schedule 0.9 beta_N -> beta_N (Eqs. 23-24).
+      * P_L against N_SA at N_beta = 100 with randomized greedy references
+        (Alg. 6), and the greedy-matching decoder (Alg. 5) alone (Figs. 6-8);
+      * P_L against N_beta at N_SA = 10 for the three reference constructions
+        of Sec. V.C: boundary, greedy (same), greedy (different) (Figs. 9-11,
+        which plot the ratio to an exact decoder; P_L itself is reported here).
+    Every rate is over the same seeded syndromes, so two settings can also be
+    compared pair by pair: `better`/`worse` count syndromes that one setting
+    decodes and the other does not (each check lists `better` and `worse`
+    for the setting the paper finds better)."""
+    import torch
+
+    from paper_2509_17837_amd import _lib as X
+    from paper_2509_17837_amd import decoder as D
+    from paper_2509_17837_amd import inputs
+
+    d, p, n = args.trend_d, args.trend_p, args.trend_samples
+    etas = [float(x) for x in args.trend_etas.split(",")]
+    nsas = [int(x) for x in args.trend_nsa.split(",")]
+    nbetas = [int(x) for x in args.trend_nbeta.split(",")]
+    dev = torch.device("cuda:0")
+    lat = D.Lattice(X.PLANAR, d)
+    gs, as_ = 0x7E4D0000 + d, 0xA11E7E4D0000 + d
+    t_start = time.perf_counter()
+
+    def rate(fail):
+        m = float(fail.mean())
+        return [m, float(np.sqrt(max(m * (1 - m), 1e-300) / len(fail)))]
+
+    def paired(fa, fb):
+        """Failure arrays of settings a (the one the paper finds better) and b:
+        syndromes only a decodes (better) and only b decodes (worse)."""
+        return {"better": int(np.count_nonzero(~fa & fb)), "worse": int(np.count_nonzero(fa & ~fb))}
+
+    out = {"mode": "paper_trends", "data": "synthetic",
+           "config": {"layout": "planar", "d": d, "p": p, "etas": etas, "channel": "p_x:p_y:p_z = 1:eta:1",
+                      "schedule": "paper_log 0.9 -> 1.0 (units of beta_N)", "syndromes": n},
+           "p_l_vs_n_sa": {}, "greedy_decoder": {}, "p_l_vs_n_beta": {}, "checks": {}}
+    for eta in etas:
+        key = f"eta{eta:g}"
+        w, wg = D.weights(p, D.noise(p, eta, X.BIAS_PAPER))
+        err = inputs.sample_errors(n, lat.nq, inputs.channel(p, eta, 1), 4242, stream=int(eta * 10))
+        uid = torch.from_numpy(inputs.sample_uids(n).view(np.int32)).to(dev)
+        plans = {nb: D.Plan(lat, w, wg, D.schedule(X.SCHED_PAPER_LOG, 0.9, 1.0, nb)) for nb in set(nbetas) | {100}}
+        syn = D.syndrome(plans[100], torch.from_numpy(err).to(dev))
+        # greedy-matching decoder: the reference of Alg. 5 is the recovery
+        refs, _ = D.greedy_init(plans[100], syn, uid, 1, gs, X.GREEDY_SAME)
+        f_greedy = logical_failures(lat, err, refs[:, 0].cpu().numpy())
+        out["greedy_decoder"][key] = rate(f_greedy)
+        fails = {}
+        for nsa in nsas:
+            o = D.decode(plans[100], syn, uid, nsa, gs, as_, X.GREEDY_RANDOM)
+            fails[nsa] = logical_failures(lat, err, o.recovery.cpu().numpy())
+        out["p_l_vs_n_sa"][key] = {str(k): rate(v) for k, v in fails.items()}
+        byinit = {}
+        for mname, mode in (("boundary", X.GREEDY_BOUNDARY), ("greedy_same", X.GREEDY_SAME),
+                            ("greedy_different", X.GREEDY_RANDOM)):
+            byinit[mname] = {}
+            for nb in nbetas:
+                o = D.decode(plans[nb], syn, uid, 10, gs, as_, mode)
+                byinit[mname][nb] = logical_failures(lat, err, o.recovery.cpu().numpy())
+        out["p_l_vs_n_beta"][key] = {m: {str(nb): rate(f) for nb, f in v.items()} for m, v in byinit.items()}
+        # pair-by-pair comparisons behind the paper's statements
+        ks = sorted(fails)
+        out["checks"][key] = {
+            "n_sa_steps": {f"{a}->{b}": paired(fails[b], fails[a]) for a, b in zip(ks, ks[1:])},
+            "sa_vs_greedy": {str(k): paired(fails[k], f_greedy) for k in ks},
+            "different_vs_same": {str(nb): paired(byinit["greedy_different"][nb], byinit["greedy_same"][nb])
+                                  for nb in nbetas},
+            "same_vs_boundary": {str(nb): paired(byinit["greedy_same"][nb], byinit["boundary"][nb])
+                                 for nb in nbetas},
+        }
+        print(f"[trends] eta={eta:g} greedy {out['greedy_decoder'][key][0]:.4f} "
+              + " ".join(f"N_SA={k}:{fails[k].mean():.4f}" for k in ks), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    out["seconds"] = time.perf_counter() - t_start
+    print(json.dumps(out), flush=True)
 
 
 def serve_bench(args):

@@ -38,8 +38,11 @@ def sample_uids(n: int, first: int = 0) -> np.ndarray:
     return np.arange(first, first + n, dtype=np.uint32)
 
 
-# The five measured workloads (rotated layout).  Seeds: sample 1000+k,
-# greedy 2000+k, anneal 3000+k for workload k.
+# The measured workloads.  The first five use the rotated layout and the
+# channel of convention 0; the last is the paper's own set-up (Sec. IV.B, Sec. V):
+# planar layout, p_x:p_y:p_z = 1:eta:1, the log schedule of Eqs. 23-24 from
+# 0.9 beta_N to beta_N with N_beta = 100, N_SA = 10 references per syndrome.
+# Seeds: sample 1000+k, greedy 2000+k, anneal 3000+k for workload k.
 WORKLOADS = {
     "d3_small": dict(d=[3], p=[0.15], eta=[10.0], n_syn=1000, n_rep=1, sweeps=200,
                      schedule=("linear", 0.1, 5.0)),
@@ -52,9 +55,21 @@ WORKLOADS = {
                           rates=[1e3, 3e3, 1e4, 3e4, 1e5]),
     "d31_large": dict(d=[31], p=[0.20], eta=[10.0], n_syn=10000, n_rep=128, sweeps=10000,
                       schedule=("geometric", 0.02, 20.0)),
+    "planar_paper_d9": dict(layout="planar", convention="paper", d=[9], p=[0.10, 0.15], eta=[1.0, 5.0, 10.0],
+                            n_syn=100000, n_rep=10, sweeps=100, schedule=("paper_log", 0.9, 1.0)),
 }
 WORKLOAD_INDEX = {name: k for k, name in enumerate(WORKLOADS)}
 SCHEDULE_KIND = {"linear": 0, "geometric": 1, "paper_log": 2}
+LAYOUT_KIND = {"rotated": 0, "planar": 1}
+CONVENTION_KIND = {"baseline": 0, "paper": 1}
+
+
+def layout_of(wl) -> int:
+    return LAYOUT_KIND[wl.get("layout", "rotated")]
+
+
+def convention_of(wl) -> int:
+    return CONVENTION_KIND[wl.get("convention", "baseline")]
 
 
 def seeds(name: str):

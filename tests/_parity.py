@@ -24,7 +24,7 @@ def pool():
 class Problem:
     def __init__(self, layout, d, p, eta, n_syn, n_rep, n_sweeps, sched=("geometric", 0.05, 10.0),
                  seed=11, conv=0, uid0=0, beta=None):
-        self.layout, self.d, self.p, self.eta = layout, d, p, eta
+        self.layout, self.d, self.p, self.eta, self.conv = layout, d, p, eta, conv
         self.n_syn, self.n_rep, self.n_sweeps = n_syn, n_rep, n_sweeps
         self.olat = O.Lattice(layout, d)
         self.pxyz = O.noise(p, eta, conv)
@@ -65,7 +65,7 @@ class Problem:
 def gpu_plan(prob, lanes=None):
     from paper_2509_17837_amd import decoder as D
     lat = D.Lattice(prob.layout, prob.d)
-    w, wg = D.weights(prob.p, D.noise(prob.p, prob.eta))
+    w, wg = D.weights(prob.p, D.noise(prob.p, prob.eta, prob.conv))
     assert np.array_equal(w, prob.w) and np.array_equal(wg, prob.wg)
     beta = D.schedule(*prob.sched, prob.n_sweeps) if prob.custom_beta is None else prob.custom_beta
     plan = D.Plan(lat, w, wg, beta)

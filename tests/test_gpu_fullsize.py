@@ -30,20 +30,21 @@ def build_launch(name, n_per_group, graph):
     kind = inputs.SCHEDULE_KIND[wl["schedule"][0]]
     beta = D.schedule(kind, wl["schedule"][1], wl["schedule"][2], wl["sweeps"])
     specs = [(d, p, eta) for d in wl["d"] for p in wl["p"] for eta in wl["eta"]]
+    layout, conv = inputs.layout_of(wl), inputs.convention_of(wl)
     groups, outs, meta = [], [], []
     for gi, (d, p, eta) in enumerate(specs):
-        lat = D.Lattice(X.ROTATED, d)
-        w, wg = D.weights(p, D.noise(p, eta))
+        lat = D.Lattice(layout, d)
+        w, wg = D.weights(p, D.noise(p, eta, conv))
         plan = D.Plan(lat, w, wg, beta)
-        olat = O.Lattice(O.ROTATED, d)
-        err = inputs.sample_errors(n_per_group, lat.nq, inputs.channel(p, eta), seeds["sample"], stream=gi)
+        olat = O.Lattice(layout, d)
+        err = inputs.sample_errors(n_per_group, lat.nq, inputs.channel(p, eta, conv), seeds["sample"], stream=gi)
         syn = np.stack([olat.syndrome(e) for e in err])
         uid = inputs.sample_uids(n_per_group, gi * n_per_group)
         g, o = D.make_group(plan, wl["n_rep"], torch.from_numpy(uid.view(np.int32)).cuda(),
                             syn=torch.from_numpy(syn).cuda(), want_chains=True)
         groups.append(g)
         outs.append(o)
-        meta.append(dict(d=d, p=p, eta=eta, syn=syn, uid=uid, olat=olat, lat=lat, plan=plan))
+        meta.append(dict(d=d, p=p, eta=eta, layout=layout, conv=conv, syn=syn, uid=uid, olat=olat, lat=lat, plan=plan))
     print(f"[fullsize] {name}: {len(groups)} groups x {n_per_group} syndromes, R={wl['n_rep']}, "
           f"sweeps={wl['sweeps']}, graph={graph}", flush=True)
     if graph:
@@ -62,7 +63,7 @@ def check_properties(wl, outs, meta):
         eb = o.e_best.cpu().numpy()
         cls = o.cls.cpu().numpy()
         refs0 = o.refs[:, 0].cpu().numpy()
-        w = O.weights(m["p"], O.noise(m["p"], m["eta"]))[0]
+        w = O.weights(m["p"], O.noise(m["p"], m["eta"], m["conv"]))[0]
         emin = o.chain_emin.cpu().numpy()
         for i in range(len(rec)):
             assert np.array_equal(m["olat"].syndrome(rec[i]), m["syn"][i])
@@ -79,8 +80,8 @@ def oracle_syndromes(wl, seeds, outs, meta, picks):
     def one(job):
         gi, i = job
         m = meta[gi]
-        lat = O.Lattice(O.ROTATED, m["d"])
-        w, wg = O.weights(m["p"], O.noise(m["p"], m["eta"]))
+        lat = O.Lattice(m["layout"], m["d"])
+        w, wg = O.weights(m["p"], O.noise(m["p"], m["eta"], m["conv"]))
         return lat.decode(w, wg, m["syn"][i], int(m["uid"][i]), wl["n_rep"], beta, seeds["greedy"],
                           seeds["anneal"], chains=True)
 
@@ -103,8 +104,8 @@ def oracle_chains(wl, seeds, outs, meta, picks):
     def one(job):
         gi, i, c = job
         m = meta[gi]
-        lat = O.Lattice(O.ROTATED, m["d"])
-        w, wg = O.weights(m["p"], O.noise(m["p"], m["eta"]))
+        lat = O.Lattice(m["layout"], m["d"])
+        w, wg = O.weights(m["p"], O.noise(m["p"], m["eta"], m["conv"]))
         ref = lat.greedy(wg, m["syn"][i], int(m["uid"][i]), c // 4, seeds["greedy"])
         res = lat.anneal_chain(w, beta, seeds["anneal"], int(m["uid"][i]), c, ref ^ lat.logical(c % 4),
                                want_snap=False)
@@ -141,3 +142,13 @@ def test_d31_full_launch():
     rng = np.random.default_rng(6)
     picks = [(int(rng.integers(1)), int(rng.integers(2)), int(rng.integers(4 * wl["n_rep"]))) for _ in range(12)]
     oracle_chains(wl, seeds, outs, meta, picks)
+
+
+def test_planar_paper_full_launch():
+    """The paper's own set-up: planar layout, 1:eta:1 channel, log schedule
+    0.9 beta_N -> beta_N over N_beta = 100, N_SA = 10; six (p, eta) groups of
+    2048 syndromes in one captured launch, as the benchmark times them."""
+    wl, seeds, outs, meta = build_launch("planar_paper_d9", 2048, graph=True)
+    check_properties(wl, outs, meta)
+    picks = [(g, i) for g in range(len(outs)) for i in (0, 1, 1023, 2047)]
+    oracle_syndromes(wl, seeds, outs, meta, picks)

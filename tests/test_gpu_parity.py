@@ -88,6 +88,17 @@ def test_decode_layouts(layout, d):
     compare_decode(prob, out, prob.oracle_decode())
 
 
+@pytest.mark.parametrize("d,eta,n_beta", [(5, 1.0, 100), (9, 5.0, 100), (9, 10.0, 100), (9, 10.0, 7), (7, 5.0, 1)])
+@pytest.mark.parametrize("mode", [X.GREEDY_RANDOM, X.GREEDY_SAME, X.GREEDY_BOUNDARY])
+def test_paper_setup(d, eta, n_beta, mode):
+    """The paper's own set-up (Sec. V): planar layout, p_x:p_y:p_z = 1:eta:1,
+    log schedule 0.9 beta_N -> beta_N over N_beta sweeps (Eqs. 23-24, gamma = 0
+    at N_beta = 1), N_SA = 10, each reference construction of Sec. V.C."""
+    prob = Problem(1, d, 0.15, eta, 24, 10, n_beta, sched=("paper_log", 0.9, 1.0), seed=40 + d + n_beta, conv=1)
+    out = run_decode(prob, mode=mode)
+    compare_decode(prob, out, prob.oracle_decode(mode=mode))
+
+
 @pytest.mark.parametrize("d", [9, 25])
 def test_all_lane_counts_agree(d):
     """Lanes per chain (chains per wavefront) is a result-invariant knob."""
