@@ -21,6 +21,7 @@ ROTATED, PLANAR = 0, 1
 CONV_BASELINE, CONV_PAPER = 0, 1
 SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
+ORDER_COLOUR, ORDER_RANDOM_SITE = 0, 1   # colour-class sweeps; literal random-site steps (Alg. 3)
 
 
 def build(force: bool = False) -> str:
@@ -75,11 +76,14 @@ def lib():
                                       C.c_int, i32p]
         L.or_anneal_chain.argtypes = [P, i32p, f64p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32,
                                       u8p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.or_anneal_chain_site.argtypes = L.or_anneal_chain.argtypes
+        L.or_site_of.argtypes = [C.c_uint32, C.c_int]
+        L.or_site_of.restype = C.c_uint32
         L.or_decode.argtypes = [P, i32p, i32p, u8p, C.c_uint32, C.c_int, f64p, C.c_int,
                                 C.c_uint64, C.c_uint64, C.c_int,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                C.c_void_p, C.c_void_p, C.c_int]
+                                C.c_void_p, C.c_void_p, C.c_int, C.c_int]
         _lib = L
     return _lib
 
@@ -117,6 +121,11 @@ def schedule(kind, b0, b1, n):
     if rc:
         raise ValueError("or_schedule: invalid arguments")
     return beta[:n]
+
+
+def site_of(u, nstab):
+    """Generator picked by a 32-bit site draw u among nstab (Alg. 3 step)."""
+    return int(lib().or_site_of(int(u), int(nstab)))
 
 
 def threshold(beta, dE):
@@ -204,14 +213,15 @@ class Lattice:
             raise RuntimeError(f"or_greedy_pairs rc={n}")
         return pairs[:n]
 
-    def anneal_chain(self, w, beta, seed, uid, chain, init, check=False, want_snap=True):
+    def anneal_chain(self, w, beta, seed, uid, chain, init, check=False, want_snap=True, order=ORDER_COLOUR):
         cfg = np.array(init, np.uint8, copy=True)
         e = np.zeros(1, np.int64)
         emin = np.zeros(1, np.int64)
         stop = np.zeros(1, np.int32)
         snap = np.zeros(self.nq, np.uint8) if want_snap else None
         beta = np.ascontiguousarray(beta, np.float64)
-        rc = lib().or_anneal_chain(self.h, np.ascontiguousarray(w, np.int32), beta, len(beta),
+        fn = lib().or_anneal_chain_site if order == ORDER_RANDOM_SITE else lib().or_anneal_chain
+        rc = fn(self.h, np.ascontiguousarray(w, np.int32), beta, len(beta),
                                    seed, uid, chain, cfg, _ptr(e), _ptr(emin), _ptr(stop),
                                    _ptr(snap), 1 if check else 0)
         if rc:
@@ -219,7 +229,7 @@ class Lattice:
         return dict(final=cfg, e=int(e[0]), emin=int(emin[0]), stop=int(stop[0]), snap=snap)
 
     def decode(self, w, wg, syn, uid, n_rep, beta, greedy_seed, anneal_seed,
-               greedy_mode=GREEDY_RANDOM, check=False, chains=False):
+               greedy_mode=GREEDY_RANDOM, check=False, chains=False, order=ORDER_COLOUR):
         nq = self.nq
         nc = 4 * n_rep
         e_best = np.zeros(1, np.int64)
@@ -241,7 +251,7 @@ class Lattice:
                              greedy_seed, anneal_seed, greedy_mode,
                              _ptr(e_best), _ptr(cls_best), _ptr(e_cls), _ptr(rec), _ptr(prec),
                              _ptr(best_chain), _ptr(refs), _ptr(qcls), _ptr(cemin), _ptr(cstop),
-                             _ptr(ce), _ptr(cfin), 1 if check else 0)
+                             _ptr(ce), _ptr(cfin), 1 if check else 0, order)
         if rc:
             raise RuntimeError(f"or_decode rc={rc}")
         out = dict(e_best=int(e_best[0]), cls=int(cls_best[0]), e_cls=e_cls, recovery=rec,

@@ -869,6 +869,82 @@ int or_anneal_chain(const or_lat *L, const int32_t w[4], const double *beta, int
 }
 
 /* ------------------------------------------------------------------------- */
+/* Simulated annealing with the literal random-site Metropolis step, Algs. 2-3 */
+/* as printed: every step picks one generator uniformly at random, a sweep is */
+/* N_stab steps at the sweep's beta, and E_min is updated after every step.   */
+/*                                                                             */
+/* Random numbers (reading): step m of sweep t of chain c of syndrome uid     */
+/* uses the block Philox(seed; uid, c, 2^31 + t, m div 2): words 2(m mod 2)   */
+/* and 2(m mod 2) + 1 are the site draw u_s and the acceptance draw u_a.  The */
+/* site is face f = floor(u_s N_stab / 2^32) in face-id order (uniform up to  */
+/* N_stab / 2^32 per site).  Acceptance is the integer rule of or_threshold.  */
+/* E_min is updated strictly, so the snapshot is the first configuration      */
+/* attaining it; stop = t N_stab + m + 1 (0 = the initial configuration).     */
+/* ------------------------------------------------------------------------- */
+uint32_t or_site_of(uint32_t u, int nstab)
+{
+    return (uint32_t)(((uint64_t)u * (uint64_t)(uint32_t)nstab) >> 32);
+}
+
+int or_anneal_chain_site(const or_lat *L, const int32_t w[4], const double *beta, int n_sweeps,
+                         uint64_t seed, uint32_t uid, uint32_t chain, uint8_t *cfg,
+                         int64_t *e_out, int64_t *emin_out, int32_t *stop_out, uint8_t *snap,
+                         int check)
+{
+    if (n_sweeps < 0) return OR_EINVAL;
+    if ((int64_t)n_sweeps * L->nstab >= ((int64_t)1 << 31)) return OR_EINVAL;
+    uint8_t *syn0 = NULL, *cfg0 = NULL;
+    if (check) {
+        syn0 = (uint8_t *)malloc(L->nstab);
+        cfg0 = (uint8_t *)malloc(L->nq);
+        if (!syn0 || !cfg0) { free(syn0); free(cfg0); return OR_ENOMEM; }
+        or_syndrome(L, cfg, syn0);
+        memcpy(cfg0, cfg, L->nq);
+    }
+    int64_t e = or_energy(L, w, cfg);
+    int64_t emin = e;
+    int32_t stop = 0;
+    if (snap) memcpy(snap, cfg, L->nq);
+    int rc = OR_OK;
+    for (int t = 0; t < n_sweeps; ++t) {
+        double b = beta[t];
+        for (int m = 0; m < L->nstab; ++m) {
+            uint32_t ctr[4] = {uid, chain, 0x80000000u + (uint32_t)t, (uint32_t)m >> 1};
+            uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+            uint32_t r[4];
+            or_philox4x32_10(ctr, key, r);
+            uint32_t u_site = r[2 * (m & 1)], u_acc = r[2 * (m & 1) + 1];
+            int f = (int)or_site_of(u_site, L->nstab);
+            int64_t dE = 0;
+            for (int s = 0; s < 4; ++s) {
+                int q = L->fq[4 * f + s];
+                if (q < 0) continue;
+                uint8_t c = cfg[q];
+                dE += (int64_t)w[c ^ L->fm[4 * f + s]] - (int64_t)w[c];
+            }
+            if (accept_move(b, dE, u_acc)) {
+                for (int s = 0; s < 4; ++s) {
+                    int q = L->fq[4 * f + s];
+                    if (q >= 0) cfg[q] ^= L->fm[4 * f + s];
+                }
+                e += dE;
+            }
+            if (e < emin) {
+                emin = e;
+                stop = t * L->nstab + m + 1;
+                if (snap) memcpy(snap, cfg, L->nq);
+            }
+        }
+        if (check && (rc = check_chain(L, w, cfg, syn0, cfg0, e, emin)) != OR_OK) break;
+    }
+    free(syn0); free(cfg0);
+    if (e_out) *e_out = e;
+    if (emin_out) *emin_out = emin;
+    if (stop_out) *stop_out = stop;
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Decoder, Alg. 7 (Alg. 1 when every replica uses the same reference).       */
 /*                                                                             */
 /* Replica r (the paper's SA-run index i) gets reference R_r from the greedy  */
@@ -878,7 +954,9 @@ int or_anneal_chain(const or_lat *L, const int32_t w[4], const double *beta, int
 /* P* = argmin E_P (Eq. (21)), ties to the lowest index I<X<Y<Z.  The         */
 /* returned recovery is the minimum-energy configuration found: the snapshot  */
 /* of the lowest-index chain of class P* whose E_min equals E_P*.  R_0 L_P*,  */
-/* the output form of Alg. 7, is returned as well.                            */
+/* the output form of Alg. 7, is returned as well.  `order` selects the      */
+/* chain: colour-class sweeps (or_anneal_chain) or the literal random-site    */
+/* steps of Alg. 3 (or_anneal_chain_site).                                    */
 /* ------------------------------------------------------------------------- */
 int or_decode(or_lat *L, const int32_t w[4], const int32_t wg[2], const uint8_t *syn, uint32_t uid,
               int n_rep, const double *beta, int n_sweeps, uint64_t greedy_seed,
@@ -888,8 +966,9 @@ int or_decode(or_lat *L, const int32_t w[4], const int32_t wg[2], const uint8_t 
               uint8_t *refs /*[n_rep][nq] or NULL*/, int32_t *qcls /*[n_rep] or NULL*/,
               int64_t *chain_emin /*[4 n_rep] or NULL*/, int32_t *chain_stop,
               int64_t *chain_e, uint8_t *chain_final /*[4 n_rep][nq] or NULL*/,
-              int check)
+              int check, int order /*0: colour sweeps, 1: random-site steps*/)
 {
+    if (order != 0 && order != 1) return OR_EINVAL;
     if (n_rep < 1) return OR_EINVAL;
     int nq = L->nq;
     int rc = OR_OK;
@@ -917,8 +996,9 @@ int or_decode(or_lat *L, const int32_t w[4], const int32_t wg[2], const uint8_t 
             for (int q = 0; q < nq; ++q) cfg[q] = R[(size_t)r * nq + q] ^ lp[q];
             int64_t e, emin;
             int32_t stop;
-            rc = or_anneal_chain(L, w, beta, n_sweeps, anneal_seed, uid, (uint32_t)c, cfg, &e, &emin,
-                                 &stop, snap, check);
+            rc = (order ? or_anneal_chain_site : or_anneal_chain)(L, w, beta, n_sweeps, anneal_seed, uid,
+                                                                   (uint32_t)c, cfg, &e, &emin, &stop, snap,
+                                                                   check);
             if (rc) goto done;
             int cls = or_class_mul(Q[r], P);
             if (emin < best[cls]) {

@@ -187,3 +187,145 @@ def test_coset_relabelling():
             fin = out["chain_final"][4 * r + P]
             assert np.array_equal(L.syndrome(fin), syn)
             assert L.cls(fin, refs[0]) == O.lib().or_class_mul(expect, P)
+
+
+# --- the literal random-site chain (Alg. 3 as printed) -------------------------
+
+SITE = O.ORDER_RANDOM_SITE
+
+
+def test_site_draw_bins():
+    """The site of a 32-bit draw u is floor(u N / 2^32): the draws that pick
+    generator f are the u in [ceil(f 2^32 / N), ceil((f + 1) 2^32 / N)), so
+    every generator gets the same number of draws up to one (uniform within
+    N / 2^32)."""
+    for n in (8, 24, 120, 144, 960):
+        starts = [-((-f << 32) // n) for f in range(n + 1)]   # ceil(f 2^32 / n)
+        sizes = np.diff(starts)
+        assert sizes.max() - sizes.min() <= 1
+        for f in range(n):
+            assert O.site_of(starts[f], n) == f
+            assert O.site_of(starts[f + 1] - 1, n) == f
+
+
+@pytest.mark.parametrize("layout,d", [(O.ROTATED, 3), (O.ROTATED, 7), (O.PLANAR, 5)])
+def test_site_beta_zero_closed_form(layout, d):
+    """beta = 0: every step's move is accepted (u_a = 2^32-1 aside, probability
+    2^-32), so step m of sweep t multiplies by the generator its Philox site
+    draw names (block (uid, c, 2^31 + t, m div 2), word 2(m mod 2)); E_min
+    and its step are tracked after every step (Alg. 2)."""
+    L = O.Lattice(layout, d)
+    G = _gf2.generator_matrix(L.fq, L.fm, L.nq)
+    w, _ = O.weights(0.12, O.noise(0.12, 10.0))
+    rng = np.random.default_rng(12)
+    init = rng.integers(0, 4, L.nq).astype(np.uint8)
+    seed, uid, chain, n = 0xABCDEF0123, 5, 6, 3
+    r = L.anneal_chain(w, np.zeros(n), seed, uid, chain, init, order=SITE)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    cfg = init.copy()
+    e_min, stop, snap = int(w[cfg].sum()), 0, cfg.copy()
+    for t in range(n):
+        for m in range(L.nstab):
+            block = O.philox((uid, chain, 0x80000000 + t, m >> 1), key)
+            f = O.site_of(block[2 * (m & 1)], L.nstab)
+            cfg = cfg ^ G[f]
+            e = int(w[cfg].sum())
+            if e < e_min:
+                e_min, stop, snap = e, t * L.nstab + m + 1, cfg.copy()
+    assert np.array_equal(r["final"], cfg)
+    assert r["e"] == int(w[cfg].sum())
+    assert (r["emin"], r["stop"]) == (e_min, stop)
+    assert np.array_equal(r["snap"], snap)
+
+
+@pytest.mark.parametrize("layout,d", [(O.ROTATED, 5), (O.PLANAR, 5)])
+def test_site_zero_temperature_descent(layout, d):
+    L = O.Lattice(layout, d)
+    w, _ = O.weights(0.15, O.noise(0.15, 10.0))
+    rng = np.random.default_rng(13)
+    init = rng.integers(0, 4, L.nq).astype(np.uint8)
+    beta = np.full(12, 1e6)
+    es = [L.anneal_chain(w, beta[:s], 4, 1, 0, init, order=SITE)["e"] for s in range(13)]
+    assert all(a >= b for a, b in zip(es, es[1:]))
+    r = L.anneal_chain(w, beta, 4, 1, 0, init, order=SITE)
+    assert r["emin"] == r["e"] == es[-1] and es[-1] < es[0]
+
+
+@pytest.mark.parametrize("layout,d", [(O.ROTATED, 5), (O.ROTATED, 9), (O.PLANAR, 7)])
+def test_site_invariants_every_sweep(layout, d):
+    L = O.Lattice(layout, d)
+    w, _ = O.weights(0.2, O.noise(0.2, 10.0))
+    rng = np.random.default_rng(14)
+    beta = O.schedule(O.SCHED_GEOMETRIC, 0.05, 10.0, 40)
+    for c in range(6):
+        init = rng.integers(0, 4, L.nq).astype(np.uint8)
+        r = L.anneal_chain(w, beta, 17, 8, c, init, check=True, order=SITE)
+        assert L.energy(w, r["snap"]) == r["emin"] <= r["e"]
+        assert np.array_equal(L.syndrome(r["snap"]), L.syndrome(init))
+        assert L.cls(r["snap"], init) == 0 and L.cls(r["final"], init) == 0
+
+
+def test_site_boltzmann_law_fixed_beta():
+    """A uniformly chosen generator is a symmetric proposal (each G_f is its
+    own inverse), so each random-site step satisfies detailed balance for
+    pi_beta of Eq. (22); final states of independent chains at a fixed beta
+    follow the exact law over the 256-element coset (d = 3).  From this
+    start the two degenerate ground states are separated by a barrier, so the
+    chains run 100 sweeps (25 do not mix for either sweep order)."""
+    L = O.Lattice(O.ROTATED, 3)
+    G = _gf2.generator_matrix(L.fq, L.fm, L.nq)
+    w, _ = O.weights(0.15, O.noise(0.15, 10.0))
+    rng = np.random.default_rng(16)
+    init = rng.integers(0, 4, L.nq).astype(np.uint8)
+    elems = _gf2.group_elements(G) ^ _gf2.pack(init)
+    index = {int(v): i for i, v in enumerate(elems)}
+    energies = _gf2.packed_energy(elems, w).astype(np.float64)
+    beta = 0.35
+    n_chains, n_sweeps = 8000, 100
+    counts = np.zeros(len(elems))
+    bs = np.full(n_sweeps, beta)
+    for c in range(n_chains):
+        r = L.anneal_chain(w, bs, 2025, 78, c, init, want_snap=False, order=SITE)
+        counts[index[int(_gf2.pack(r["final"]))]] += 1
+
+    def chi2_p(b):
+        pr = np.exp(-b * (energies - energies.min()) / 65536.0)
+        pr /= pr.sum()
+        exp = pr * n_chains
+        keep = exp >= 5
+        obs = np.append(counts[keep], counts[~keep].sum())
+        ex = np.append(exp[keep], exp[~keep].sum())
+        if ex[-1] == 0:
+            obs, ex = obs[:-1], ex[:-1]
+        return stats.chisquare(obs, ex).pvalue
+
+    assert chi2_p(beta) > 1e-3
+    assert chi2_p(1.3 * beta) < 1e-6
+
+
+@pytest.mark.parametrize("layout,d,n_syn", [(O.ROTATED, 3, 120), (O.PLANAR, 3, 40)])
+def test_site_decoder_against_brute_force(layout, d, n_syn):
+    """The decoder on random-site chains: E_P bounds the exact coset minimum
+    from above, the recovery is consistent, and a slow schedule reaches the
+    exact minimum in nearly every sample."""
+    L = O.Lattice(layout, d)
+    p, eta = 0.15, 10.0
+    w, wg = O.weights(p, O.noise(p, eta))
+    beta = O.schedule(O.SCHED_LINEAR, 0.1, 5.0, 200)
+    rng = np.random.default_rng(20 + d)
+    hits = 0
+    for uid in range(n_syn):
+        _, syn = random_problem(L, p, eta, rng)
+        out = L.decode(w, wg, syn, uid, 2, beta, 5, 6, order=SITE, chains=True)
+        r0 = out["refs"][0]
+        exact = _exact_coset_minima(L, w, r0)
+        for P in range(4):
+            assert out["e_cls"][P] >= exact[P]
+        assert out["e_best"] == min(out["e_cls"])
+        rec = out["recovery"]
+        assert np.array_equal(L.syndrome(rec), syn)
+        assert L.energy(w, rec) == out["e_best"]
+        assert L.cls(rec, r0) == out["cls"]
+        assert out["chain_stop"].max() <= len(beta) * L.nstab
+        hits += out["e_best"] == min(exact)
+    assert hits >= 0.95 * n_syn
