@@ -108,6 +108,8 @@ def parse():
     ap.add_argument("--by-distance", action="store_true",
                     help="annealing rate of the default kernel for each odd d in --distances")
     ap.add_argument("--distances", default="11,13,15,17,21,25,29,31")
+    ap.add_argument("--order", choices=["colour", "site"], default="colour",
+                    help="Metropolis step order: colour-class sweeps, or random-site steps (Alg. 3 as printed)")
     ap.add_argument("--paper-trends", action="store_true",
                     help="logical error rates of the paper's set-up against N_SA and N_beta (planar, 1:eta:1)")
     ap.add_argument("--trend-d", type=int, default=9)
@@ -157,6 +159,8 @@ def main():
             lats[d] = D.Lattice(layout, d)
         w, wg = D.weights(p, D.noise(p, eta, conv))
         plans.append(D.Plan(lats[d], w, wg, beta))
+        if args.order == "site":
+            plans[-1].set_order(X.ORDER_RANDOM_SITE)
     ng = len(plans)
     tuned = {}
     if not args.no_tune:
@@ -243,7 +247,9 @@ def main():
         ler[f"d{d}_p{p}_eta{eta:g}"] = fails / B
 
     kinds = {pl.info()["kernel"] for pl in plans}
-    if kinds == {X.KERNEL_ROWS} and len(set(wl["d"])) == 1 and (4 * R) % 64 == 0:
+    if kinds == {X.KERNEL_SITE}:
+        kernel_name = "k_anneal_site"
+    elif kinds == {X.KERNEL_ROWS} and len(set(wl["d"])) == 1 and (4 * R) % 64 == 0:
         kernel_name = f"k_anneal_rows_d{wl['d'][0]}"   # packed rows specialised to d
     elif kinds <= {X.KERNEL_ROWS, X.KERNEL_ROWS_GENERIC}:
         kernel_name = "k_anneal_rows"
@@ -268,6 +274,7 @@ def main():
                         f"{R} replicas ({4 * R} chains)/syndrome, {sweeps} sweeps {wl['schedule'][0]} "
                         f"{wl['schedule'][1]}->{wl['schedule'][2]}",
             "name": args.workload,
+            "step_order": "random-site (Alg. 3)" if args.order == "site" else "colour-class sweeps",
             "syndromes_per_step": syndromes_step,
             "attempts_per_step": attempts_step,
             "graphs": graphs is not None,
@@ -344,7 +351,8 @@ def cpu_baseline(args, wl, specs, plans, syn0, uid0, outs, R, sweeps, gs, as_):
         g, i = job
         d = specs[g][0]
         lat = O.Lattice(layout, d)
-        return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, gs, as_)
+        return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, gs, as_,
+                          order=O.ORDER_RANDOM_SITE if args.order == "site" else O.ORDER_COLOUR)
 
     # size the sample from one timed syndrome
     t = time.perf_counter()
@@ -499,6 +507,13 @@ def trends_bench(args):
                 o = D.decode(plans[nb], syn, uid, 10, gs, as_, mode)
                 byinit[mname][nb] = logical_failures(lat, err, o.recovery.cpu().numpy())
         out["p_l_vs_n_beta"][key] = {m: {str(nb): rate(f) for nb, f in v.items()} for m, v in byinit.items()}
+        # step order: the literal random-site chain against colour-class sweeps
+        site_plan = D.Plan(lat, w, wg, D.schedule(X.SCHED_PAPER_LOG, 0.9, 1.0, 100))
+        site_plan.set_order(X.ORDER_RANDOM_SITE)
+        o = D.decode(site_plan, syn, uid, 10, gs, as_, X.GREEDY_RANDOM)
+        f_site = logical_failures(lat, err, o.recovery.cpu().numpy())
+        out.setdefault("step_order_n_sa10", {})[key] = {"colour": rate(fails[10]) if 10 in fails else None,
+                                                        "random_site": rate(f_site)}
         # pair-by-pair comparisons behind the paper's statements
         ks = sorted(fails)
         out["checks"][key] = {
@@ -509,6 +524,8 @@ def trends_bench(args):
             "same_vs_boundary": {str(nb): paired(byinit["greedy_same"][nb], byinit["boundary"][nb])
                                  for nb in nbetas},
         }
+        if 10 in fails:
+            out["checks"][key]["colour_vs_random_site"] = paired(fails[10], f_site)
         print(f"[trends] eta={eta:g} greedy {out['greedy_decoder'][key][0]:.4f} "
               + " ".join(f"N_SA={k}:{fails[k].mean():.4f}" for k in ks), file=sys.stderr, flush=True)
     torch.cuda.synchronize()

@@ -155,7 +155,8 @@ void xzzx_plan_destroy(xzzx_plan *plan);
 
 /* Plan facts (any pointer may be NULL): sizes, number of distinct move
  * energies, lanes per chain of the byte-state kernel, and the annealing kernel
- * in use (XZZX_KERNEL_ROWS or XZZX_KERNEL_BYTES). */
+ * in use (XZZX_KERNEL_ROWS, XZZX_KERNEL_ROWS_GENERIC, XZZX_KERNEL_BYTES, or
+ * XZZX_KERNEL_SITE for the random-site order). */
 int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sweeps,
                    int *n_dE, int *lanes_per_chain, int *kernel);
 
@@ -178,8 +179,28 @@ int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain);
  *   XZZX_KERNEL_AUTO: ROWS where it applies, else BYTES (the default).
  * EINVAL for ROWS or ROWS_GENERIC on a lattice they do not cover.
  * xzzx_plan_info reports ROWS only where the specialised variant runs. */
-enum { XZZX_KERNEL_AUTO = 0, XZZX_KERNEL_ROWS = 1, XZZX_KERNEL_BYTES = 2, XZZX_KERNEL_ROWS_GENERIC = 3 };
+enum { XZZX_KERNEL_AUTO = 0, XZZX_KERNEL_ROWS = 1, XZZX_KERNEL_BYTES = 2, XZZX_KERNEL_ROWS_GENERIC = 3,
+       XZZX_KERNEL_SITE = 4 };
 int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel);
+
+/* Step order of the Metropolis chains (Algs. 2-3).
+ *   XZZX_ORDER_COLOUR (default): a sweep visits every generator once, colour
+ *     class by colour class (generators of one class act on disjoint qubits);
+ *     E_min is updated after each class; chain_stop counts phases 4t + k + 1.
+ *   XZZX_ORDER_RANDOM_SITE: Alg. 3 as printed: each of the N_stab steps of
+ *     sweep t picks one generator uniformly at random and E_min is updated
+ *     after every step.  Step m draws the Philox block (uid, chain,
+ *     2^31 + t, m div 2); words 2 (m mod 2) and 2 (m mod 2) + 1 are the site
+ *     draw u (generator floor(u N_stab / 2^32) in face-id order) and the
+ *     acceptance draw.  chain_stop counts steps t N_stab + m + 1 (0 = the
+ *     start).  One chain per lane (XZZX_KERNEL_SITE); the kernel knobs do not
+ *     apply, the autotuner leaves the plan unchanged and the serving loop
+ *     rejects such plans (EINVAL).
+ * The two orders give different, equally valid chains.  EINVAL for an unknown
+ * order; ERANGE if n_sweeps * n_stabs >= 2^31 or 64 random-site chains do not
+ * fit in 64 KiB of LDS. */
+enum { XZZX_ORDER_COLOUR = 0, XZZX_ORDER_RANDOM_SITE = 1 };
+int xzzx_plan_set_order(xzzx_plan *plan, int order);
 
 /* Autotuner of the result-invariant knobs (kernel family, lanes per chain).
  * Builds a probe plan with the same lattice and weights and the first

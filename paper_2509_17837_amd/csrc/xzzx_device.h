@@ -417,6 +417,128 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
 }
 
 // ---------------------------------------------------------------------------
+// Random-site core (Algs. 2-3 as printed): every step picks one generator
+// uniformly at random, so the steps of a chain are sequential and the
+// parallelism is across chains: one chain per lane, 64 per wavefront.  The
+// state of chain c is packed 2 bits per qubit, qubit q at bits 2 (q mod 16)
+// of word q div 16, and word w of chain c at LDS word 64 w + c: whatever
+// qubits the lanes pick, one instruction's accesses fall in distinct banks.
+// Position nq is scratch for absent generator slots.  Step m of sweep t uses
+// Philox(uid, chain, 2^31 + t, m div 2): words 2 (m mod 2) and 2 (m mod 2) + 1
+// are the site draw (site = floor(u N_stab / 2^32), face-id order) and the
+// acceptance draw.  E_min is tracked after every step; stop = t N_stab + m + 1
+// (0 = the start).  REPLAY re-runs each syndrome's best chain to its stop step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int site_words(int nq) { return nq / 16 + 1; }
+
+template <bool REPLAY>
+__device__ inline void site_core(const PlanDev *pl, const ChainJob &J, uint32_t seed_lo, uint32_t seed_hi,
+                                 uint8_t *smem)
+{
+    const int c = threadIdx.x;
+    const int nq = pl->nq, nstab = pl->nstab, nranks = pl->nranks, n_sweeps = pl->n_sweeps;
+    const uint32_t kneg = (uint32_t)pl->kneg;
+    int32_t W[4];
+    W[0] = pl->W[0]; W[1] = pl->W[1]; W[2] = pl->W[2]; W[3] = pl->W[3];
+    const LdsLayout lo = lds_layout(pl->M, pl->ntypes, nranks);
+    const uint2 *desc_s = reinterpret_cast<const uint2 *>(smem + lo.desc);   // by face id
+    const uint8_t *lut_s = smem + lo.lut;
+    int2 *et_s = reinterpret_cast<int2 *>(smem + lo.et);
+    uint32_t *st = reinterpret_cast<uint32_t *>(smem + lo.state);
+    const int nw = site_words(nq);
+    const uint32_t uid = J.uid, cc = J.cc;
+
+    const bool use_x = (J.lp == 1 || J.lp == 2), use_z = (J.lp == 2 || J.lp == 3);
+    int32_t E = 0;
+    for (int w = 0; w < nw; ++w) {
+        uint32_t word = 0;
+        for (int i = 0; i < 16; ++i) {
+            const int q = 16 * w + i;
+            if (q >= nq) break;
+            uint32_t v = J.active ? (J.src[q] & 3u) : 0u;
+            if (use_x) v ^= pl->lx[q];
+            if (use_z) v ^= pl->lz[q];
+            word |= v << (2 * i);
+            E += weight_of(W, v);
+        }
+        st[w * kWave + c] = word;
+    }
+    int32_t Emin = E, stop = 0;
+    wave_lds_fence();
+
+    auto save_state = [&](uint8_t *dst) {
+        for (int q = 0; q < nq; ++q) dst[q] = (uint8_t)((st[(q >> 4) * kWave + c] >> (2 * (q & 15))) & 3u);
+    };
+    int32_t last = n_sweeps * nstab;
+    const int32_t target = REPLAY && J.active ? J.target : -1;
+    if (REPLAY) {
+        if (target == 0) save_state(J.snap);
+        int32_t tmax = max(target, 0);
+#pragma unroll
+        for (int sh = 1; sh < kWave; sh <<= 1) tmax = max(tmax, __shfl_xor(tmax, sh, kWave));
+        last = tmax;
+    }
+
+    constexpr int kThrPerLane = (kMaxRanks + kWave - 1) / kWave;
+    uint32_t thr_next[kThrPerLane];
+    auto fetch_thr = [&](int t) {
+#pragma unroll
+        for (int j = 0; j < kThrPerLane; ++j) {
+            const int i = c + j * kWave;
+            thr_next[j] = (t < n_sweeps && i < nranks) ? pl->thr[(size_t)t * nranks + i] : 0u;
+        }
+    };
+    fetch_thr(0);
+
+    auto step = [&](uint32_t u_site, uint32_t u_acc, int32_t s) {
+        const uint32_t f = __umulhi(u_site, (uint32_t)nstab);
+        const uint2 d = desc_s[f];
+        const uint32_t q0 = d.x & 0xFFFFu, q1 = d.x >> 16, q2 = d.y & 0xFFFFu, q3 = (d.y >> 16) & 0x7FFu;
+        uint32_t *a0 = st + (q0 >> 4) * kWave + c, *a1 = st + (q1 >> 4) * kWave + c;
+        uint32_t *a2 = st + (q2 >> 4) * kWave + c, *a3 = st + (q3 >> 4) * kWave + c;
+        const uint32_t s0 = 2u * (q0 & 15u), s1 = 2u * (q1 & 15u), s2 = 2u * (q2 & 15u), s3 = 2u * (q3 & 15u);
+        const uint32_t pat = ((*a0 >> s0) & 3u) | (((*a1 >> s1) & 3u) << 2) | (((*a2 >> s2) & 3u) << 4) |
+                             (((*a3 >> s3) & 3u) << 6);
+        const uint32_t rank = lut_s[((d.y >> 27) << 8) | pat];
+        const int2 et = et_s[rank];
+        if (rank < kneg || u_acc < (uint32_t)et.y) {
+            // slots 0 and 3 carry X, slots 1 and 2 carry Z; slots of one
+            // generator may share a word, so each is read, flipped and written
+            *a0 ^= 2u << s0;
+            *a1 ^= 1u << s1;
+            *a2 ^= 1u << s2;
+            *a3 ^= 2u << s3;
+            E += et.x;
+        }
+        if (E < Emin) { Emin = E; stop = s + 1; }
+        if (REPLAY && s + 1 == target) save_state(J.snap);
+    };
+
+    for (int t = 0; t < n_sweeps && t * nstab < last; ++t) {
+#pragma unroll
+        for (int j = 0; j < kThrPerLane; ++j)
+            if (c + j * kWave < nranks) et_s[c + j * kWave].y = (int)thr_next[j];
+        wave_lds_fence();
+        fetch_thr(t + 1);
+        const int32_t s0 = t * nstab;
+        for (int m = 0; m < nstab; m += 2) {
+            const uint4 r = philox4x32_10(make_uint4(uid, cc, 0x80000000u + (uint32_t)t, (uint32_t)m >> 1),
+                                          seed_lo, seed_hi);
+            step(r.x, r.y, s0 + m);
+            if (m + 1 < nstab) step(r.z, r.w, s0 + m + 1);
+        }
+        wave_lds_fence();
+    }
+    if (!REPLAY && J.active) {
+        J.emin[J.ci] = Emin;
+        J.stop[J.ci] = stop;
+        J.efin[J.ci] = E;
+        if (J.states) save_state(J.states + (size_t)J.ci * nq);
+    }
+    wave_lds_fence();
+}
+
+// ---------------------------------------------------------------------------
 // Packed-row core (rotated lattices, d <= 29): one chain per lane.  The padded
 // grid (columns and rows -1..d) is stored as 2-bit codes, each lattice row in
 // NW 32-bit words; word w of row Y of the chain in lane l sits at
@@ -999,12 +1121,14 @@ __device__ inline void load_rows_tables(const PlanDev *pl, uint8_t *smem)
     wave_lds_fence();
 }
 
-__device__ inline void load_plan_tables(const PlanDev *pl, uint8_t *smem)
+// by_face: descriptors in face-id order (random-site core) instead of by
+// (colour class, rank)
+__device__ inline void load_plan_tables(const PlanDev *pl, uint8_t *smem, bool by_face = false)
 {
     const int lane = threadIdx.x;
     const LdsLayout lo = lds_layout(pl->M, pl->ntypes, pl->nranks);
     uint2 *desc_s = reinterpret_cast<uint2 *>(smem + lo.desc);
-    const uint2 *desc_g = reinterpret_cast<const uint2 *>(pl->desc);
+    const uint2 *desc_g = reinterpret_cast<const uint2 *>(by_face ? pl->face_desc : pl->desc);
     for (int i = lane; i < 4 * pl->M; i += kWave) desc_s[i] = desc_g[i];
     const uint32_t *lut_g = reinterpret_cast<const uint32_t *>(pl->lut);
     uint32_t *lut_s = reinterpret_cast<uint32_t *>(smem + lo.lut);
@@ -1057,6 +1181,42 @@ __device__ __forceinline__ void batch_kernel_body(const AnnealArgs &A)
             // a replay from a checkpoint runs one chain per wavefront (uniform t0)
             bytes_core<lg, REPLAY>(G.plan, J, REPLAY ? J.t0 : 0, n_sweeps, A.seed_lo, A.seed_hi, smem);
         }
+    }
+}
+
+// Batch body of the random-site core (MODE as in batch_kernel_body): tasks of
+// 64 chains, or in replay 64 >> log_lanes syndromes (a replay of few
+// syndromes spreads them over more wavefronts; the other lanes idle); the
+// face descriptors are staged by face id.
+template <int MODE, bool REPLAY>
+__device__ __forceinline__ void site_kernel_body(const AnnealArgs &A)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const PlanDev *loaded = nullptr;
+    for (int iter = 0;; ++iter) {
+        uint32_t task = 0;
+        if (MODE == 2) {
+            if (iter > 0) break;
+            task = blockIdx.x;
+        } else {
+            if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
+            task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
+        }
+        if (task >= A.n_tasks) break;
+        int gi = 0;
+        while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
+        const GroupArgs &G = A.g[gi];
+        const int lgc = 6 - G.log_lanes;
+        const int64_t unit0 = ((int64_t)task - G.task_begin) << lgc;
+        if (G.plan != loaded) {
+            wave_lds_fence();
+            load_plan_tables(G.plan, smem, true);
+            loaded = G.plan;
+        }
+        const int lane = threadIdx.x;
+        ChainJob J = batch_job(G, unit0 + (lane & ((1 << lgc) - 1)), REPLAY);
+        if (lane >> lgc) J.active = false;
+        site_core<REPLAY>(G.plan, J, A.seed_lo, A.seed_hi, smem);
     }
 }
 

@@ -180,6 +180,20 @@ uint32_t accept_threshold(double beta, int64_t dE)
 // ---------------------------------------------------------------------------
 // Plan tables.
 // ---------------------------------------------------------------------------
+// Random-site kernel: the tables as above (descriptors in face-id order),
+// then 64 chains of nq / 16 + 1 packed words.
+size_t Plan::lds_bytes_site() const
+{
+    size_t off = 0;
+    off += sizeof(Desc) * 4 * lat.per_class;
+    off += 256 * (size_t)ntypes;
+    off = (off + 7) & ~size_t(7);
+    off += 8 * dE.size();
+    off = (off + 15) & ~size_t(15);
+    off += 4 * (size_t)(lat.nq / 16 + 1) * kWave;
+    return (off + 15) & ~size_t(15);
+}
+
 size_t Plan::lds_bytes_anneal(int lanes_per_chain) const
 {
     const int C = kWave / lanes_per_chain;
@@ -758,13 +772,30 @@ int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sw
                    int *lanes_per_chain, int *kernel)
 {
     if (plan && kernel)
-        *kernel = !plan->P.use_rows ? XZZX_KERNEL_BYTES : plan->P.static_d ? XZZX_KERNEL_ROWS : XZZX_KERNEL_ROWS_GENERIC;
+        *kernel = plan->P.order ? XZZX_KERNEL_SITE
+                  : !plan->P.use_rows ? XZZX_KERNEL_BYTES
+                  : plan->P.static_d ? XZZX_KERNEL_ROWS : XZZX_KERNEL_ROWS_GENERIC;
     if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
     if (n_qubits) *n_qubits = plan->P.lat.nq;
     if (n_stabs) *n_stabs = plan->P.lat.nstab;
     if (n_sweeps) *n_sweeps = plan->P.n_sweeps;
     if (n_dE) *n_dE = (int)plan->P.dE.size();
     if (lanes_per_chain) *lanes_per_chain = plan->P.lanes;
+    return XZZX_OK;
+}
+
+int xzzx_plan_set_order(xzzx_plan *plan, int order)
+{
+    if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
+    if (order != XZZX_ORDER_COLOUR && order != XZZX_ORDER_RANDOM_SITE) { set_error("unknown step order"); return XZZX_EINVAL; }
+    if (order == XZZX_ORDER_RANDOM_SITE) {
+        if ((int64_t)plan->P.n_sweeps * plan->P.lat.nstab >= ((int64_t)1 << 31)) {
+            set_error("random-site steps of a chain must number below 2^31");
+            return XZZX_ERANGE;
+        }
+        if (plan->P.lds_bytes_site() > 65536) { set_error("random-site chains do not fit in LDS"); return XZZX_ERANGE; }
+    }
+    plan->P.order = order;
     return XZZX_OK;
 }
 

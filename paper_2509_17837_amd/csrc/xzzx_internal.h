@@ -158,6 +158,7 @@ struct Plan {
     int static_d = 0;              // d if the packed-row kernel specialised to d applies, else 0
     int static_ok = 0;             // the plan's tables match the specialised schedule
     int static_words = 0;          // words per row of the specialised kernel's rows (2(d+1) bits)
+    int order = 0;                 // XZZX_ORDER_COLOUR or XZZX_ORDER_RANDOM_SITE
     int nranks() const { return (int)dE.size(); }
     int device = 0;
     void *dmem = nullptr;          // device allocation holding every table
@@ -166,6 +167,7 @@ struct Plan {
     PlanDev *ddev = nullptr;       // device copy of hdev (inside dmem)
     size_t lds_bytes_anneal(int lanes) const;
     size_t lds_bytes_rows() const;
+    size_t lds_bytes_site() const;
 };
 
 

@@ -372,6 +372,9 @@ template <int LOGG>
 __global__ __launch_bounds__(kWave) void k_replay(AnnealArgs A) { batch_kernel_body<0, false, LOGG, true>(A); }
 template <int LOGG>
 __global__ __launch_bounds__(kWave) void k_anneal_plain(AnnealArgs A) { batch_kernel_body<2, false, LOGG, false>(A); }
+__global__ __launch_bounds__(kWave) void k_anneal_site(AnnealArgs A) { site_kernel_body<0, false>(A); }
+__global__ __launch_bounds__(kWave) void k_replay_site(AnnealArgs A) { site_kernel_body<0, true>(A); }
+__global__ __launch_bounds__(kWave) void k_anneal_site_plain(AnnealArgs A) { site_kernel_body<2, false>(A); }
 __global__ __launch_bounds__(kWave) void k_anneal_rows(AnnealArgs A) { batch_kernel_body<0, true, 0, false>(A); }
 __global__ __launch_bounds__(kWave) void k_anneal_rows_plain(AnnealArgs A) { batch_kernel_body<2, true, 0, false>(A); }
 
@@ -624,7 +627,8 @@ struct GroupWs {
 static bool uses_static(const xzzx_group &g, int64_t unit_offset)
 {
     const Plan &P = g.plan->P;
-    return P.use_rows && P.static_d && (4 * g.n_rep) % kWave == 0 && unit_offset % kWave == 0;
+    return P.order == XZZX_ORDER_COLOUR && P.use_rows && P.static_d && (4 * g.n_rep) % kWave == 0 &&
+           unit_offset % kWave == 0;
 }
 
 // Sweeps between the checkpoints of a plan: kCheckpointEvery, or the least
@@ -732,7 +736,7 @@ enum class AnnealMode { Persistent, Replay, Plain };
 // over more lanes when that is needed to give every CU several wavefronts.
 static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::vector<int> &sel, bool rows, int lanes,
                       AnnealMode mode, uint64_t seed, int64_t unit_offset, int64_t units_override,
-                      uint32_t *d_counter, hipStream_t stream, int static_d = 0)
+                      uint32_t *d_counter, hipStream_t stream, int static_d = 0, bool site = false)
 {
     const bool replay = mode == AnnealMode::Replay;
     AnnealArgs A{};
@@ -780,7 +784,10 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         G.task_begin = (int64_t)tasks;
         const int C = kWave / lanes;
         tasks += (uint64_t)((units + C - 1) / C);
-        lds = std::max(lds, static_d ? (size_t)0 : rows ? P.lds_bytes_rows() : P.lds_bytes_anneal(lanes));
+        lds = std::max(lds, static_d ? (size_t)0
+                            : site   ? P.lds_bytes_site()
+                            : rows   ? P.lds_bytes_rows()
+                                     : P.lds_bytes_anneal(lanes));
     }
     if (ng == 0 || tasks == 0) return XZZX_OK;
     if (tasks >= 0xFFFFFFF0ull) { set_error("too many anneal tasks in one launch"); return XZZX_ERANGE; }
@@ -788,7 +795,9 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
     A.n_tasks = (uint32_t)tasks;
     if (lds > 65536) { set_error("LDS demand above 64 KiB"); return XZZX_ERANGE; }
     if (mode == AnnealMode::Plain) {
-        if (static_d)
+        if (site)
+            hipLaunchKernelGGL(k_anneal_site_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
+        else if (static_d)
             hipLaunchKernelGGL(static_rows_kernel(static_d, true), dim3((unsigned)tasks), dim3(kWave), 0, stream, A);
         else if (rows)
             hipLaunchKernelGGL(k_anneal_rows_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
@@ -796,8 +805,10 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
             hipLaunchKernelGGL(bytes_kernel(2, lg), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         return check_hip(hipGetLastError(), "plain anneal launch");
     }
-    const AnnealKernel kern =
-        static_d ? static_rows_kernel(static_d, false) : rows ? k_anneal_rows : bytes_kernel(replay ? 1 : 0, lg);
+    const AnnealKernel kern = site       ? (replay ? k_replay_site : k_anneal_site)
+                              : static_d ? static_rows_kernel(static_d, false)
+                              : rows     ? k_anneal_rows
+                                         : bytes_kernel(replay ? 1 : 0, lg);
     unsigned grid = 0;
     int rc = anneal_grid((const void *)kern, lds, A.n_tasks, &grid);
     if (rc) return rc;
@@ -871,8 +882,10 @@ static int fork_join(hipStream_t stream, int n, F launch)
 // launch; byte-state groups are launched per lanes-per-chain value.  The
 // replay re-runs one chain per syndrome with the byte-state kernel, spreading
 // a chain over more lanes when that is needed to give every CU several
-// wavefronts.  Each launch has its own queue counter (d_counters[0..8], and
-// [16..21] for the kernels specialised to d = 3, 5, ..., 13).
+// wavefronts.  Each launch has its own queue counter: d_counters[0] packed
+// rows, [1..7] byte states by lanes per chain, [16..30] the kernels
+// specialised to d = 3, 5, ..., 31, [40] random-site chains; a replay (with
+// its own d_counters base) uses [0], [2] and [4].
 static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
                          uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
                          hipStream_t stream)
@@ -881,11 +894,16 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
     std::vector<int> bytes_sel[7];
     std::vector<int> static_sel[kStaticMaxD + 1];
     std::vector<int> replay_cp;   // replays starting from checkpoints: one chain per wavefront
+    std::vector<int> site_sel;    // random-site plans: one chain (replay: syndrome) per lane
     int64_t total_syn = 0;
     for (int i = 0; i < n_groups; ++i) {
         if (groups[i].n_syn <= 0) continue;
-        total_syn += groups[i].n_syn;
         const Plan &P = groups[i].plan->P;
+        if (P.order == XZZX_ORDER_RANDOM_SITE) {
+            site_sel.push_back(i);
+            continue;
+        }
+        total_syn += groups[i].n_syn;
         if (mode != AnnealMode::Replay && uses_static(groups[i], unit_offset)) static_sel[P.static_d].push_back(i);
         else if (mode == AnnealMode::Replay && checkpoints_of(groups[i]) > 0) replay_cp.push_back(i);
         else if (mode != AnnealMode::Replay && P.use_rows && P.row_words) rows_sel.push_back(i);
@@ -907,6 +925,15 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         if (!rc)
             rc = launch_set(groups, ws, replay_cp, false, kWave, mode, seed, unit_offset, units_override,
                             d_counters + 2, stream);
+        // random-site replays: each lane re-runs a chain step by step, so
+        // few syndromes per wavefront keep more wavefronts in flight
+        int64_t site_syn = 0;
+        for (int i : site_sel) site_syn += groups[i].n_syn;
+        int Cs = kWave;
+        while (Cs > 1 && site_syn / Cs < want) Cs >>= 1;
+        if (!rc)
+            rc = launch_set(groups, ws, site_sel, false, kWave / Cs, mode, seed, unit_offset, units_override,
+                            d_counters + 4, stream, 0, true);
         return rc;
     }
     // the launches of one call (one per kernel family and distance) run
@@ -918,26 +945,28 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         int lanes;
         uint32_t *counter;
         int static_d;
+        bool site;
     };
     std::vector<Set> sets;
-    if (!rows_sel.empty()) sets.push_back({&rows_sel, true, 1, d_counters, 0});
+    if (!rows_sel.empty()) sets.push_back({&rows_sel, true, 1, d_counters, 0, false});
+    if (!site_sel.empty()) sets.push_back({&site_sel, false, 1, d_counters + 40, 0, true});
     for (int d = kStaticMinD; d <= kStaticMaxD; d += 2)
         if (!static_sel[d].empty())
-            sets.push_back({&static_sel[d], true, 1, d_counters + 16 + (d - kStaticMinD) / 2, d});
+            sets.push_back({&static_sel[d], true, 1, d_counters + 16 + (d - kStaticMinD) / 2, d, false});
     for (int l = 0; l < 7; ++l)
-        if (!bytes_sel[l].empty()) sets.push_back({&bytes_sel[l], false, 1 << l, d_counters + 1 + l, 0});
+        if (!bytes_sel[l].empty()) sets.push_back({&bytes_sel[l], false, 1 << l, d_counters + 1 + l, 0, false});
     if (sets.size() <= 1 || mode == AnnealMode::Plain) {
         int rc = XZZX_OK;
         for (const Set &S : sets)
             if (!rc)
                 rc = launch_set(groups, ws, *S.sel, S.rows, S.lanes, mode, seed, unit_offset, units_override, S.counter,
-                                stream, S.static_d);
+                                stream, S.static_d, S.site);
         return rc;
     }
     return fork_join(stream, (int)sets.size(), [&](int i, hipStream_t s) {
         const Set &S = sets[i];
         return launch_set(groups, ws, *S.sel, S.rows, S.lanes, mode, seed, unit_offset, units_override, S.counter, s,
-                          S.static_d);
+                          S.static_d, S.site);
     });
 }
 

@@ -31,6 +31,15 @@ extern "C" int xzzx_plan_autotune(xzzx_plan *plan, int n_rep, int n_syn, int pro
 {
     if (!plan || n_rep < 1 || n_syn < 1 || probe_sweeps < 1) { set_error("bad autotune arguments"); return XZZX_EINVAL; }
     Plan &P = plan->P;
+    if (P.order) {
+        // the random-site kernel has no knobs
+        if (out) {
+            out->kernel = XZZX_KERNEL_SITE;
+            out->lanes_per_chain = 1;
+            for (float &t : out->times_ms) t = -1.0f;
+        }
+        return XZZX_OK;
+    }
     const int sweeps = std::min(probe_sweeps, std::max(P.n_sweeps, 1));
     std::vector<double> beta(P.beta.begin(), P.beta.begin() + std::min<size_t>(sweeps, P.beta.size()));
     while ((int)beta.size() < sweeps) beta.push_back(1.0);

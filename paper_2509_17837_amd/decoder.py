@@ -127,12 +127,16 @@ class Plan:
     def set_kernel(self, kernel):
         call("xzzx_plan_set_kernel", self.h, int(kernel))
 
+    def set_order(self, order):
+        """X.ORDER_COLOUR (colour-class sweeps) or X.ORDER_RANDOM_SITE (Alg. 3 as printed)."""
+        call("xzzx_plan_set_order", self.h, int(order))
+
     def autotune(self, n_rep, n_syn=256, probe_sweeps=50, stream=None):
         """Pick the fastest result-invariant launch knobs for this plan."""
         r = X.TuneResult()
         call("xzzx_plan_autotune", self.h, n_rep, n_syn, probe_sweeps, _stream(stream), C.byref(r))
         names = ["rows"] + [f"bytes{1 << i}" for i in range(7)]
-        kind = {X.KERNEL_ROWS: "rows", X.KERNEL_ROWS_GENERIC: "rows_generic"}.get(r.kernel, "bytes")
+        kind = {X.KERNEL_ROWS: "rows", X.KERNEL_ROWS_GENERIC: "rows_generic", X.KERNEL_SITE: "site"}.get(r.kernel, "bytes")
         return {"kernel": kind, "lanes_per_chain": r.lanes_per_chain,
                 "times_ms": {n: round(t, 3) for n, t in zip(names, r.times_ms) if t >= 0}}
 

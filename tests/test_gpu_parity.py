@@ -99,6 +99,50 @@ def test_paper_setup(d, eta, n_beta, mode):
     compare_decode(prob, out, prob.oracle_decode(mode=mode))
 
 
+@pytest.mark.parametrize("layout,d,n_syn,R,sweeps", [(0, 3, 200, 1, 50), (0, 11, 21, 7, 30), (0, 31, 2, 16, 4),
+                                                     (1, 9, 30, 10, 100), (1, 5, 70, 3, 7), (0, 7, 5, 2, 0)])
+def test_random_site_order(layout, d, n_syn, R, sweeps):
+    """Algs. 2-3 as printed: each step picks a generator uniformly at random
+    and E_min is tracked after every step.  Every chain (E, E_min, stop step,
+    final state) and the recovery, replayed to the best chain's stop step,
+    equal the oracle's random-site chains; ragged tails of 64-chain tasks."""
+    prob = Problem(layout, d, 0.15, 5.0, n_syn, R, sweeps, sched=("paper_log", 0.9, 1.0), seed=900 + d, conv=1)
+    plan = gpu_plan(prob)
+    plan.set_order(X.ORDER_RANDOM_SITE)
+    assert plan.info()["kernel"] == X.KERNEL_SITE
+    out = run_decode(prob, plan)
+    compare_decode(prob, out, prob.oracle_decode(order=O.ORDER_RANDOM_SITE))
+
+
+def test_random_site_plain_graph_and_mixed():
+    """The random-site order in the plain form (one launch per syndrome), in a
+    captured hipGraph, and beside a colour-sweep group in one call."""
+    ps = Problem(0, 9, 0.2, 10.0, 9, 4, 20, seed=77)
+    pc = Problem(0, 11, 0.2, 10.0, 6, 16, 20, seed=77)   # same seeds: one call decodes both
+    ref_s = ps.oracle_decode(order=O.ORDER_RANDOM_SITE)
+    ref_c = pc.oracle_decode()
+    plan_s = gpu_plan(ps)
+    plan_s.set_order(X.ORDER_RANDOM_SITE)
+    compare_decode(ps, run_decode(ps, plan_s, flags=X.FLAG_PLAIN), ref_s)
+    plan_c = gpu_plan(pc)
+    gs_, os_ = D.make_group(plan_s, ps.n_rep, to_dev(ps.uid.view(np.int32)), syn=to_dev(ps.syn), want_chains=True)
+    gc_, oc_ = D.make_group(plan_c, pc.n_rep, to_dev(pc.uid.view(np.int32)), syn=to_dev(pc.syn), want_chains=True)
+    G = D.Graph([gs_, gc_], ps.greedy_seed, ps.anneal_seed)
+    for _ in range(3):
+        G.launch()
+        G.stream.synchronize()
+        torch.cuda.synchronize()
+        compare_decode(ps, os_, ref_s)
+        compare_decode(pc, oc_, ref_c)
+    with pytest.raises(X.XzzxError):
+        plan_s.set_order(7)
+    srv = D.Server(max_slots=8, max_rep=4, max_qubits=81)
+    with pytest.raises(X.XzzxError) as e:
+        srv.submit(plan_s, ps.syn[0], 0, 4)
+    assert e.value.rc == X.XZZX_EINVAL
+    srv.close()
+
+
 @pytest.mark.parametrize("d", [9, 25])
 def test_all_lane_counts_agree(d):
     """Lanes per chain (chains per wavefront) is a result-invariant knob."""
