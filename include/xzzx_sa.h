@@ -174,9 +174,13 @@ int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain);
  *     are not a multiple of 64 run the generic variant instead (d <= 29),
  *     or the byte-state kernel (d = 31);
  *   XZZX_KERNEL_ROWS_GENERIC: the packed-row kernel without that
- *     specialisation (rows in LDS, schedule read from the plan; d <= 29);
+ *     specialisation (rows in LDS, schedule read from the plan): rotated
+ *     d <= 29, and planar d <= 15, whose lattice turned by 45 degrees has the
+ *     same 2 x 2 generator blocks (rows of 2d + 1 columns);
  *   XZZX_KERNEL_BYTES: byte-per-qubit states, lanes_per_chain lanes per chain;
- *   XZZX_KERNEL_AUTO: ROWS where it applies, else BYTES (the default).
+ *   XZZX_KERNEL_AUTO (the default): on rotated lattices ROWS where it
+ *     applies, else ROWS_GENERIC where it applies, else BYTES; on planar
+ *     lattices BYTES (measured faster than ROWS_GENERIC at d = 9).
  * EINVAL for ROWS or ROWS_GENERIC on a lattice they do not cover.
  * xzzx_plan_info reports ROWS only where the specialised variant runs. */
 enum { XZZX_KERNEL_AUTO = 0, XZZX_KERNEL_ROWS = 1, XZZX_KERNEL_BYTES = 2, XZZX_KERNEL_ROWS_GENERIC = 3,

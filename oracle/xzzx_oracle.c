@@ -237,9 +237,28 @@ or_lat *or_lattice_new(int layout, int d)
         or_lattice_free(L);
         return NULL;
     }
-    /* rank inside each colour class in face-id order */
+    /* Rank inside each colour class (reading; it only names the random word
+     * each generator draws).  Rotated: face-id order, i.e. row-major over
+     * the cells (j, i).  Planar: row-major over ((x + y)/2, (x - y)/2), the
+     * face's position in the frame turned by 45 degrees, where each planar
+     * generator covers a 2 x 2 block of qubits; ties cannot occur. */
     for (int k = 0; k < 4; ++k) L->ncls[k] = 0;
-    for (int g = 0; g < ns; ++g) L->frank[g] = L->ncls[L->fclass[g]]++;
+    for (int g = 0; g < ns; ++g) L->frank[g] = 0;
+    for (int g = 0; g < ns; ++g) {
+        L->ncls[L->fclass[g]]++;
+        for (int h = 0; h < ns; ++h) {
+            if (h == g || L->fclass[h] != L->fclass[g]) continue;
+            int before;
+            if (layout == OR_ROTATED) {
+                before = h < g;
+            } else {
+                int sg = (L->fx[g] + L->fy[g]) / 2, rg = (L->fx[g] - L->fy[g]) / 2;
+                int sh = (L->fx[h] + L->fy[h]) / 2, rh = (L->fx[h] - L->fy[h]) / 2;
+                before = sh < sg || (sh == sg && rh < rg);
+            }
+            L->frank[g] += before;
+        }
+    }
     for (int k = 0; k < 4; ++k) {
         L->cls_face[k] = (int *)malloc(sizeof(int) * (L->ncls[k] > 0 ? L->ncls[k] : 1));
         if (!L->cls_face[k]) { or_lattice_free(L); return NULL; }

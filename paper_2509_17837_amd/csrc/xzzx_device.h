@@ -617,10 +617,10 @@ __device__ inline void rows_core(const PlanDev *pl, const ChainJob &J, int t_beg
                           uint32_t seed_hi, uint8_t *smem)
 {
     const int lane = threadIdx.x;
-    const int d = (int)uni(pl->d), nq = (int)uni(pl->nq), nblk = (int)uni(pl->nblk);
+    const int nq = (int)uni(pl->nq), nblk = (int)uni(pl->nblk);
     const int nranks = (int)uni(pl->nranks), ntypes = (int)uni(pl->ntypes);
     const uint32_t kneg = uni(pl->kneg);
-    const int rows = d + 2;
+    const int rows = (int)uni(pl->rows);
     const int Mpad = 4 * nblk;
     int32_t W[4];
     W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
@@ -633,28 +633,18 @@ __device__ inline void rows_core(const PlanDev *pl, const ChainJob &J, int t_beg
 
     // serving: a fresh request's replay entries start at the references
     if (J.cp_meta && t_begin == 0 && J.active) J.cp_meta[J.ci] = -1;
-    // pack the state into rows; E of the state on the way
+    // pack the state into rows (qubit q at row qpos >> 8, column qpos & 0xFF);
+    // E of the state on the way
     int32_t E = 0;
-    for (int Y = 0; Y < rows; ++Y) {
-        const int y = Y - 1;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            uint32_t word = 0;
-            if (J.active && y >= 0 && y < d) {
-                for (int j = 0; j < 16; ++j) {
-                    const int x = 16 * w + j - 1;
-                    if (x >= 0 && x < d) {
-                        const int q = y * d + x;
-                        uint32_t v = J.src[q] & 3u;
-                        if (use_x) v ^= pl->lx[q];
-                        if (use_z) v ^= pl->lz[q];
-                        word |= v << (2 * j);
-                        E += weight_of(W, v);
-                    }
-                }
-            }
-            rw[(Y * NW + w) * kWave] = word;
-        }
+    for (int i = 0; i < rows * NW; ++i) rw[i * kWave] = 0;
+    for (int q = 0; q < nq; ++q) {
+        const uint32_t p = uni(pl->qpos[q]);
+        uint32_t v = J.active ? (J.src[q] & 3u) : 0u;
+        if (use_x) v ^= pl->lx[q];
+        if (use_z) v ^= pl->lz[q];
+        if (!J.active) v = 0u;
+        rw[((p >> 8) * NW + ((p & 0xFFu) >> 4)) * kWave] |= v << (2 * (p & 15u));
+        E += weight_of(W, v);
     }
     int32_t Emin = E, stop = 0;
     if (J.resume && J.active) {
@@ -738,9 +728,9 @@ __device__ inline void rows_core(const PlanDev *pl, const ChainJob &J, int t_beg
         if (J.states) {
             uint8_t *dst = J.states + (size_t)J.ci * nq;
             for (int q = 0; q < nq; ++q) {
-                const int y = q / d, x = q - y * d;
-                const uint32_t word = rw[((y + 1) * NW + (x + 1) / 16) * kWave];
-                dst[q] = (uint8_t)((word >> (2 * ((x + 1) % 16))) & 3u);
+                const uint32_t p = uni(pl->qpos[q]);
+                const uint32_t word = rw[((p >> 8) * NW + ((p & 0xFFu) >> 4)) * kWave];
+                dst[q] = (uint8_t)((word >> (2 * (p & 15u))) & 3u);
             }
         }
     }

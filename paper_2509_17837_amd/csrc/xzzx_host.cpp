@@ -54,7 +54,6 @@ static void finish_lattice(Lattice &L, std::vector<FaceRec> &faces)
     L.fcx.resize(L.nstab);
     L.fcy.resize(L.nstab);
     L.by_class.assign(4 * L.per_class, -1);
-    int seen[4] = {0, 0, 0, 0};
     for (int f = 0; f < L.nstab; ++f) {
         for (int s = 0; s < 4; ++s) {
             L.fq[4 * f + s] = faces[f].q[s];
@@ -64,9 +63,25 @@ static void finish_lattice(Lattice &L, std::vector<FaceRec> &faces)
         L.fcolour[f] = faces[f].colour;
         L.fcx[f] = faces[f].cx;
         L.fcy[f] = faces[f].cy;
-        int r = seen[faces[f].cls]++;
-        L.frank[f] = r;
-        if (r < L.per_class) L.by_class[faces[f].cls * L.per_class + r] = f;
+    }
+    // Rank inside each colour class: face-id order on the rotated lattice;
+    // on the planar lattice row-major over ((x + y)/2, (x - y)/2), the face's
+    // 2 x 2 block in the frame turned by 45 degrees, so that consecutive ranks
+    // share a row pair of the packed-row kernel.  The rank names the random
+    // word each generator draws.
+    for (int k = 0; k < 4; ++k) {
+        std::vector<int> members;
+        for (int f = 0; f < L.nstab; ++f)
+            if (L.fclass[f] == k) members.push_back(f);
+        if (L.layout == XZZX_PLANAR)
+            std::sort(members.begin(), members.end(), [&](int a, int b) {
+                return std::make_pair((L.fcx[a] + L.fcy[a]) / 2, (L.fcx[a] - L.fcy[a]) / 2) <
+                       std::make_pair((L.fcx[b] + L.fcy[b]) / 2, (L.fcx[b] - L.fcy[b]) / 2);
+            });
+        for (int r = 0; r < (int)members.size(); ++r) {
+            L.frank[members[r]] = r;
+            if (r < L.per_class) L.by_class[k * L.per_class + r] = members[r];
+        }
     }
 }
 
@@ -207,13 +222,23 @@ size_t Plan::lds_bytes_anneal(int lanes_per_chain) const
     return (off + 15) & ~size_t(15);
 }
 
+// Packed-row grid.  Rotated: rows y = -1..d and columns x = -1..d (padding
+// around the d x d qubits).  Planar: the lattice turned by 45 degrees, where
+// qubit (x, y) of the doubled coordinates sits at row (x + y - 1)/2 - 1 and
+// column (x - y - 1)/2 + d - 1, and generator (x, y) covers the 2 x 2 block
+// with top-left corner at row (x + y)/2 - 2, column (x - y)/2 + d - 2: X on
+// the diagonal, Z on the anti-diagonal, as on the rotated lattice.  Its 2d - 1
+// rows hold a diamond of qubits; columns 2d - 1 and 2d are padding.
+static int rows_of(const Lattice &L) { return L.layout == XZZX_ROTATED ? L.d + 2 : 2 * L.d - 1; }
+static int row_columns(const Lattice &L) { return L.layout == XZZX_ROTATED ? L.d + 2 : 2 * L.d + 1; }
+
 size_t Plan::lds_bytes_rows() const
 {
     size_t off = 256 * (size_t)ntypes;               // move-energy ranks
     off = (off + 7) & ~size_t(7);
     off += 8 * dE.size();                            // (dE, threshold) pairs
     off = (off + 15) & ~size_t(15);
-    off += (size_t)4 * kWave * row_words * (lat.d + 2);
+    off += (size_t)4 * kWave * row_words * rows_of(lat);
     return (off + 15) & ~size_t(15);
 }
 
@@ -255,10 +280,18 @@ static bool static_schedule_matches(int d, const std::vector<uint32_t> &rowface,
 // Packed-row layout (rotated lattice): the padded grid has columns and rows
 // -1..d; a row of 2-bit codes takes 2(d+2) bits, so 1 word for d <= 13 and 2
 // words for d <= 29.
+// The default kernel: packed rows on rotated lattices; on the planar lattice
+// the byte-state kernel, which measured faster at d = 9 (its packed rows need
+// two words and half the grid is padding); the packed rows stay available to
+// set_kernel and the autotuner.
+static bool rows_by_default(const Plan &P)
+{
+    return P.static_ok || (P.row_words && P.lat.layout == XZZX_ROTATED);
+}
+
 static int row_words_for(const Lattice &L)
 {
-    if (L.layout != XZZX_ROTATED) return 0;
-    const int bits = 2 * (L.d + 2);
+    const int bits = 2 * row_columns(L);
     return bits <= 32 ? 1 : (bits <= 64 ? 2 : 0);
 }
 
@@ -445,6 +478,51 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     // multiple of 4 entries so a block of four is read at once
     const int mpad = 4 * ((L.per_class + 3) / 4);
     std::vector<uint32_t> rowface(4 * mpad, 0);
+    std::vector<uint32_t> qpos(L.nq, 0);
+    if (L.layout == XZZX_ROTATED) {
+        for (int q = 0; q < L.nq; ++q) qpos[q] = (uint32_t)((q / L.d + 1) << 8) | (uint32_t)(q % L.d + 1);
+    } else if (P.row_words) {
+        // planar slots: 0 top-left (X), 1 bottom-left (Z), 2 top-right (Z),
+        // 3 bottom-right (X) of the generator's block; the packed-row
+        // pattern orders them top-left, top-right, bottom-left, bottom-right,
+        // so a generator takes the shape with slots 1 and 2 exchanged
+        auto swap12 = [](int m) { return (m & 9) | ((m & 2) << 1) | ((m & 4) >> 1); };
+        std::vector<int> rows_shape(L.nstab, -1);
+        for (int f = 0; f < L.nstab; ++f) {
+            const int want = swap12(mask_of_face[f]);
+            for (int t = 0; t < (int)shapes.size(); ++t)
+                if (shapes[t] == want) rows_shape[f] = t;
+            if (rows_shape[f] < 0) P.row_words = 0;   // exchanged shape absent: no packed-row kernel
+        }
+        std::vector<int> placed(L.nq, 0);
+        const int d = L.d;
+        for (int f = 0; f < L.nstab && P.row_words; ++f) {
+            const int x = L.fcx[f], y = L.fcy[f];
+            const int top = (x + y) / 2 - 2, left = (x - y) / 2 + d - 2;
+            const int dy[4] = {0, 1, 0, 1}, dx[4] = {0, 0, 1, 1};
+            for (int sl = 0; sl < 4; ++sl) {
+                const int q = L.fq[4 * f + sl];
+                if (q < 0) continue;
+                const uint32_t p = (uint32_t)((top + dy[sl]) << 8) | (uint32_t)(left + dx[sl]);
+                if (placed[q] && qpos[q] != p) { set_error("inconsistent planar row positions"); return XZZX_EINVAL; }
+                placed[q] = 1;
+                qpos[q] = p;
+            }
+        }
+        for (int q = 0; q < L.nq && P.row_words; ++q)
+            if (!placed[q]) { set_error("planar qubit outside every generator"); return XZZX_EINVAL; }
+        if (P.row_words) {
+            const uint32_t pad = 0u | ((2u * (uint32_t)(2 * d - 1)) << 8) | ((uint32_t)null_shape << 16);
+            for (int k = 0; k < 4; ++k)
+                for (int m = 0; m < mpad; ++m) {
+                    if (m >= L.per_class) { rowface[k * mpad + m] = pad; continue; }
+                    const int f = L.by_class[k * L.per_class + m];
+                    const int x = L.fcx[f], y = L.fcy[f];
+                    const uint32_t Y = (uint32_t)((x + y) / 2 - 2), C = (uint32_t)((x - y) / 2 + d - 2);
+                    rowface[k * mpad + m] = Y | ((2u * C) << 8) | ((uint32_t)rows_shape[f] << 16);
+                }
+        }
+    }
     if (L.layout == XZZX_ROTATED && L.d <= kStaticMaxD) {
         // padding entries: the null shape on the nibble at column d+1 of rows
         // 0 and 1, which holds only padding bits (never a qubit)
@@ -487,6 +565,7 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     const size_t o_thr = take(thr.size() * 4);
     const size_t o_lx = take(L.nq);
     const size_t o_lz = take(L.nq);
+    const size_t o_qpos = take(qpos.size() * 4);
     size_t o_cf[2], o_dint[2], o_db[2], o_adj[2];
     for (int g = 0; g < 2; ++g) {
         o_cf[g] = take(G[g].n * 4);
@@ -507,6 +586,7 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     put(o_thr, thr.data(), thr.size() * 4);
     put(o_lx, L.lx.data(), L.nq);
     put(o_lz, L.lz.data(), L.nq);
+    put(o_qpos, qpos.data(), qpos.size() * 4);
     for (int g = 0; g < 2; ++g) {
         put(o_cf[g], G[g].col_face.data(), G[g].n * 4);
         put(o_dint[g], G[g].dint.data(), (size_t)G[g].n * G[g].n * 4);
@@ -532,9 +612,9 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     h.layout = L.layout;
     h.d = L.d;
     h.row_words = P.row_words;
-    h.rows = L.d + 2;
+    h.rows = rows_of(L);
     h.static_words = P.static_words;
-    P.use_rows = (P.row_words || P.static_ok) ? 1 : 0;
+    P.use_rows = rows_by_default(P) ? 1 : 0;
     h.rowface = reinterpret_cast<const uint32_t *>(base + o_rowface);
     std::memcpy(h.W, w, sizeof(h.W));
     h.desc = reinterpret_cast<const Desc *>(base + o_desc);
@@ -544,6 +624,7 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
     h.thr = reinterpret_cast<const uint32_t *>(base + o_thr);
     h.lx = base + o_lx;
     h.lz = base + o_lz;
+    h.qpos = reinterpret_cast<const uint32_t *>(base + o_qpos);
     for (int g = 0; g < 2; ++g) {
         h.ncol[g] = G[g].n;
         h.col_face[g] = reinterpret_cast<const int32_t *>(base + o_cf[g]);
@@ -746,17 +827,17 @@ int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel)
 {
     if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
     if (kernel == XZZX_KERNEL_AUTO) {
-        plan->P.use_rows = (plan->P.row_words || plan->P.static_ok) ? 1 : 0;
+        plan->P.use_rows = rows_by_default(plan->P) ? 1 : 0;
         plan->P.static_d = plan->P.static_ok ? plan->P.lat.d : 0;
     } else if (kernel == XZZX_KERNEL_ROWS) {
         if (!plan->P.row_words && !plan->P.static_ok) {
-            set_error("the packed-row kernel needs a rotated lattice with d <= 31");
+            set_error("the packed-row kernel needs a rotated lattice with d <= 31 or a planar one with d <= 15");
             return XZZX_EINVAL;
         }
         plan->P.use_rows = 1;
         plan->P.static_d = plan->P.static_ok ? plan->P.lat.d : 0;
     } else if (kernel == XZZX_KERNEL_ROWS_GENERIC) {
-        if (!plan->P.row_words) { set_error("the generic packed-row kernel needs a rotated lattice with d <= 29"); return XZZX_EINVAL; }
+        if (!plan->P.row_words) { set_error("the generic packed-row kernel needs a rotated lattice with d <= 29 or a planar one with d <= 15"); return XZZX_EINVAL; }
         plan->P.use_rows = 1;
         plan->P.static_d = 0;
     } else if (kernel == XZZX_KERNEL_BYTES) {
@@ -807,7 +888,7 @@ int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain)
     if (plan->P.lds_bytes_anneal(g) > 65536) { set_error("chains per wavefront do not fit in LDS"); return XZZX_ERANGE; }
     plan->P.lanes = g;
     plan->P.hdev.lanes = g;
-    plan->P.use_rows = (lanes_per_chain == 0 && (plan->P.row_words || plan->P.static_ok)) ? 1 : 0;
+    plan->P.use_rows = (lanes_per_chain == 0 && rows_by_default(plan->P)) ? 1 : 0;
     if (hipMemcpy(&plan->P.ddev->lanes, &g, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
         set_error("plan update failed");
         return XZZX_EDEVICE;

@@ -126,10 +126,11 @@ struct PlanDev {
     int lanes;                     // lanes per chain (1..64)
     int layout, d;
     int row_words;                 // packed-row kernel: 32-bit words per lattice row (0 = unavailable)
-    int rows;                      // rows of the padded grid (d + 2)
+    int rows;                      // packed-row kernels: rows of the grid (rotated d + 2, planar 2d - 1)
     int static_words;              // specialised kernel: words per unpadded row (0 = unavailable)
     int32_t W[4];
     const uint32_t *rowface;       // [4][4*nblk] row | bit offset << 8 | shape << 16 (packed-row kernel)
+    const uint32_t *qpos;          // [nq] packed-row kernel: row << 8 | column of each qubit
     const Desc *desc;              // [4][M] by (class, rank)
     const Desc *face_desc;         // [nstab] by face id
     const uint8_t *lut;            // [ntypes][256] move-energy rank of a slot pattern
