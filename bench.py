@@ -41,8 +41,9 @@ ALU_PEAK_OPS = 256 * 128 * 2.4e9
 def kernel_source_sha256(kernel=""):
     """Digest of the sources a kernel is built from, in name order.  The
     annealing kernels specialised to a distance (k_anneal_rows_d<D>) come
-    from the headers and the xzzx_static_*.hip units alone; any other kernel
-    is digested with every device source."""
+    from the headers and the xzzx_static_*.hip units alone, the planar ones
+    (k_anneal_planar_d<D>) from the headers and xzzx_planar.hip; any other
+    kernel is digested with every device source."""
     import glob
     import hashlib
 
@@ -51,6 +52,8 @@ def kernel_source_sha256(kernel=""):
     files = glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(inc, "*.h"))
     if kernel.startswith("k_anneal_rows_d"):
         files += glob.glob(os.path.join(csrc, "xzzx_static_*.hip"))
+    elif kernel.startswith("k_anneal_planar_d"):
+        files += [os.path.join(csrc, "xzzx_planar.hip")]
     else:
         files += glob.glob(os.path.join(csrc, "*.hip"))
     h = hashlib.sha256()
@@ -249,6 +252,8 @@ def main():
     kinds = {pl.info()["kernel"] for pl in plans}
     if kinds == {X.KERNEL_SITE}:
         kernel_name = "k_anneal_site"
+    elif kinds == {X.KERNEL_ROWS} and layout == X.PLANAR and len(set(wl["d"])) == 1:
+        kernel_name = f"k_anneal_planar_d{wl['d'][0]}"   # planar packed rows specialised to d
     elif kinds == {X.KERNEL_ROWS} and len(set(wl["d"])) == 1 and (4 * R) % 64 == 0:
         kernel_name = f"k_anneal_rows_d{wl['d'][0]}"   # packed rows specialised to d
     elif kinds <= {X.KERNEL_ROWS, X.KERNEL_ROWS_GENERIC}:

@@ -1392,6 +1392,8 @@ void k_serve_rows_class(const ServeTask *tasks, uint32_t slo, uint32_t shi)
 }
 
 typedef void (*AnnealKernel)(AnnealArgs);
+// kernels specialised to the planar lattice at odd d <= 15 (NULL otherwise)
+AnnealKernel planar_rows_kernel(int d, bool plain);
 typedef void (*ServeKernel)(const ServeTask *, uint32_t, uint32_t);
 
 // The specialised kernels live in several translation units (compiled in

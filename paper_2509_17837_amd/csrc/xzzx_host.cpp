@@ -280,13 +280,14 @@ static bool static_schedule_matches(int d, const std::vector<uint32_t> &rowface,
 // Packed-row layout (rotated lattice): the padded grid has columns and rows
 // -1..d; a row of 2-bit codes takes 2(d+2) bits, so 1 word for d <= 13 and 2
 // words for d <= 29.
-// The default kernel: packed rows on rotated lattices; on the planar lattice
-// the byte-state kernel, which measured faster at d = 9 (its packed rows need
-// two words and half the grid is padding); the packed rows stay available to
-// set_kernel and the autotuner.
+// The default kernel: packed rows on rotated lattices, and on planar ones
+// where the kernel specialised to d applies; otherwise the byte-state kernel
+// on the planar lattice, which measured faster than the generic packed rows
+// at d = 9 (two words per row, half the grid padding).  Every kernel stays
+// available to set_kernel and the autotuner.
 static bool rows_by_default(const Plan &P)
 {
-    return P.static_ok || (P.row_words && P.lat.layout == XZZX_ROTATED);
+    return P.static_ok || P.planar_ok || (P.row_words && P.lat.layout == XZZX_ROTATED);
 }
 
 static int row_words_for(const Lattice &L)
@@ -535,6 +536,14 @@ int build_plan(const Lattice &L, const int32_t w[4], const int32_t wg[2], const 
                 rowface[k * mpad + m] = Y | ((2u * X) << 8) | ((uint32_t)shape_of_face[f] << 16);
             }
     }
+    // the planar kernel specialised to d applies when its compile-time
+    // schedule and qubit positions are exactly this plan's tables
+    P.planar_ok = 0;
+    if (L.layout == XZZX_PLANAR && P.row_words && L.d <= kPlanarStaticMaxD && nranks <= kStaticRanks &&
+        shapes == std::vector<int>(kPlanarShapeMasks, kPlanarShapeMasks + 6) &&
+        planar_schedule_matches(L.d, rowface, mpad, qpos))
+        P.planar_ok = 1;
+    P.planar_d = P.planar_ok ? L.d : 0;
     // the specialised packed-row kernel applies when its compile-time
     // schedule is exactly this plan's table
     P.static_d = 0;
@@ -829,6 +838,7 @@ int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel)
     if (kernel == XZZX_KERNEL_AUTO) {
         plan->P.use_rows = rows_by_default(plan->P) ? 1 : 0;
         plan->P.static_d = plan->P.static_ok ? plan->P.lat.d : 0;
+        plan->P.planar_d = plan->P.planar_ok ? plan->P.lat.d : 0;
     } else if (kernel == XZZX_KERNEL_ROWS) {
         if (!plan->P.row_words && !plan->P.static_ok) {
             set_error("the packed-row kernel needs a rotated lattice with d <= 31 or a planar one with d <= 15");
@@ -836,10 +846,12 @@ int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel)
         }
         plan->P.use_rows = 1;
         plan->P.static_d = plan->P.static_ok ? plan->P.lat.d : 0;
+        plan->P.planar_d = plan->P.planar_ok ? plan->P.lat.d : 0;
     } else if (kernel == XZZX_KERNEL_ROWS_GENERIC) {
         if (!plan->P.row_words) { set_error("the generic packed-row kernel needs a rotated lattice with d <= 29 or a planar one with d <= 15"); return XZZX_EINVAL; }
         plan->P.use_rows = 1;
         plan->P.static_d = 0;
+        plan->P.planar_d = 0;
     } else if (kernel == XZZX_KERNEL_BYTES) {
         plan->P.use_rows = 0;
     } else {
@@ -855,7 +867,7 @@ int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sw
     if (plan && kernel)
         *kernel = plan->P.order ? XZZX_KERNEL_SITE
                   : !plan->P.use_rows ? XZZX_KERNEL_BYTES
-                  : plan->P.static_d ? XZZX_KERNEL_ROWS : XZZX_KERNEL_ROWS_GENERIC;
+                  : (plan->P.static_d || plan->P.planar_d) ? XZZX_KERNEL_ROWS : XZZX_KERNEL_ROWS_GENERIC;
     if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
     if (n_qubits) *n_qubits = plan->P.lat.nq;
     if (n_stabs) *n_stabs = plan->P.lat.nstab;

@@ -79,6 +79,86 @@ struct RotSchedule {
     }
 };
 
+// Compile-time schedule of the planar lattice at distance D for the
+// packed-row kernel specialised to it.  Turned by 45 degrees, qubit (x, y) of
+// the doubled coordinates sits at row (x + y - 1)/2 - 1, column
+// (x - y - 1)/2 + D - 1, and generator (x, y) covers the 2 x 2 block at row
+// (x + y)/2 - 2, column (x - y)/2 + D - 2 (X on the diagonal, Z on the
+// anti-diagonal); its slots 1 and 2 trade places in the block, so its shape
+// is the one with those slots exchanged.  Ranks within a class run row-major
+// over ((x + y)/2, (x - y)/2), as in the plan; each class is padded to a
+// multiple of four with null generators on the padding columns 2D - 1, 2D of
+// rows 0 and 1.  The qubit numbering is the plan's: (odd, even) qubits first,
+// then (even, odd).  This is the plan's own table, against which the host
+// checks it.
+constexpr int kPlanarShapeMasks[6] = {15, 14, 13, 11, 7, 0};
+
+template <int D>
+struct PlanarSchedule {
+    static constexpr int NS = 2 * D * (D - 1);
+    static constexpr int M = NS / 4;
+    static constexpr int MP = (M + 3) / 4 * 4;
+    static constexpr int NQ = D * D + (D - 1) * (D - 1);
+    RotGen g[4][MP];
+    uint16_t qpos[NQ];   // row << 8 | column
+    static constexpr int qubit(int x, int y)
+    {
+        if ((x & 1) && !(y & 1) && x >= 3 && x <= 2 * D - 1 && y >= 2 && y <= 2 * D - 2)
+            return (y / 2 - 1) * (D - 1) + (x - 3) / 2;
+        if (!(x & 1) && (y & 1) && x >= 2 && x <= 2 * D && y >= 1 && y <= 2 * D - 1)
+            return (D - 1) * (D - 1) + (y / 2) * D + (x / 2 - 1);
+        return -1;
+    }
+    constexpr PlanarSchedule() : g{}, qpos{}
+    {
+        int fx[NS] = {}, fy[NS] = {}, fk[NS] = {}, used[NS] = {};
+        int n = 0;
+        for (int i = 1; i <= D; ++i)
+            for (int j = 1; j <= D - 1; ++j) { fx[n] = 2 * i; fy[n] = 2 * j; ++n; }
+        for (int i = 1; i <= D - 1; ++i)
+            for (int j = 1; j <= D; ++j) { fx[n] = 2 * i + 1; fy[n] = 2 * j - 1; ++n; }
+        for (int f = 0; f < NS; ++f) {
+            const int a = fx[f] + fy[f], b = fx[f] - fy[f];
+            fk[f] = ((a / 2) & 1) | (((b >= 0 ? b / 2 : -((-b) / 2)) & 1) << 1);
+        }
+        for (int k = 0; k < 4; ++k) {
+            int m = 0;
+            for (;; ++m) {
+                int best = -1;
+                for (int f = 0; f < NS; ++f) {
+                    if (used[f] || fk[f] != k) continue;
+                    if (best < 0 || (fx[f] + fy[f] < fx[best] + fy[best]) ||
+                        (fx[f] + fy[f] == fx[best] + fy[best] && fx[f] - fy[f] < fx[best] - fy[best]))
+                        best = f;
+                }
+                if (best < 0) break;
+                used[best] = 1;
+                const int x = fx[best], y = fy[best];
+                const int q[4] = {qubit(x - 1, y), qubit(x, y + 1), qubit(x, y - 1), qubit(x + 1, y)};
+                int mask = 0;
+                for (int sl = 0; sl < 4; ++sl) mask |= (q[sl] >= 0 ? 1 : 0) << sl;
+                const int rows_mask = (mask & 9) | ((mask & 2) << 1) | ((mask & 4) >> 1);
+                int shp = 0;
+                while (kPlanarShapeMasks[shp] != rows_mask) ++shp;
+                const int top = (x + y) / 2 - 2, left = (x - y) / 2 + D - 2;
+                g[k][m] = RotGen{(uint8_t)top, (uint8_t)(2 * left), (uint8_t)shp};
+                const int dy[4] = {0, 1, 0, 1}, dx[4] = {0, 0, 1, 1};
+                for (int sl = 0; sl < 4; ++sl)
+                    if (q[sl] >= 0) qpos[q[sl]] = (uint16_t)(((top + dy[sl]) << 8) | (left + dx[sl]));
+            }
+            for (; m < MP; ++m) g[k][m] = RotGen{0, (uint8_t)(2 * (2 * D - 1)), 5};
+        }
+    }
+};
+template <int D>
+inline constexpr PlanarSchedule<D> kPlanarSchedule{};
+
+// Planar distances with a specialised packed-row kernel (rows of 2D + 1
+// columns in at most two words), and the host check that a plan's packed-row
+// tables are its compile-time schedule.
+constexpr int kPlanarStaticMaxD = 15;
+bool planar_schedule_matches(int d, const std::vector<uint32_t> &rowface, int mpad, const std::vector<uint32_t> &qpos);
+
 // Distances with a specialised packed-row kernel, and the largest number of
 // distinct move energies its static tables hold.
 constexpr int kStaticMinD = 3, kStaticMaxD = 31;
@@ -160,6 +240,8 @@ struct Plan {
     int static_ok = 0;             // the plan's tables match the specialised schedule
     int static_words = 0;          // words per row of the specialised kernel's rows (2(d+1) bits)
     int order = 0;                 // XZZX_ORDER_COLOUR or XZZX_ORDER_RANDOM_SITE
+    int planar_ok = 0;             // the planar kernel specialised to d applies
+    int planar_d = 0;              // d while that kernel is in use, else 0
     int nranks() const { return (int)dE.size(); }
     int device = 0;
     void *dmem = nullptr;          // device allocation holding every table

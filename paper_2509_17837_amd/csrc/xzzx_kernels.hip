@@ -736,7 +736,8 @@ enum class AnnealMode { Persistent, Replay, Plain };
 // over more lanes when that is needed to give every CU several wavefronts.
 static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::vector<int> &sel, bool rows, int lanes,
                       AnnealMode mode, uint64_t seed, int64_t unit_offset, int64_t units_override,
-                      uint32_t *d_counter, hipStream_t stream, int static_d = 0, bool site = false)
+                      uint32_t *d_counter, hipStream_t stream, int static_d = 0, bool site = false,
+                      int planar_d = 0)
 {
     const bool replay = mode == AnnealMode::Replay;
     AnnealArgs A{};
@@ -784,7 +785,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         G.task_begin = (int64_t)tasks;
         const int C = kWave / lanes;
         tasks += (uint64_t)((units + C - 1) / C);
-        lds = std::max(lds, static_d ? (size_t)0
+        lds = std::max(lds, (static_d || planar_d) ? (size_t)0
                             : site   ? P.lds_bytes_site()
                             : rows   ? P.lds_bytes_rows()
                                      : P.lds_bytes_anneal(lanes));
@@ -797,6 +798,8 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
     if (mode == AnnealMode::Plain) {
         if (site)
             hipLaunchKernelGGL(k_anneal_site_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
+        else if (planar_d)
+            hipLaunchKernelGGL(planar_rows_kernel(planar_d, true), dim3((unsigned)tasks), dim3(kWave), 0, stream, A);
         else if (static_d)
             hipLaunchKernelGGL(static_rows_kernel(static_d, true), dim3((unsigned)tasks), dim3(kWave), 0, stream, A);
         else if (rows)
@@ -806,6 +809,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         return check_hip(hipGetLastError(), "plain anneal launch");
     }
     const AnnealKernel kern = site       ? (replay ? k_replay_site : k_anneal_site)
+                              : planar_d ? planar_rows_kernel(planar_d, false)
                               : static_d ? static_rows_kernel(static_d, false)
                               : rows     ? k_anneal_rows
                                          : bytes_kernel(replay ? 1 : 0, lg);
@@ -884,7 +888,8 @@ static int fork_join(hipStream_t stream, int n, F launch)
 // a chain over more lanes when that is needed to give every CU several
 // wavefronts.  Each launch has its own queue counter: d_counters[0] packed
 // rows, [1..7] byte states by lanes per chain, [16..30] the kernels
-// specialised to d = 3, 5, ..., 31, [40] random-site chains; a replay (with
+// specialised to d = 3, 5, ..., 31, [40] random-site chains, [41..47] the
+// planar kernels specialised to d = 3, 5, ..., 15; a replay (with
 // its own d_counters base) uses [0], [2] and [4].
 static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
                          uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
@@ -895,6 +900,7 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
     std::vector<int> static_sel[kStaticMaxD + 1];
     std::vector<int> replay_cp;   // replays starting from checkpoints: one chain per wavefront
     std::vector<int> site_sel;    // random-site plans: one chain (replay: syndrome) per lane
+    std::vector<int> planar_sel[kPlanarStaticMaxD + 1];   // planar kernels specialised to d
     int64_t total_syn = 0;
     for (int i = 0; i < n_groups; ++i) {
         if (groups[i].n_syn <= 0) continue;
@@ -904,7 +910,8 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
             continue;
         }
         total_syn += groups[i].n_syn;
-        if (mode != AnnealMode::Replay && uses_static(groups[i], unit_offset)) static_sel[P.static_d].push_back(i);
+        if (mode != AnnealMode::Replay && P.use_rows && P.planar_d) planar_sel[P.planar_d].push_back(i);
+        else if (mode != AnnealMode::Replay && uses_static(groups[i], unit_offset)) static_sel[P.static_d].push_back(i);
         else if (mode == AnnealMode::Replay && checkpoints_of(groups[i]) > 0) replay_cp.push_back(i);
         else if (mode != AnnealMode::Replay && P.use_rows && P.row_words) rows_sel.push_back(i);
         else bytes_sel[log2_int(P.lanes)].push_back(i);
@@ -946,27 +953,31 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         uint32_t *counter;
         int static_d;
         bool site;
+        int planar_d;
     };
     std::vector<Set> sets;
-    if (!rows_sel.empty()) sets.push_back({&rows_sel, true, 1, d_counters, 0, false});
-    if (!site_sel.empty()) sets.push_back({&site_sel, false, 1, d_counters + 40, 0, true});
+    if (!rows_sel.empty()) sets.push_back({&rows_sel, true, 1, d_counters, 0, false, 0});
+    if (!site_sel.empty()) sets.push_back({&site_sel, false, 1, d_counters + 40, 0, true, 0});
+    for (int d = 3; d <= kPlanarStaticMaxD; d += 2)
+        if (!planar_sel[d].empty())
+            sets.push_back({&planar_sel[d], true, 1, d_counters + 41 + (d - 3) / 2, 0, false, d});
     for (int d = kStaticMinD; d <= kStaticMaxD; d += 2)
         if (!static_sel[d].empty())
-            sets.push_back({&static_sel[d], true, 1, d_counters + 16 + (d - kStaticMinD) / 2, d, false});
+            sets.push_back({&static_sel[d], true, 1, d_counters + 16 + (d - kStaticMinD) / 2, d, false, 0});
     for (int l = 0; l < 7; ++l)
-        if (!bytes_sel[l].empty()) sets.push_back({&bytes_sel[l], false, 1 << l, d_counters + 1 + l, 0, false});
+        if (!bytes_sel[l].empty()) sets.push_back({&bytes_sel[l], false, 1 << l, d_counters + 1 + l, 0, false, 0});
     if (sets.size() <= 1 || mode == AnnealMode::Plain) {
         int rc = XZZX_OK;
         for (const Set &S : sets)
             if (!rc)
                 rc = launch_set(groups, ws, *S.sel, S.rows, S.lanes, mode, seed, unit_offset, units_override, S.counter,
-                                stream, S.static_d, S.site);
+                                stream, S.static_d, S.site, S.planar_d);
         return rc;
     }
     return fork_join(stream, (int)sets.size(), [&](int i, hipStream_t s) {
         const Set &S = sets[i];
         return launch_set(groups, ws, *S.sel, S.rows, S.lanes, mode, seed, unit_offset, units_override, S.counter, s,
-                          S.static_d, S.site);
+                          S.static_d, S.site, S.planar_d);
     });
 }
 

@@ -120,7 +120,8 @@ extern "C" int xzzx_plan_autotune(xzzx_plan *plan, int n_rep, int n_syn, int pro
     }
     if (rc) return rc;
     if (out) {
-        out->kernel = !P.use_rows ? XZZX_KERNEL_BYTES : P.static_d ? XZZX_KERNEL_ROWS : XZZX_KERNEL_ROWS_GENERIC;
+        out->kernel = !P.use_rows ? XZZX_KERNEL_BYTES
+                      : (P.static_d || P.planar_d) ? XZZX_KERNEL_ROWS : XZZX_KERNEL_ROWS_GENERIC;
         out->lanes_per_chain = P.lanes;
         std::memcpy(out->times_ms, times, sizeof(times));
     }

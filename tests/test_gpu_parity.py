@@ -174,18 +174,22 @@ def test_row_and_byte_kernels_agree(d):
 
 
 @pytest.mark.parametrize("d,n_syn,R,sweeps", [(3, 60, 3, 40), (5, 20, 10, 100), (7, 9, 7, 30), (9, 24, 10, 100),
-                                              (15, 3, 16, 12)])
+                                              (11, 5, 10, 20), (13, 3, 12, 10), (15, 3, 16, 12)])
 def test_planar_packed_rows(d, n_syn, R, sweeps):
-    """Planar lattices on the packed-row kernel: turned by 45 degrees, each
+    """Planar lattices on the packed-row kernels: turned by 45 degrees, each
     generator covers a 2 x 2 block of a diamond of rows (one word per row up
-    to d = 7, two up to d = 15).  The paper's set-up (1:eta:1, log schedule);
+    to d = 7, two up to d = 15), in registers for the kernel specialised to
+    d, in LDS for the generic one.  The paper's set-up (1:eta:1, log
+    schedule; N_SA = 10 gives tasks of 64 chains spanning syndromes); both,
     the byte-state kernel and the oracle agree chain by chain."""
     prob = Problem(1, d, 0.15, 5.0, n_syn, R, sweeps, sched=("paper_log", 0.9, 1.0), seed=600 + d, conv=1)
     ref = prob.oracle_decode()
-    for kernel in (X.KERNEL_ROWS_GENERIC, X.KERNEL_BYTES):
+    for kernel in (X.KERNEL_ROWS, X.KERNEL_ROWS_GENERIC, X.KERNEL_BYTES):
         plan = gpu_plan(prob)
         plan.set_kernel(kernel)
+        assert plan.info()["kernel"] == kernel
         compare_decode(prob, run_decode(prob, plan, want_final=True), ref)
+        compare_decode(prob, run_decode(prob, plan, flags=X.FLAG_PLAIN), ref)
 
 
 @pytest.mark.parametrize("d", list(range(3, 32, 2)))
@@ -230,17 +234,17 @@ def test_replay_from_checkpoints(d, sweeps):
 
 
 def test_specialised_kernel_not_applicable():
-    """The planar layout has no specialised kernel: it runs on the byte-state
-    kernel by default, and on the generic packed-row kernel (d <= 15) when
-    asked; at d = 31 a replica count that splits 64-chain tasks over
-    syndromes runs on the byte-state kernel (there is no generic packed-row
-    kernel at d = 31)."""
+    """Planar lattices run on the kernel specialised to d (odd d <= 15) by
+    default, on the generic packed-row kernel when asked, and on the
+    byte-state kernel beyond d = 15; at rotated d = 31 a replica count that
+    splits 64-chain tasks over syndromes runs on the byte-state kernel (there
+    is no generic packed-row kernel at d = 31)."""
     plan = gpu_plan(Problem(1, 5, 0.2, 10.0, 1, 1, 1))
-    assert plan.info()["kernel"] == X.KERNEL_BYTES
+    assert plan.info()["kernel"] == X.KERNEL_ROWS
     plan.set_kernel(X.KERNEL_ROWS_GENERIC)
     assert plan.info()["kernel"] == X.KERNEL_ROWS_GENERIC
     plan.set_kernel(X.KERNEL_AUTO)
-    assert plan.info()["kernel"] == X.KERNEL_BYTES
+    assert plan.info()["kernel"] == X.KERNEL_ROWS
     assert gpu_plan(Problem(1, 17, 0.2, 10.0, 1, 1, 1)).info()["kernel"] == X.KERNEL_BYTES
     prob = Problem(0, 31, 0.2, 10.0, 3, 5, 6, seed=931)
     compare_decode(prob, run_decode(prob, gpu_plan(prob)), prob.oracle_decode())
