@@ -172,6 +172,7 @@ struct GroupArgs {
     uint32_t *cp_rows;            // specialised packed-row kernel: checkpoints [n_cp][d][n_chains]
     int64_t n_chains;             // chains of the whole group
     int cp_every;                 // sweeps between checkpoints (0 = none)
+    uint32_t *site_snap;          // random-site kernel: state at E_min, packed words [word][n_chains]
 };
 
 struct AnnealArgs {
@@ -427,13 +428,13 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
 // Philox(uid, chain, 2^31 + t, m div 2): words 2 (m mod 2) and 2 (m mod 2) + 1
 // are the site draw (site = floor(u N_stab / 2^32), face-id order) and the
 // acceptance draw.  E_min is tracked after every step; stop = t N_stab + m + 1
-// (0 = the start).  REPLAY re-runs each syndrome's best chain to its stop step.
+// (0 = the start), and the state at the first E_min is kept in `snap` (word w
+// of chain ci at snap[w * snap_stride + ci]) for the recovery.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int site_words(int nq) { return nq / 16 + 1; }
 
-template <bool REPLAY>
 __device__ inline void site_core(const PlanDev *pl, const ChainJob &J, uint32_t seed_lo, uint32_t seed_hi,
-                                 uint8_t *smem)
+                                 uint8_t *smem, uint32_t *snap, int64_t snap_stride)
 {
     const int c = threadIdx.x;
     const int nq = pl->nq, nstab = pl->nstab, nranks = pl->nranks, n_sweeps = pl->n_sweeps;
@@ -469,15 +470,11 @@ __device__ inline void site_core(const PlanDev *pl, const ChainJob &J, uint32_t 
     auto save_state = [&](uint8_t *dst) {
         for (int q = 0; q < nq; ++q) dst[q] = (uint8_t)((st[(q >> 4) * kWave + c] >> (2 * (q & 15))) & 3u);
     };
-    int32_t last = n_sweeps * nstab;
-    const int32_t target = REPLAY && J.active ? J.target : -1;
-    if (REPLAY) {
-        if (target == 0) save_state(J.snap);
-        int32_t tmax = max(target, 0);
-#pragma unroll
-        for (int sh = 1; sh < kWave; sh <<= 1) tmax = max(tmax, __shfl_xor(tmax, sh, kWave));
-        last = tmax;
-    }
+    auto keep_min = [&]() {
+        for (int w = 0; w < nw; ++w) snap[(int64_t)w * snap_stride + J.ci] = st[w * kWave + c];
+    };
+    const bool keep = snap != nullptr && J.active;
+    if (keep) keep_min();
 
     constexpr int kThrPerLane = (kMaxRanks + kWave - 1) / kWave;
     uint32_t thr_next[kThrPerLane];
@@ -510,11 +507,14 @@ __device__ inline void site_core(const PlanDev *pl, const ChainJob &J, uint32_t 
             *a3 ^= 2u << s3;
             E += et.x;
         }
-        if (E < Emin) { Emin = E; stop = s + 1; }
-        if (REPLAY && s + 1 == target) save_state(J.snap);
+        if (E < Emin) {
+            Emin = E;
+            stop = s + 1;
+            if (keep) keep_min();
+        }
     };
 
-    for (int t = 0; t < n_sweeps && t * nstab < last; ++t) {
+    for (int t = 0; t < n_sweeps; ++t) {
 #pragma unroll
         for (int j = 0; j < kThrPerLane; ++j)
             if (c + j * kWave < nranks) et_s[c + j * kWave].y = (int)thr_next[j];
@@ -529,7 +529,7 @@ __device__ inline void site_core(const PlanDev *pl, const ChainJob &J, uint32_t 
         }
         wave_lds_fence();
     }
-    if (!REPLAY && J.active) {
+    if (J.active) {
         J.emin[J.ci] = Emin;
         J.stop[J.ci] = stop;
         J.efin[J.ci] = E;
@@ -1175,10 +1175,8 @@ __device__ __forceinline__ void batch_kernel_body(const AnnealArgs &A)
 }
 
 // Batch body of the random-site core (MODE as in batch_kernel_body): tasks of
-// 64 chains, or in replay 64 >> log_lanes syndromes (a replay of few
-// syndromes spreads them over more wavefronts; the other lanes idle); the
-// face descriptors are staged by face id.
-template <int MODE, bool REPLAY>
+// 64 chains; the face descriptors are staged by face id.
+template <int MODE>
 __device__ __forceinline__ void site_kernel_body(const AnnealArgs &A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -1196,17 +1194,14 @@ __device__ __forceinline__ void site_kernel_body(const AnnealArgs &A)
         int gi = 0;
         while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
         const GroupArgs &G = A.g[gi];
-        const int lgc = 6 - G.log_lanes;
-        const int64_t unit0 = ((int64_t)task - G.task_begin) << lgc;
+        const int64_t unit0 = ((int64_t)task - G.task_begin) << 6;
         if (G.plan != loaded) {
             wave_lds_fence();
             load_plan_tables(G.plan, smem, true);
             loaded = G.plan;
         }
-        const int lane = threadIdx.x;
-        ChainJob J = batch_job(G, unit0 + (lane & ((1 << lgc) - 1)), REPLAY);
-        if (lane >> lgc) J.active = false;
-        site_core<REPLAY>(G.plan, J, A.seed_lo, A.seed_hi, smem);
+        const ChainJob J = batch_job(G, unit0 + threadIdx.x, false);
+        site_core(G.plan, J, A.seed_lo, A.seed_hi, smem, G.site_snap, G.n_chains);
     }
 }
 

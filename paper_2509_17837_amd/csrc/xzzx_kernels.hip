@@ -372,9 +372,23 @@ template <int LOGG>
 __global__ __launch_bounds__(kWave) void k_replay(AnnealArgs A) { batch_kernel_body<0, false, LOGG, true>(A); }
 template <int LOGG>
 __global__ __launch_bounds__(kWave) void k_anneal_plain(AnnealArgs A) { batch_kernel_body<2, false, LOGG, false>(A); }
-__global__ __launch_bounds__(kWave) void k_anneal_site(AnnealArgs A) { site_kernel_body<0, false>(A); }
-__global__ __launch_bounds__(kWave) void k_replay_site(AnnealArgs A) { site_kernel_body<0, true>(A); }
-__global__ __launch_bounds__(kWave) void k_anneal_site_plain(AnnealArgs A) { site_kernel_body<2, false>(A); }
+__global__ __launch_bounds__(kWave) void k_anneal_site(AnnealArgs A) { site_kernel_body<0>(A); }
+__global__ __launch_bounds__(kWave) void k_anneal_site_plain(AnnealArgs A) { site_kernel_body<2>(A); }
+
+// Random-site order: each syndrome's recovery is its best chain's state kept
+// at that chain's first E_min (packed words [word][chain]); one thread per
+// (syndrome, qubit).
+__global__ void k_site_recovery(const uint32_t *__restrict__ snap, int64_t n_chains,
+                                const int32_t *__restrict__ best_chain, int n_rep, int nq, int64_t n_syn,
+                                uint8_t *__restrict__ recovery)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_syn * nq) return;
+    const int64_t s = idx / nq;
+    const int q = (int)(idx - s * nq);
+    const int64_t ci = s * 4 * n_rep + best_chain[s];
+    recovery[idx] = (uint8_t)((snap[(int64_t)(q >> 4) * n_chains + ci] >> (2 * (q & 15))) & 3u);
+}
 __global__ __launch_bounds__(kWave) void k_anneal_rows(AnnealArgs A) { batch_kernel_body<0, true, 0, false>(A); }
 __global__ __launch_bounds__(kWave) void k_anneal_rows_plain(AnnealArgs A) { batch_kernel_body<2, true, 0, false>(A); }
 
@@ -620,7 +634,11 @@ struct GroupWs {
     uint8_t *refs, *qraw, *qcls;
     int32_t *emin, *stop, *efin, *best_chain;
     uint32_t *cp_rows;     // checkpoints of groups on the specialised packed-row kernel
+    uint32_t *site_snap;   // random-site groups: each chain's state at its first E_min
 };
+
+// packed words per chain of a random-site state (position nq is scratch)
+static int64_t site_words_of(const Plan &P) { return P.lat.nq / 16 + 1; }
 
 // A group runs on the packed-row kernel specialised to its distance when the
 // plan allows it and every 64-chain task lies inside one syndrome.
@@ -660,6 +678,7 @@ static size_t group_ws_bytes(const xzzx_group &g, bool decode)
     if (!g.d_chain_e) b += align256(nc * 4);
     if (!g.d_best_chain) b += align256(ns * 4);
     b += align256((size_t)checkpoints_of(g) * P.lat.d * P.static_words * nc * 4);
+    if (P.order == XZZX_ORDER_RANDOM_SITE) b += align256((size_t)site_words_of(P) * nc * 4);
     return b;
 }
 
@@ -678,6 +697,8 @@ static GroupWs carve_group(const xzzx_group &g, bool decode, uint8_t *&p)
     w.best_chain = g.d_best_chain ? g.d_best_chain : reinterpret_cast<int32_t *>(take(ns * 4));
     const int ncp = checkpoints_of(g);
     w.cp_rows = ncp ? reinterpret_cast<uint32_t *>(take((size_t)ncp * P.lat.d * P.static_words * nc * 4)) : nullptr;
+    w.site_snap = P.order == XZZX_ORDER_RANDOM_SITE
+                      ? reinterpret_cast<uint32_t *>(take((size_t)site_words_of(P) * nc * 4)) : nullptr;
     return w;
 }
 
@@ -779,6 +800,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         G.cp_rows = cp ? ws[i].cp_rows : nullptr;
         G.cp_every = cp ? checkpoint_interval(P) : 0;
         G.n_chains = g.n_syn * 4 * g.n_rep;
+        G.site_snap = site ? ws[i].site_snap : nullptr;
         G.unit_offset = unit_offset;
         const int64_t units = units_of(i);
         G.n_units = units;
@@ -808,7 +830,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
             hipLaunchKernelGGL(bytes_kernel(2, lg), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         return check_hip(hipGetLastError(), "plain anneal launch");
     }
-    const AnnealKernel kern = site       ? (replay ? k_replay_site : k_anneal_site)
+    const AnnealKernel kern = site       ? k_anneal_site
                               : planar_d ? planar_rows_kernel(planar_d, false)
                               : static_d ? static_rows_kernel(static_d, false)
                               : rows     ? k_anneal_rows
@@ -890,7 +912,7 @@ static int fork_join(hipStream_t stream, int n, F launch)
 // rows, [1..7] byte states by lanes per chain, [16..30] the kernels
 // specialised to d = 3, 5, ..., 31, [40] random-site chains, [41..47] the
 // planar kernels specialised to d = 3, 5, ..., 15; a replay (with
-// its own d_counters base) uses [0], [2] and [4].
+// its own d_counters base) uses [0] and [2].
 static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
                          uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
                          hipStream_t stream)
@@ -932,15 +954,18 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         if (!rc)
             rc = launch_set(groups, ws, replay_cp, false, kWave, mode, seed, unit_offset, units_override,
                             d_counters + 2, stream);
-        // random-site replays: each lane re-runs a chain step by step, so
-        // few syndromes per wavefront keep more wavefronts in flight
-        int64_t site_syn = 0;
-        for (int i : site_sel) site_syn += groups[i].n_syn;
-        int Cs = kWave;
-        while (Cs > 1 && site_syn / Cs < want) Cs >>= 1;
-        if (!rc)
-            rc = launch_set(groups, ws, site_sel, false, kWave / Cs, mode, seed, unit_offset, units_override,
-                            d_counters + 4, stream, 0, true);
+        // random-site groups kept each chain's state at its E_min: gather
+        for (int i : site_sel) {
+            if (rc) break;
+            const xzzx_group &g = groups[i];
+            const Plan &P = g.plan->P;
+            const int64_t n = g.n_syn * (int64_t)P.lat.nq;
+            if ((n + 255) / 256 > 0x7FFFFFFF) { set_error("too many recovery bytes in one group"); return XZZX_ERANGE; }
+            hipLaunchKernelGGL(k_site_recovery, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                               ws[i].site_snap, g.n_syn * 4 * (int64_t)g.n_rep, ws[i].best_chain, g.n_rep, P.lat.nq,
+                               g.n_syn, g.d_recovery);
+            rc = check_hip(hipGetLastError(), "k_site_recovery launch");
+        }
         return rc;
     }
     // the launches of one call (one per kernel family and distance) run

@@ -104,8 +104,9 @@ def test_paper_setup(d, eta, n_beta, mode):
 def test_random_site_order(layout, d, n_syn, R, sweeps):
     """Algs. 2-3 as printed: each step picks a generator uniformly at random
     and E_min is tracked after every step.  Every chain (E, E_min, stop step,
-    final state) and the recovery, replayed to the best chain's stop step,
-    equal the oracle's random-site chains; ragged tails of 64-chain tasks."""
+    final state) and the recovery (the best chain's state kept at its first
+    E_min) equal the oracle's random-site chains; ragged tails of 64-chain
+    tasks."""
     prob = Problem(layout, d, 0.15, 5.0, n_syn, R, sweeps, sched=("paper_log", 0.9, 1.0), seed=900 + d, conv=1)
     plan = gpu_plan(prob)
     plan.set_order(X.ORDER_RANDOM_SITE)

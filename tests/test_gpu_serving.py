@@ -26,14 +26,15 @@ def _gpu():
 
 
 class Spec:
-    def __init__(self, d, p, eta, sweeps, n, stream, uid0):
-        self.d, self.p, self.eta, self.sweeps = d, p, eta, sweeps
-        self.lat = D.Lattice(X.ROTATED, d)
-        w, wg = D.weights(p, D.noise(p, eta))
-        beta = D.schedule(X.SCHED_GEOMETRIC, 0.05, 10.0, sweeps)
+    def __init__(self, d, p, eta, sweeps, n, stream, uid0, layout=X.ROTATED, conv=0,
+                 sched=(X.SCHED_GEOMETRIC, 0.05, 10.0)):
+        self.d, self.p, self.eta, self.sweeps, self.conv, self.sched = d, p, eta, sweeps, conv, sched
+        self.lat = D.Lattice(layout, d)
+        w, wg = D.weights(p, D.noise(p, eta, conv))
+        beta = D.schedule(sched[0], sched[1], sched[2], sweeps)
         self.plan = D.Plan(self.lat, w, wg, beta)
-        self.olat = O.Lattice(O.ROTATED, d)
-        err = inputs.sample_errors(n, self.lat.nq, inputs.channel(p, eta), 77, stream=stream)
+        self.olat = O.Lattice(layout, d)
+        err = inputs.sample_errors(n, self.lat.nq, inputs.channel(p, eta, conv), 77, stream=stream)
         self.syn = np.stack([self.olat.syndrome(e) for e in err])
         self.uid = inputs.sample_uids(n, uid0)
 
@@ -194,3 +195,30 @@ def test_every_specialised_serving_class():
     outs = {id(s): s.batch(R) for s in specs}
     for s, i, r in res:
         assert same(r, outs[id(s)], i), f"d={s.d} request {i}"
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 64], ids=["adaptive", "plan-kernel", "up-to-64-lanes"])
+def test_planar_requests(lanes):
+    """The paper's set-up served: planar d = 5, 7, 9, p_x:p_y:p_z = 1:eta:1, log
+    schedule over N_beta = 100, N_SA = 10.  The server runs them on the
+    generic packed-row or the byte-state serving kernels; every result equals
+    the batch decoder's (the planar kernel specialised to d) and, on a
+    sample, the oracle's."""
+    R = 10
+    specs = [Spec(d, 0.15, eta, 100, 3, 60 + d, 30000 + 100 * d, layout=X.PLANAR, conv=1,
+                  sched=(X.SCHED_PAPER_LOG, 0.9, 1.0)) for d, eta in ((5, 1.0), (7, 5.0), (9, 10.0))]
+    srv = D.Server(max_slots=16, max_rep=R, max_qubits=145, sweeps_per_slice=30, greedy_seed=GS, anneal_seed=AS,
+                   max_lanes_per_chain=lanes)
+    tk = [(s, i, srv.submit(s.plan, s.syn[i], s.uid[i], R)) for s in specs for i in range(3)]
+    srv.drain()
+    res = [(s, i, srv.poll(t)) for s, i, t in tk]
+    srv.close()
+    outs = {id(s): s.batch(R) for s in specs}
+    for s, i, r in res:
+        assert same(r, outs[id(s)], i), f"planar d={s.d} request {i}"
+    s = specs[2]
+    w, wg = O.weights(s.p, O.noise(s.p, s.eta, 1))
+    beta = O.schedule(O.SCHED_PAPER_LOG, 0.9, 1.0, s.sweeps)
+    ref = s.olat.decode(w, wg, s.syn[1], int(s.uid[1]), R, beta, GS, AS)
+    r = [x for t, i, x in res if t is s and i == 1][0]
+    assert r["e_best"] == ref["e_best"] and np.array_equal(r["recovery"], ref["recovery"])
