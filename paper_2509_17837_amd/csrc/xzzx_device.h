@@ -172,7 +172,9 @@ struct GroupArgs {
     uint32_t *cp_rows;            // specialised packed-row kernel: checkpoints [n_cp][d][n_chains]
     int64_t n_chains;             // chains of the whole group
     int cp_every;                 // sweeps between checkpoints (0 = none)
-    uint32_t *site_snap;          // random-site kernel: state at E_min, packed words [word][n_chains]
+    uint32_t *min_snap;           // each chain's state at its first E_min: random-site kernel, packed
+                                  // words [word][n_chains]; planar kernel specialised to d, its rows
+                                  // [n_chains][planar_state_words(d)]
 };
 
 struct AnnealArgs {
@@ -1201,7 +1203,7 @@ __device__ __forceinline__ void site_kernel_body(const AnnealArgs &A)
             loaded = G.plan;
         }
         const ChainJob J = batch_job(G, unit0 + threadIdx.x, false);
-        site_core(G.plan, J, A.seed_lo, A.seed_hi, smem, G.site_snap, G.n_chains);
+        site_core(G.plan, J, A.seed_lo, A.seed_hi, smem, G.min_snap, G.n_chains);
     }
 }
 
@@ -1387,8 +1389,11 @@ void k_serve_rows_class(const ServeTask *tasks, uint32_t slo, uint32_t shi)
 }
 
 typedef void (*AnnealKernel)(AnnealArgs);
-// kernels specialised to the planar lattice at odd d <= 15 (NULL otherwise)
+// kernels specialised to the planar lattice at odd d <= 15 (NULL otherwise),
+// and the words of one chain's state they keep at its E_min (its rows,
+// padded to a multiple of four)
 AnnealKernel planar_rows_kernel(int d, bool plain);
+int planar_state_words(int d);
 typedef void (*ServeKernel)(const ServeTask *, uint32_t, uint32_t);
 
 // The specialised kernels live in several translation units (compiled in

@@ -389,6 +389,23 @@ __global__ void k_site_recovery(const uint32_t *__restrict__ snap, int64_t n_cha
     const int64_t ci = s * 4 * n_rep + best_chain[s];
     recovery[idx] = (uint8_t)((snap[(int64_t)(q >> 4) * n_chains + ci] >> (2 * (q & 15))) & 3u);
 }
+
+// Planar kernel specialised to d: the same from its rows, chain-major with
+// `words` words per chain (word Y * nw + c / 16 holds the qubit at row Y,
+// column c), one thread per (syndrome, qubit).
+__global__ void k_rows_recovery(const uint32_t *__restrict__ snap, int words,
+                                const int32_t *__restrict__ best_chain, int n_rep, int nq, int64_t n_syn,
+                                const PlanDev *__restrict__ pl, int nw, uint8_t *__restrict__ recovery)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_syn * nq) return;
+    const int64_t s = idx / nq;
+    const int q = (int)(idx - s * nq);
+    const int64_t ci = s * 4 * n_rep + best_chain[s];
+    const uint32_t p = pl->qpos[q];
+    const uint32_t word = snap[ci * words + (int64_t)((p >> 8) * nw + ((p & 0xFFu) >> 4))];
+    recovery[idx] = (uint8_t)((word >> (2 * (p & 15u))) & 3u);
+}
 __global__ __launch_bounds__(kWave) void k_anneal_rows(AnnealArgs A) { batch_kernel_body<0, true, 0, false>(A); }
 __global__ __launch_bounds__(kWave) void k_anneal_rows_plain(AnnealArgs A) { batch_kernel_body<2, true, 0, false>(A); }
 
@@ -634,11 +651,19 @@ struct GroupWs {
     uint8_t *refs, *qraw, *qcls;
     int32_t *emin, *stop, *efin, *best_chain;
     uint32_t *cp_rows;     // checkpoints of groups on the specialised packed-row kernel
-    uint32_t *site_snap;   // random-site groups: each chain's state at its first E_min
+    uint32_t *min_snap;    // random-site and planar specialised groups: each chain's state at its first E_min
 };
 
-// packed words per chain of a random-site state (position nq is scratch)
-static int64_t site_words_of(const Plan &P) { return P.lat.nq / 16 + 1; }
+// Words per chain of the state kept at E_min: random-site chains (packed, the
+// position nq scratch) and the planar kernel specialised to d (its rows);
+// 0 for other groups.  A plan's kernel must not change between the stages of
+// one decode.
+static int64_t min_snap_words(const Plan &P)
+{
+    if (P.order == XZZX_ORDER_RANDOM_SITE) return P.lat.nq / 16 + 1;
+    if (P.use_rows && P.planar_d) return planar_state_words(P.planar_d);
+    return 0;
+}
 
 // A group runs on the packed-row kernel specialised to its distance when the
 // plan allows it and every 64-chain task lies inside one syndrome.
@@ -678,7 +703,7 @@ static size_t group_ws_bytes(const xzzx_group &g, bool decode)
     if (!g.d_chain_e) b += align256(nc * 4);
     if (!g.d_best_chain) b += align256(ns * 4);
     b += align256((size_t)checkpoints_of(g) * P.lat.d * P.static_words * nc * 4);
-    if (P.order == XZZX_ORDER_RANDOM_SITE) b += align256((size_t)site_words_of(P) * nc * 4);
+    b += align256((size_t)min_snap_words(P) * nc * 4);
     return b;
 }
 
@@ -697,8 +722,7 @@ static GroupWs carve_group(const xzzx_group &g, bool decode, uint8_t *&p)
     w.best_chain = g.d_best_chain ? g.d_best_chain : reinterpret_cast<int32_t *>(take(ns * 4));
     const int ncp = checkpoints_of(g);
     w.cp_rows = ncp ? reinterpret_cast<uint32_t *>(take((size_t)ncp * P.lat.d * P.static_words * nc * 4)) : nullptr;
-    w.site_snap = P.order == XZZX_ORDER_RANDOM_SITE
-                      ? reinterpret_cast<uint32_t *>(take((size_t)site_words_of(P) * nc * 4)) : nullptr;
+    w.min_snap = min_snap_words(P) ? reinterpret_cast<uint32_t *>(take((size_t)min_snap_words(P) * nc * 4)) : nullptr;
     return w;
 }
 
@@ -800,7 +824,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         G.cp_rows = cp ? ws[i].cp_rows : nullptr;
         G.cp_every = cp ? checkpoint_interval(P) : 0;
         G.n_chains = g.n_syn * 4 * g.n_rep;
-        G.site_snap = site ? ws[i].site_snap : nullptr;
+        G.min_snap = (site || planar_d) ? ws[i].min_snap : nullptr;
         G.unit_offset = unit_offset;
         const int64_t units = units_of(i);
         G.n_units = units;
@@ -923,12 +947,13 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
     std::vector<int> replay_cp;   // replays starting from checkpoints: one chain per wavefront
     std::vector<int> site_sel;    // random-site plans: one chain (replay: syndrome) per lane
     std::vector<int> planar_sel[kPlanarStaticMaxD + 1];   // planar kernels specialised to d
+    std::vector<int> gather_sel;  // replay: recoveries gathered from the states kept at E_min
     int64_t total_syn = 0;
     for (int i = 0; i < n_groups; ++i) {
         if (groups[i].n_syn <= 0) continue;
         const Plan &P = groups[i].plan->P;
-        if (P.order == XZZX_ORDER_RANDOM_SITE) {
-            site_sel.push_back(i);
+        if (P.order == XZZX_ORDER_RANDOM_SITE || (mode == AnnealMode::Replay && min_snap_words(P))) {
+            (mode == AnnealMode::Replay ? gather_sel : site_sel).push_back(i);
             continue;
         }
         total_syn += groups[i].n_syn;
@@ -954,17 +979,21 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         if (!rc)
             rc = launch_set(groups, ws, replay_cp, false, kWave, mode, seed, unit_offset, units_override,
                             d_counters + 2, stream);
-        // random-site groups kept each chain's state at its E_min: gather
-        for (int i : site_sel) {
+        // groups that kept each chain's state at its E_min: gather
+        for (int i : gather_sel) {
             if (rc) break;
             const xzzx_group &g = groups[i];
             const Plan &P = g.plan->P;
-            const int64_t n = g.n_syn * (int64_t)P.lat.nq;
+            const int64_t n = g.n_syn * (int64_t)P.lat.nq, nc = g.n_syn * 4 * (int64_t)g.n_rep;
             if ((n + 255) / 256 > 0x7FFFFFFF) { set_error("too many recovery bytes in one group"); return XZZX_ERANGE; }
-            hipLaunchKernelGGL(k_site_recovery, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                               ws[i].site_snap, g.n_syn * 4 * (int64_t)g.n_rep, ws[i].best_chain, g.n_rep, P.lat.nq,
-                               g.n_syn, g.d_recovery);
-            rc = check_hip(hipGetLastError(), "k_site_recovery launch");
+            const dim3 grid((unsigned)((n + 255) / 256));
+            if (P.order == XZZX_ORDER_RANDOM_SITE)
+                hipLaunchKernelGGL(k_site_recovery, grid, dim3(256), 0, stream, ws[i].min_snap, nc, ws[i].best_chain,
+                                   g.n_rep, P.lat.nq, g.n_syn, g.d_recovery);
+            else
+                hipLaunchKernelGGL(k_rows_recovery, grid, dim3(256), 0, stream, ws[i].min_snap, (int)min_snap_words(P),
+                                   ws[i].best_chain, g.n_rep, P.lat.nq, g.n_syn, P.ddev, P.row_words, g.d_recovery);
+            rc = check_hip(hipGetLastError(), "recovery gather launch");
         }
         return rc;
     }

@@ -90,9 +90,14 @@ __device__ __forceinline__ int planar_qubit_at(int Y, int C)
     return PlanarSchedule<D>::qubit(u + v + 1, u - v);
 }
 
+// snap: each chain's rows at its first E_min, chain-major (word i of chain ci
+// at snap[ci * planar_state_words(D) + i], 16-byte aligned rows of words, so
+// a lane stores them with a few wide stores from one base address), from
+// which the recovery is gathered
 template <int D>
 __device__ __forceinline__ void planar_static_core(const PlanDev *pl, const ChainJob &J, uint32_t seed_lo,
-                                                   uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s)
+                                                   uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s,
+                                                   uint32_t *snap)
 {
     using PR = PlanarRows<D>;
     constexpr int NW = PR::NW;
@@ -129,6 +134,15 @@ __device__ __forceinline__ void planar_static_core(const PlanDev *pl, const Chai
         }
     }
     int32_t Emin = E, stop = 0;
+    constexpr int NP = (PR::N + 3) / 4 * 4;
+    uint4 *keep = (snap && J.active) ? reinterpret_cast<uint4 *>(snap + J.ci * NP) : nullptr;
+    auto keep_min = [&]() {
+#pragma unroll
+        for (int i = 0; i < NP / 4; ++i)
+            keep[i] = make_uint4(r[4 * i], 4 * i + 1 < PR::N ? r[4 * i + 1] : 0u, 4 * i + 2 < PR::N ? r[4 * i + 2] : 0u,
+                                 4 * i + 3 < PR::N ? r[4 * i + 3] : 0u);
+    };
+    if (keep) keep_min();
     for (int t = 0; t < n_sweeps; ++t) {
         wave_lds_fence();
         for (int i = lane; i < nranks; i += kWave) et_s[i].y = pl->thr[(size_t)t * nranks + i];
@@ -137,19 +151,19 @@ __device__ __forceinline__ void planar_static_core(const PlanDev *pl, const Chai
         int32_t acc = 0;
         planar_class<D, 0>(r, uid, cc, c2, k0, k1, lut_s, et_s, acc, Blocks{});
         E += acc;
-        if (E < Emin) { Emin = E; stop = 4 * t + 1; }
+        if (E < Emin) { Emin = E; stop = 4 * t + 1; if (keep) keep_min(); }
         acc = 0;
         planar_class<D, 1>(r, uid, cc, c2 + 1u, k0, k1, lut_s, et_s, acc, Blocks{});
         E += acc;
-        if (E < Emin) { Emin = E; stop = 4 * t + 2; }
+        if (E < Emin) { Emin = E; stop = 4 * t + 2; if (keep) keep_min(); }
         acc = 0;
         planar_class<D, 2>(r, uid, cc, c2 + 2u, k0, k1, lut_s, et_s, acc, Blocks{});
         E += acc;
-        if (E < Emin) { Emin = E; stop = 4 * t + 3; }
+        if (E < Emin) { Emin = E; stop = 4 * t + 3; if (keep) keep_min(); }
         acc = 0;
         planar_class<D, 3>(r, uid, cc, c2 + 3u, k0, k1, lut_s, et_s, acc, Blocks{});
         E += acc;
-        if (E < Emin) { Emin = E; stop = 4 * t + 4; }
+        if (E < Emin) { Emin = E; stop = 4 * t + 4; if (keep) keep_min(); }
     }
     if (J.active) {
         J.emin[J.ci] = Emin;
@@ -198,7 +212,7 @@ __device__ __forceinline__ void planar_rows_body(const AnnealArgs &A)
             loaded = G.plan;
         }
         const ChainJob J = batch_job(G, unit0 + threadIdx.x, false);
-        planar_static_core<D>(G.plan, J, A.seed_lo, A.seed_hi, lut_s, et_s);
+        planar_static_core<D>(G.plan, J, A.seed_lo, A.seed_hi, lut_s, et_s, G.min_snap);
     }
 }
 
@@ -214,6 +228,11 @@ void k_anneal_planar_d(AnnealArgs A) { planar_rows_body<0, D>(A); }
 template <int D>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(planar_waves(D), planar_waves(D))))
 void k_anneal_planar_d_plain(AnnealArgs A) { planar_rows_body<2, D>(A); }
+
+int planar_state_words(int d)
+{
+    return ((2 * d - 1) * (2 * (2 * d + 1) <= 32 ? 1 : 2) + 3) / 4 * 4;
+}
 
 AnnealKernel planar_rows_kernel(int d, bool plain)
 {
