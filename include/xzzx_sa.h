@@ -167,20 +167,21 @@ int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sw
 int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain);
 
 /* Which annealing kernel a plan uses (results are identical):
- *   XZZX_KERNEL_ROWS: one chain per lane, 2-bit codes packed row by row
- *     (rotated lattices with d <= 31); a variant specialised to the distance
- *     keeps every row in registers and its generator schedule in the
- *     instruction stream.  Batch groups whose 4 n_rep chains per syndrome
- *     are not a multiple of 64 run the generic variant instead (d <= 29),
- *     or the byte-state kernel (d = 31);
+ *   XZZX_KERNEL_ROWS: one chain per lane, 2-bit codes packed row by row;
+ *     a variant specialised to the distance keeps every row in registers
+ *     and its generator schedule in the instruction stream: rotated lattices
+ *     with d <= 31 (batch groups whose 4 n_rep chains per syndrome are not a
+ *     multiple of 64 run the generic variant instead, d <= 29, or the
+ *     byte-state kernel, d = 31), and planar lattices with d <= 15 (turned
+ *     by 45 degrees, any n_rep);
  *   XZZX_KERNEL_ROWS_GENERIC: the packed-row kernel without that
  *     specialisation (rows in LDS, schedule read from the plan): rotated
  *     d <= 29, and planar d <= 15, whose lattice turned by 45 degrees has the
  *     same 2 x 2 generator blocks (rows of 2d + 1 columns);
  *   XZZX_KERNEL_BYTES: byte-per-qubit states, lanes_per_chain lanes per chain;
- *   XZZX_KERNEL_AUTO (the default): on rotated lattices ROWS where it
- *     applies, else ROWS_GENERIC where it applies, else BYTES; on planar
- *     lattices BYTES (measured faster than ROWS_GENERIC at d = 9).
+ *   XZZX_KERNEL_AUTO (the default): ROWS where it applies, else on rotated
+ *     lattices ROWS_GENERIC where it applies, else BYTES (on planar lattices
+ *     BYTES measured faster than ROWS_GENERIC at d = 9).
  * EINVAL for ROWS or ROWS_GENERIC on a lattice they do not cover.
  * xzzx_plan_info reports ROWS only where the specialised variant runs. */
 enum { XZZX_KERNEL_AUTO = 0, XZZX_KERNEL_ROWS = 1, XZZX_KERNEL_BYTES = 2, XZZX_KERNEL_ROWS_GENERIC = 3,
