@@ -1076,14 +1076,20 @@ static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_se
     for (int i = 0; i < n_groups; ++i) ws[i] = carve_group(groups[i], decode, p);
     const int stage_bits = XZZX_FLAG_STAGE_GREEDY | XZZX_FLAG_STAGE_ANNEAL | XZZX_FLAG_STAGE_FINISH;
     const int stages = (flags & stage_bits) ? (flags & stage_bits) : stage_bits;
-    for (int i = 0; i < n_groups; ++i) {
+    // the groups' greedy launches run concurrently (one group's launch alone
+    // leaves the device idle in its tail)
+    std::vector<int> gsel;
+    for (int i = 0; i < n_groups; ++i)
+        if (decode && groups[i].n_syn > 0 && (stages & XZZX_FLAG_STAGE_GREEDY)) gsel.push_back(i);
+    rc = fork_join(stream, (int)gsel.size(), [&](int k, hipStream_t s) {
+        const int i = gsel[k];
         const xzzx_group &g = groups[i];
-        if (!decode || g.n_syn == 0 || !(stages & XZZX_FLAG_STAGE_GREEDY)) continue;
-        rc = launch_greedy(g.plan->P, g.d_syn, g.d_uid, g.n_syn, g.n_rep, greedy_seed, greedy_mode, ws[i].refs,
-                           ws[i].qraw, stream);
-        if (!rc) rc = launch_qcls(ws[i].qraw, g.n_syn, g.n_rep, ws[i].qcls, stream);
-        if (rc) return rc;
-    }
+        int r = launch_greedy(g.plan->P, g.d_syn, g.d_uid, g.n_syn, g.n_rep, greedy_seed, greedy_mode, ws[i].refs,
+                              ws[i].qraw, s);
+        if (!r) r = launch_qcls(ws[i].qraw, g.n_syn, g.n_rep, ws[i].qcls, s);
+        return r;
+    });
+    if (rc) return rc;
     if (!(stages & XZZX_FLAG_STAGE_ANNEAL)) {
         // annealing skipped in this call
     } else if (flags & XZZX_FLAG_PLAIN) {
