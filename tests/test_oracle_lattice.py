@@ -158,3 +158,25 @@ def test_class_function(layout, d):
     for a in range(4):
         for b in range(4):
             assert O.lib().or_class_mul(a, b) == table[a][b]
+
+
+@pytest.mark.parametrize("layout,d", [(O.ROTATED, 5), (O.ROTATED, 9), (O.PLANAR, 3), (O.PLANAR, 7), (O.PLANAR, 9)])
+def test_within_class_rank_order(layout, d):
+    """The rank of a generator in its colour class (it names the random word
+    the generator draws): face-id order on the rotated lattice; on the planar
+    lattice row-major over ((x + y)/2, (x - y)/2), the generator's 2 x 2 block
+    in the lattice turned by 45 degrees, where consecutive ranks of a class
+    share a pair of rows."""
+    L = O.Lattice(layout, d)
+    for k in range(4):
+        faces = np.where(L.fclass == k)[0]
+        ordered = faces[np.argsort(L.frank[faces])]
+        if layout == O.ROTATED:
+            assert ordered.tolist() == sorted(faces.tolist())
+        else:
+            x, y = L.fxy[ordered, 0], L.fxy[ordered, 1]
+            keys = list(zip(((x + y) // 2).tolist(), ((x - y) // 2).tolist()))
+            assert keys == sorted(keys) and len(set(keys)) == len(keys)
+            # a class's blocks of one row pair are disjoint and consecutive
+            rows = [a for a, _ in keys]
+            assert rows == sorted(rows)
