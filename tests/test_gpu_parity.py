@@ -117,7 +117,8 @@ def test_random_site_order(layout, d, n_syn, R, sweeps):
 
 def test_random_site_plain_graph_and_mixed():
     """The random-site order in the plain form (one launch per syndrome), in a
-    captured hipGraph, and beside a colour-sweep group in one call."""
+    captured hipGraph, and beside colour-sweep groups (rotated, and planar on
+    its specialised kernel) in one call."""
     ps = Problem(0, 9, 0.2, 10.0, 9, 4, 20, seed=77)
     pc = Problem(0, 11, 0.2, 10.0, 6, 16, 20, seed=77)   # same seeds: one call decodes both
     ref_s = ps.oracle_decode(order=O.ORDER_RANDOM_SITE)
@@ -126,15 +127,22 @@ def test_random_site_plain_graph_and_mixed():
     plan_s.set_order(X.ORDER_RANDOM_SITE)
     compare_decode(ps, run_decode(ps, plan_s, flags=X.FLAG_PLAIN), ref_s)
     plan_c = gpu_plan(pc)
+    # and a planar group on its kernel specialised to d (paper set-up, N_SA = 10)
+    pp = Problem(1, 7, 0.15, 5.0, 7, 10, 20, sched=("paper_log", 0.9, 1.0), seed=77, conv=1)
+    ref_p = pp.oracle_decode()
+    plan_p = gpu_plan(pp)
+    assert plan_p.info()["kernel"] == X.KERNEL_ROWS
     gs_, os_ = D.make_group(plan_s, ps.n_rep, to_dev(ps.uid.view(np.int32)), syn=to_dev(ps.syn), want_chains=True)
     gc_, oc_ = D.make_group(plan_c, pc.n_rep, to_dev(pc.uid.view(np.int32)), syn=to_dev(pc.syn), want_chains=True)
-    G = D.Graph([gs_, gc_], ps.greedy_seed, ps.anneal_seed)
+    gp_, op_ = D.make_group(plan_p, pp.n_rep, to_dev(pp.uid.view(np.int32)), syn=to_dev(pp.syn), want_chains=True)
+    G = D.Graph([gs_, gc_, gp_], ps.greedy_seed, ps.anneal_seed)
     for _ in range(3):
         G.launch()
         G.stream.synchronize()
         torch.cuda.synchronize()
         compare_decode(ps, os_, ref_s)
         compare_decode(pc, oc_, ref_c)
+        compare_decode(pp, op_, ref_p)
     with pytest.raises(X.XzzxError):
         plan_s.set_order(7)
     srv = D.Server(max_slots=8, max_rep=4, max_qubits=81)
