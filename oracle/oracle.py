@@ -21,7 +21,7 @@ ROTATED, PLANAR = 0, 1
 CONV_BASELINE, CONV_PAPER = 0, 1
 SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
-ORDER_COLOUR, ORDER_RANDOM_SITE = 0, 1   # colour-class sweeps; literal random-site steps (Alg. 3)
+ORDER_COLOUR, ORDER_RANDOM_SITE, ORDER_LADDER = 0, 1, 2   # colour sweeps; random-site steps (Alg. 3); replica exchange
 
 
 def build(force: bool = False) -> str:
@@ -83,7 +83,15 @@ def lib():
                                 C.c_uint64, C.c_uint64, C.c_int,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                C.c_void_p, C.c_void_p, C.c_int, C.c_int]
+                                C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double]
+        L.or_swap_powers.argtypes = [C.c_double, C.c_void_p]
+        L.or_swap_threshold.argtypes = [C.c_void_p, C.c_int64]
+        L.or_swap_threshold.restype = C.c_uint32
+        L.or_ladder_beta.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
+        L.or_ladder_beta.restype = C.c_double
+        L.or_anneal_ladder.argtypes = [P, i32p, C.c_double, C.c_double, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
+                                       C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -121,6 +129,21 @@ def schedule(kind, b0, b1, n):
     if rc:
         raise ValueError("or_schedule: invalid arguments")
     return beta[:n]
+
+
+def swap_powers(delta):
+    out = np.zeros(32, np.uint64)
+    lib().or_swap_powers(float(delta), _ptr(out))
+    return out
+
+
+def swap_threshold(R, n):
+    R = np.ascontiguousarray(R, np.uint64)
+    return int(lib().or_swap_threshold(_ptr(R), int(n)))
+
+
+def ladder_beta(beta_lo, beta_hi, K, k):
+    return float(lib().or_ladder_beta(float(beta_lo), float(beta_hi), int(K), int(k)))
 
 
 def site_of(u, nstab):
@@ -228,8 +251,27 @@ class Lattice:
             raise RuntimeError(f"or_anneal_chain rc={rc}")
         return dict(final=cfg, e=int(e[0]), emin=int(emin[0]), stop=int(stop[0]), snap=snap)
 
+    def anneal_ladder(self, w, beta_lo, beta_hi, K, n_sweeps, seed, uid, ladder, chain_ids, init, want_snap=True):
+        """One ladder of K chains (replica exchange), all started from init [K][nq]."""
+        cfg = np.array(init, np.uint8, copy=True).reshape(K, self.nq)
+        e = np.zeros(K, np.int64)
+        emin = np.zeros(K, np.int64)
+        stop = np.zeros(K, np.int32)
+        level = np.zeros(K, np.int32)
+        snap = np.zeros((K, self.nq), np.uint8) if want_snap else None
+        ids = np.ascontiguousarray(chain_ids, np.uint32)
+        rc = lib().or_anneal_ladder(self.h, np.ascontiguousarray(w, np.int32), float(beta_lo), float(beta_hi), K,
+                                    n_sweeps, seed, uid, ladder, _ptr(ids), _ptr(cfg), _ptr(e), _ptr(emin),
+                                    _ptr(stop), _ptr(snap), _ptr(level))
+        if rc:
+            raise RuntimeError(f"or_anneal_ladder rc={rc}")
+        return dict(final=cfg, e=e, emin=emin, stop=stop, snap=snap, level=level)
+
     def decode(self, w, wg, syn, uid, n_rep, beta, greedy_seed, anneal_seed,
-               greedy_mode=GREEDY_RANDOM, check=False, chains=False, order=ORDER_COLOUR):
+               greedy_mode=GREEDY_RANDOM, check=False, chains=False, order=ORDER_COLOUR, ladder=(1, 1.0, 1.0)):
+        """order ORDER_LADDER: replicas come in ladders of K = ladder[0] consecutive
+        replicas sharing one greedy reference, at fixed levels from ladder[1] to
+        ladder[2] (beta is then ignored except for its length, the sweep count)."""
         nq = self.nq
         nc = 4 * n_rep
         e_best = np.zeros(1, np.int64)
@@ -251,7 +293,8 @@ class Lattice:
                              greedy_seed, anneal_seed, greedy_mode,
                              _ptr(e_best), _ptr(cls_best), _ptr(e_cls), _ptr(rec), _ptr(prec),
                              _ptr(best_chain), _ptr(refs), _ptr(qcls), _ptr(cemin), _ptr(cstop),
-                             _ptr(ce), _ptr(cfin), 1 if check else 0, order)
+                             _ptr(ce), _ptr(cfin), 1 if check else 0, order, int(ladder[0]),
+                             float(ladder[1]), float(ladder[2]))
         if rc:
             raise RuntimeError(f"or_decode rc={rc}")
         out = dict(e_best=int(e_best[0]), cls=int(cls_best[0]), e_cls=e_cls, recovery=rec,

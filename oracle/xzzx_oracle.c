@@ -964,6 +964,120 @@ int or_anneal_chain_site(const or_lat *L, const int32_t w[4], const double *beta
 }
 
 /* ------------------------------------------------------------------------- */
+/* Replica exchange (parallel tempering), the extension the paper names as    */
+/* future work (Sec. VI).  Reading: a ladder of K chains of one coset, all    */
+/* started from the same configuration, at fixed inverse temperatures        */
+/* beta_k = beta_lo + k delta, delta = (beta_hi - beta_lo)/(K - 1) (beta_lo   */
+/* alone when K = 1); chain j starts at level j.  Every sweep t, each chain   */
+/* makes one colour-class sweep at its level's beta with the draws of         */
+/* or_anneal_chain for its own chain id, E_min and stop tracked per chain per */
+/* phase; then the pairs of levels (k, k+1) with k = t mod 2, t mod 2 + 2, .. */
+/* exchange their chains with probability min(1, exp(delta (E_hi - E_lo)))    */
+/* (E_hi: the chain at level k+1; energies in 2^-16 nats).  Pair p = (k -     */
+/* t mod 2)/2 draws word p mod 4 of Philox(seed; uid, 2^31 + ladder, t,      */
+/* p div 4).  The exchange is accepted iff E_hi >= E_lo or u < T(E_lo - E_hi) */
+/* with the fixed-point power T(n) = floor(prod over the set bits i of n of  */
+/* R_i / 2^32), the product taken from 2^64 - 1 with each step truncated to  */
+/* the high 64 bits of the 128-bit product, R_0 = min(floor(2^64 exp(-delta  */
+/* 2^-16)), 2^64 - 1) and R_{i+1} = floor(R_i^2 / 2^64).                      */
+/* ------------------------------------------------------------------------- */
+void or_swap_powers(double delta, uint64_t R[32])
+{
+    double r0 = ldexp(exp(-delta * 0x1p-16), 64);
+    R[0] = (r0 >= 18446744073709551615.0) ? UINT64_MAX : (uint64_t)r0;
+    for (int i = 1; i < 32; ++i) R[i] = (uint64_t)(((unsigned __int128)R[i - 1] * R[i - 1]) >> 64);
+}
+
+uint32_t or_swap_threshold(const uint64_t R[32], int64_t n)
+{
+    uint64_t p = UINT64_MAX;
+    for (int i = 0; i < 32; ++i)
+        if ((n >> i) & 1) p = (uint64_t)(((unsigned __int128)p * R[i]) >> 64);
+    if (n >> 32) p = 0;
+    return (uint32_t)(p >> 32);
+}
+
+double or_ladder_beta(double beta_lo, double beta_hi, int K, int k)
+{
+    if (K <= 1) return beta_lo;
+    double delta = (beta_hi - beta_lo) / (double)(K - 1);
+    return beta_lo + (double)k * delta;
+}
+
+int or_anneal_ladder(const or_lat *L, const int32_t w[4], double beta_lo, double beta_hi, int K, int n_sweeps,
+                     uint64_t seed, uint32_t uid, uint32_t ladder, const uint32_t *chain_ids, uint8_t *cfg,
+                     int64_t *e_out, int64_t *emin_out, int32_t *stop_out, uint8_t *snap, int32_t *level_out)
+{
+    if (K < 1 || K > 64 || n_sweeps < 0) return OR_EINVAL;
+    int nq = L->nq;
+    double delta = (K > 1) ? (beta_hi - beta_lo) / (double)(K - 1) : 0.0;
+    uint64_t R[32];
+    or_swap_powers(delta, R);
+    int64_t e[64], emin[64];
+    int32_t stop[64];
+    int level[64];
+    for (int j = 0; j < K; ++j) {
+        e[j] = or_energy(L, w, cfg + (size_t)j * nq);
+        emin[j] = e[j];
+        stop[j] = 0;
+        level[j] = j;
+        if (snap) memcpy(snap + (size_t)j * nq, cfg + (size_t)j * nq, nq);
+    }
+    for (int t = 0; t < n_sweeps; ++t) {
+        for (int j = 0; j < K; ++j) {
+            uint8_t *c = cfg + (size_t)j * nq;
+            double b = or_ladder_beta(beta_lo, beta_hi, K, level[j]);
+            for (int k = 0; k < 4; ++k) {
+                for (int m = 0; m < L->ncls[k]; ++m) {
+                    int f = L->cls_face[k][m];
+                    int64_t dE = 0;
+                    for (int s = 0; s < 4; ++s) {
+                        int q = L->fq[4 * f + s];
+                        if (q < 0) continue;
+                        dE += (int64_t)w[c[q] ^ L->fm[4 * f + s]] - (int64_t)w[c[q]];
+                    }
+                    uint32_t u = philox_word(seed, uid, chain_ids[j], 4u * (uint32_t)t + (uint32_t)k,
+                                             (uint32_t)m >> 2, m & 3);
+                    if (accept_move(b, dE, u)) {
+                        for (int s = 0; s < 4; ++s) {
+                            int q = L->fq[4 * f + s];
+                            if (q >= 0) c[q] ^= L->fm[4 * f + s];
+                        }
+                        e[j] += dE;
+                    }
+                }
+                if (e[j] < emin[j]) {
+                    emin[j] = e[j];
+                    stop[j] = 4 * t + k + 1;
+                    if (snap) memcpy(snap + (size_t)j * nq, c, nq);
+                }
+            }
+        }
+        int par = t & 1;
+        for (int k = par; k + 1 < K; k += 2) {
+            int lo = -1, hi = -1;
+            for (int j = 0; j < K; ++j) {
+                if (level[j] == k) lo = j;
+                if (level[j] == k + 1) hi = j;
+            }
+            int p = (k - par) / 2;
+            uint32_t u = philox_word(seed, uid, 0x80000000u | ladder, (uint32_t)t, (uint32_t)p >> 2, p & 3);
+            if (e[hi] >= e[lo] || u < or_swap_threshold(R, e[lo] - e[hi])) {
+                level[lo] = k + 1;
+                level[hi] = k;
+            }
+        }
+    }
+    for (int j = 0; j < K; ++j) {
+        if (e_out) e_out[j] = e[j];
+        if (emin_out) emin_out[j] = emin[j];
+        if (stop_out) stop_out[j] = stop[j];
+        if (level_out) level_out[j] = level[j];
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Decoder, Alg. 7 (Alg. 1 when every replica uses the same reference).       */
 /*                                                                             */
 /* Replica r (the paper's SA-run index i) gets reference R_r from the greedy  */
@@ -985,9 +1099,11 @@ int or_decode(or_lat *L, const int32_t w[4], const int32_t wg[2], const uint8_t 
               uint8_t *refs /*[n_rep][nq] or NULL*/, int32_t *qcls /*[n_rep] or NULL*/,
               int64_t *chain_emin /*[4 n_rep] or NULL*/, int32_t *chain_stop,
               int64_t *chain_e, uint8_t *chain_final /*[4 n_rep][nq] or NULL*/,
-              int check, int order /*0: colour sweeps, 1: random-site steps*/)
+              int check, int order /*0: colour sweeps, 1: random-site steps, 2: ladders*/,
+              int ladder_k, double beta_lo, double beta_hi)
 {
-    if (order != 0 && order != 1) return OR_EINVAL;
+    if (order < 0 || order > 2) return OR_EINVAL;
+    if (order == 2 && (ladder_k < 1 || ladder_k > 64 || n_rep % ladder_k != 0)) return OR_EINVAL;
     if (n_rep < 1) return OR_EINVAL;
     int nq = L->nq;
     int rc = OR_OK;
@@ -997,9 +1113,17 @@ int or_decode(or_lat *L, const int32_t w[4], const int32_t wg[2], const uint8_t 
     uint8_t *lp = (uint8_t *)malloc(nq);
     int *Q = (int *)malloc(sizeof(int) * n_rep);
     uint8_t *keep = (uint8_t *)malloc((size_t)4 * nq); /* snapshot of each class's best chain */
-    if (!R || !cfg || !snap || !lp || !Q || !keep) { rc = OR_ENOMEM; goto done; }
+    /* ladders: the K chains of the current ladder of each coset */
+    uint8_t *lcfg = NULL, *lsnap = NULL;
+    int kk = (order == 2) ? ladder_k : 1;
+    uint8_t *lcfg_all = (uint8_t *)malloc((size_t)4 * kk * nq), *lsnap_all = (uint8_t *)malloc((size_t)4 * kk * nq);
+    int64_t le[4][64], lemin[4][64];
+    int32_t lstop[4][64];
+    if (!R || !cfg || !snap || !lp || !Q || !keep || !lcfg_all || !lsnap_all) { rc = OR_ENOMEM; goto done; }
     for (int r = 0; r < n_rep; ++r) {
-        rc = or_greedy(L, wg, syn, uid, (uint32_t)r, greedy_seed, greedy_mode, R + (size_t)r * nq);
+        /* ladders: replicas r = b K + j share the reference of greedy replica b */
+        uint32_t grep = (uint32_t)(order == 2 ? r / ladder_k : r);
+        rc = or_greedy(L, wg, syn, uid, grep, greedy_seed, greedy_mode, R + (size_t)r * nq);
         if (rc) goto done;
         Q[r] = or_class(L, R + (size_t)r * nq, R);
         if (Q[r] < 0) { rc = OR_EINVARIANT; goto done; }
@@ -1008,17 +1132,44 @@ int or_decode(or_lat *L, const int32_t w[4], const int32_t wg[2], const uint8_t 
     }
     int64_t best[4] = {INT64_MAX, INT64_MAX, INT64_MAX, INT64_MAX};
     int bestc[4] = {-1, -1, -1, -1};
+    int K = (order == 2) ? ladder_k : 1;
+    lcfg = (uint8_t *)malloc((size_t)K * nq);
+    lsnap = (uint8_t *)malloc((size_t)K * nq);
+    if (!lcfg || !lsnap) { rc = OR_ENOMEM; goto done; }
     for (int r = 0; r < n_rep; ++r) {
         for (int P = 0; P < 4; ++P) {
             int c = 4 * r + P;
             or_logical(L, P, lp);
-            for (int q = 0; q < nq; ++q) cfg[q] = R[(size_t)r * nq + q] ^ lp[q];
             int64_t e, emin;
             int32_t stop;
-            rc = (order ? or_anneal_chain_site : or_anneal_chain)(L, w, beta, n_sweeps, anneal_seed, uid,
-                                                                   (uint32_t)c, cfg, &e, &emin, &stop, snap,
-                                                                   check);
-            if (rc) goto done;
+            if (order == 2) {
+                /* ladder of replicas r0 .. r0 + K - 1 (coset P), run when its first chain comes up */
+                int j = r % K, r0 = r - j;
+                if (j == 0) {
+                    uint32_t ids[64];
+                    for (int i = 0; i < K; ++i) {
+                        ids[i] = (uint32_t)(4 * (r0 + i) + P);
+                        for (int q = 0; q < nq; ++q) lcfg[(size_t)i * nq + q] = R[(size_t)(r0 + i) * nq + q] ^ lp[q];
+                    }
+                    rc = or_anneal_ladder(L, w, beta_lo, beta_hi, K, n_sweeps, anneal_seed, uid,
+                                          (uint32_t)(4 * (r0 / K) + P), ids, lcfg, le[P], lemin[P], lstop[P],
+                                          lsnap, NULL);
+                    if (rc) goto done;
+                    memcpy(lsnap_all + (size_t)P * K * nq, lsnap, (size_t)K * nq);
+                    memcpy(lcfg_all + (size_t)P * K * nq, lcfg, (size_t)K * nq);
+                }
+                e = le[P][j];
+                emin = lemin[P][j];
+                stop = lstop[P][j];
+                memcpy(cfg, lcfg_all + ((size_t)P * K + j) * nq, nq);
+                memcpy(snap, lsnap_all + ((size_t)P * K + j) * nq, nq);
+            } else {
+                for (int q = 0; q < nq; ++q) cfg[q] = R[(size_t)r * nq + q] ^ lp[q];
+                rc = (order ? or_anneal_chain_site : or_anneal_chain)(L, w, beta, n_sweeps, anneal_seed, uid,
+                                                                       (uint32_t)c, cfg, &e, &emin, &stop, snap,
+                                                                       check);
+                if (rc) goto done;
+            }
             int cls = or_class_mul(Q[r], P);
             if (emin < best[cls]) {
                 best[cls] = emin;
@@ -1044,5 +1195,6 @@ int or_decode(or_lat *L, const int32_t w[4], const int32_t wg[2], const uint8_t 
     }
 done:
     free(R); free(cfg); free(snap); free(lp); free(Q); free(keep);
+    free(lcfg); free(lsnap); free(lcfg_all); free(lsnap_all);
     return rc;
 }

@@ -331,3 +331,127 @@ def test_site_decoder_against_brute_force(layout, d, n_syn):
         assert out["chain_stop"].max() <= len(beta) * L.nstab
         hits += out["e_best"] == min(exact)
     assert hits >= 0.95 * n_syn
+
+
+# --- replica exchange (ladders of fixed inverse temperatures) -------------------
+
+LADDER = O.ORDER_LADDER
+
+
+@pytest.mark.parametrize("delta", [0.05, 0.5, 3.0])
+def test_swap_threshold_closed_form(delta):
+    """T(n) is floor(2^32 exp(-delta n 2^-16)) up to the truncations of the
+    fixed-point product (relative error below n 2^-50 + 2^-58) and one unit."""
+    R = O.swap_powers(delta)
+    rng = np.random.default_rng(30)
+    ns = [1, 2, 3, 255, 65536, 1 << 20, (1 << 31) - 1] + rng.integers(1, 1 << 24, 200).tolist()
+    for n in ns:
+        exact = 2.0 ** 32 * np.exp(-delta * n / 65536.0)
+        tol = exact * (n * 2.0 ** -50 + 2.0 ** -58) + 1.0
+        assert abs(O.swap_threshold(R, n) - exact) <= tol, n
+    # delta = 0: every exchange accepted but for the top few draws
+    R0 = O.swap_powers(0.0)
+    assert all(O.swap_threshold(R0, n) >= 2 ** 32 - 64 for n in (1, 1000, (1 << 31) - 1))
+
+
+def test_ladder_of_one_is_a_constant_beta_chain():
+    """K = 1: the ladder's only chain is the colour-sweep chain at the constant
+    beta_lo, draw for draw."""
+    L = O.Lattice(O.ROTATED, 5)
+    w, _ = O.weights(0.15, O.noise(0.15, 10.0))
+    rng = np.random.default_rng(31)
+    init = rng.integers(0, 4, L.nq).astype(np.uint8)
+    lad = L.anneal_ladder(w, 0.7, 0.7, 1, 30, 11, 5, 2, [9], init[None])
+    ref = L.anneal_chain(w, np.full(30, 0.7), 11, 5, 9, init)
+    assert lad["e"][0] == ref["e"] and lad["emin"][0] == ref["emin"] and lad["stop"][0] == ref["stop"]
+    assert np.array_equal(lad["final"][0], ref["final"]) and np.array_equal(lad["snap"][0], ref["snap"])
+
+
+def test_ladder_of_equal_levels():
+    """beta_lo = beta_hi: every level sweeps at the same beta, so each chain is
+    the constant-beta chain of its own id, and every exchange is accepted:
+    the levels follow the alternating even/odd transpositions."""
+    L = O.Lattice(O.PLANAR, 5)
+    w, _ = O.weights(0.15, O.noise(0.15, 5.0, 1))
+    rng = np.random.default_rng(32)
+    init = rng.integers(0, 4, (4, L.nq)).astype(np.uint8)
+    ids = [3, 7, 11, 15]
+    n = 9
+    lad = L.anneal_ladder(w, 0.8, 0.8, 4, n, 12, 6, 3, ids, init)
+    for j in range(4):
+        ref = L.anneal_chain(w, np.full(n, 0.8), 12, 6, ids[j], init[j])
+        assert (lad["e"][j], lad["emin"][j], lad["stop"][j]) == (ref["e"], ref["emin"], ref["stop"])
+        assert np.array_equal(lad["final"][j], ref["final"])
+    level = list(range(4))
+    for t in range(n):
+        for k in range(t & 1, 3, 2):
+            lo, hi = level.index(k), level.index(k + 1)
+            level[lo], level[hi] = k + 1, k
+    assert lad["level"].tolist() == level
+
+
+def test_ladder_boltzmann_law():
+    """Each level's sweep leaves pi_beta of Eq. (22) stationary and the
+    exchange satisfies detailed balance for the product law over levels, so
+    the chain at each level of many independent two-level ladders follows the
+    exact law at that level's beta over the 256-element coset (d = 3)."""
+    L = O.Lattice(O.ROTATED, 3)
+    G = _gf2.generator_matrix(L.fq, L.fm, L.nq)
+    w, _ = O.weights(0.15, O.noise(0.15, 10.0))
+    rng = np.random.default_rng(33)
+    init = rng.integers(0, 4, L.nq).astype(np.uint8)
+    elems = _gf2.group_elements(G) ^ _gf2.pack(init)
+    index = {int(v): i for i, v in enumerate(elems)}
+    energies = _gf2.packed_energy(elems, w).astype(np.float64)
+    betas = (0.15, 0.45)
+    n_ladders, n_sweeps = 6000, 60
+    counts = np.zeros((2, len(elems)))
+    for c in range(n_ladders):
+        r = L.anneal_ladder(w, betas[0], betas[1], 2, n_sweeps, 2026, 79, c, [2 * c, 2 * c + 1],
+                            np.stack([init, init]), want_snap=False)
+        for j in range(2):
+            counts[r["level"][j], index[int(_gf2.pack(r["final"][j]))]] += 1
+
+    def chi2_p(level, b):
+        pr = np.exp(-b * (energies - energies.min()) / 65536.0)
+        pr /= pr.sum()
+        exp = pr * n_ladders
+        keep = exp >= 5
+        obs = np.append(counts[level][keep], counts[level][~keep].sum())
+        ex = np.append(exp[keep], exp[~keep].sum())
+        if ex[-1] == 0:
+            obs, ex = obs[:-1], ex[:-1]
+        return stats.chisquare(obs, ex).pvalue
+
+    assert chi2_p(0, betas[0]) > 1e-3 and chi2_p(1, betas[1]) > 1e-3
+    # negative controls: the two levels' laws are told apart decisively
+    assert chi2_p(1, betas[0]) < 1e-6 and chi2_p(0, betas[1]) < 1e-6
+
+
+@pytest.mark.parametrize("layout,d,n_syn", [(O.ROTATED, 3, 120), (O.PLANAR, 3, 60)])
+def test_ladder_decoder_against_brute_force(layout, d, n_syn):
+    """The decoder on ladders (K = 4 levels from beta 0.5 to 3): replicas of a
+    ladder share one greedy reference, E_P bounds the exact coset minimum from
+    above, the recovery is consistent, and the exact minimum is reached in
+    nearly every sample."""
+    L = O.Lattice(layout, d)
+    p, eta = 0.15, 10.0
+    w, wg = O.weights(p, O.noise(p, eta))
+    rng = np.random.default_rng(40 + d)
+    hits = 0
+    for uid in range(n_syn):
+        _, syn = random_problem(L, p, eta, rng)
+        out = L.decode(w, wg, syn, uid, 8, np.ones(100), 5, 6, order=LADDER, ladder=(4, 0.5, 3.0), chains=True)
+        refs = out["refs"]
+        assert all(np.array_equal(refs[r], refs[4 * (r // 4)]) for r in range(8))
+        r0 = refs[0]
+        exact = _exact_coset_minima(L, w, r0)
+        for P in range(4):
+            assert out["e_cls"][P] >= exact[P]
+        assert out["e_best"] == min(out["e_cls"])
+        rec = out["recovery"]
+        assert np.array_equal(L.syndrome(rec), syn)
+        assert L.energy(w, rec) == out["e_best"]
+        assert L.cls(rec, r0) == out["cls"]
+        hits += out["e_best"] == min(exact)
+    assert hits >= 0.92 * n_syn
