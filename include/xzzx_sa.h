@@ -185,7 +185,7 @@ int xzzx_plan_set_lanes(xzzx_plan *plan, int lanes_per_chain);
  * EINVAL for ROWS or ROWS_GENERIC on a lattice they do not cover.
  * xzzx_plan_info reports ROWS only where the specialised variant runs. */
 enum { XZZX_KERNEL_AUTO = 0, XZZX_KERNEL_ROWS = 1, XZZX_KERNEL_BYTES = 2, XZZX_KERNEL_ROWS_GENERIC = 3,
-       XZZX_KERNEL_SITE = 4 };
+       XZZX_KERNEL_SITE = 4, XZZX_KERNEL_LADDER = 5 };
 int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel);
 
 /* Step order of the Metropolis chains (Algs. 2-3).
@@ -206,6 +206,31 @@ int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel);
  * fit in 64 KiB of LDS. */
 enum { XZZX_ORDER_COLOUR = 0, XZZX_ORDER_RANDOM_SITE = 1 };
 int xzzx_plan_set_order(xzzx_plan *plan, int order);
+
+/* Replica exchange (parallel tempering; the paper names it as future work,
+ * Sec. VI) instead of the annealing schedule.  levels = K in {1, 2, 4, 8,
+ * 16} turns it on, 0 off.  Replicas come in ladders of K consecutive
+ * replicas r = bK + j that share the greedy reference of replica b (n_rep of
+ * every group must be a multiple of K, else EINVAL at decode).  For each
+ * coset P the ladder's chains 4(bK + j) + P run at fixed levels
+ * beta_k = beta_lo + k (beta_hi - beta_lo)/(K - 1) (beta_lo when K = 1),
+ * chain j starting at level j; the plan's schedule gives only the number of
+ * sweeps.  Each sweep is a colour-class sweep with the chain's own draws (as
+ * XZZX_ORDER_COLOUR) at its level's beta.  After sweep t the levels
+ * (k, k + 1), k = t mod 2, t mod 2 + 2, ..., exchange their chains with
+ * probability min(1, exp(delta (E_hi - E_lo))), delta the level spacing and
+ * E_hi the energy of the chain at level k + 1: pair p = (k - t mod 2)/2
+ * draws word p mod 4 of Philox(uid, 2^31 + 4b + P, t, p div 4), and the
+ * exchange is accepted iff E_hi >= E_lo or u < T(E_lo - E_hi), where
+ * T(n) = floor(prod over the set bits i of n of R_i / 2^32) in 64-bit fixed
+ * point (the product starts at 2^64 - 1, each step keeps the high 64 bits),
+ * R_0 = min(floor(2^64 exp(-delta 2^-16)), 2^64 - 1), R_{i+1} =
+ * floor(R_i^2 / 2^64).  E_min, stop (phase 4t + k + 1) and the recovery are
+ * as for colour sweeps.  EINVAL for another K or with the random-site order;
+ * ERANGE if the ladder's tables and 64 chains do not fit in 64 KiB of LDS.
+ * One chain per lane (XZZX_KERNEL_LADDER); the autotuner leaves the plan
+ * unchanged and the serving loop rejects such plans. */
+int xzzx_plan_set_ladder(xzzx_plan *plan, int levels, double beta_lo, double beta_hi);
 
 /* Autotuner of the result-invariant knobs (kernel family, lanes per chain).
  * Builds a probe plan with the same lattice and weights and the first

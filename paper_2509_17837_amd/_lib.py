@@ -19,7 +19,7 @@ SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
 FLAG_PLAIN = 1
 STAGE_GREEDY, STAGE_ANNEAL, STAGE_FINISH = 2, 4, 8
-KERNEL_AUTO, KERNEL_ROWS, KERNEL_BYTES, KERNEL_ROWS_GENERIC, KERNEL_SITE = 0, 1, 2, 3, 4
+KERNEL_AUTO, KERNEL_ROWS, KERNEL_BYTES, KERNEL_ROWS_GENERIC, KERNEL_SITE, KERNEL_LADDER = 0, 1, 2, 3, 4, 5
 ORDER_COLOUR, ORDER_RANDOM_SITE = 0, 1
 
 _STATUS = {
@@ -144,6 +144,7 @@ def lib():
         "xzzx_plan_set_lanes": (I, [V, I]),
         "xzzx_plan_set_kernel": (I, [V, I]),
         "xzzx_plan_set_order": (I, [V, I]),
+        "xzzx_plan_set_ladder": (I, [V, I, C.c_double, C.c_double]),
         "xzzx_plan_autotune": (I, [V, I, I, I, V, P(TuneResult)]),
         "xzzx_syndrome": (I, [V, V, I64, V, V]),
         "xzzx_greedy_init": (I, [V, V, V, I64, I, U64, I, V, V, V]),

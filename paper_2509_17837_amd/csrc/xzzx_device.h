@@ -1394,6 +1394,8 @@ typedef void (*AnnealKernel)(AnnealArgs);
 // padded to a multiple of four)
 AnnealKernel planar_rows_kernel(int d, bool plain);
 int planar_state_words(int d);
+// replica-exchange kernel (ladders of fixed inverse temperatures)
+AnnealKernel ladder_kernel(bool plain);
 typedef void (*ServeKernel)(const ServeTask *, uint32_t, uint32_t);
 
 // The specialised kernels live in several translation units (compiled in

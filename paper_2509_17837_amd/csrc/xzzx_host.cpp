@@ -195,6 +195,21 @@ uint32_t accept_threshold(double beta, int64_t dE)
 // ---------------------------------------------------------------------------
 // Plan tables.
 // ---------------------------------------------------------------------------
+// Ladder kernel: the tables as above with thresholds per level, 64 chains of
+// nq / 16 + 1 packed words, and each lane's energy and level slot.
+size_t Plan::lds_bytes_ladder() const
+{
+    size_t off = 0;
+    off += sizeof(Desc) * 4 * lat.per_class;
+    off += 256 * (size_t)ntypes;
+    off = (off + 7) & ~size_t(7);
+    off += 8 * dE.size() * (size_t)std::max(ladder_k, 1);
+    off = (off + 15) & ~size_t(15);
+    off += 4 * (size_t)(lat.nq / 16 + 1) * kWave;
+    off += 8 * (size_t)kWave;
+    return (off + 15) & ~size_t(15);
+}
+
 // Random-site kernel: the tables as above (descriptors in face-id order),
 // then 64 chains of nq / 16 + 1 packed words.
 size_t Plan::lds_bytes_site() const
@@ -822,14 +837,81 @@ int xzzx_plan_create(const xzzx_lattice *lat, const int32_t w[4], const int32_t 
 void xzzx_plan_destroy(xzzx_plan *plan)
 {
     if (!plan) return;
-    if (plan->P.dmem) {
+    if (plan->P.dmem || plan->P.ladder_mem) {
         int cur = 0;
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(plan->P.device);
-        (void)hipFree(plan->P.dmem);
+        if (plan->P.dmem) (void)hipFree(plan->P.dmem);
+        if (plan->P.ladder_mem) (void)hipFree(plan->P.ladder_mem);
         (void)hipSetDevice(cur);
     }
     delete plan;
+}
+
+int xzzx_plan_set_ladder(xzzx_plan *plan, int levels, double beta_lo, double beta_hi)
+{
+    if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
+    Plan &P = plan->P;
+    if (levels != 0 && levels != 1 && levels != 2 && levels != 4 && levels != 8 && levels != 16) {
+        set_error("ladder levels must be 0 (off) or 1, 2, 4, 8, 16");
+        return XZZX_EINVAL;
+    }
+    if (levels && P.order != XZZX_ORDER_COLOUR) { set_error("ladders run colour-class sweeps only"); return XZZX_EINVAL; }
+    if (levels && (!(beta_lo >= 0.0) || !(beta_hi >= beta_lo) || !std::isfinite(beta_hi))) {
+        set_error("ladder needs 0 <= beta_lo <= beta_hi, finite");
+        return XZZX_EINVAL;
+    }
+    const int old_k = P.ladder_k;
+    P.ladder_k = levels;
+    if (levels && P.lds_bytes_ladder() > 65536) {
+        P.ladder_k = old_k;
+        set_error("ladder tables and chains do not fit in LDS");
+        return XZZX_ERANGE;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != P.device) { P.ladder_k = old_k; set_error("plan was created on another device"); return XZZX_EINVAL; }
+    void *mem = nullptr;
+    if (levels) {
+        // levels beta_k = beta_lo + k delta, and the exchange rule's powers
+        const int nranks = P.nranks();
+        const double delta = levels > 1 ? (beta_hi - beta_lo) / (double)(levels - 1) : 0.0;
+        std::vector<uint32_t> thr((size_t)levels * nranks);
+        for (int k = 0; k < levels; ++k) {
+            const double b = levels > 1 ? beta_lo + (double)k * delta : beta_lo;
+            for (int r = 0; r < nranks; ++r) thr[(size_t)k * nranks + r] = accept_threshold(b, P.dE[r]);
+        }
+        uint64_t R[32];
+        const double r0 = std::ldexp(std::exp(-delta * 0x1p-16), 64);
+        R[0] = r0 >= 18446744073709551615.0 ? UINT64_MAX : (uint64_t)r0;
+        for (int i = 1; i < 32; ++i) R[i] = (uint64_t)(((unsigned __int128)R[i - 1] * R[i - 1]) >> 64);
+        const size_t bytes = 256 + thr.size() * 4;
+        if (hipMalloc(&mem, bytes) != hipSuccess) { P.ladder_k = old_k; set_error("hipMalloc of ladder tables failed"); return XZZX_ENOMEM; }
+        std::vector<uint8_t> host(bytes, 0);
+        std::memcpy(host.data(), R, sizeof(R));
+        std::memcpy(host.data() + 256, thr.data(), thr.size() * 4);
+        if (hipMemcpy(mem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(mem);
+            P.ladder_k = old_k;
+            set_error("upload of ladder tables failed");
+            return XZZX_EDEVICE;
+        }
+    }
+    // publish the new tables in the device copy of the plan, then free the old ones
+    PlanDev &h = P.hdev;
+    h.ladder_k = levels;
+    h.ladder_pow = levels ? static_cast<const uint64_t *>(mem) : nullptr;
+    h.ladder_thr = levels ? reinterpret_cast<const uint32_t *>(static_cast<uint8_t *>(mem) + 256) : nullptr;
+    if (hipMemcpy(P.ddev, &h, sizeof(PlanDev), hipMemcpyHostToDevice) != hipSuccess) {
+        if (mem) (void)hipFree(mem);
+        P.ladder_k = old_k;
+        set_error("plan update failed");
+        return XZZX_EDEVICE;
+    }
+    if (P.ladder_mem) (void)hipFree(P.ladder_mem);
+    P.ladder_mem = mem;
+    P.ladder_lo = beta_lo;
+    P.ladder_hi = beta_hi;
+    return XZZX_OK;
 }
 
 int xzzx_plan_set_kernel(xzzx_plan *plan, int kernel)
@@ -866,6 +948,7 @@ int xzzx_plan_info(const xzzx_plan *plan, int *n_qubits, int *n_stabs, int *n_sw
 {
     if (plan && kernel)
         *kernel = plan->P.order ? XZZX_KERNEL_SITE
+                  : plan->P.ladder_k ? XZZX_KERNEL_LADDER
                   : !plan->P.use_rows ? XZZX_KERNEL_BYTES
                   : (plan->P.static_d || plan->P.planar_d) ? XZZX_KERNEL_ROWS : XZZX_KERNEL_ROWS_GENERIC;
     if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
@@ -881,6 +964,7 @@ int xzzx_plan_set_order(xzzx_plan *plan, int order)
 {
     if (!plan) { set_error("plan is NULL"); return XZZX_EINVAL; }
     if (order != XZZX_ORDER_COLOUR && order != XZZX_ORDER_RANDOM_SITE) { set_error("unknown step order"); return XZZX_EINVAL; }
+    if (order != XZZX_ORDER_COLOUR && plan->P.ladder_k) { set_error("ladders run colour-class sweeps only"); return XZZX_EINVAL; }
     if (order == XZZX_ORDER_RANDOM_SITE) {
         if ((int64_t)plan->P.n_sweeps * plan->P.lat.nstab >= ((int64_t)1 << 31)) {
             set_error("random-site steps of a chain must number below 2^31");

@@ -211,6 +211,9 @@ struct PlanDev {
     int32_t W[4];
     const uint32_t *rowface;       // [4][4*nblk] row | bit offset << 8 | shape << 16 (packed-row kernel)
     const uint32_t *qpos;          // [nq] packed-row kernel: row << 8 | column of each qubit
+    int ladder_k;                  // replica exchange: levels per ladder (0 = off)
+    const uint32_t *ladder_thr;    // [ladder_k][nranks] acceptance thresholds of each level
+    const uint64_t *ladder_pow;    // [32] fixed-point powers R_i of the exchange rule
     const Desc *desc;              // [4][M] by (class, rank)
     const Desc *face_desc;         // [nstab] by face id
     const uint8_t *lut;            // [ntypes][256] move-energy rank of a slot pattern
@@ -242,6 +245,10 @@ struct Plan {
     int order = 0;                 // XZZX_ORDER_COLOUR or XZZX_ORDER_RANDOM_SITE
     int planar_ok = 0;             // the planar kernel specialised to d applies
     int planar_d = 0;              // d while that kernel is in use, else 0
+    int ladder_k = 0;              // replica exchange: levels per ladder (0 = off)
+    double ladder_lo = 0, ladder_hi = 0;
+    void *ladder_mem = nullptr;    // device tables of the ladder (thresholds per level, exchange powers)
+    size_t lds_bytes_ladder() const;
     int nranks() const { return (int)dE.size(); }
     int device = 0;
     void *dmem = nullptr;          // device allocation holding every table

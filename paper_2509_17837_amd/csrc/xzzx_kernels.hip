@@ -92,6 +92,7 @@ struct GreedyArgs {
     int mode;
     uint32_t seed_lo, seed_hi;
     int max_nodes;
+    int rep_div;               // ladders: replica r draws the keys of replica r / rep_div (0 or 1: itself)
 };
 
 __device__ __forceinline__ void xor_edge(uint32_t *cfgw, int eid)
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     const int64_t sr = blockIdx.x;
     const int64_t s = sr / A.n_rep;
     const uint32_t r = (uint32_t)(sr - s * A.n_rep);
+    const uint32_t rkey = A.rep_div > 1 ? r / (uint32_t)A.rep_div : r;
     const uint32_t uid = A.uid[s];
     const int nwords = (nq + 3) / 4;
     constexpr int kHalf = SPLIT ? kWave / 2 : kWave;   // lanes per colour
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
                     if (randomized && nt > 1) {
                         auto pair_id = [&](int j) { return (uint32_t)(min(i, j) * na + max(i, j)); };
                         auto pair_key = [&](uint32_t id) {
-                            return philox4x32_10(make_uint4(uid, r, 0x100u + (uint32_t)g, id), A.seed_lo, A.seed_hi).x;
+                            return philox4x32_10(make_uint4(uid, rkey, 0x100u + (uint32_t)g, id), A.seed_lo, A.seed_hi).x;
                         };
                         uint32_t bid = pair_id(bj), bk = pair_key(bid);
                         if (nt <= kGreedyTies) {
@@ -628,6 +630,7 @@ static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_
     A.n_syn = n_syn;
     A.n_rep = n_rep;
     A.mode = mode;
+    A.rep_div = P.ladder_k;
     A.syn_stride = P.lat.nstab;
     A.seed_lo = (uint32_t)seed;
     A.seed_hi = (uint32_t)(seed >> 32);
@@ -660,7 +663,7 @@ struct GroupWs {
 // one decode.
 static int64_t min_snap_words(const Plan &P)
 {
-    if (P.order == XZZX_ORDER_RANDOM_SITE) return P.lat.nq / 16 + 1;
+    if (P.order == XZZX_ORDER_RANDOM_SITE || P.ladder_k) return P.lat.nq / 16 + 1;
     if (P.use_rows && P.planar_d) return planar_state_words(P.planar_d);
     return 0;
 }
@@ -737,6 +740,7 @@ static int validate_groups(const xzzx_group *groups, int n_groups, bool decode)
     for (int i = 0; i < n_groups; ++i) {
         const xzzx_group &g = groups[i];
         if (!g.plan || g.n_syn < 0 || g.n_rep < 1 || g.n_rep > (1 << 20)) { set_error("bad group (plan, n_syn or n_rep)"); return XZZX_EINVAL; }
+        if (g.plan->P.ladder_k && g.n_rep % g.plan->P.ladder_k) { set_error("n_rep must be a multiple of the ladder's levels"); return XZZX_EINVAL; }
         if (g.plan->P.device != dev) { set_error("plan was created on another device"); return XZZX_EINVAL; }
         if (g.n_syn == 0) continue;
         if (!g.d_uid || !g.d_e_best || !g.d_cls || !g.d_recovery) { set_error("missing required group buffer"); return XZZX_EINVAL; }
@@ -782,7 +786,7 @@ enum class AnnealMode { Persistent, Replay, Plain };
 static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::vector<int> &sel, bool rows, int lanes,
                       AnnealMode mode, uint64_t seed, int64_t unit_offset, int64_t units_override,
                       uint32_t *d_counter, hipStream_t stream, int static_d = 0, bool site = false,
-                      int planar_d = 0)
+                      int planar_d = 0, bool ladder = false)
 {
     const bool replay = mode == AnnealMode::Replay;
     AnnealArgs A{};
@@ -824,7 +828,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         G.cp_rows = cp ? ws[i].cp_rows : nullptr;
         G.cp_every = cp ? checkpoint_interval(P) : 0;
         G.n_chains = g.n_syn * 4 * g.n_rep;
-        G.min_snap = (site || planar_d) ? ws[i].min_snap : nullptr;
+        G.min_snap = (site || planar_d || ladder) ? ws[i].min_snap : nullptr;
         G.unit_offset = unit_offset;
         const int64_t units = units_of(i);
         G.n_units = units;
@@ -832,6 +836,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         const int C = kWave / lanes;
         tasks += (uint64_t)((units + C - 1) / C);
         lds = std::max(lds, (static_d || planar_d) ? (size_t)0
+                            : ladder ? P.lds_bytes_ladder()
                             : site   ? P.lds_bytes_site()
                             : rows   ? P.lds_bytes_rows()
                                      : P.lds_bytes_anneal(lanes));
@@ -842,7 +847,9 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
     A.n_tasks = (uint32_t)tasks;
     if (lds > 65536) { set_error("LDS demand above 64 KiB"); return XZZX_ERANGE; }
     if (mode == AnnealMode::Plain) {
-        if (site)
+        if (ladder)
+            hipLaunchKernelGGL(ladder_kernel(true), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
+        else if (site)
             hipLaunchKernelGGL(k_anneal_site_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         else if (planar_d)
             hipLaunchKernelGGL(planar_rows_kernel(planar_d, true), dim3((unsigned)tasks), dim3(kWave), 0, stream, A);
@@ -854,7 +861,8 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
             hipLaunchKernelGGL(bytes_kernel(2, lg), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         return check_hip(hipGetLastError(), "plain anneal launch");
     }
-    const AnnealKernel kern = site       ? k_anneal_site
+    const AnnealKernel kern = ladder     ? ladder_kernel(false)
+                              : site     ? k_anneal_site
                               : planar_d ? planar_rows_kernel(planar_d, false)
                               : static_d ? static_rows_kernel(static_d, false)
                               : rows     ? k_anneal_rows
@@ -935,7 +943,7 @@ static int fork_join(hipStream_t stream, int n, F launch)
 // wavefronts.  Each launch has its own queue counter: d_counters[0] packed
 // rows, [1..7] byte states by lanes per chain, [16..30] the kernels
 // specialised to d = 3, 5, ..., 31, [40] random-site chains, [41..47] the
-// planar kernels specialised to d = 3, 5, ..., 15; a replay (with
+// planar kernels specialised to d = 3, 5, ..., 15, [48] ladders; a replay (with
 // its own d_counters base) uses [0] and [2].
 static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
                          uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
@@ -948,12 +956,13 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
     std::vector<int> site_sel;    // random-site plans: one chain (replay: syndrome) per lane
     std::vector<int> planar_sel[kPlanarStaticMaxD + 1];   // planar kernels specialised to d
     std::vector<int> gather_sel;  // replay: recoveries gathered from the states kept at E_min
+    std::vector<int> ladder_sel;  // replica exchange: one chain per lane
     int64_t total_syn = 0;
     for (int i = 0; i < n_groups; ++i) {
         if (groups[i].n_syn <= 0) continue;
         const Plan &P = groups[i].plan->P;
-        if (P.order == XZZX_ORDER_RANDOM_SITE || (mode == AnnealMode::Replay && min_snap_words(P))) {
-            (mode == AnnealMode::Replay ? gather_sel : site_sel).push_back(i);
+        if (P.order == XZZX_ORDER_RANDOM_SITE || P.ladder_k || (mode == AnnealMode::Replay && min_snap_words(P))) {
+            (mode == AnnealMode::Replay ? gather_sel : P.ladder_k ? ladder_sel : site_sel).push_back(i);
             continue;
         }
         total_syn += groups[i].n_syn;
@@ -987,7 +996,7 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
             const int64_t n = g.n_syn * (int64_t)P.lat.nq, nc = g.n_syn * 4 * (int64_t)g.n_rep;
             if ((n + 255) / 256 > 0x7FFFFFFF) { set_error("too many recovery bytes in one group"); return XZZX_ERANGE; }
             const dim3 grid((unsigned)((n + 255) / 256));
-            if (P.order == XZZX_ORDER_RANDOM_SITE)
+            if (P.order == XZZX_ORDER_RANDOM_SITE || P.ladder_k)
                 hipLaunchKernelGGL(k_site_recovery, grid, dim3(256), 0, stream, ws[i].min_snap, nc, ws[i].best_chain,
                                    g.n_rep, P.lat.nq, g.n_syn, g.d_recovery);
             else
@@ -1008,30 +1017,33 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         int static_d;
         bool site;
         int planar_d;
+        bool ladder;
     };
     std::vector<Set> sets;
-    if (!rows_sel.empty()) sets.push_back({&rows_sel, true, 1, d_counters, 0, false, 0});
-    if (!site_sel.empty()) sets.push_back({&site_sel, false, 1, d_counters + 40, 0, true, 0});
+    if (!rows_sel.empty()) sets.push_back({&rows_sel, true, 1, d_counters, 0, false, 0, false});
+    if (!site_sel.empty()) sets.push_back({&site_sel, false, 1, d_counters + 40, 0, true, 0, false});
+    if (!ladder_sel.empty()) sets.push_back({&ladder_sel, false, 1, d_counters + 48, 0, false, 0, true});
     for (int d = 3; d <= kPlanarStaticMaxD; d += 2)
         if (!planar_sel[d].empty())
-            sets.push_back({&planar_sel[d], true, 1, d_counters + 41 + (d - 3) / 2, 0, false, d});
+            sets.push_back({&planar_sel[d], true, 1, d_counters + 41 + (d - 3) / 2, 0, false, d, false});
     for (int d = kStaticMinD; d <= kStaticMaxD; d += 2)
         if (!static_sel[d].empty())
-            sets.push_back({&static_sel[d], true, 1, d_counters + 16 + (d - kStaticMinD) / 2, d, false, 0});
+            sets.push_back({&static_sel[d], true, 1, d_counters + 16 + (d - kStaticMinD) / 2, d, false, 0, false});
     for (int l = 0; l < 7; ++l)
-        if (!bytes_sel[l].empty()) sets.push_back({&bytes_sel[l], false, 1 << l, d_counters + 1 + l, 0, false, 0});
+        if (!bytes_sel[l].empty())
+            sets.push_back({&bytes_sel[l], false, 1 << l, d_counters + 1 + l, 0, false, 0, false});
     if (sets.size() <= 1 || mode == AnnealMode::Plain) {
         int rc = XZZX_OK;
         for (const Set &S : sets)
             if (!rc)
                 rc = launch_set(groups, ws, *S.sel, S.rows, S.lanes, mode, seed, unit_offset, units_override, S.counter,
-                                stream, S.static_d, S.site, S.planar_d);
+                                stream, S.static_d, S.site, S.planar_d, S.ladder);
         return rc;
     }
     return fork_join(stream, (int)sets.size(), [&](int i, hipStream_t s) {
         const Set &S = sets[i];
         return launch_set(groups, ws, *S.sel, S.rows, S.lanes, mode, seed, unit_offset, units_override, S.counter, s,
-                          S.static_d, S.site, S.planar_d);
+                          S.static_d, S.site, S.planar_d, S.ladder);
     });
 }
 

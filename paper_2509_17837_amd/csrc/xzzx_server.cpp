@@ -548,7 +548,10 @@ int xzzx_server_submit(xzzx_server *srv, const xzzx_request *req, uint64_t *tick
 {
     if (!srv || !req || !ticket || !req->plan || !req->syndrome) { set_error("NULL argument"); return XZZX_EINVAL; }
     const Plan &P = req->plan->P;
-    if (P.order != XZZX_ORDER_COLOUR) { set_error("the serving loop runs colour-sweep plans only"); return XZZX_EINVAL; }
+    if (P.order != XZZX_ORDER_COLOUR || P.ladder_k) {
+        set_error("the serving loop runs annealing plans with colour sweeps only");
+        return XZZX_EINVAL;
+    }
     if (req->n_rep < 1 || req->n_rep > srv->cfg.max_rep || P.lat.nq > srv->cfg.max_qubits || P.device != srv->device) {
         set_error("request does not fit the server's slots (n_rep, qubits or device)");
         return XZZX_EINVAL;

@@ -31,10 +31,10 @@ extern "C" int xzzx_plan_autotune(xzzx_plan *plan, int n_rep, int n_syn, int pro
 {
     if (!plan || n_rep < 1 || n_syn < 1 || probe_sweeps < 1) { set_error("bad autotune arguments"); return XZZX_EINVAL; }
     Plan &P = plan->P;
-    if (P.order) {
-        // the random-site kernel has no knobs
+    if (P.order || P.ladder_k) {
+        // the random-site and ladder kernels have no knobs
         if (out) {
-            out->kernel = XZZX_KERNEL_SITE;
+            out->kernel = P.order ? XZZX_KERNEL_SITE : XZZX_KERNEL_LADDER;
             out->lanes_per_chain = 1;
             for (float &t : out->times_ms) t = -1.0f;
         }

@@ -127,6 +127,12 @@ class Plan:
     def set_kernel(self, kernel):
         call("xzzx_plan_set_kernel", self.h, int(kernel))
 
+    def set_ladder(self, levels, beta_lo=0.0, beta_hi=0.0):
+        """Replica exchange on ladders of `levels` fixed inverse temperatures
+        from beta_lo to beta_hi (0 levels: back to the annealing schedule);
+        n_rep of a decode must then be a multiple of `levels`."""
+        call("xzzx_plan_set_ladder", self.h, int(levels), float(beta_lo), float(beta_hi))
+
     def set_order(self, order):
         """X.ORDER_COLOUR (colour-class sweeps) or X.ORDER_RANDOM_SITE (Alg. 3 as printed)."""
         call("xzzx_plan_set_order", self.h, int(order))
@@ -136,7 +142,8 @@ class Plan:
         r = X.TuneResult()
         call("xzzx_plan_autotune", self.h, n_rep, n_syn, probe_sweeps, _stream(stream), C.byref(r))
         names = ["rows"] + [f"bytes{1 << i}" for i in range(7)]
-        kind = {X.KERNEL_ROWS: "rows", X.KERNEL_ROWS_GENERIC: "rows_generic", X.KERNEL_SITE: "site"}.get(r.kernel, "bytes")
+        kind = {X.KERNEL_ROWS: "rows", X.KERNEL_ROWS_GENERIC: "rows_generic", X.KERNEL_SITE: "site",
+                X.KERNEL_LADDER: "ladder"}.get(r.kernel, "bytes")
         return {"kernel": kind, "lanes_per_chain": r.lanes_per_chain,
                 "times_ms": {n: round(t, 3) for n, t in zip(names, r.times_ms) if t >= 0}}
 

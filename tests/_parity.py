@@ -40,13 +40,13 @@ class Problem:
         self.greedy_seed = 0x5EED_0000 + seed
         self.anneal_seed = 0xA11E_0000_0000 + seed
 
-    def oracle_decode(self, idx=None, mode=O.GREEDY_RANDOM, chains=True, order=O.ORDER_COLOUR):
+    def oracle_decode(self, idx=None, mode=O.GREEDY_RANDOM, chains=True, order=O.ORDER_COLOUR, ladder=(1, 1.0, 1.0)):
         idx = range(self.n_syn) if idx is None else idx
 
         def one(i):
             lat = O.Lattice(self.layout, self.d)  # per-thread handle (greedy tables are cached per handle)
             return lat.decode(self.w, self.wg, self.syn[i], int(self.uid[i]), self.n_rep, self.beta,
-                              self.greedy_seed, self.anneal_seed, mode, chains=chains, order=order)
+                              self.greedy_seed, self.anneal_seed, mode, chains=chains, order=order, ladder=ladder)
 
         return list(pool().map(one, list(idx)))
 

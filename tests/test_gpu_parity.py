@@ -152,6 +152,58 @@ def test_random_site_plain_graph_and_mixed():
     srv.close()
 
 
+@pytest.mark.parametrize("layout,d,n_syn,R,K,sweeps", [(0, 3, 40, 4, 4, 30), (0, 11, 9, 8, 2, 20),
+                                                       (0, 11, 5, 16, 16, 10), (1, 9, 7, 10, 1, 25),
+                                                       (1, 7, 6, 8, 8, 15), (0, 21, 2, 4, 4, 6), (0, 5, 3, 2, 2, 0)])
+def test_replica_exchange_ladders(layout, d, n_syn, R, K, sweeps):
+    """Replica exchange: ladders of K levels from beta 0.4 to 1.6 (replicas
+    of a ladder share one greedy reference); every chain (E, E_min, stop,
+    final state), the coset minima and the recovery (the best chain's state
+    kept at its first E_min) equal the oracle's ladders, for ladders of one
+    to sixteen levels, both layouts, ragged tails and zero sweeps."""
+    prob = Problem(layout, d, 0.15, 5.0, n_syn, R, sweeps, seed=1200 + d + K, conv=1 if layout else 0)
+    plan = gpu_plan(prob)
+    plan.set_ladder(K, 0.4, 1.6)
+    assert plan.info()["kernel"] == X.KERNEL_LADDER
+    out = run_decode(prob, plan)
+    compare_decode(prob, out, prob.oracle_decode(order=O.ORDER_LADDER, ladder=(K, 0.4, 1.6)))
+
+
+def test_replica_exchange_plain_graph_and_errors():
+    """Ladders in the plain form, in a captured hipGraph beside an annealing
+    group, and their argument checks."""
+    pl_ = Problem(0, 9, 0.2, 10.0, 5, 8, 12, seed=88)
+    pa = Problem(0, 11, 0.2, 10.0, 4, 16, 12, seed=88)
+    ref_l = pl_.oracle_decode(order=O.ORDER_LADDER, ladder=(4, 0.3, 2.0))
+    ref_a = pa.oracle_decode()
+    plan_l = gpu_plan(pl_)
+    plan_l.set_ladder(4, 0.3, 2.0)
+    compare_decode(pl_, run_decode(pl_, plan_l, flags=X.FLAG_PLAIN), ref_l)
+    plan_a = gpu_plan(pa)
+    gl_, ol_ = D.make_group(plan_l, pl_.n_rep, to_dev(pl_.uid.view(np.int32)), syn=to_dev(pl_.syn), want_chains=True)
+    ga_, oa_ = D.make_group(plan_a, pa.n_rep, to_dev(pa.uid.view(np.int32)), syn=to_dev(pa.syn), want_chains=True)
+    G = D.Graph([gl_, ga_], pl_.greedy_seed, pl_.anneal_seed)
+    for _ in range(3):
+        G.launch()
+        G.stream.synchronize()
+        torch.cuda.synchronize()
+        compare_decode(pl_, ol_, ref_l)
+        compare_decode(pa, oa_, ref_a)
+    with pytest.raises(X.XzzxError):
+        plan_l.set_ladder(3, 0.3, 2.0)
+    with pytest.raises(X.XzzxError):
+        plan_l.set_order(X.ORDER_RANDOM_SITE)
+    with pytest.raises(X.XzzxError) as e:
+        D.decode(plan_l, to_dev(pl_.syn), to_dev(pl_.uid.view(np.int32)), 6, 1, 2)
+    assert e.value.rc == X.XZZX_EINVAL
+    srv = D.Server(max_slots=8, max_rep=8, max_qubits=81)
+    with pytest.raises(X.XzzxError):
+        srv.submit(plan_l, pl_.syn[0], 0, 8)
+    srv.close()
+    plan_l.set_ladder(0)
+    assert plan_l.info()["kernel"] != X.KERNEL_LADDER
+
+
 @pytest.mark.parametrize("d", [9, 25])
 def test_all_lane_counts_agree(d):
     """Lanes per chain (chains per wavefront) is a result-invariant knob."""
