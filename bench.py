@@ -113,6 +113,9 @@ def parse():
     ap.add_argument("--distances", default="11,13,15,17,21,25,29,31")
     ap.add_argument("--order", choices=["colour", "site"], default="colour",
                     help="Metropolis step order: colour-class sweeps, or random-site steps (Alg. 3 as printed)")
+    ap.add_argument("--ladder", default="",
+                    help="replica exchange instead of annealing: 'K,beta_lo,beta_hi' (levels per ladder; n_rep of the "
+                         "workload must be a multiple of K)")
     ap.add_argument("--paper-trends", action="store_true",
                     help="logical error rates of the paper's set-up against N_SA and N_beta (planar, 1:eta:1)")
     ap.add_argument("--trend-d", type=int, default=9)
@@ -164,6 +167,9 @@ def main():
         plans.append(D.Plan(lats[d], w, wg, beta))
         if args.order == "site":
             plans[-1].set_order(X.ORDER_RANDOM_SITE)
+        if args.ladder:
+            k, blo, bhi = args.ladder.split(",")
+            plans[-1].set_ladder(int(k), float(blo), float(bhi))
     ng = len(plans)
     tuned = {}
     if not args.no_tune:
@@ -252,6 +258,8 @@ def main():
     kinds = {pl.info()["kernel"] for pl in plans}
     if kinds == {X.KERNEL_SITE}:
         kernel_name = "k_anneal_site"
+    elif kinds == {X.KERNEL_LADDER}:
+        kernel_name = "k_anneal_ladder"
     elif kinds == {X.KERNEL_ROWS} and layout == X.PLANAR and len(set(wl["d"])) == 1:
         kernel_name = f"k_anneal_planar_d{wl['d'][0]}"   # planar packed rows specialised to d
     elif kinds == {X.KERNEL_ROWS} and len(set(wl["d"])) == 1 and (4 * R) % 64 == 0:
@@ -280,6 +288,9 @@ def main():
                         f"{wl['schedule'][1]}->{wl['schedule'][2]}",
             "name": args.workload,
             "step_order": "random-site (Alg. 3)" if args.order == "site" else "colour-class sweeps",
+            "replica_exchange": (f"ladders of {args.ladder.split(',')[0]} levels, beta "
+                                 f"{args.ladder.split(',')[1]} -> {args.ladder.split(',')[2]} (schedule unused)")
+                                if args.ladder else None,
             "syndromes_per_step": syndromes_step,
             "attempts_per_step": attempts_step,
             "graphs": graphs is not None,
@@ -356,6 +367,10 @@ def cpu_baseline(args, wl, specs, plans, syn0, uid0, outs, R, sweeps, gs, as_):
         g, i = job
         d = specs[g][0]
         lat = O.Lattice(layout, d)
+        if args.ladder:
+            k, blo, bhi = args.ladder.split(",")
+            return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, gs, as_,
+                              order=O.ORDER_LADDER, ladder=(int(k), float(blo), float(bhi)))
         return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, gs, as_,
                           order=O.ORDER_RANDOM_SITE if args.order == "site" else O.ORDER_COLOUR)
 
@@ -519,6 +534,18 @@ def trends_bench(args):
         f_site = logical_failures(lat, err, o.recovery.cpu().numpy())
         out.setdefault("step_order_n_sa10", {})[key] = {"colour": rate(fails[10]) if 10 in fails else None,
                                                         "random_site": rate(f_site)}
+        # replica exchange against annealing at equal work: 8 replicas x 4
+        # cosets x 100 sweeps; ladders of K levels at fixed beta 0.9 .. 1.0
+        f_sa8 = logical_failures(lat, err, D.decode(plans[100], syn, uid, 8, gs, as_).recovery.cpu().numpy())
+        lad = {"anneal_log_0.9_1.0": rate(f_sa8)}
+        lad_checks = {}
+        for K, blo in ((1, 0.9), (2, 0.9), (4, 0.9), (8, 0.9), (8, 0.3)):
+            lp = D.Plan(lat, w, wg, D.schedule(X.SCHED_PAPER_LOG, 0.9, 1.0, 100))
+            lp.set_ladder(K, blo, 1.0)
+            f_l = logical_failures(lat, err, D.decode(lp, syn, uid, 8, gs, as_).recovery.cpu().numpy())
+            lad[f"ladder_K{K}_{blo}_1.0"] = rate(f_l)
+            lad_checks[f"ladder_K{K}_{blo}_1.0_vs_anneal"] = paired(f_l, f_sa8)
+        out.setdefault("replica_exchange_n_rep8", {})[key] = lad
         # pair-by-pair comparisons behind the paper's statements
         ks = sorted(fails)
         out["checks"][key] = {
@@ -531,6 +558,7 @@ def trends_bench(args):
         }
         if 10 in fails:
             out["checks"][key]["colour_vs_random_site"] = paired(fails[10], f_site)
+        out["checks"][key].update(lad_checks)
         print(f"[trends] eta={eta:g} greedy {out['greedy_decoder'][key][0]:.4f} "
               + " ".join(f"N_SA={k}:{fails[k].mean():.4f}" for k in ks), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
