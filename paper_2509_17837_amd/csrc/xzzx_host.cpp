@@ -176,6 +176,21 @@ int build_lattice(int layout, int d, Lattice &L)
                 set_error("colour classes are not of equal size");
                 return XZZX_EINVAL;
             }
+    // every kernel moves the generators of one class at once (or merges their
+    // flips), which is exact only if a class's generators act on disjoint
+    // qubits: checked for every lattice built
+    std::vector<int> owner(L.nq, -1);
+    for (int k = 0; k < 4; ++k) {
+        for (int m = 0; m < L.per_class; ++m) {
+            const int f = L.by_class[k * L.per_class + m];
+            for (int s = 0; s < 4; ++s) {
+                const int q = L.fq[4 * f + s];
+                if (q < 0) continue;
+                if (owner[q] == k) { set_error("a colour class has generators sharing a qubit"); return XZZX_EINVAL; }
+                owner[q] = k;
+            }
+        }
+    }
     return XZZX_OK;
 }
 

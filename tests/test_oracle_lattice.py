@@ -7,6 +7,7 @@ import itertools
 
 import numpy as np
 import pytest
+from hypothesis import HealthCheck, given, settings, strategies as st
 
 from oracle import oracle as O
 from tests import _gf2
@@ -180,3 +181,29 @@ def test_within_class_rank_order(layout, d):
             # a class's blocks of one row pair are disjoint and consecutive
             rows = [a for a, _ in keys]
             assert rows == sorted(rows)
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(layout=st.sampled_from([O.ROTATED, O.PLANAR]), d=st.sampled_from([3, 5, 7]),
+       seed=st.integers(0, 2**32 - 1), p=st.floats(0.02, 0.3), eta=st.floats(0.5, 200.0))
+def test_random_problems_keep_the_invariants(layout, d, seed, p, eta):
+    """Property test over random lattices, channels and seeds: a short
+    annealing chain keeps its syndrome, coset and incremental energy after
+    every sweep (the oracle's check mode), its snapshot has energy E_min, and
+    the greedy reference has the sampled syndrome."""
+    L = O.Lattice(layout, d)
+    pxyz = O.noise(p, eta)
+    w, wg = O.weights(p, pxyz)
+    rng = np.random.default_rng(seed)
+    u = rng.random(L.nq)
+    err = np.zeros(L.nq, np.uint8)
+    err[u < pxyz[0] + pxyz[1] + pxyz[2]] = 1
+    err[u < pxyz[0] + pxyz[1]] = 3
+    err[u < pxyz[0]] = 2
+    syn = L.syndrome(err)
+    ref = L.greedy(wg, syn, seed & 0xFFFF, 1, seed)
+    assert np.array_equal(L.syndrome(ref), syn)
+    beta = O.schedule(O.SCHED_GEOMETRIC, 0.1, 5.0, 12)
+    r = L.anneal_chain(w, beta, seed, seed & 0xFFFF, 3, ref, check=True)
+    assert L.energy(w, r["snap"]) == r["emin"] <= r["e"]
+    assert L.cls(r["final"], ref) == 0
