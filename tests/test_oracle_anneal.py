@@ -11,7 +11,7 @@ import pytest
 from scipy import stats
 
 from oracle import oracle as O
-from tests import _gf2
+from tests import _exact, _gf2
 
 
 def random_problem(L, p, eta, rng):
@@ -455,3 +455,41 @@ def test_ladder_decoder_against_brute_force(layout, d, n_syn):
         assert L.cls(rec, r0) == out["cls"]
         hits += out["e_best"] == min(exact)
     assert hits >= 0.92 * n_syn
+
+
+# --- exact coset minima beyond brute force (frontier dynamic program) ----------
+
+@pytest.mark.parametrize("layout,d", [(O.ROTATED, 3), (O.PLANAR, 3), (O.ROTATED, 5)])
+def test_frontier_program_equals_brute_force(layout, d):
+    """The exact minimiser used below agrees with enumeration of the whole
+    stabilizer group where that is feasible."""
+    L = O.Lattice(layout, d)
+    w, _ = O.weights(0.15, O.noise(0.15, 10.0))
+    rng = np.random.default_rng(50 + d)
+    G = _gf2.generator_matrix(L.fq, L.fm, L.nq)
+    group = _gf2.group_elements(G)
+    for _ in range(3):
+        c0 = rng.integers(0, 4, L.nq).astype(np.uint8)
+        exact = _gf2.coset_minima(group, [c0], w)[0]
+        assert _exact.coset_minimum(L.fq, L.fm, c0, w) == exact
+
+
+@pytest.mark.parametrize("layout,d,n_syn", [(O.ROTATED, 7, 4), (O.PLANAR, 5, 4)])
+def test_decoder_against_exact_minima(layout, d, n_syn):
+    """Beyond brute force: E_P bounds the exact coset minimum from above for
+    every coset, and a slow schedule reaches the exact least coset minimum."""
+    L = O.Lattice(layout, d)
+    p, eta = 0.12, 10.0
+    w, wg = O.weights(p, O.noise(p, eta))
+    beta = O.schedule(O.SCHED_LINEAR, 0.1, 5.0, 400)
+    rng = np.random.default_rng(60 + d)
+    hits = 0
+    for uid in range(n_syn):
+        _, syn = random_problem(L, p, eta, rng)
+        out = L.decode(w, wg, syn, uid, 4, beta, 5, 6)
+        r0 = out["refs"][0]
+        exact = [_exact.coset_minimum(L.fq, L.fm, r0 ^ L.logical(P), w) for P in range(4)]
+        for P in range(4):
+            assert out["e_cls"][P] >= exact[P]
+        hits += out["e_best"] == min(exact)
+    assert hits >= n_syn - 1
