@@ -93,6 +93,7 @@ struct GreedyArgs {
     uint32_t seed_lo, seed_hi;
     int max_nodes;
     int rep_div;               // ladders: replica r draws the keys of replica r / rep_div (0 or 1: itself)
+    int64_t block0;            // (syndrome, replica) pair of workgroup 0 of this launch
 };
 
 __device__ __forceinline__ void xor_edge(uint32_t *cfgw, int eid)
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     const PlanDev *pl = A.plan;
     const int lane = threadIdx.x;
     const int nq = pl->nq;
-    const int64_t sr = blockIdx.x;
+    const int64_t sr = A.block0 + blockIdx.x;
     const int64_t s = sr / A.n_rep;
     const uint32_t r = (uint32_t)(sr - s * A.n_rep);
     const uint32_t rkey = A.rep_div > 1 ? r / (uint32_t)A.rep_div : r;
@@ -592,6 +593,11 @@ __global__ __launch_bounds__(kWave) void k_serve_reduce(const ServeFinish *fin)
 // ---------------------------------------------------------------------------
 // Host-side launch logic.
 // ---------------------------------------------------------------------------
+// A launch addresses at most 2^32 - 1 work-items (larger grids wrap
+// silently), i.e. this many wavefronts of 64.
+constexpr int64_t kMaxLaunchItems = 0xFFFFFFFFll;
+constexpr int64_t kMaxLaunchWaves = kMaxLaunchItems / kWave;
+
 static int check_hip(hipError_t e, const char *what)
 {
     if (e == hipSuccess) return XZZX_OK;
@@ -635,11 +641,18 @@ static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_
     A.seed_lo = (uint32_t)seed;
     A.seed_hi = (uint32_t)(seed >> 32);
     const int lds = greedy_lds(P, &A.max_nodes);
+    // one launch addresses fewer than 2^32 work-items: the (syndrome, replica)
+    // pairs go in chunks of at most that many wavefronts
     const int64_t blocks = n_syn * n_rep;
-    if (blocks > 0x7FFFFFFF) { set_error("too many (syndrome, replica) pairs"); return XZZX_ERANGE; }
-    hipLaunchKernelGGL(greedy_split(P) ? k_greedy<true> : k_greedy<false>, dim3((unsigned)blocks), dim3(kWave), lds,
-                       stream, A);
-    return check_hip(hipGetLastError(), "k_greedy launch");
+    for (int64_t b0 = 0; b0 < blocks; b0 += kMaxLaunchWaves) {
+        A.block0 = b0;
+        const int64_t nb = std::min<int64_t>(kMaxLaunchWaves, blocks - b0);
+        hipLaunchKernelGGL(greedy_split(P) ? k_greedy<true> : k_greedy<false>, dim3((unsigned)nb), dim3(kWave), lds,
+                           stream, A);
+        const int rc = check_hip(hipGetLastError(), "k_greedy launch");
+        if (rc) return rc;
+    }
+    return XZZX_OK;
 }
 
 static int launch_qcls(const uint8_t *d_qraw, int64_t n_syn, int n_rep, uint8_t *d_qcls, hipStream_t stream)
@@ -994,7 +1007,7 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
             const xzzx_group &g = groups[i];
             const Plan &P = g.plan->P;
             const int64_t n = g.n_syn * (int64_t)P.lat.nq, nc = g.n_syn * 4 * (int64_t)g.n_rep;
-            if ((n + 255) / 256 > 0x7FFFFFFF) { set_error("too many recovery bytes in one group"); return XZZX_ERANGE; }
+            if ((n + 255) / 256 * 256 > kMaxLaunchItems) { set_error("too many recovery bytes in one group"); return XZZX_ERANGE; }
             const dim3 grid((unsigned)((n + 255) / 256));
             if (P.order == XZZX_ORDER_RANDOM_SITE || P.ladder_k)
                 hipLaunchKernelGGL(k_site_recovery, grid, dim3(256), 0, stream, ws[i].min_snap, nc, ws[i].best_chain,
@@ -1062,7 +1075,7 @@ static int launch_reduce(const xzzx_group &g, const GroupWs &w, hipStream_t stre
     A.paper_recovery = g.d_paper_recovery;
     A.n_syn = g.n_syn;
     A.n_rep = g.n_rep;
-    if (g.n_syn > 0x7FFFFFFF) { set_error("too many syndromes"); return XZZX_ERANGE; }
+    if (g.n_syn * kWave > kMaxLaunchItems) { set_error("too many syndromes in one group for one launch"); return XZZX_ERANGE; }
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)g.n_syn), dim3(kWave), 0, stream, A);
     return check_hip(hipGetLastError(), "k_reduce launch");
 }
@@ -1213,7 +1226,7 @@ int xzzx_syndrome(const xzzx_plan *plan, const uint8_t *d_cfg, int64_t n, uint8_
     if (n == 0) return XZZX_OK;
     const int64_t total = n * plan->P.lat.nstab;
     const int64_t blocks = (total + 255) / 256;
-    if (blocks > 0x7FFFFFFF) { set_error("batch too large"); return XZZX_ERANGE; }
+    if (blocks * 256 > kMaxLaunchItems) { set_error("batch too large for one launch (2^32 work-items)"); return XZZX_ERANGE; }
     hipLaunchKernelGGL(k_syndrome, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, plan->P.ddev, d_cfg, n, d_syn);
     return check_hip(hipGetLastError(), "k_syndrome launch");
 }

@@ -12,6 +12,7 @@ import torch
 from oracle import oracle as O
 from paper_2509_17837_amd import _lib as X
 from paper_2509_17837_amd import decoder as D
+from paper_2509_17837_amd import inputs
 from tests._parity import Problem, compare_decode, gpu_plan, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -65,6 +66,30 @@ def test_greedy_kernel(layout, d, p, eta, mode):
             exp = prob.oracle_greedy(i, r, mode)
             assert np.array_equal(refs[i, r], exp), f"syndrome {i} replica {r}"
             assert qcls[i, r] == prob.olat.cls(refs[i, r], refs[i, 0])
+
+
+def test_greedy_beyond_one_launch():
+    """More (syndrome, replica) pairs than one launch can address (2^32
+    work-items = 67108863 wavefronts): the greedy references go in chunks;
+    pairs sampled on both sides of the chunk boundary equal the oracle's."""
+    n_syn, R = 1_000_000, 70
+    prob = Problem(0, 3, 0.15, 10.0, 0, R, 0, seed=4)
+    plan = gpu_plan(prob)
+    err = inputs.sample_errors(n_syn, prob.olat.nq, inputs.channel(0.15, 10.0), 91, stream=3)
+    syn = D.syndrome(plan, to_dev(err))
+    uid = to_dev(inputs.sample_uids(n_syn).view(np.int32))
+    print(f"[greedy] {n_syn} syndromes x {R} replicas", flush=True)
+    refs, _ = D.greedy_init(plan, syn, uid, R, prob.greedy_seed, X.GREEDY_RANDOM)
+    torch.cuda.synchronize()
+    syn_h = syn.cpu().numpy()
+    boundary = (2**32 - 1) // 64
+    picks = [(0, 0), (boundary // R - 1, R - 1), (boundary // R, boundary % R), (boundary // R, R - 1),
+             (n_syn - 1, 0), (n_syn - 1, R - 1), (777_777, 33)]
+    for s, r in picks:
+        exp = prob.olat.greedy(prob.wg, syn_h[s], s, r, prob.greedy_seed, O.GREEDY_RANDOM)
+        got = refs[s, r].cpu().numpy()
+        assert np.array_equal(got, exp), (s, r)
+        assert np.array_equal(prob.olat.syndrome(got), syn_h[s])
 
 
 def test_decode_small_d3_all():
