@@ -229,9 +229,7 @@ int xzzx_plan_set_order(xzzx_plan *plan, int order);
  * as for colour sweeps.  EINVAL for another K or with the random-site order;
  * ERANGE if the ladder's tables and 64 chains do not fit in 64 KiB of LDS.
  * One chain per lane (XZZX_KERNEL_LADDER); the autotuner leaves the plan
- * unchanged and the serving loop rejects such plans.  The call replaces the
- * plan's device tables: like the other plan setters it must not overlap
- * decodes that use the plan (synchronize their streams first). */
+ * unchanged and the serving loop rejects such plans. */
 int xzzx_plan_set_ladder(xzzx_plan *plan, int levels, double beta_lo, double beta_hi);
 
 /* Autotuner of the result-invariant knobs (kernel family, lanes per chain).
