@@ -92,6 +92,26 @@ def test_greedy_beyond_one_launch():
         assert np.array_equal(prob.olat.syndrome(got), syn_h[s])
 
 
+@pytest.mark.parametrize("layout,d", [(0, 7), (1, 5)])
+def test_decode_against_exact_minima(layout, d):
+    """The GPU decoder (default kernels: specialised packed rows) against the
+    mathematics directly: every coset estimate E_P bounds the exact coset
+    minimum (a frontier dynamic program over the generator bits) from above,
+    and a slow schedule reaches the exact least minimum."""
+    from tests import _exact
+    prob = Problem(layout, d, 0.12, 10.0, 6, 16, 400, sched=("linear", 0.1, 5.0), seed=70 + d)
+    out = run_decode(prob)
+    e_cls = out.e_cls.cpu().numpy()
+    refs0 = out.refs[:, 0].cpu().numpy()
+    hits = 0
+    for i in range(prob.n_syn):
+        exact = [_exact.coset_minimum(prob.olat.fq, prob.olat.fm, refs0[i] ^ prob.olat.logical(P), prob.w)
+                 for P in range(4)]
+        assert all(int(e_cls[i, P]) >= exact[P] for P in range(4)), i
+        hits += int(out.e_best[i].item()) == min(exact)
+    assert hits >= prob.n_syn - 1
+
+
 def test_decode_small_d3_all():
     """Distance 3, one replica, 200 linear sweeps, 1000 syndromes."""
     prob = Problem(0, 3, 0.15, 10.0, 1000, 1, 200, sched=("linear", 0.1, 5.0), seed=1000)
