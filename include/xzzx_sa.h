@@ -208,7 +208,7 @@ enum { XZZX_ORDER_COLOUR = 0, XZZX_ORDER_RANDOM_SITE = 1 };
 int xzzx_plan_set_order(xzzx_plan *plan, int order);
 
 /* Replica exchange (parallel tempering; the paper names it as future work,
- * Sec. VI) instead of the annealing schedule.  levels = K in {1, 2, 4, 8,
+ * Sec. VII) instead of the annealing schedule.  levels = K in {1, 2, 4, 8,
  * 16} turns it on, 0 off.  Replicas come in ladders of K consecutive
  * replicas r = bK + j that share the greedy reference of replica b (n_rep of
  * every group must be a multiple of K, else EINVAL at decode).  For each

@@ -22,6 +22,7 @@ CONV_BASELINE, CONV_PAPER = 0, 1
 SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
 ORDER_COLOUR, ORDER_RANDOM_SITE, ORDER_LADDER = 0, 1, 2   # colour sweeps; random-site steps (Alg. 3); replica exchange
+RANK_DEFAULT, RANK_FACE_ID = 0, 1   # within-class rank orders (test hook: the reading of Alg. 3's visiting order)
 
 
 def build(force: bool = False) -> str:
@@ -56,6 +57,7 @@ def lib():
         L.or_lattice_nq.argtypes = [P]
         L.or_lattice_nstab.argtypes = [P]
         L.or_lattice_ncls.argtypes = [P, C.c_int]
+        L.or_lattice_set_rank_order.argtypes = [P, C.c_int]
         L.or_lattice_export.argtypes = [P, i32p, u8p, i32p, i32p, i32p, i32p, u8p, u8p]
         L.or_noise.argtypes = [C.c_double, C.c_double, C.c_int, f64p]
         L.or_weights.argtypes = [C.c_double, f64p, i32p, i32p]
@@ -175,6 +177,14 @@ class Lattice:
         self.frank = np.zeros(ns, np.int32)
         self.lx = np.zeros(nq, np.uint8)
         self.lz = np.zeros(nq, np.uint8)
+        lib().or_lattice_export(self.h, self.fq, self.fm, self.fxy, self.fclass, self.fcolour,
+                                self.frank, self.lx, self.lz)
+
+    def set_rank_order(self, order):
+        """Test hook: RANK_DEFAULT (the oracle's reading) or RANK_FACE_ID (the
+        alternative reading, face-id order on both layouts)."""
+        if lib().or_lattice_set_rank_order(self.h, int(order)):
+            raise ValueError(f"unknown rank order {order}")
         lib().or_lattice_export(self.h, self.fq, self.fm, self.fxy, self.fclass, self.fcolour,
                                 self.frank, self.lx, self.lz)
 

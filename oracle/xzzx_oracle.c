@@ -150,6 +150,39 @@ static int mod2(int a) { return ((a % 2) + 2) % 2; }
 
 void or_lattice_free(or_lat *L);
 
+/* Rank of each generator inside its colour class (Alg. 3 leaves the visiting
+ * order open; in the colour sweep the rank only names the Philox word a
+ * generator draws, so any fixed order gives chains of the same law).
+ *   OR_RANK_DEFAULT: rotated: face-id order, i.e. row-major over the cells
+ *     (j, i); planar: row-major over ((x + y)/2, (x - y)/2), the face's place
+ *     in the lattice turned by 45 degrees, where each planar generator covers
+ *     a 2 x 2 block of qubits (no ties can occur).
+ *   OR_RANK_FACE_ID: face-id order on both layouts (row-major over (y, x) of
+ *     doubled coordinates for planar).  An alternative reading, kept for the
+ *     test that shows the decoder's statistics do not depend on the choice. */
+#define OR_RANK_DEFAULT 0
+#define OR_RANK_FACE_ID 1
+static void assign_ranks(or_lat *L, int order)
+{
+    const int ns = L->nstab;
+    for (int g = 0; g < ns; ++g) L->frank[g] = 0;
+    for (int g = 0; g < ns; ++g) {
+        for (int h = 0; h < ns; ++h) {
+            if (h == g || L->fclass[h] != L->fclass[g]) continue;
+            int before;
+            if (L->layout == OR_ROTATED || order == OR_RANK_FACE_ID) {
+                before = h < g;
+            } else {
+                int sg = (L->fx[g] + L->fy[g]) / 2, rg = (L->fx[g] - L->fy[g]) / 2;
+                int sh = (L->fx[h] + L->fy[h]) / 2, rh = (L->fx[h] - L->fy[h]) / 2;
+                before = sh < sg || (sh == sg && rh < rg);
+            }
+            L->frank[g] += before;
+        }
+    }
+    for (int g = 0; g < ns; ++g) L->cls_face[L->fclass[g]][L->frank[g]] = g;
+}
+
 or_lat *or_lattice_new(int layout, int d)
 {
     if (d < 3 || (d & 1) == 0 || d > 63) return NULL;
@@ -237,34 +270,24 @@ or_lat *or_lattice_new(int layout, int d)
         or_lattice_free(L);
         return NULL;
     }
-    /* Rank inside each colour class (reading; it only names the random word
-     * each generator draws).  Rotated: face-id order, i.e. row-major over
-     * the cells (j, i).  Planar: row-major over ((x + y)/2, (x - y)/2), the
-     * face's position in the frame turned by 45 degrees, where each planar
-     * generator covers a 2 x 2 block of qubits; ties cannot occur. */
     for (int k = 0; k < 4; ++k) L->ncls[k] = 0;
-    for (int g = 0; g < ns; ++g) L->frank[g] = 0;
-    for (int g = 0; g < ns; ++g) {
-        L->ncls[L->fclass[g]]++;
-        for (int h = 0; h < ns; ++h) {
-            if (h == g || L->fclass[h] != L->fclass[g]) continue;
-            int before;
-            if (layout == OR_ROTATED) {
-                before = h < g;
-            } else {
-                int sg = (L->fx[g] + L->fy[g]) / 2, rg = (L->fx[g] - L->fy[g]) / 2;
-                int sh = (L->fx[h] + L->fy[h]) / 2, rh = (L->fx[h] - L->fy[h]) / 2;
-                before = sh < sg || (sh == sg && rh < rg);
-            }
-            L->frank[g] += before;
-        }
-    }
+    for (int g = 0; g < ns; ++g) L->ncls[L->fclass[g]]++;
     for (int k = 0; k < 4; ++k) {
         L->cls_face[k] = (int *)malloc(sizeof(int) * (L->ncls[k] > 0 ? L->ncls[k] : 1));
         if (!L->cls_face[k]) { or_lattice_free(L); return NULL; }
     }
-    for (int g = 0; g < ns; ++g) L->cls_face[L->fclass[g]][L->frank[g]] = g;
+    assign_ranks(L, OR_RANK_DEFAULT);
     return L;
+}
+
+/* Test hook: re-rank the generators of every colour class (OR_RANK_DEFAULT or
+ * OR_RANK_FACE_ID).  Used only by the statistical test that compares the two
+ * planar readings; returns OR_EINVAL for an unknown order. */
+int or_lattice_set_rank_order(or_lat *L, int order)
+{
+    if (order != OR_RANK_DEFAULT && order != OR_RANK_FACE_ID) return OR_EINVAL;
+    assign_ranks(L, order);
+    return OR_OK;
 }
 
 void or_lattice_free(or_lat *L)
@@ -965,7 +988,7 @@ int or_anneal_chain_site(const or_lat *L, const int32_t w[4], const double *beta
 
 /* ------------------------------------------------------------------------- */
 /* Replica exchange (parallel tempering), the extension the paper names as    */
-/* future work (Sec. VI).  Reading: a ladder of K chains of one coset, all    */
+/* future work (Sec. VII).  Reading: a ladder of K chains of one coset, all    */
 /* started from the same configuration, at fixed inverse temperatures        */
 /* beta_k = beta_lo + k delta, delta = (beta_hi - beta_lo)/(K - 1) (beta_lo   */
 /* alone when K = 1); chain j starts at level j.  Every sweep t, each chain   */
