@@ -41,10 +41,21 @@
  *   failure outputs are undefined and xzzx_last_error() returns a message
  *   (thread-local).  No C++ exception crosses this interface.
  *
- * Thread safety
+ * Thread safety and streams
  *   Calls on distinct handles may run concurrently.  A plan may be used by
- *   several concurrent decode calls on different streams.  Server submit/poll
- *   are thread-safe; other calls on one handle need external synchronisation.
+ *   several concurrent decode, anneal or graph-capture calls on different
+ *   streams: a call that runs launches concurrently does so on side streams
+ *   of its own caller stream (created on first use, kept until the process
+ *   ends), so calls on different streams share no internal stream and a
+ *   capture on one stream never records another call's work.  (xzzx_graph_create
+ *   creates them before it begins capturing; a caller capturing a decode in
+ *   its own graph in global capture mode makes one call on that stream
+ *   first.)  The plan
+ *   setters (set_lanes, set_kernel, set_order, set_ladder, autotune) change
+ *   what later calls launch, and set_ladder replaces device tables: none may
+ *   run while a call that uses the plan is being enqueued or its work is in
+ *   flight (synchronise those streams first).  Server submit/poll are
+ *   thread-safe; other calls on one handle need external synchronisation.
  */
 #ifndef XZZX_SA_H
 #define XZZX_SA_H
@@ -274,9 +285,9 @@ typedef struct {
     int64_t n_syn;
     int n_rep;
     const uint32_t *d_uid;       /* [n_syn] syndrome ids (RNG counters) */
-    const uint8_t *d_syn;        /* [n_syn][n_stabs] */
-    uint8_t *d_refs;             /* [n_syn][n_rep][n_qubits]; decode writes it if non-NULL */
-    uint8_t *d_qcls;             /* [n_syn][n_rep]; decode writes it if non-NULL */
+    const uint8_t *d_syn;        /* [n_syn][n_stabs]; anneal: optional, checked against d_refs */
+    uint8_t *d_refs;             /* [n_syn][n_rep][n_qubits]; decode writes it if non-NULL; anneal input */
+    uint8_t *d_qcls;             /* [n_syn][n_rep] reference classes; written if non-NULL */
     int32_t *d_e_best;           /* [n_syn] min over cosets of E_P */
     uint8_t *d_cls;              /* [n_syn] P* */
     uint8_t *d_recovery;         /* [n_syn][n_qubits] minimum-energy configuration */
@@ -300,7 +311,16 @@ int xzzx_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_seed,
                 uint64_t anneal_seed, int greedy_mode, int flags, void *d_workspace,
                 size_t workspace_bytes, void *stream);
 
-/* As xzzx_decode, from caller-supplied references d_refs / d_qcls (no greedy). */
+/* As xzzx_decode, from caller-supplied references d_refs (no greedy
+ * matching).  Its first stage (XZZX_FLAG_STAGE_GREEDY, included when no stage
+ * is selected) takes the place of the greedy stage: it computes each
+ * reference's class relative to replica 0 on the device (Alg. 7, Eqs.
+ * (35)-(36); written to d_qcls if non-NULL) and, for groups whose d_syn is
+ * non-NULL, checks that every reference has the group's syndrome (Alg. 7
+ * requires boundary(C) = S), returning EINVAL if one does not.  That check
+ * reads its result back, so it synchronizes `stream`; with d_syn set it is
+ * refused (EINVAL) while `stream` is being captured.  Groups with d_syn NULL
+ * are not checked and the call stays asynchronous. */
 int xzzx_anneal(const xzzx_group *groups, int n_groups, uint64_t anneal_seed, int flags,
                 void *d_workspace, size_t workspace_bytes, void *stream);
 

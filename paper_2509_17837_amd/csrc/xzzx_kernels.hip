@@ -369,6 +369,43 @@ __global__ void k_qcls(const uint8_t *qraw, int64_t n_syn, int n_rep, uint8_t *q
     }
 }
 
+// Caller-supplied references (the anneal-only entry point), one wavefront per
+// (syndrome, replica): the raw symplectic products with L_Z and L_X, as the
+// greedy kernel writes them, and, when syndromes are given, whether the
+// reference has syndrome S (Alg. 7 requires a configuration with boundary S;
+// Eq. (2)).  A mismatch sets *bad.
+__global__ __launch_bounds__(kWave) void k_ref_check(const PlanDev *__restrict__ pl, const uint8_t *__restrict__ refs,
+                                                     const uint8_t *__restrict__ syn, int n_rep, int64_t block0,
+                                                     uint8_t *__restrict__ qraw, uint32_t *bad)
+{
+    const int nq = pl->nq, nstab = pl->nstab, lane = threadIdx.x;
+    const int64_t sr = block0 + blockIdx.x;
+    const uint8_t *c = refs + sr * nq;
+    uint32_t vz = 0, vx = 0;
+    for (int q = lane; q < nq; q += kWave) {
+        const uint32_t v = c[q], z = pl->lz[q], x = pl->lx[q];
+        vz ^= (((v >> 1) & z) ^ (v & (z >> 1))) & 1;
+        vx ^= (((v >> 1) & x) ^ (v & (x >> 1))) & 1;
+    }
+    const int az = __popcll(__ballot(vz)) & 1;
+    const int ax = __popcll(__ballot(vx)) & 1;
+    if (lane == 0) qraw[sr] = (uint8_t)(az | (ax << 1));
+    if (!syn) return;
+    const uint8_t *S = syn + (sr / n_rep) * nstab;
+    uint32_t diff = 0;
+    for (int f = lane; f < nstab; f += kWave) {
+        const Desc d = pl->face_desc[f];
+        const int q[4] = {(int)(d.x & 0xFFFF), (int)(d.x >> 16), (int)(d.y & 0xFFFF), (int)((d.y >> 16) & 0x7FF)};
+        uint32_t bit = 0;
+        if (q[0] < nq) bit ^= c[q[0]] & 1;
+        if (q[1] < nq) bit ^= (c[q[1]] >> 1) & 1;
+        if (q[2] < nq) bit ^= (c[q[2]] >> 1) & 1;
+        if (q[3] < nq) bit ^= c[q[3]] & 1;
+        diff |= bit ^ (S[f] & 1u);
+    }
+    if (__ballot(diff) && lane == 0) atomicOr(bad, 1u);
+}
+
 template <int LOGG>
 __global__ __launch_bounds__(kWave) void k_anneal(AnnealArgs A) { batch_kernel_body<0, false, LOGG, false>(A); }
 template <int LOGG>
@@ -713,7 +750,7 @@ static size_t group_ws_bytes(const xzzx_group &g, bool decode)
     size_t b = 0;
     if (decode && !g.d_refs) b += align256(ns * R * nq);
     b += align256(ns * R);                                  // qraw
-    if (decode && !g.d_qcls) b += align256(ns * R);
+    if (!g.d_qcls) b += align256(ns * R);
     if (!g.d_chain_emin) b += align256(nc * 4);
     if (!g.d_chain_stop) b += align256(nc * 4);
     if (!g.d_chain_e) b += align256(nc * 4);
@@ -731,7 +768,7 @@ static GroupWs carve_group(const xzzx_group &g, bool decode, uint8_t *&p)
     auto take = [&](size_t bytes) { uint8_t *r = p; p += align256(bytes); return r; };
     w.refs = g.d_refs ? g.d_refs : (decode ? take(ns * R * nq) : nullptr);
     w.qraw = take(ns * R);
-    w.qcls = g.d_qcls ? g.d_qcls : (decode ? take(ns * R) : nullptr);
+    w.qcls = g.d_qcls ? g.d_qcls : take(ns * R);
     w.emin = g.d_chain_emin ? g.d_chain_emin : reinterpret_cast<int32_t *>(take(nc * 4));
     w.stop = g.d_chain_stop ? g.d_chain_stop : reinterpret_cast<int32_t *>(take(nc * 4));
     w.efin = g.d_chain_e ? g.d_chain_e : reinterpret_cast<int32_t *>(take(nc * 4));
@@ -758,7 +795,7 @@ static int validate_groups(const xzzx_group *groups, int n_groups, bool decode)
         if (g.n_syn == 0) continue;
         if (!g.d_uid || !g.d_e_best || !g.d_cls || !g.d_recovery) { set_error("missing required group buffer"); return XZZX_EINVAL; }
         if (decode && !g.d_syn) { set_error("decode needs d_syn"); return XZZX_EINVAL; }
-        if (!decode && (!g.d_refs || !g.d_qcls)) { set_error("anneal needs d_refs and d_qcls"); return XZZX_EINVAL; }
+        if (!decode && !g.d_refs) { set_error("anneal needs d_refs"); return XZZX_EINVAL; }
         if ((int64_t)g.n_syn * 4 * g.n_rep >= ((int64_t)1 << 31)) { set_error("too many chains in one group"); return XZZX_ERANGE; }
     }
     return XZZX_OK;
@@ -888,64 +925,102 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
     return check_hip(hipGetLastError(), "anneal launch");
 }
 
-// Side streams of the current device (default priority, created once) for
-// running independent launches of one call concurrently.
+// Side streams (default priority) and reusable events for running the
+// independent launches of one call concurrently.  Each (device, caller stream)
+// pair has a set of its own, created on first use and kept until the process
+// ends, so calls on different streams -- among them a graph capture on one
+// stream and a serving loop on another -- never share a side stream; calls on
+// one caller stream hold the set's lock while they fork and join.  Past
+// kMaxSideSets sets, calls run their launches one after another on the caller
+// stream instead (same results).
 constexpr int kSideStreams = 3;
+constexpr int kMaxSideSets = 256;
 
-static int side_streams(hipStream_t out[kSideStreams])
+struct SideSet {
+    std::mutex mu;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
+};
+
+// The set of `caller` on the current device, nullptr when the table is full;
+// an error status if a stream or event cannot be created.
+static int side_set(hipStream_t caller, SideSet **out)
 {
     static std::mutex mu;
-    static hipStream_t streams[64][kSideStreams] = {};
+    static std::vector<std::pair<std::pair<int, hipStream_t>, SideSet *>> sets;   // never freed
+    *out = nullptr;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { set_error("hipGetDevice failed"); return XZZX_EDEVICE; }
+    if (hipGetDevice(&dev) != hipSuccess) { set_error("hipGetDevice failed"); return XZZX_EDEVICE; }
+    const std::pair<int, hipStream_t> key(dev, caller);
     std::lock_guard<std::mutex> lk(mu);
-    for (int i = 0; i < kSideStreams; ++i) {
-        if (!streams[dev][i] && hipStreamCreateWithFlags(&streams[dev][i], hipStreamNonBlocking) != hipSuccess) {
-            streams[dev][i] = nullptr;
-            set_error("side stream creation failed");
-            return XZZX_EDEVICE;
+    for (auto &e : sets)
+        if (e.first == key) { *out = e.second; return XZZX_OK; }
+    if ((int)sets.size() >= kMaxSideSets) return XZZX_OK;
+    auto *S = new SideSet();
+    bool ok = hipEventCreateWithFlags(&S->fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kSideStreams && ok; ++i)
+        ok = hipStreamCreateWithFlags(&S->side[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&S->join[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        for (int i = 0; i < kSideStreams; ++i) {
+            if (S->side[i]) (void)hipStreamDestroy(S->side[i]);
+            if (S->join[i]) (void)hipEventDestroy(S->join[i]);
         }
-        out[i] = streams[dev][i];
+        if (S->fork) (void)hipEventDestroy(S->fork);
+        delete S;
+        set_error("side stream or event creation failed");
+        return XZZX_EDEVICE;
     }
+    sets.emplace_back(key, S);
+    *out = S;
     return XZZX_OK;
 }
 
-// Runs launch(i, stream_i) for i < n: launch 0 on `stream`, the others on side
-// streams that wait for `stream`'s prior work; `stream` then waits for all.
-// Works under hipGraph capture (the events become graph dependencies).
+// Runs launch(i, stream_i) for i < n: launch 0 on `stream`, the others on the
+// caller's side streams, which wait for `stream`'s prior work; `stream` then
+// waits for all.  Works under hipGraph capture (the events become graph
+// dependencies).  serial: every launch on `stream`, in order (no side
+// streams or events are created or used).
 template <typename F>
-static int fork_join(hipStream_t stream, int n, F launch)
+static int fork_join(hipStream_t stream, int n, F launch, bool serial = false)
 {
-    hipStream_t side[kSideStreams];
-    int rc = side_streams(side);
+    if (serial) {
+        int rc = XZZX_OK;
+        for (int i = 0; i < n && !rc; ++i) rc = launch(i, stream);
+        return rc;
+    }
+    if (n <= 1) return n ? launch(0, stream) : XZZX_OK;
+    SideSet *S = nullptr;
+    int rc = side_set(stream, &S);
     if (rc) return rc;
-    hipEvent_t fork = nullptr;
-    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) { set_error("event creation failed"); return XZZX_EDEVICE; }
-    rc = check_hip(hipEventRecord(fork, stream), "fork record");
-    std::vector<hipEvent_t> joins;
-    bool waited[kSideStreams] = {false, false, false};
+    if (!S) {
+        for (int i = 0; i < n && !rc; ++i) rc = launch(i, stream);
+        return rc;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    rc = check_hip(hipEventRecord(S->fork, stream), "fork record");
+    bool used[kSideStreams] = {false, false, false};
     for (int i = 0; i < n && !rc; ++i) {
         hipStream_t s = stream;
         if (i > 0) {
             const int k = (i - 1) % kSideStreams;
-            s = side[k];
-            if (!waited[k]) {
-                rc = check_hip(hipStreamWaitEvent(s, fork, 0), "fork wait");
-                waited[k] = true;
+            s = S->side[k];
+            if (!used[k]) {
+                rc = check_hip(hipStreamWaitEvent(s, S->fork, 0), "fork wait");
+                used[k] = true;
             }
         }
         if (!rc) rc = launch(i, s);
     }
-    for (int k = 0; k < kSideStreams && !rc; ++k) {
-        if (!waited[k]) continue;
-        hipEvent_t e = nullptr;
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { set_error("event creation failed"); rc = XZZX_EDEVICE; break; }
-        joins.push_back(e);
-        rc = check_hip(hipEventRecord(e, side[k]), "join record");
-        if (!rc) rc = check_hip(hipStreamWaitEvent(stream, e, 0), "join wait");
+    // join every side stream that waited, also after a failed launch, so no
+    // side stream is left inside a capture of `stream`
+    for (int k = 0; k < kSideStreams; ++k) {
+        if (!used[k]) continue;
+        int r = check_hip(hipEventRecord(S->join[k], S->side[k]), "join record");
+        if (!r) r = check_hip(hipStreamWaitEvent(stream, S->join[k], 0), "join wait");
+        if (!rc) rc = r;
     }
-    (void)hipEventDestroy(fork);
-    for (hipEvent_t e : joins) (void)hipEventDestroy(e);
     return rc;
 }
 
@@ -960,7 +1035,7 @@ static int fork_join(hipStream_t stream, int n, F launch)
 // its own d_counters base) uses [0] and [2].
 static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
                          uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
-                         hipStream_t stream)
+                         hipStream_t stream, bool serial = false)
 {
     std::vector<int> rows_sel;
     std::vector<int> bytes_sel[7];
@@ -1057,7 +1132,7 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
         const Set &S = sets[i];
         return launch_set(groups, ws, *S.sel, S.rows, S.lanes, mode, seed, unit_offset, units_override, S.counter, s,
                           S.static_d, S.site, S.planar_d, S.ladder);
-    });
+    }, serial);
 }
 
 static int launch_reduce(const xzzx_group &g, const GroupWs &w, hipStream_t stream)
@@ -1080,9 +1155,55 @@ static int launch_reduce(const xzzx_group &g, const GroupWs &w, hipStream_t stre
     return check_hip(hipGetLastError(), "k_reduce launch");
 }
 
+// The reference stage of the anneal-only entry point: the class of every
+// caller reference relative to replica 0 (Alg. 7, Eqs. (35)-(36)), and, for
+// groups that pass their syndromes, the check that every reference has
+// syndrome S.  The check reads a flag back, so it synchronizes `stream` and
+// is refused while `stream` is being captured.
+static int check_references(const xzzx_group *groups, const GroupWs *ws, int n_groups, uint32_t *d_flag,
+                            hipStream_t stream)
+{
+    bool any_syn = false;
+    for (int i = 0; i < n_groups; ++i) any_syn |= groups[i].n_syn > 0 && groups[i].d_syn;
+    if (any_syn) {
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        int rc = check_hip(hipStreamIsCapturing(stream, &st), "hipStreamIsCapturing");
+        if (rc) return rc;
+        if (st != hipStreamCaptureStatusNone) {
+            set_error("checking references against d_syn synchronizes the stream: not allowed under capture");
+            return XZZX_EINVAL;
+        }
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d_flag, 1);
+        rc = check_hip(hipGetLastError(), "flag clear launch");
+        if (rc) return rc;
+    }
+    for (int i = 0; i < n_groups; ++i) {
+        const xzzx_group &g = groups[i];
+        if (g.n_syn <= 0) continue;
+        const int64_t blocks = g.n_syn * g.n_rep;
+        for (int64_t b0 = 0; b0 < blocks; b0 += kMaxLaunchWaves) {
+            const int64_t nb = std::min<int64_t>(kMaxLaunchWaves, blocks - b0);
+            hipLaunchKernelGGL(k_ref_check, dim3((unsigned)nb), dim3(kWave), 0, stream, g.plan->P.ddev, ws[i].refs,
+                               g.d_syn, g.n_rep, b0, ws[i].qraw, d_flag);
+            const int rc = check_hip(hipGetLastError(), "k_ref_check launch");
+            if (rc) return rc;
+        }
+        const int rc = launch_qcls(ws[i].qraw, g.n_syn, g.n_rep, ws[i].qcls, stream);
+        if (rc) return rc;
+    }
+    if (!any_syn) return XZZX_OK;
+    uint32_t bad = 0;
+    int rc = check_hip(hipMemcpyAsync(&bad, d_flag, sizeof(bad), hipMemcpyDeviceToHost, stream), "flag read");
+    if (!rc) rc = check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (rc) return rc;
+    if (bad) { set_error("a reference's syndrome differs from the group's syndrome S"); return XZZX_EINVAL; }
+    return XZZX_OK;
+}
+
+// serial: every launch on `stream`, in order, with no side streams or events
 static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_seed, uint64_t anneal_seed,
                       int greedy_mode, int flags, void *d_workspace, size_t workspace_bytes,
-                      hipStream_t stream, bool decode)
+                      hipStream_t stream, bool decode, bool serial = false)
 {
     int rc = validate_groups(groups, n_groups, decode);
     if (rc) return rc;
@@ -1113,8 +1234,12 @@ static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_se
                               ws[i].qraw, s);
         if (!r) r = launch_qcls(ws[i].qraw, g.n_syn, g.n_rep, ws[i].qcls, s);
         return r;
-    });
+    }, serial);
     if (rc) return rc;
+    if (!decode && (stages & XZZX_FLAG_STAGE_GREEDY)) {
+        rc = check_references(groups, ws.data(), n_groups, counter + 63, stream);
+        if (rc) return rc;
+    }
     if (!(stages & XZZX_FLAG_STAGE_ANNEAL)) {
         // annealing skipped in this call
     } else if (flags & XZZX_FLAG_PLAIN) {
@@ -1128,7 +1253,8 @@ static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_se
             }
         }
     } else {
-        rc = launch_anneal(groups, ws.data(), n_groups, AnnealMode::Persistent, anneal_seed, 0, -1, counter, stream);
+        rc = launch_anneal(groups, ws.data(), n_groups, AnnealMode::Persistent, anneal_seed, 0, -1, counter, stream,
+                           serial);
         if (rc) return rc;
     }
     if (!(stages & XZZX_FLAG_STAGE_FINISH)) return XZZX_OK;
@@ -1136,7 +1262,8 @@ static int run_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_se
         rc = launch_reduce(groups[i], ws[i], stream);
         if (rc) return rc;
     }
-    return launch_anneal(groups, ws.data(), n_groups, AnnealMode::Replay, anneal_seed, 0, -1, counter + 8, stream);
+    return launch_anneal(groups, ws.data(), n_groups, AnnealMode::Replay, anneal_seed, 0, -1, counter + 8, stream,
+                         serial);
 }
 
 
@@ -1290,7 +1417,11 @@ int xzzx_graph_create(const xzzx_group *groups, int n_groups, uint64_t greedy_se
     *out = nullptr;
     if (!stream) { set_error("graph capture needs a non-null stream"); return XZZX_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
-    int rc = check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    // the stream's side streams and events exist before the capture begins
+    SideSet *side = nullptr;
+    int rc = side_set(s, &side);
+    if (rc) return rc;
+    rc = check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     if (rc) return rc;
     const int drc = run_decode(groups, n_groups, greedy_seed, anneal_seed, greedy_mode, flags, d_workspace,
                                workspace_bytes, s, true);

@@ -6,6 +6,7 @@ device allocations and the current HIP stream.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 from dataclasses import dataclass
 
@@ -27,6 +28,22 @@ def _np_p(a):
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def _on(stream):
+    """Allocation context for buffers a call on `stream` writes: the caching
+    allocator then reuses their memory only in `stream`'s order."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
+def _used_on(stream, *tensors):
+    """Tensors allocated elsewhere that work on `stream` reads: their memory is
+    not reused before that work is done (torch's record_stream)."""
+    if stream is None:
+        return
+    for t in tensors:
+        if t is not None and t.is_cuda:
+            t.record_stream(stream)
 
 
 def _dev(t, dtype, name):
@@ -160,7 +177,9 @@ class Plan:
 def syndrome(plan: Plan, cfg: torch.Tensor, stream=None) -> torch.Tensor:
     cfg = _dev(cfg, torch.uint8, "cfg")
     n = cfg.shape[0]
-    syn = torch.empty((n, plan.nstab), dtype=torch.uint8, device=cfg.device)
+    with _on(stream):
+        syn = torch.empty((n, plan.nstab), dtype=torch.uint8, device=cfg.device)
+    _used_on(stream, cfg)
     call("xzzx_syndrome", plan.h, _p(cfg), n, _p(syn), _stream(stream))
     return syn
 
@@ -169,8 +188,10 @@ def greedy_init(plan: Plan, syn, uid, n_rep, seed, mode=X.GREEDY_RANDOM, stream=
     syn = _dev(syn, torch.uint8, "syn")
     uid = _dev(uid, torch.int32, "uid") if uid.dtype == torch.int32 else _dev(uid, torch.uint32, "uid")
     n = syn.shape[0]
-    refs = torch.empty((n, n_rep, plan.nq), dtype=torch.uint8, device=syn.device)
-    qcls = torch.empty((n, n_rep), dtype=torch.uint8, device=syn.device)
+    with _on(stream):
+        refs = torch.empty((n, n_rep, plan.nq), dtype=torch.uint8, device=syn.device)
+        qcls = torch.empty((n, n_rep), dtype=torch.uint8, device=syn.device)
+    _used_on(stream, syn, uid)
     call("xzzx_greedy_init", plan.h, _p(syn), _p(uid), n, n_rep, seed, mode, _p(refs), _p(qcls), _stream(stream))
     return refs, qcls
 
@@ -193,8 +214,17 @@ class GroupOut:
 
 
 def make_group(plan: Plan, n_rep: int, uid: torch.Tensor, syn=None, refs=None, qcls=None,
-               want_chains=False, want_final=False, want_extra=True):
-    """Allocate the outputs of one group and build its C descriptor."""
+               want_chains=False, want_final=False, want_extra=True, stream=None):
+    """Allocate the outputs of one group and build its C descriptor.  With a
+    stream, the outputs are allocated for work on that stream and the inputs
+    are marked as used by it."""
+    with _on(stream):
+        g, o = _make_group(plan, n_rep, uid, syn, refs, qcls, want_chains, want_final, want_extra)
+    _used_on(stream, uid, syn, refs, qcls)
+    return g, o
+
+
+def _make_group(plan, n_rep, uid, syn, refs, qcls, want_chains, want_final, want_extra):
     dev = uid.device
     n = uid.shape[0]
     nc = 4 * n_rep
@@ -236,17 +266,22 @@ def _groups_array(groups):
     return arr
 
 
-def workspace(groups, device="cuda"):
+def workspace(groups, device="cuda", stream=None):
     arr = _groups_array(groups)
     nb = C.c_size_t()
     call("xzzx_decode_workspace", arr, len(groups), C.byref(nb))
-    return torch.empty(nb.value, dtype=torch.uint8, device=device)
+    with _on(stream):
+        return torch.empty(nb.value, dtype=torch.uint8, device=device)
 
 
 def decode_groups(groups, greedy_seed, anneal_seed, greedy_mode=X.GREEDY_RANDOM, flags=0, ws=None, stream=None):
+    """xzzx_decode over C group descriptors; returns the workspace, which must
+    stay alive until the decode's stream has completed."""
     arr = _groups_array(groups)
     if ws is None:
-        ws = workspace(groups)
+        ws = workspace(groups, stream=stream)
+    else:
+        _used_on(stream, ws)
     call("xzzx_decode", arr, len(groups), greedy_seed, anneal_seed, greedy_mode, flags, _p(ws), ws.numel(),
          _stream(stream))
     return ws
@@ -255,17 +290,21 @@ def decode_groups(groups, greedy_seed, anneal_seed, greedy_mode=X.GREEDY_RANDOM,
 def anneal_groups(groups, anneal_seed, flags=0, ws=None, stream=None):
     arr = _groups_array(groups)
     if ws is None:
-        ws = workspace(groups)
+        ws = workspace(groups, stream=stream)
+    else:
+        _used_on(stream, ws)
     call("xzzx_anneal", arr, len(groups), anneal_seed, flags, _p(ws), ws.numel(), _stream(stream))
     return ws
 
 
 def decode(plan: Plan, syn: torch.Tensor, uid: torch.Tensor, n_rep: int, greedy_seed: int, anneal_seed: int,
            greedy_mode=X.GREEDY_RANDOM, flags=0, want_chains=False, want_final=False, stream=None) -> GroupOut:
-    """Alg. 7 for a batch of syndromes of one plan."""
+    """Alg. 7 for a batch of syndromes of one plan (on `stream`, default the
+    current stream); the outputs are valid once that stream has completed."""
     _dev(syn, torch.uint8, "syn")
-    g, o = make_group(plan, n_rep, uid, syn=syn, want_chains=want_chains, want_final=want_final)
-    decode_groups([g], greedy_seed, anneal_seed, greedy_mode, flags, stream=stream)
+    g, o = make_group(plan, n_rep, uid, syn=syn, want_chains=want_chains, want_final=want_final, stream=stream)
+    ws = decode_groups([g], greedy_seed, anneal_seed, greedy_mode, flags, stream=stream)
+    o.keep = o.keep + (ws,)
     return o
 
 

@@ -91,3 +91,25 @@ def test_class_host_matches_oracle():
             assert a.cls(base, base ^ e) == b.cls(base, base ^ e)
             P = int(rng.integers(0, 4))
             assert a.cls(base, base ^ b.logical(P)) == P
+
+
+def test_energy_overflow_is_erange():
+    """ERANGE when n_qubits * max(W) >= 2^31 (energies are int32 sums of the
+    weights of Eq. (10)); checked before any device work, so it runs without
+    a GPU.  One unit below the limit passes that check (and then needs a GPU
+    for the plan's device tables)."""
+    lat = D.Lattice(X.ROTATED, 31)
+    assert lat.nq == 961
+    at_limit = -(-(1 << 31) // lat.nq)            # least w with 961 w >= 2^31
+    assert lat.nq * at_limit >= 1 << 31 > lat.nq * (at_limit - 1)
+    for slot in (1, 2, 3):
+        w = np.array([0, 1000, 1000, 1000], np.int32)
+        w[slot] = at_limit
+        with pytest.raises(X.XzzxError) as e:
+            D.Plan(lat, w, np.array([500, 500], np.int32), np.zeros(0))
+        assert e.value.rc == X.XZZX_ERANGE
+    w = np.array([0, at_limit - 1, 1000, 1000], np.int32)
+    try:
+        D.Plan(lat, w, np.array([500, 500], np.int32), np.zeros(0))
+    except X.XzzxError as e:
+        assert e.rc != X.XZZX_ERANGE
