@@ -49,8 +49,8 @@
  *   ends), so calls on different streams share no internal stream and a
  *   capture on one stream never records another call's work.  (xzzx_graph_create
  *   creates them before it begins capturing; a caller capturing a decode in
- *   its own graph in global capture mode makes one call on that stream
- *   first.)  The plan
+ *   its own graph in global capture mode makes one call on that stream first,
+ *   or uses xzzx_decode_noalloc, which creates none.)  The plan
  *   setters (set_lanes, set_kernel, set_order, set_ladder, autotune) change
  *   what later calls launch, and set_ladder replaces device tables: none may
  *   run while a call that uses the plan is being enqueued or its work is in
@@ -323,6 +323,24 @@ int xzzx_decode(const xzzx_group *groups, int n_groups, uint64_t greedy_seed,
  * are not checked and the call stays asynchronous. */
 int xzzx_anneal(const xzzx_group *groups, int n_groups, uint64_t anneal_seed, int flags,
                 void *d_workspace, size_t workspace_bytes, void *stream);
+
+/* ---- decode without allocation -------------------------------------------- */
+
+/* For callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): xzzx_decode with the
+ * workspace taken from a static device array of XZZX_NOALLOC_SCRATCH_BYTES
+ * held by the library on each device it runs on, until the process ends.
+ * The call allocates nothing: no device memory, and no stream or event (its
+ * launches run in order on `stream`, so groups do not overlap each other).
+ * The caller still allocates every group's inputs and outputs.  ERANGE if
+ * xzzx_decode_workspace() for these groups exceeds the limit.  Every call on
+ * one device shares that device's array, which keeps the last call's contents
+ * (the decode clears what must start at zero itself): calls whose work
+ * overlaps on one device -- on different streams or threads -- race and give
+ * undefined results; serialise them.  Results equal xzzx_decode's. */
+#define XZZX_NOALLOC_SCRATCH_BYTES (64u << 20)
+int xzzx_decode_noalloc(const xzzx_group *groups, int n_groups, uint64_t greedy_seed,
+                        uint64_t anneal_seed, int greedy_mode, int flags, void *stream);
 
 /* ---- captured decode (hipGraph) -------------------------------------------- */
 

@@ -19,6 +19,7 @@ SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
 FLAG_PLAIN = 1
 STAGE_GREEDY, STAGE_ANNEAL, STAGE_FINISH = 2, 4, 8
+NOALLOC_SCRATCH_BYTES = 64 << 20   # XZZX_NOALLOC_SCRATCH_BYTES
 KERNEL_AUTO, KERNEL_ROWS, KERNEL_BYTES, KERNEL_ROWS_GENERIC, KERNEL_SITE, KERNEL_LADDER = 0, 1, 2, 3, 4, 5
 ORDER_COLOUR, ORDER_RANDOM_SITE = 0, 1
 
@@ -151,6 +152,7 @@ def lib():
         "xzzx_decode_workspace": (I, [P(Group), I, P(C.c_size_t)]),
         "xzzx_decode": (I, [P(Group), I, U64, U64, I, I, V, C.c_size_t, V]),
         "xzzx_anneal": (I, [P(Group), I, U64, I, V, C.c_size_t, V]),
+        "xzzx_decode_noalloc": (I, [P(Group), I, U64, U64, I, I, V]),
         "xzzx_graph_create": (I, [P(Group), I, U64, U64, I, I, V, C.c_size_t, V, P(V)]),
         "xzzx_graph_launch": (I, [V, V]),
         "xzzx_graph_destroy": (None, [V]),

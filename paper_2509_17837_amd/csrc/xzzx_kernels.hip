@@ -1402,6 +1402,53 @@ int xzzx_anneal(const xzzx_group *groups, int n_groups, uint64_t anneal_seed, in
 
 }  // extern "C"
 
+// ---- decode without allocation ----
+// The workspace of xzzx_decode_noalloc: one array per device, resident from
+// the library's load on that device until the process ends.  Host code never
+// passes the array's name to a kernel (in host code it is only a stand-in for
+// the symbol): it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device.
+static __device__ __align__(256) uint8_t scratch[XZZX_NOALLOC_SCRATCH_BYTES];
+
+static int scratch_address(void **out)
+{
+    static std::mutex mu;
+    static void *addr[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { set_error("hipGetDevice failed"); return XZZX_EDEVICE; }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const int rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+        if (rc) return rc;
+        if (!p) { set_error("hipGetSymbolAddress returned NULL"); return XZZX_EDEVICE; }
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return XZZX_OK;
+}
+
+extern "C" {
+
+int xzzx_decode_noalloc(const xzzx_group *groups, int n_groups, uint64_t greedy_seed, uint64_t anneal_seed,
+                        int greedy_mode, int flags, void *stream)
+{
+    size_t need = 0;
+    int rc = xzzx_decode_workspace(groups, n_groups, &need);
+    if (rc) return rc;
+    if (need > (size_t)XZZX_NOALLOC_SCRATCH_BYTES) {
+        set_error("workspace of these groups exceeds XZZX_NOALLOC_SCRATCH_BYTES");
+        return XZZX_ERANGE;
+    }
+    void *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    return run_decode(groups, n_groups, greedy_seed, anneal_seed, greedy_mode, flags, ws,
+                      (size_t)XZZX_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream, true, true);
+}
+
+}  // extern "C"
+
 struct xzzx_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

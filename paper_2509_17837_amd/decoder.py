@@ -287,6 +287,13 @@ def decode_groups(groups, greedy_seed, anneal_seed, greedy_mode=X.GREEDY_RANDOM,
     return ws
 
 
+def decode_groups_noalloc(groups, greedy_seed, anneal_seed, greedy_mode=X.GREEDY_RANDOM, flags=0, stream=None):
+    """xzzx_decode_noalloc: the decode with the library's static per-device
+    workspace (no allocation; calls that overlap on one device race)."""
+    arr = _groups_array(groups)
+    call("xzzx_decode_noalloc", arr, len(groups), greedy_seed, anneal_seed, greedy_mode, flags, _stream(stream))
+
+
 def anneal_groups(groups, anneal_seed, flags=0, ws=None, stream=None):
     arr = _groups_array(groups)
     if ws is None:
