@@ -86,6 +86,7 @@ def lib():
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double]
+        L.or_reduce.argtypes = [C.c_int, i64p, i32p, i64p, C.c_void_p, C.c_void_p]
         L.or_swap_powers.argtypes = [C.c_double, C.c_void_p]
         L.or_swap_threshold.argtypes = [C.c_void_p, C.c_int64]
         L.or_swap_threshold.restype = C.c_uint32
@@ -146,6 +147,24 @@ def swap_threshold(R, n):
 
 def ladder_beta(beta_lo, beta_hi, K, k):
     return float(lib().or_ladder_beta(float(beta_lo), float(beta_hi), int(K), int(k)))
+
+
+def reduce(emin, cls):
+    """Selection of Alg. 7 / Eq. (21) over chains with minima emin and cosets
+    cls: (E_P[4], P*, best chain)."""
+    emin = np.ascontiguousarray(emin, np.int64)
+    cls = np.ascontiguousarray(cls, np.int32)
+    e_cls = np.zeros(4, np.int64)
+    ps = np.zeros(1, np.int32)
+    bc = np.zeros(1, np.int32)
+    if lib().or_reduce(len(emin), emin, cls, e_cls, _ptr(ps), _ptr(bc)):
+        raise ValueError("or_reduce: class outside 0..3")
+    return e_cls, int(ps[0]), int(bc[0])
+
+
+def class_mul(a, b):
+    """Product of two logical classes (I=0, X=1, Y=2, Z=3)."""
+    return int(lib().or_class_mul(int(a), int(b)))
 
 
 def site_of(u, nstab):

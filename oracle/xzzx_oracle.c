@@ -1114,6 +1114,34 @@ int or_anneal_ladder(const or_lat *L, const int32_t w[4], double beta_lo, double
 /* chain: colour-class sweeps (or_anneal_chain) or the literal random-site    */
 /* steps of Alg. 3 (or_anneal_chain_site).                                    */
 /* ------------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------- */
+/* Selection of the logical class (Alg. 7, last step; Eq. (21)).              */
+/* E_P = least E_min over the chains whose coset is P (INT64_MAX if none);    */
+/* P* = argmin_P E_P, ties to the lower index I < X < Y < Z (reading); the    */
+/* best chain is the lowest-numbered chain of coset P* with E_min = E_P*.     */
+/* Used where a test runs one syndrome's chains one by one on several threads */
+/* and selects afterwards; or_decode makes the same selection as it goes.     */
+/* ------------------------------------------------------------------------- */
+int or_reduce(int n_chains, const int64_t *emin, const int32_t *cls, int64_t e_cls[4], int32_t *p_star,
+              int32_t *best_chain)
+{
+    int64_t best[4] = {INT64_MAX, INT64_MAX, INT64_MAX, INT64_MAX};
+    int bestc[4] = {-1, -1, -1, -1};
+    for (int c = 0; c < n_chains; ++c) {
+        if (cls[c] < 0 || cls[c] > 3) return OR_EINVAL;
+        if (emin[c] < best[cls[c]]) {
+            best[cls[c]] = emin[c];
+            bestc[cls[c]] = c;
+        }
+    }
+    int ps = 0;
+    for (int P = 1; P < 4; ++P) if (best[P] < best[ps]) ps = P;
+    for (int P = 0; P < 4; ++P) e_cls[P] = best[P];
+    *p_star = ps;
+    *best_chain = bestc[ps];
+    return OR_OK;
+}
+
 int or_decode(or_lat *L, const int32_t w[4], const int32_t wg[2], const uint8_t *syn, uint32_t uid,
               int n_rep, const double *beta, int n_sweeps, uint64_t greedy_seed,
               uint64_t anneal_seed, int greedy_mode,

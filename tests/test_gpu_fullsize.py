@@ -1,9 +1,12 @@
 """Parity at the measured workload shapes, in the launch configuration the
 benchmark times (all groups of a workload in one persistent launch, captured
-in a hipGraph where the benchmark uses one).  The oracle recomputes sampled
-syndromes end to end, or sampled chains where a whole syndrome would take it
-minutes; every syndrome of the launch is also checked for properties that hold
-at any size (syndrome-consistent recovery of energy E_best in coset P*)."""
+in a hipGraph).  The oracle decodes the leading syndromes of every group end
+to end -- 200 per p at d = 11, 20 per distance in the mixed launch, 4 at
+d = 31 -- and every chain of those syndromes is compared (E_min, the phase of
+the minimum, final energy), with the references, their classes, E_P, P*, the
+best chain and the recovery.  Every syndrome of the launch is also checked
+for properties that hold at any size (syndrome-consistent recovery of energy
+E_best in coset P*)."""
 import numpy as np
 import pytest
 import torch
@@ -12,7 +15,7 @@ from oracle import oracle as O
 from paper_2509_17837_amd import _lib as X
 from paper_2509_17837_amd import decoder as D
 from paper_2509_17837_amd import inputs
-from tests._parity import pool
+from tests._parity import oracle_decode_by_chain, pool
 
 pytestmark = pytest.mark.gpu
 
@@ -72,10 +75,26 @@ def check_properties(wl, outs, meta):
             assert eb[i] == emin[i].min()
 
 
+def compare_syndrome(o, i, r, tag):
+    assert np.array_equal(o.refs[i].cpu().numpy(), r["refs"]), tag + " refs"
+    assert np.array_equal(o.qcls[i].cpu().numpy(), r["qcls"]), tag + " classes"
+    assert np.array_equal(o.chain_emin[i].cpu().numpy(), r["chain_emin"]), tag + " chain E_min"
+    assert np.array_equal(o.chain_stop[i].cpu().numpy(), r["chain_stop"]), tag + " chain stop"
+    assert np.array_equal(o.chain_e[i].cpu().numpy(), r["chain_e"]), tag + " chain E"
+    assert np.array_equal(o.e_cls[i].cpu().numpy().astype(np.int64), r["e_cls"]), tag + " E_P"
+    assert o.e_best[i].item() == r["e_best"] and o.cls[i].item() == r["cls"], tag + " E_best, P*"
+    assert o.best_chain[i].item() == r["best_chain"], tag + " best chain"
+    assert np.array_equal(o.recovery[i].cpu().numpy(), r["recovery"]), tag + " recovery"
+    if "paper_recovery" in r:
+        assert np.array_equal(o.paper_recovery[i].cpu().numpy(), r["paper_recovery"]), tag + " R_0 L_P*"
+
+
 def oracle_syndromes(wl, seeds, outs, meta, picks):
-    """Full oracle decode of the picked (group, syndrome) pairs."""
+    """Full oracle decode of the picked (group, syndrome) pairs, one syndrome
+    per host thread, the largest lattices first."""
     sched = wl["schedule"]
     beta = O.schedule(inputs.SCHEDULE_KIND[sched[0]], sched[1], sched[2], wl["sweeps"])
+    picks = sorted(picks, key=lambda j: -meta[j[0]]["olat"].nstab)
 
     def one(job):
         gi, i = job
@@ -85,63 +104,45 @@ def oracle_syndromes(wl, seeds, outs, meta, picks):
         return lat.decode(w, wg, m["syn"][i], int(m["uid"][i]), wl["n_rep"], beta, seeds["greedy"],
                           seeds["anneal"], chains=True)
 
+    print(f"[fullsize] oracle on {len(picks)} syndromes", flush=True)
     for (gi, i), r in zip(picks, pool().map(one, picks)):
-        o = outs[gi]
-        tag = f"group {gi} syndrome {i}"
-        assert np.array_equal(o.refs[i].cpu().numpy(), r["refs"]), tag
-        assert np.array_equal(o.chain_emin[i].cpu().numpy(), r["chain_emin"]), tag
-        assert np.array_equal(o.chain_stop[i].cpu().numpy(), r["chain_stop"]), tag
-        assert np.array_equal(o.chain_e[i].cpu().numpy(), r["chain_e"]), tag
-        assert o.e_best[i].item() == r["e_best"] and o.cls[i].item() == r["cls"], tag
-        assert np.array_equal(o.recovery[i].cpu().numpy(), r["recovery"]), tag
-
-
-def oracle_chains(wl, seeds, outs, meta, picks):
-    """Oracle greedy reference and single-chain annealing of picked chains."""
-    sched = wl["schedule"]
-    beta = O.schedule(inputs.SCHEDULE_KIND[sched[0]], sched[1], sched[2], wl["sweeps"])
-
-    def one(job):
-        gi, i, c = job
-        m = meta[gi]
-        lat = O.Lattice(m["layout"], m["d"])
-        w, wg = O.weights(m["p"], O.noise(m["p"], m["eta"], m["conv"]))
-        ref = lat.greedy(wg, m["syn"][i], int(m["uid"][i]), c // 4, seeds["greedy"])
-        res = lat.anneal_chain(w, beta, seeds["anneal"], int(m["uid"][i]), c, ref ^ lat.logical(c % 4),
-                               want_snap=False)
-        return ref, res
-
-    for (gi, i, c), (ref, r) in zip(picks, pool().map(one, picks)):
-        o = outs[gi]
-        tag = f"group {gi} syndrome {i} chain {c}"
-        assert np.array_equal(o.refs[i, c // 4].cpu().numpy(), ref), tag
-        assert o.chain_emin[i, c].item() == r["emin"], tag
-        assert o.chain_stop[i, c].item() == r["stop"], tag
-        assert o.chain_e[i, c].item() == r["e"], tag
+        compare_syndrome(outs[gi], i, r, f"group {gi} syndrome {i}")
 
 
 def test_d11_full_launch():
+    """The headline launch: four p groups of 2048 syndromes (d = 11, 32
+    replicas, 2000 sweeps) captured in one graph; the oracle decodes the
+    first 200 syndromes of every p (800 syndromes, 102400 chains)."""
     wl, seeds, outs, meta = build_launch("d11_bias100", 2048, graph=True)
     check_properties(wl, outs, meta)
-    picks = [(g, i) for g in range(len(outs)) for i in (0, 777, 2047)]
-    oracle_syndromes(wl, seeds, outs, meta, picks)
+    oracle_syndromes(wl, seeds, outs, meta, [(g, i) for g in range(len(outs)) for i in range(200)])
 
 
 def test_mixed_distances_full_launch():
-    wl, seeds, outs, meta = build_launch("mixed_d5_21", 96, graph=True)
+    """One launch of d = 5, 9, 13, 17, 21 (256 syndromes each, 64 replicas,
+    5000 sweeps); the oracle decodes the first 20 syndromes of every
+    distance."""
+    wl, seeds, outs, meta = build_launch("mixed_d5_21", 256, graph=True)
     check_properties(wl, outs, meta)
-    rng = np.random.default_rng(5)
-    picks = [(g, int(rng.integers(96)), int(rng.integers(4 * wl["n_rep"]))) for g in range(len(outs)) for _ in range(4)]
-    oracle_chains(wl, seeds, outs, meta, picks)
-    oracle_syndromes(wl, seeds, outs, meta, [(0, 3), (1, 50)])
+    oracle_syndromes(wl, seeds, outs, meta, [(g, i) for g in range(len(outs)) for i in range(20)])
 
 
 def test_d31_full_launch():
-    wl, seeds, outs, meta = build_launch("d31_large", 2, graph=False)
+    """d = 31, 128 replicas (512 chains), 10^4 sweeps of the geometric
+    schedule 0.02 -> 20 (checkpoints every 313 sweeps), 16 syndromes in one
+    captured launch; the oracle decodes the first 4 syndromes, each one's 512
+    chains spread over the host threads."""
+    wl, seeds, outs, meta = build_launch("d31_large", 16, graph=True)
     check_properties(wl, outs, meta)
-    rng = np.random.default_rng(6)
-    picks = [(int(rng.integers(1)), int(rng.integers(2)), int(rng.integers(4 * wl["n_rep"]))) for _ in range(12)]
-    oracle_chains(wl, seeds, outs, meta, picks)
+    m = meta[0]
+    sched = wl["schedule"]
+    beta = O.schedule(inputs.SCHEDULE_KIND[sched[0]], sched[1], sched[2], wl["sweeps"])
+    w, wg = O.weights(m["p"], O.noise(m["p"], m["eta"], m["conv"]))
+    for i in range(4):
+        print(f"[fullsize] d31 oracle syndrome {i}", flush=True)
+        r = oracle_decode_by_chain(m["layout"], m["d"], w, wg, m["syn"][i], m["uid"][i], wl["n_rep"], beta,
+                                   seeds["greedy"], seeds["anneal"])
+        compare_syndrome(outs[0], i, r, f"d31 syndrome {i}")
 
 
 def test_planar_paper_full_launch():

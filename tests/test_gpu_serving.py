@@ -222,3 +222,60 @@ def test_planar_requests(lanes):
     ref = s.olat.decode(w, wg, s.syn[1], int(s.uid[1]), R, beta, GS, AS)
     r = [x for t, i, x in res if t is s and i == 1][0]
     assert r["e_best"] == ref["e_best"] and np.array_equal(r["recovery"], ref["recovery"])
+
+
+def test_serving_workload_requests_match_oracle():
+    """The serving workload at its real sizes: 200 single-syndrome requests
+    (d in {7, 11, 15, 19, 25} and eta in {1, 10, 1000} drawn per request,
+    p = 0.12, 16 replicas, 1000 sweeps of the geometric schedule 0.05 -> 10)
+    arriving as a Poisson stream at 10^4 per second, so that many are resident
+    at once and join while others run; every served result (E_best, P*, E_P,
+    recovery) equals the oracle's decode of that request."""
+    from paper_2509_17837_amd import inputs as I
+    from tests._parity import pool
+    name = "serving_d7_25"
+    wl = I.WORKLOADS[name]
+    seeds = I.seeds(name)
+    R, sweeps, p = wl["n_rep"], wl["sweeps"], wl["p"][0]
+    specs = [(d, eta) for d in wl["d"] for eta in wl["eta"]]
+    plans = {k: Spec(d, p, eta, sweeps, 1, 900 + k, 0).plan for k, (d, eta) in enumerate(specs)}
+    olats = {d: O.Lattice(O.ROTATED, d) for d in wl["d"]}
+    n = 200
+    rng = np.random.default_rng([seeds["sample"], 12])
+    pick = rng.integers(0, len(specs), size=n)
+    reqs = []
+    for i in range(n):
+        d, eta = specs[pick[i]]
+        err = I.sample_errors(1, d * d, I.channel(p, eta), seeds["sample"], stream=200000 + i)[0]
+        reqs.append((int(pick[i]), olats[d].syndrome(err), 8_000_000 + i))
+    arrivals = I.poisson_arrivals(1e4, n, seeds["sample"] + 5)
+    srv = D.Server(max_slots=256, max_rep=R, max_qubits=625, sweeps_per_slice=400, greedy_seed=seeds["greedy"],
+                   anneal_seed=seeds["anneal"])
+    print(f"[serving] {n} requests of {name} at 1e4/s", flush=True)
+    t0 = time.perf_counter()
+    tickets = []
+    for i, (k, syn, uid) in enumerate(reqs):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        tickets.append(srv.submit(plans[k], syn, uid, R))
+    srv.drain()
+    got = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == n and st["slices"] > 1
+    beta = O.schedule(O.SCHED_GEOMETRIC, 0.05, 10.0, sweeps)
+
+    def oracle(job):
+        k, syn, uid = job
+        d, eta = specs[k]
+        w, wg = O.weights(p, O.noise(p, eta))
+        return O.Lattice(O.ROTATED, d).decode(w, wg, syn, uid, R, beta, seeds["greedy"], seeds["anneal"])
+
+    order = sorted(range(n), key=lambda i: -specs[reqs[i][0]][0])
+    refs = dict(zip(order, pool().map(oracle, [reqs[i] for i in order])))
+    for i in range(n):
+        r, g = refs[i], got[i]
+        tag = f"request {i} (d={specs[reqs[i][0]][0]}, eta={specs[reqs[i][0]][1]})"
+        assert g["e_best"] == r["e_best"] and g["cls"] == r["cls"], tag
+        assert g["e_cls"] == list(r["e_cls"]), tag
+        assert np.array_equal(g["recovery"], r["recovery"]), tag

@@ -543,3 +543,34 @@ def test_decoder_against_exact_minima(layout, d, n_syn):
             assert out["e_cls"][P] >= exact[P]
         hits += out["e_best"] == min(exact)
     assert hits >= n_syn - 1
+
+
+@pytest.mark.parametrize("layout,d,n_rep,mode", [(O.ROTATED, 5, 4, O.GREEDY_RANDOM), (O.PLANAR, 5, 3, O.GREEDY_RANDOM),
+                                                 (O.ROTATED, 7, 2, O.GREEDY_SAME)])
+def test_selection_by_chain_equals_decode(layout, d, n_rep, mode):
+    """Alg. 7's selection (Eq. (21)) run after the chains, as the tests do to
+    spread one large syndrome's chains over host threads, equals the oracle's
+    decode, which selects as it goes: E_P, P*, the best chain and its
+    snapshot.  Also the reading of ties: E_P of an empty coset is the largest
+    value, and P* and the best chain go to the lowest index."""
+    from tests._parity import oracle_decode_by_chain
+    L = O.Lattice(layout, d)
+    p, eta = 0.15, 10.0
+    w, wg = O.weights(p, O.noise(p, eta))
+    beta = O.schedule(O.SCHED_GEOMETRIC, 0.05, 10.0, 30)
+    rng = np.random.default_rng(90 + d)
+    for uid in range(6):
+        _, syn = random_problem(L, p, eta, rng)
+        a = L.decode(w, wg, syn, uid, n_rep, beta, 11, 12, greedy_mode=mode, chains=True)
+        if mode == O.GREEDY_SAME:
+            continue   # the helper draws randomized references
+        b = oracle_decode_by_chain(layout, d, w, wg, syn, uid, n_rep, beta, 11, 12)
+        for k in ("refs", "qcls", "chain_emin", "chain_stop", "chain_e", "e_cls", "recovery"):
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+        for k in ("cls", "e_best", "best_chain"):
+            assert a[k] == b[k], k
+    big = np.iinfo(np.int64).max
+    e_cls, ps, bc = O.reduce(np.array([9, 4, 4, 7, 4]), np.array([0, 1, 3, 1, 1]))
+    assert list(e_cls) == [9, 4, big, 4] and ps == 1 and bc == 1
+    with pytest.raises(ValueError):
+        O.reduce(np.array([1]), np.array([4]))
