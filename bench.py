@@ -33,9 +33,18 @@ sys.path.insert(0, ROOT)
 #   index (1), acceptance compares (2), energy update (1), flip of the two row
 #   words (2) = 9;  total 19.
 OPS_PER_ATTEMPT = 19
-# MI355X int32 vector issue peak: 256 CUs x 128 lane-ops per clock x 2.4 GHz
-# (the rate of its 157.3 TFLOP/s fp32 vector figure, counting an FMA as 2).
+# MI355X int32 vector issue peak from its unit counts and clock: 256 CUs x 4
+# SIMDs x 32 lanes per clock (a wave64 instruction every two clocks) x 2.4 GHz
+# = 78.6 T lane-ops/s, the lane rate of the published 157.3 TFLOP/s fp32
+# vector figure (an FMA counts two).  bench.py --peaks measures it.
 ALU_PEAK_OPS = 256 * 128 * 2.4e9
+# LDS bytes a flip attempt reads in the packed-row kernels specialised to d:
+# the generator's (shape, pattern) -> entry offset lookup (2 B) and the
+# 12 bytes of its (dE, threshold, always-accept) entry.
+LDS_BYTES_PER_ATTEMPT = 14
+# MI355X LDS read peak from its unit counts and clock: 256 CUs x 128 bytes
+# per clock x 2.4 GHz; bench.py --peaks measures it.
+LDS_PEAK_BYTES = 256 * 128 * 2.4e9
 
 
 def kernel_source_sha256(kernel=""):
@@ -63,25 +72,23 @@ def kernel_source_sha256(kernel=""):
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload, batch):
-    """HBM bytes per launch of the annealing kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of known
-    size), or None when the summary is for another kernel source, kernel or
+def profile_values(kernel, workload, batch):
+    """Key = value lines of the committed counter summary of an annealing
+    kernel on a workload (HBM traffic from FETCH_SIZE + WRITE_SIZE
+    calibrated against a copy of known size, LDS bank-conflict cycles per
+    wave-step), or {} when the summary is for another kernel source, kernel or
     workload."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(path):
-        return None
+        return {}
     kv = {}
     for line in open(path):
         if " = " in line:
             k, v = line.split(" = ", 1)
             kv[k.strip()] = v.strip()
-    sha = kernel_source_sha256(kernel)
-    if kv.get("kernel_source_sha256") != sha or kv.get("workload") != f"{workload} batch {batch}":
-        return None
-    return int(kv["traffic_bytes_per_launch"])
+    if kv.get("kernel_source_sha256") != kernel_source_sha256(kernel) or kv.get("workload") != f"{workload} batch {batch}":
+        return {}
+    return kv
 
 
 def parse():
@@ -94,6 +101,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only (no d31_large, mixed_d5_21 and serving lines)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure the int32 VALU issue rate and the LDS read bandwidth (microbenchmarks) and exit")
+    ap.add_argument("--cpu-one-core-seconds", type=float, default=6.0)
     ap.add_argument("--plain-syndromes", type=int, default=32)
     ap.add_argument("--eager", action="store_true", help="no hipGraph capture")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-knob autotuner")
@@ -135,27 +147,89 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_2509_17837_amd import _lib as X
-    from paper_2509_17837_amd import decoder as D
-    from paper_2509_17837_amd import inputs
-
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    if args.peaks:
+        print(json.dumps({"mode": "peaks", **measure_peaks(full=True)}), flush=True)
+        return
     if args.serve:
         return serve_bench(args)
     if args.by_distance:
         return distance_bench(args)
     if args.paper_trends:
         return trends_bench(args)
-    wl = inputs.WORKLOADS[args.workload]
-    seeds = inputs.seeds(args.workload)
+    run = run_batch(args, args.workload, args.batch, args.steps, args.warmup, tune=not args.no_tune,
+                    order=args.order, ladder=args.ladder)
+    wl, R, sweeps = run["wl"], run["R"], run["sweeps"]
+    peaks = measure_peaks()
+    result = {
+        "metric": "stabilizer-flip attempts/s",
+        "value": run["value"],
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": describe(run),
+            "name": args.workload,
+            "step_order": "random-site (Alg. 3)" if args.order == "site" else "colour-class sweeps",
+            "replica_exchange": (f"ladders of {args.ladder.split(',')[0]} levels, beta "
+                                 f"{args.ladder.split(',')[1]} -> {args.ladder.split(',')[2]} (schedule unused)")
+                                if args.ladder else None,
+            "syndromes_per_step": run["syndromes_step"],
+            "attempts_per_step": run["attempts_step"],
+            "graphs": run["graphs"],
+            "autotuned": run["tuned"],
+            "seeds": run["seeds"],
+        },
+        "decodes_per_s": run["decodes"],
+        "stage_ms": run["stage_ms"],
+        "roofline": roofline(run, peaks, args.workload, args.batch),
+        "peaks_measured": peaks,
+        "logical_error_rate": run["ler"],
+    }
+    if not args.no_plain:
+        result["plain_form"] = plain_form(args, run)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(args, run)
+    if not args.no_extras and args.workload == "d11_bias100" and not args.order == "site" and not args.ladder:
+        result["d31_large"] = extra_batch(args, "d31_large", 1024, peaks)
+        result["mixed_d5_21"] = extra_batch(args, "mixed_d5_21", 2048, peaks)
+        result["serving"] = serve_extra(args, peaks)
+    print(json.dumps(result), flush=True)
+
+
+def describe(run):
+    wl, conv = run["wl"], run["conv"]
+    return (f"{wl.get('layout', 'rotated')} XZZX d={','.join(str(d) for d in wl['d'])}, "
+            f"{'p_x:p_y:p_z = 1:eta:1' if conv else 'p_y = p eta/(eta+1)'}, eta={wl['eta']}, p={wl['p']}, "
+            f"{run['R']} replicas ({4 * run['R']} chains)/syndrome, {run['sweeps']} sweeps {wl['schedule'][0]} "
+            f"{wl['schedule'][1]}->{wl['schedule'][2]}")
+
+
+def run_batch(args, name, B, steps, warm, tune=True, order="colour", ladder=""):
+    """Time `steps` decode steps of workload `name` after `warm` untimed ones:
+    one group per (d, p, eta) of B syndromes, all groups in one call, each
+    stage captured in a hipGraph (unless --eager) and launched on torch's
+    current stream; fresh syndromes every step, resident in HBM before the
+    timed region."""
+    import torch
+
+    from paper_2509_17837_amd import _lib as X
+    from paper_2509_17837_amd import decoder as D
+    from paper_2509_17837_amd import inputs
+
+    wl = inputs.WORKLOADS[name]
+    seeds = inputs.seeds(name)
     sched_kind = inputs.SCHEDULE_KIND[wl["schedule"][0]]
     sweeps = wl["sweeps"]
     R = wl["n_rep"]
-    B = args.batch
-    steps, warm = args.steps, args.warmup
     dev = torch.device("cuda:0")
-
-    # ---- plans: one group per (d, p, eta) --------------------------------
     specs = [(d, p, eta) for d in wl["d"] for p in wl["p"] for eta in wl["eta"]]
     layout, conv = inputs.layout_of(wl), inputs.convention_of(wl)
     plans, lats = [], {}
@@ -165,27 +239,24 @@ def main():
             lats[d] = D.Lattice(layout, d)
         w, wg = D.weights(p, D.noise(p, eta, conv))
         plans.append(D.Plan(lats[d], w, wg, beta))
-        if args.order == "site":
+        if order == "site":
             plans[-1].set_order(X.ORDER_RANDOM_SITE)
-        if args.ladder:
-            k, blo, bhi = args.ladder.split(",")
+        if ladder:
+            k, blo, bhi = ladder.split(",")
             plans[-1].set_ladder(int(k), float(blo), float(bhi))
     ng = len(plans)
     tuned = {}
-    if not args.no_tune:
+    if tune:
         for (d, p, eta), plan in zip(specs, plans):
             # probe at the launch's real size (all groups share one launch)
             tuned[f"d{d}_p{p}_eta{eta:g}"] = plan.autotune(R, n_syn=B * ng, probe_sweeps=10)
 
-    # ---- inputs for every step, resident in HBM before timing ------------
     syn_all, uid_all, err_all = [], [], []
     for k in range(steps + warm):
         row_s, row_u, row_e = [], [], []
         for gi, ((d, p, eta), plan) in enumerate(zip(specs, plans)):
-            err = inputs.sample_errors(B, plan.nq, inputs.channel(p, eta, conv), seeds["sample"],
-                                       stream=k * 64 + gi)
-            e_dev = torch.from_numpy(err).to(dev)
-            row_s.append(D.syndrome(plan, e_dev))
+            err = inputs.sample_errors(B, plan.nq, inputs.channel(p, eta, conv), seeds["sample"], stream=k * 64 + gi)
+            row_s.append(D.syndrome(plan, torch.from_numpy(err).to(dev)))
             row_u.append(torch.from_numpy(inputs.sample_uids(B, (k * ng + gi) * B).view(np.int32)).to(dev))
             row_e.append(err)
         syn_all.append(row_s)
@@ -208,7 +279,6 @@ def main():
         cap = torch.cuda.Stream()
         graphs = [D.Graph(groups, gs, as_, X.GREEDY_RANDOM, f, stream=cap, ws=ws) for f in stage_flags]
         torch.cuda.synchronize()
-
     cur = torch.cuda.current_stream()
 
     def run_step(k, ev=None):
@@ -234,26 +304,16 @@ def main():
     for k in range(steps):
         run_step(warm + k, events[k])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
     stage_ms = [float(np.mean([events[k][i].elapsed_time(events[k][i + 1]) for k in range(steps)])) for i in range(3)]
-
-    nstab = [plan.nstab for plan in plans]
-    attempts_step = sum(B * 4 * R * sweeps * ns for ns in nstab)
-    syndromes_step = B * ng
-    value = steps * attempts_step / elapsed
-    decodes = steps * syndromes_step / elapsed
-    anneal_s = stage_ms[1] / 1e3
-    achieved_ops = attempts_step * OPS_PER_ATTEMPT / anneal_s
+    attempts_step = sum(B * 4 * R * sweeps * plan.nstab for plan in plans)
 
     # logical error rate of the last timed batch: [C_true * recovery] != I
     last = warm + steps - 1
     ler = {}
     for g, (d, p, eta) in enumerate(specs):
-        rec = outs[g].recovery.cpu().numpy()
-        err = err_all[last][g]
-        fails = sum(1 for i in range(B) if lats[d].cls(err[i], rec[i]) != 0)
-        ler[f"d{d}_p{p}_eta{eta:g}"] = fails / B
+        fails = logical_failures(lats[d], err_all[last][g], outs[g].recovery.cpu().numpy())
+        ler[f"d{d}_p{p}_eta{eta:g}"] = float(fails.mean())
 
     kinds = {pl.info()["kernel"] for pl in plans}
     if kinds == {X.KERNEL_SITE}:
@@ -264,143 +324,226 @@ def main():
         kernel_name = f"k_anneal_planar_d{wl['d'][0]}"   # planar packed rows specialised to d
     elif kinds == {X.KERNEL_ROWS} and len(set(wl["d"])) == 1 and (4 * R) % 64 == 0:
         kernel_name = f"k_anneal_rows_d{wl['d'][0]}"   # packed rows specialised to d
+    elif kinds == {X.KERNEL_ROWS} and (4 * R) % 64 == 0:
+        kernel_name = "k_anneal_rows_d<D>"   # one specialised launch per distance, run concurrently
     elif kinds <= {X.KERNEL_ROWS, X.KERNEL_ROWS_GENERIC}:
         kernel_name = "k_anneal_rows"
     else:
         kernel_name = "k_anneal"
-    result = {
-        "metric": "stabilizer-flip attempts/s",
-        "value": value,
-        "unit": "attempts/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": warm,
-        "ms_per_step": 1e3 * elapsed / steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{wl.get('layout', 'rotated')} XZZX d={','.join(str(d) for d in wl['d'])}, "
-                        f"{'p_x:p_y:p_z = 1:eta:1' if conv else 'p_y = p eta/(eta+1)'}, eta={wl['eta']}, p={wl['p']}, "
-                        f"{R} replicas ({4 * R} chains)/syndrome, {sweeps} sweeps {wl['schedule'][0]} "
-                        f"{wl['schedule'][1]}->{wl['schedule'][2]}",
-            "name": args.workload,
-            "step_order": "random-site (Alg. 3)" if args.order == "site" else "colour-class sweeps",
-            "replica_exchange": (f"ladders of {args.ladder.split(',')[0]} levels, beta "
-                                 f"{args.ladder.split(',')[1]} -> {args.ladder.split(',')[2]} (schedule unused)")
-                                if args.ladder else None,
-            "syndromes_per_step": syndromes_step,
-            "attempts_per_step": attempts_step,
-            "graphs": graphs is not None,
-            "autotuned": tuned,
-            "seeds": seeds,
-        },
-        "decodes_per_s": decodes,
-        "stage_ms": {"greedy": stage_ms[0], "anneal": stage_ms[1], "finish": stage_ms[2]},
-        "roofline": {
-            "bound": "alu",
-            "kernel": kernel_name,
-            "achieved": achieved_ops / 1e12,
-            "peak": ALU_PEAK_OPS / 1e12,
-            "unit": "Tops/s (int32 lane-ops)",
-            "frac": achieved_ops / ALU_PEAK_OPS,
-            "traffic": measured_traffic(kernel_name, args.workload, B),
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "ops_per_attempt": OPS_PER_ATTEMPT,
-            "anneal_ms_per_launch": stage_ms[1],
-        },
-        "logical_error_rate": ler,
+    return dict(wl=wl, seeds=seeds, specs=specs, plans=plans, lats=lats, layout=layout, conv=conv, R=R,
+                sweeps=sweeps, B=B, ng=ng, tuned=tuned, graphs=graphs is not None, stage_ms=dict(
+                    greedy=stage_ms[0], anneal=stage_ms[1], finish=stage_ms[2]),
+                anneal_s=stage_ms[1] / 1e3, attempts_step=attempts_step, syndromes_step=B * ng,
+                value=steps * attempts_step / elapsed, decodes=steps * B * ng / elapsed,
+                ms_per_step=1e3 * elapsed / steps, ler=ler, kernel=kernel_name, outs=outs,
+                syn_last=syn_all[last], uid_last=uid_all[last], gs=gs, as_=as_, order=order, ladder=ladder)
+
+
+def measure_peaks(full=False):
+    """The two device limits, measured by the library's microbenchmarks: int32
+    VALU lane-ops/s (v_xor_b32, v_add_u32, v_bitop3_b32; v_mad_u64_u32 apart)
+    and conflict-free LDS read bytes/s, with eight wavefronts per SIMD (and
+    four, with full)."""
+    from paper_2509_17837_amd import decoder as D
+
+    out = {}
+    waves = (8, 4) if full else (8,)
+    for wv in waves:
+        sfx = "" if wv == 8 else f"_w{wv}"
+        simple = [D.probe_valu(k, wv, 4000) for k in (0, 1, 2)]
+        out["valu_xor_ops" + sfx] = simple[0]
+        out["valu_add_ops" + sfx] = simple[1]
+        out["valu_bitop3_ops" + sfx] = simple[2]
+        out["valu_mad_u64_ops" + sfx] = D.probe_valu(3, wv, 2000)
+        for b in ((4, 8, 16) if full else (16,)):
+            out[f"lds_b{8 * b}_bytes" + sfx] = D.probe_lds(b, wv, 4000)
+    out["valu_simple_ops"] = max(out["valu_xor_ops"], out["valu_add_ops"], out["valu_bitop3_ops"])
+    out["lds_bytes"] = out["lds_b128_bytes"]
+    out["note"] = ("lane-ops/s and bytes/s over all CUs at the clock the device ran; peaks from unit counts: "
+                   f"VALU {ALU_PEAK_OPS:.4g} lane-ops/s, LDS {LDS_PEAK_BYTES:.4g} B/s")
+    return out
+
+
+def roofline(run, peaks, workload, batch):
+    """The annealing kernel against both limits that can bind it: int32 VALU
+    issue (19 algorithmic lane-ops per attempt) and LDS reads (14 bytes per
+    attempt), each against the peak from unit counts and clock and against the
+    measured one; `bound` names the side with the larger fraction."""
+    attempts, t = run["attempts_step"], run["anneal_s"]
+    alu = OPS_PER_ATTEMPT * attempts / t
+    lds = LDS_BYTES_PER_ATTEMPT * attempts / t
+    kv = profile_values(run["kernel"], workload, batch)
+    traffic = int(kv["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in kv else None
+    sides = {
+        "alu": {"achieved": alu / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (int32 lane-ops)",
+                "frac": alu / ALU_PEAK_OPS, "peak_measured": peaks["valu_simple_ops"] / 1e12,
+                "frac_of_measured": alu / peaks["valu_simple_ops"], "ops_per_attempt": OPS_PER_ATTEMPT},
+        "lds": {"achieved": lds / 1e12, "peak": LDS_PEAK_BYTES / 1e12, "unit": "TB/s (LDS reads)",
+                "frac": lds / LDS_PEAK_BYTES, "peak_measured": peaks["lds_bytes"] / 1e12,
+                "frac_of_measured": lds / peaks["lds_bytes"], "bytes_per_attempt": LDS_BYTES_PER_ATTEMPT,
+                "bank_conflict_cycles_per_wave_step": (float(kv["lds_bank_conflict_cycles_per_wave_step"])
+                                                       if "lds_bank_conflict_cycles_per_wave_step" in kv else None)},
     }
-
-    if not args.no_plain:
-        # plain form: one annealing launch per syndrome (no persistence, no graph)
-        g0 = 0
-        n = min(args.plain_syndromes, B)
-        pg, po = D.make_group(plans[g0], R, uid_all[last][g0][:n].contiguous(), syn=syn_all[last][g0][:n].contiguous(),
-                              want_extra=False)
-        pws = D.workspace([pg])
-        D.decode_groups([pg], gs, as_, X.GREEDY_RANDOM, X.STAGE_GREEDY, ws=pws)
-        torch.cuda.synchronize()
-        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ea.record(cur)
-        D.decode_groups([pg], gs, as_, X.GREEDY_RANDOM, X.STAGE_ANNEAL | X.FLAG_PLAIN, ws=pws)
-        eb.record(cur)
-        torch.cuda.synchronize()
-        plain_s = ea.elapsed_time(eb) / 1e3
-        D.decode_groups([pg], gs, as_, X.GREEDY_RANDOM, X.STAGE_FINISH, ws=pws)
-        torch.cuda.synchronize()
-        same = bool(torch.equal(po.recovery, outs[g0].recovery[:n]) and torch.equal(po.e_best, outs[g0].e_best[:n]))
-        plain_rate = n * 4 * R * sweeps * nstab[g0] / plain_s
-        result["plain_form"] = {
-            "value": plain_rate, "unit": "attempts/s", "syndromes": n,
-            "batched_over_plain": (attempts_step / anneal_s) / plain_rate,
-            "same_results_as_batched": same,
-        }
-
-    if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(args, wl, specs, plans, syn_all[last], uid_all[last], outs,
-                                              R, sweeps, gs, as_)
-    print(json.dumps(result), flush=True)
+    bound = "alu" if sides["alu"]["frac"] >= sides["lds"]["frac"] else "lds"
+    top = sides[bound]
+    return {"bound": bound, "kernel": run["kernel"], "achieved": top["achieved"], "peak": top["peak"],
+            "unit": top["unit"], "frac": top["frac"], "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "anneal_ms_per_launch": 1e3 * t, "alu": sides["alu"], "lds": sides["lds"]}
 
 
-def cpu_baseline(args, wl, specs, plans, syn0, uid0, outs, R, sweeps, gs, as_):
-    """Time the oracle (plain C, one thread per syndrome) on a bounded sample
-    of the last timed batch, and check the sample against the GPU results."""
+def plain_form(args, run):
+    """One annealing launch per syndrome (no persistence, no graph) on the
+    first syndromes of the last timed batch; same results required."""
+    import torch
+
+    from paper_2509_17837_amd import _lib as X
+    from paper_2509_17837_amd import decoder as D
+
+    n = min(args.plain_syndromes, run["B"])
+    R, gs, as_ = run["R"], run["gs"], run["as_"]
+    pg, po = D.make_group(run["plans"][0], R, run["uid_last"][0][:n].contiguous(),
+                          syn=run["syn_last"][0][:n].contiguous(), want_extra=False)
+    pws = D.workspace([pg])
+    D.decode_groups([pg], gs, as_, X.GREEDY_RANDOM, X.STAGE_GREEDY, ws=pws)
+    torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ea.record(cur)
+    D.decode_groups([pg], gs, as_, X.GREEDY_RANDOM, X.STAGE_ANNEAL | X.FLAG_PLAIN, ws=pws)
+    eb.record(cur)
+    torch.cuda.synchronize()
+    plain_s = ea.elapsed_time(eb) / 1e3
+    D.decode_groups([pg], gs, as_, X.GREEDY_RANDOM, X.STAGE_FINISH, ws=pws)
+    torch.cuda.synchronize()
+    o0 = run["outs"][0]
+    same = bool(torch.equal(po.recovery, o0.recovery[:n]) and torch.equal(po.e_best, o0.e_best[:n]))
+    rate = n * 4 * R * run["sweeps"] * run["plans"][0].nstab / plain_s
+    return {"value": rate, "unit": "attempts/s", "syndromes": n,
+            "batched_over_plain": (run["attempts_step"] / run["anneal_s"]) / rate, "same_results_as_batched": same}
+
+
+def host_cpu():
+    """(usable threads, model name) of the host."""
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return threads, model
+
+
+def cpu_baseline(args, run):
+    """Time the oracle (plain C, one syndrome per thread) on bounded samples
+    of the last timed batch: on every usable host thread, and on one; the
+    samples are checked against the GPU results."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle as O
-
-    threads = max(1, min(16, os.cpu_count() or 1))
-    ng = len(specs)
-    sched = wl["schedule"]
-    obeta = O.schedule({"linear": 0, "geometric": 1, "paper_log": 2}[sched[0]], sched[1], sched[2], sweeps)
     from paper_2509_17837_amd import inputs
 
-    layout, conv = inputs.layout_of(wl), inputs.convention_of(wl)
-    owts = [O.weights(p, O.noise(p, eta, conv)) for (_, p, eta) in specs]
-    syn = [s.cpu().numpy() for s in syn0]
-    uid = [u.cpu().numpy().view(np.uint32) for u in uid0]
+    threads, model = host_cpu()
+    wl, specs, plans, R, sweeps = run["wl"], run["specs"], run["plans"], run["R"], run["sweeps"]
+    ng = len(specs)
+    sched = wl["schedule"]
+    obeta = O.schedule(inputs.SCHEDULE_KIND[sched[0]], sched[1], sched[2], sweeps)
+    owts = [O.weights(p, O.noise(p, eta, run["conv"])) for (_, p, eta) in specs]
+    syn = [s.cpu().numpy() for s in run["syn_last"]]
+    uid = [u.cpu().numpy().view(np.uint32) for u in run["uid_last"]]
+    outs = run["outs"]
 
     def one(job):
         g, i = job
-        d = specs[g][0]
-        lat = O.Lattice(layout, d)
-        if args.ladder:
-            k, blo, bhi = args.ladder.split(",")
-            return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, gs, as_,
+        lat = O.Lattice(run["layout"], specs[g][0])
+        if run["ladder"]:
+            k, blo, bhi = run["ladder"].split(",")
+            return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, run["gs"], run["as_"],
                               order=O.ORDER_LADDER, ladder=(int(k), float(blo), float(bhi)))
-        return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, gs, as_,
-                          order=O.ORDER_RANDOM_SITE if args.order == "site" else O.ORDER_COLOUR)
+        return lat.decode(owts[g][0], owts[g][1], syn[g][i], int(uid[g][i]), R, obeta, run["gs"], run["as_"],
+                          order=O.ORDER_RANDOM_SITE if run["order"] == "site" else O.ORDER_COLOUR)
 
-    # size the sample from one timed syndrome
+    def check(jobs, res):
+        ok = 0
+        for (g, i), r in zip(jobs, res):
+            ok += int(outs[g].e_best[i].item() == r["e_best"] and outs[g].cls[i].item() == r["cls"] and
+                      np.array_equal(outs[g].recovery[i].cpu().numpy(), r["recovery"]))
+        return ok
+
+    # one core: syndromes in turn until the time is spent
+    jobs1, res1 = [], []
     t = time.perf_counter()
-    one((0, 0))
-    per = time.perf_counter() - t
+    while time.perf_counter() - t < args.cpu_one_core_seconds or not jobs1:
+        job = (len(jobs1) % ng, len(jobs1) // ng)
+        jobs1.append(job)
+        res1.append(one(job))
+    wall1 = time.perf_counter() - t
+    per = wall1 / len(jobs1)
+    # every thread: a sample sized to about --cpu-seconds
     n = max(threads, int(args.cpu_seconds * threads / max(per, 1e-6)))
     n = min(n, 4 * len(syn[0]))
-    jobs = [(i % ng, i // ng) for i in range(n)]
+    jobs = [((i + len(jobs1)) % ng, (i + len(jobs1)) // ng) for i in range(n)]
     t = time.perf_counter()
     with ThreadPoolExecutor(threads) as ex:
         res = list(ex.map(one, jobs))
     wall = time.perf_counter() - t
     attempts = sum(4 * R * sweeps * plans[g].nstab for g, _ in jobs)
-    out = {
+    attempts1 = sum(4 * R * sweeps * plans[g].nstab for g, _ in jobs1)
+    return {
         "value": attempts / wall,
         "unit": "attempts/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"{n} syndromes of the last timed batch (groups round-robin), full decode "
-                  f"({R} replicas, {sweeps} sweeps), {wall:.1f} s wall",
+                  f"({R} replicas, {sweeps} sweeps), {wall:.1f} s wall on {threads} threads; "
+                  f"{len(jobs1)} more on one thread, {wall1:.1f} s",
         "decodes_per_s": n / wall,
+        "one_core": {"value": attempts1 / wall1, "decodes_per_s": len(jobs1) / wall1},
+        "host": {"threads": threads, "nproc": os.cpu_count(), "model": model},
+        "bitexact_with_gpu": f"{check(jobs, res) + check(jobs1, res1)}/{n + len(jobs1)}",
     }
-    ok = 0
-    for (g, i), r in zip(jobs, res):
-        ok += int(outs[g].e_best[i].item() == r["e_best"] and outs[g].cls[i].item() == r["cls"] and
-                  np.array_equal(outs[g].recovery[i].cpu().numpy(), r["recovery"]))
-    out["bitexact_with_gpu"] = f"{ok}/{n}"
-    return out
+
+
+def extra_batch(args, name, batch, peaks):
+    """Another workload of the metric in the headline's launch configuration
+    (one step after a warm-up; no autotuning, every group on its plan's
+    default kernel), with its roofline and the oracle's decode of one
+    syndrome per group (its chains spread over the host threads) compared
+    bit for bit."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as O
+    from paper_2509_17837_amd import inputs
+
+    run = run_batch(args, name, batch, 2, 1, tune=False)
+    rl = roofline(run, peaks, name, batch)
+    wl, specs = run["wl"], run["specs"]
+    sched = wl["schedule"]
+    obeta = O.schedule(inputs.SCHEDULE_KIND[sched[0]], sched[1], sched[2], run["sweeps"])
+    threads, _ = host_cpu()
+    ok, t0 = 0, time.perf_counter()
+    with ThreadPoolExecutor(threads) as pool:
+        for g, (d, p, eta) in enumerate(specs):
+            w, wg = O.weights(p, O.noise(p, eta, run["conv"]))
+            syn = run["syn_last"][g][0].cpu().numpy()
+            uid = int(run["uid_last"][g][0].cpu().numpy().view(np.uint32))
+            r = O.decode_by_chain(run["layout"], d, w, wg, syn, uid, run["R"], obeta, run["gs"], run["as_"], pool)
+            o = run["outs"][g]
+            ok += int(o.e_best[0].item() == r["e_best"] and o.cls[0].item() == r["cls"] and
+                      np.array_equal(o.recovery[0].cpu().numpy(), r["recovery"]))
+    print(f"[bench] {name}: {run['value']:.4g} attempts/s, oracle check {ok}/{len(specs)} "
+          f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    return {"value": run["value"], "unit": "attempts/s", "decodes_per_s": run["decodes"], "steps": 2, "warmup": 1,
+            "ms_per_step": run["ms_per_step"], "workload": describe(run), "syndromes_per_step": run["syndromes_step"],
+            "stage_ms": run["stage_ms"], "roofline": rl, "logical_error_rate": run["ler"],
+            "oracle_bitexact": f"{ok}/{len(specs)} syndromes (first of each group of the last step: "
+                               "E_best, P*, recovery)"}
 
 
 def distance_bench(args):
@@ -566,11 +709,9 @@ def trends_bench(args):
     print(json.dumps(out), flush=True)
 
 
-def serve_bench(args):
-    """Serving loop under Poisson arrivals: requests of the serving workload
-    (d and eta drawn uniformly per request) are submitted at their arrival
-    times while earlier ones run; reports p50/p99 latency and throughput per
-    arrival rate."""
+def serve_setup(args):
+    """Plans and pre-sampled requests of the serving workload (d and eta drawn
+    uniformly per request, syndromes computed by the library's kernel)."""
     import torch
 
     from paper_2509_17837_amd import _lib as X
@@ -590,11 +731,8 @@ def serve_bench(args):
         if d not in lats:
             lats[d] = D.Lattice(X.ROTATED, d)
         w, wg = D.weights(p, D.noise(p, eta))
-        plan = D.Plan(lats[d], w, wg, beta)
-        plans.append(plan)
-    rates = [float(x) for x in args.rates.split(",")]
+        plans.append(D.Plan(lats[d], w, wg, beta))
     n = max(int(args.requests), 1)
-    # requests: spec index, syndrome, uid (seeded), sampled ahead of time
     rng = np.random.default_rng([seeds["sample"], 11])
     pick = rng.integers(0, len(specs), size=n)
     reqs = []
@@ -602,45 +740,114 @@ def serve_bench(args):
         d, eta = specs[pick[i]]
         err = inputs.sample_errors(1, d * d, inputs.channel(p, eta), seeds["sample"], stream=100000 + i)[0]
         reqs.append((int(pick[i]), err))
-    # syndromes through the library's own kernel (untimed setup)
-    syns = []
-    for k, err in reqs:
-        syns.append(D.syndrome(plans[k], torch.from_numpy(err[None]).cuda())[0].cpu().numpy())
+    syns = [None] * n
+    for k in range(len(specs)):   # one syndrome launch per (d, eta)
+        idx = [i for i in range(n) if reqs[i][0] == k]
+        if idx:
+            s = D.syndrome(plans[k], torch.from_numpy(np.stack([reqs[i][1] for i in idx])).cuda()).cpu().numpy()
+            for j, i in enumerate(idx):
+                syns[i] = s[j]
     torch.cuda.synchronize()
-    attempts_per_req = [4 * R * wl["sweeps"] * plans[k].nstab for k, _ in reqs]
-    out = []
-    for rate in rates:
-        n_rate = max(1, min(n, int(rate * args.serve_seconds)))
-        arr = inputs.poisson_arrivals(rate, n_rate, seeds["sample"] + int(rate))
-        srv = D.Server(max_slots=args.slots, max_rep=R, max_qubits=max(d * d for d in wl["d"]),
-                       sweeps_per_slice=args.slice, greedy_seed=seeds["greedy"], anneal_seed=seeds["anneal"],
-                       max_lanes_per_chain=args.lanes, max_waves=args.waves)
-        t0 = time.perf_counter()
-        tickets = []
-        for i, (k, _) in enumerate(reqs[:n_rate]):
-            while True:
-                now = time.perf_counter() - t0
-                if now >= arr[i]:
-                    break
-                if arr[i] - now > 2e-4:
-                    time.sleep((arr[i] - now) * 0.5)
-            tickets.append(srv.submit(plans[k], syns[i], 7_000_000 + i, R))
-        srv.drain()
-        wall = time.perf_counter() - t0
-        st = srv.stats()
-        for t in tickets:
-            srv.poll(t)
-        srv.close()
-        out.append({
-            "rate_per_s": rate, "requests": n_rate,
-            "p50_latency_ms": 1e3 * st["p50_latency_s"], "p99_latency_ms": 1e3 * st["p99_latency_s"],
-            "mean_latency_ms": 1e3 * st["mean_latency_s"],
-            "decodes_per_s": st["decodes_per_s"], "attempts_per_s": st["attempts_per_s"],
-            "offered_attempts_per_s": rate * float(np.mean(attempts_per_req[:n_rate])),
-            "slices": st["slices"], "wall_s": wall,
-        })
-        print(f"[serve] rate {rate:g}/s: p50 {out[-1]['p50_latency_ms']:.2f} ms, p99 "
-              f"{out[-1]['p99_latency_ms']:.2f} ms, {st['decodes_per_s']:.0f} decodes/s", file=sys.stderr, flush=True)
+    attempts = [4 * R * wl["sweeps"] * plans[k].nstab for k, _ in reqs]
+    return dict(name=name, wl=wl, seeds=seeds, R=R, specs=specs, plans=plans, p=p, reqs=reqs, syns=syns,
+                attempts=attempts)
+
+
+def serve_rate(args, S, rate, seconds, keep=()):
+    """Poisson arrivals at `rate` over `seconds` (at most --requests requests)
+    submitted while earlier ones run; returns the server's statistics and the
+    results of the requests listed in `keep`."""
+    from paper_2509_17837_amd import decoder as D
+    from paper_2509_17837_amd import inputs
+
+    n_rate = max(1, min(len(S["reqs"]), int(rate * seconds)))
+    arr = inputs.poisson_arrivals(rate, n_rate, S["seeds"]["sample"] + int(rate))
+    srv = D.Server(max_slots=args.slots, max_rep=S["R"], max_qubits=max(d * d for d in S["wl"]["d"]),
+                   sweeps_per_slice=args.slice, greedy_seed=S["seeds"]["greedy"], anneal_seed=S["seeds"]["anneal"],
+                   max_lanes_per_chain=args.lanes, max_waves=args.waves)
+    t0 = time.perf_counter()
+    tickets = []
+    for i, (k, _) in enumerate(S["reqs"][:n_rate]):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= arr[i]:
+                break
+            if arr[i] - now > 2e-4:
+                time.sleep((arr[i] - now) * 0.5)
+        tickets.append(srv.submit(S["plans"][k], S["syns"][i], 7_000_000 + i, S["R"]))
+    srv.drain()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    kept = {}
+    for i, t in enumerate(tickets):
+        r = srv.poll(t)
+        if i in keep:
+            kept[i] = r
+    srv.close()
+    row = {"rate_per_s": rate, "requests": n_rate,
+           "p50_latency_ms": 1e3 * st["p50_latency_s"], "p99_latency_ms": 1e3 * st["p99_latency_s"],
+           "mean_latency_ms": 1e3 * st["mean_latency_s"],
+           "decodes_per_s": st["decodes_per_s"], "attempts_per_s": st["attempts_per_s"],
+           "offered_attempts_per_s": rate * float(np.mean(S["attempts"][:n_rate])),
+           "slices": st["slices"], "wall_s": wall}
+    print(f"[serve] rate {rate:g}/s: p50 {row['p50_latency_ms']:.2f} ms, p99 {row['p99_latency_ms']:.2f} ms, "
+          f"{st['decodes_per_s']:.0f} decodes/s", file=sys.stderr, flush=True)
+    return row, kept
+
+
+def serve_extra(args, peaks):
+    """The serving workload's latency and throughput for the headline line:
+    p50/p99 at 10^3 and 10^4 requests/s, and the saturation rate under
+    10^5 requests/s offered; 24 requests of the 10^4 run compared bit for bit
+    with the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as O
+
+    S = serve_setup(args)
+    keep = tuple(range(0, 2400, 100))
+    rows = {}
+    for rate in (1e3, 1e4, 1e5):
+        rows[rate], kept = serve_rate(args, S, rate, 2.0, keep if rate == 1e4 else ())
+        if rate == 1e4:
+            check = kept
+    p, R, wl, seeds = S["p"], S["R"], S["wl"], S["seeds"]
+    beta = O.schedule(O.SCHED_GEOMETRIC, wl["schedule"][1], wl["schedule"][2], wl["sweeps"])
+
+    def oracle(i):
+        k, _ = S["reqs"][i]
+        d, eta = S["specs"][k]
+        w, wg = O.weights(p, O.noise(p, eta))
+        return O.Lattice(O.ROTATED, d).decode(w, wg, S["syns"][i], 7_000_000 + i, R, beta, seeds["greedy"],
+                                              seeds["anneal"])
+
+    threads, _ = host_cpu()
+    with ThreadPoolExecutor(threads) as pool:
+        refs = dict(zip(check, pool.map(oracle, list(check))))
+    ok = sum(int(check[i]["e_best"] == refs[i]["e_best"] and check[i]["cls"] == refs[i]["cls"] and
+                 np.array_equal(check[i]["recovery"], refs[i]["recovery"])) for i in check)
+    sat = rows[1e5]
+    return {
+        "workload": (f"single-syndrome requests, rotated XZZX d in {wl['d']}, eta in {wl['eta']}, p={p}, {R} replicas, "
+                     f"{wl['sweeps']} sweeps geometric 0.05->10, Poisson arrivals"),
+        "p50_ms_at_1e3": rows[1e3]["p50_latency_ms"], "p99_ms_at_1e3": rows[1e3]["p99_latency_ms"],
+        "p50_ms_at_1e4": rows[1e4]["p50_latency_ms"], "p99_ms_at_1e4": rows[1e4]["p99_latency_ms"],
+        "saturation_decodes_per_s": sat["decodes_per_s"], "saturation_attempts_per_s": sat["attempts_per_s"],
+        "saturation_alu_frac": sat["attempts_per_s"] * OPS_PER_ATTEMPT / ALU_PEAK_OPS,
+        "rates": list(rows.values()),
+        "sweeps_per_slice": args.slice, "max_slots": args.slots,
+        "oracle_bitexact": f"{ok}/{len(check)} requests of the 10^4/s run (E_best, P*, recovery)",
+    }
+
+
+def serve_bench(args):
+    """Serving loop under Poisson arrivals: requests of the serving workload
+    (d and eta drawn uniformly per request) are submitted at their arrival
+    times while earlier ones run; reports p50/p99 latency and throughput per
+    arrival rate."""
+    S = serve_setup(args)
+    out = [serve_rate(args, S, float(rate), args.serve_seconds)[0] for rate in args.rates.split(",")]
+    wl, R = S["wl"], S["R"]
     result = {
         "metric": "decode latency p50/p99 (serving, continuous batching)",
         "value": out[0]["p99_latency_ms"],
@@ -650,10 +857,10 @@ def serve_bench(args):
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"single-syndrome requests, rotated XZZX d in {wl['d']}, eta in {wl['eta']}, "
-                               f"p={p}, {R} replicas, {wl['sweeps']} sweeps geometric 0.05->10, Poisson arrivals",
-                   "name": name, "sweeps_per_slice": args.slice, "max_slots": args.slots,
+                               f"p={S['p']}, {R} replicas, {wl['sweeps']} sweeps geometric 0.05->10, Poisson arrivals",
+                   "name": S["name"], "sweeps_per_slice": args.slice, "max_slots": args.slots,
                    "max_lanes_per_chain": args.lanes,
-                   "max_waves": args.waves, "seeds": seeds},
+                   "max_waves": args.waves, "seeds": S["seeds"]},
         "rates": out,
     }
     print(json.dumps(result), flush=True)

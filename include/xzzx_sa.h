@@ -354,6 +354,21 @@ int xzzx_graph_create(const xzzx_group *groups, int n_groups, uint64_t greedy_se
 int xzzx_graph_launch(xzzx_graph *graph, void *stream);
 void xzzx_graph_destroy(xzzx_graph *graph);
 
+/* ---- device limits (roofline peaks) ---------------------------------------- */
+
+/* Microbenchmarks of the two limits the annealing kernels are measured
+ * against, on the current device.  xzzx_probe_valu: int32 vector lane
+ * operations per second of one instruction kind (0 v_xor_b32, 1 v_add_u32,
+ * 2 v_bitop3_b32, 3 v_mad_u64_u32) issued by waves_per_simd (1..8) wavefronts
+ * per SIMD on every CU, eight independent dependency chains per lane.
+ * xzzx_probe_lds: LDS bytes read per second with conflict-free reads of
+ * bytes_per_read (4, 8 or 16) bytes per lane.  iters (1..2^20) loop trips of
+ * 128 operations (16 reads); best of 5 timed launches after a warm-up.  Each
+ * call allocates and frees a small device buffer and synchronizes `stream`.
+ * EINVAL for arguments out of range. */
+int xzzx_probe_valu(int kind, int waves_per_simd, int iters, void *stream, double *lane_ops_per_s);
+int xzzx_probe_lds(int bytes_per_read, int waves_per_simd, int iters, void *stream, double *bytes_per_s);
+
 /* ---- serving loop (continuous batching) ------------------------------------ */
 
 /* A server decodes single-syndrome requests as they arrive.  A scheduler

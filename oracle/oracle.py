@@ -162,6 +162,39 @@ def reduce(emin, cls):
     return e_cls, int(ps[0]), int(bc[0])
 
 
+def decode_by_chain(layout, d, w, wg, syn, uid, n_rep, beta, greedy_seed, anneal_seed, pool):
+    """The oracle's decode of one syndrome (Alg. 7) assembled from its own
+    steps, so that one large syndrome's chains run on the threads of `pool`
+    (a concurrent.futures executor): the greedy reference of each replica
+    (Alg. 6), its class relative to replica 0, every chain from R_r L_P
+    (Algs. 2-3), then the selection of Eq. (21) (reduce).  Same fields as
+    Lattice.decode(chains=True) without the final states and R_0 L_P*."""
+    import threading
+    local = threading.local()
+
+    def lattice():
+        if getattr(local, "lat", None) is None:
+            local.lat = Lattice(layout, d)
+        return local.lat
+
+    uid = int(uid)
+    refs = np.stack(list(pool.map(lambda r: lattice().greedy(wg, syn, uid, r, greedy_seed), range(n_rep))))
+    lat = Lattice(layout, d)
+    qcls = np.array([lat.cls(refs[r], refs[0]) for r in range(n_rep)], np.int32)
+
+    def chain(c):
+        L = lattice()
+        return L.anneal_chain(w, beta, anneal_seed, uid, c, refs[c // 4] ^ L.logical(c % 4))
+
+    res = list(pool.map(chain, range(4 * n_rep)))
+    emin = np.array([r["emin"] for r in res], np.int64)
+    cls = np.array([class_mul(qcls[c // 4], c % 4) for c in range(4 * n_rep)], np.int32)
+    e_cls, ps, bc = reduce(emin, cls)
+    return dict(refs=refs, qcls=qcls, chain_emin=emin, chain_stop=np.array([r["stop"] for r in res], np.int32),
+                chain_e=np.array([r["e"] for r in res], np.int64), e_cls=e_cls, cls=ps, e_best=int(e_cls[ps]),
+                best_chain=bc, recovery=res[bc]["snap"])
+
+
 def class_mul(a, b):
     """Product of two logical classes (I=0, X=1, Y=2, Z=3)."""
     return int(lib().or_class_mul(int(a), int(b)))

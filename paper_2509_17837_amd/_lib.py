@@ -156,6 +156,8 @@ def lib():
         "xzzx_graph_create": (I, [P(Group), I, U64, U64, I, I, V, C.c_size_t, V, P(V)]),
         "xzzx_graph_launch": (I, [V, V]),
         "xzzx_graph_destroy": (None, [V]),
+        "xzzx_probe_valu": (I, [I, I, I, V, P(D)]),
+        "xzzx_probe_lds": (I, [I, I, I, V, P(D)]),
         "xzzx_server_create": (I, [P(ServerCfg), P(V)]),
         "xzzx_server_submit": (I, [V, P(Request), P(U64)]),
         "xzzx_server_poll": (I, [V, U64, P(Result)]),

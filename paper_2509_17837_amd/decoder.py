@@ -77,6 +77,21 @@ def schedule(kind, b0, b1, n):
     return beta[:n]
 
 
+def probe_valu(kind, waves_per_simd=8, iters=2000, stream=None):
+    """Measured int32 lane-ops/s of one VALU instruction kind (0 xor, 1 add,
+    2 bitop3, 3 mad_u64_u32) on every CU."""
+    out = C.c_double()
+    call("xzzx_probe_valu", kind, waves_per_simd, iters, _stream(stream), C.byref(out))
+    return out.value
+
+
+def probe_lds(bytes_per_read=16, waves_per_simd=8, iters=2000, stream=None):
+    """Measured LDS read bytes/s (conflict-free reads of bytes_per_read)."""
+    out = C.c_double()
+    call("xzzx_probe_lds", bytes_per_read, waves_per_simd, iters, _stream(stream), C.byref(out))
+    return out.value
+
+
 class Lattice:
     def __init__(self, layout, d):
         h = C.c_void_p()

@@ -4,7 +4,6 @@ and compare element by element."""
 from __future__ import annotations
 
 import os
-import threading
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -63,43 +62,9 @@ class Problem:
         return lat.greedy(self.wg, self.syn[i], int(self.uid[i]), r, self.greedy_seed, mode)
 
 
-_LOCAL = threading.local()
-
-
-def _lattice(layout, d):
-    """A per-thread oracle lattice handle (greedy tables are cached per handle)."""
-    cache = getattr(_LOCAL, "lats", None)
-    if cache is None:
-        cache = _LOCAL.lats = {}
-    if (layout, d) not in cache:
-        cache[(layout, d)] = O.Lattice(layout, d)
-    return cache[(layout, d)]
-
-
 def oracle_decode_by_chain(layout, d, w, wg, syn, uid, n_rep, beta, greedy_seed, anneal_seed):
-    """The oracle's decode of one syndrome (Alg. 7) assembled from its own
-    steps, so that one large syndrome's chains run on every host thread: the
-    greedy reference of each replica (Alg. 6), its class relative to replica
-    0, every chain from R_r L_P (Algs. 2-3), then the selection of Eq. (21)
-    (oracle.reduce).  Same fields as Lattice.decode(chains=True) without the
-    final states and R_0 L_P*."""
-    uid = int(uid)
-    refs = np.stack(list(pool().map(lambda r: _lattice(layout, d).greedy(wg, syn, uid, r, greedy_seed),
-                                    range(n_rep))))
-    lat = _lattice(layout, d)
-    qcls = np.array([lat.cls(refs[r], refs[0]) for r in range(n_rep)], np.int32)
-
-    def chain(c):
-        L = _lattice(layout, d)
-        return L.anneal_chain(w, beta, anneal_seed, uid, c, refs[c // 4] ^ L.logical(c % 4))
-
-    res = list(pool().map(chain, range(4 * n_rep)))
-    emin = np.array([r["emin"] for r in res], np.int64)
-    cls = np.array([O.class_mul(qcls[c // 4], c % 4) for c in range(4 * n_rep)], np.int32)
-    e_cls, ps, bc = O.reduce(emin, cls)
-    return dict(refs=refs, qcls=qcls, chain_emin=emin, chain_stop=np.array([r["stop"] for r in res], np.int32),
-                chain_e=np.array([r["e"] for r in res], np.int64), e_cls=e_cls, cls=ps, e_best=int(e_cls[ps]),
-                best_chain=bc, recovery=res[bc]["snap"])
+    """oracle.decode_by_chain on the shared host thread pool."""
+    return O.decode_by_chain(layout, d, w, wg, syn, uid, n_rep, beta, greedy_seed, anneal_seed, pool())
 
 
 def gpu_plan(prob, lanes=None):
