@@ -42,9 +42,11 @@ ALU_PEAK_OPS = 256 * 128 * 2.4e9
 # the generator's (shape, pattern) -> entry offset lookup (2 B) and the
 # 12 bytes of its (dE, threshold, always-accept) entry.
 LDS_BYTES_PER_ATTEMPT = 14
-# MI355X LDS read peak from its unit counts and clock: 256 CUs x 128 bytes
-# per clock x 2.4 GHz; bench.py --peaks measures it.
-LDS_PEAK_BYTES = 256 * 128 * 2.4e9
+# MI355X LDS read peak from its unit counts and clock: 256 CUs x 64 banks x
+# 4 bytes per clock x 2.4 GHz = 157.3 TB/s, the rate of 128-bit reads
+# (bench.py --peaks measures 1.3-1.4e14 B/s for them; 32- and 64-bit reads
+# move half as many bytes per clock).
+LDS_PEAK_BYTES = 256 * 256 * 2.4e9
 
 
 def kernel_source_sha256(kernel=""):
@@ -377,12 +379,14 @@ def roofline(run, peaks, workload, batch):
     sides = {
         "alu": {"achieved": alu / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s (int32 lane-ops)",
                 "frac": alu / ALU_PEAK_OPS, "peak_measured": peaks["valu_simple_ops"] / 1e12,
-                "frac_of_measured": alu / peaks["valu_simple_ops"], "ops_per_attempt": OPS_PER_ATTEMPT},
+                "frac_of_measured": alu / peaks["valu_simple_ops"], "ops_per_attempt": OPS_PER_ATTEMPT,
+                "valu_busy_frac": float(kv["valu_busy_frac"]) if "valu_busy_frac" in kv else None},
         "lds": {"achieved": lds / 1e12, "peak": LDS_PEAK_BYTES / 1e12, "unit": "TB/s (LDS reads)",
                 "frac": lds / LDS_PEAK_BYTES, "peak_measured": peaks["lds_bytes"] / 1e12,
                 "frac_of_measured": lds / peaks["lds_bytes"], "bytes_per_attempt": LDS_BYTES_PER_ATTEMPT,
                 "bank_conflict_cycles_per_wave_step": (float(kv["lds_bank_conflict_cycles_per_wave_step"])
-                                                       if "lds_bank_conflict_cycles_per_wave_step" in kv else None)},
+                                                       if "lds_bank_conflict_cycles_per_wave_step" in kv else None),
+                "lds_busy_frac": float(kv["lds_busy_frac"]) if "lds_busy_frac" in kv else None},
     }
     bound = "alu" if sides["alu"]["frac"] >= sides["lds"]["frac"] else "lds"
     top = sides[bound]

@@ -828,6 +828,17 @@ __device__ __forceinline__ uint32_t lt_mask(uint32_t u, uint32_t thr)
     return (uint32_t)((int32_t)__builtin_amdgcn_bitop3_b32(u, thr, u - thr, 0x8E) >> 31);
 }
 
+// Acceptance mask of a move of the specialised kernels: all ones iff
+// u < thr or the move always accepts (dE <= 0: always = all ones, and its
+// table threshold is 0, so the borrow of u - thr is 0).  Two instructions:
+// the borrow of u - thr goes through the carry into always - 0 - borrow.
+__device__ __forceinline__ uint32_t accept_sel(uint32_t u, uint32_t thr, uint32_t always)
+{
+    unsigned int borrow, unused;
+    (void)__builtin_subc(u, thr, 0u, &borrow);
+    return __builtin_subc(always, 0u, borrow, &unused);
+}
+
 // Rows of the specialised kernel: the d lattice rows only, qubit x of a row
 // at bits 2x, 2x + 1, and one spare column (x = d) at the right end that the
 // right-boundary generators may flip (its bits are never read as a qubit).
@@ -919,7 +930,7 @@ __device__ __forceinline__ void static_apply(uint32_t (&r)[StaticRows<D>::N], ui
     if constexpr (G::real) {
         uint32_t *ra = r + (G::has_a ? G::ya : 0) * NW, *rb = r + (G::has_b ? G::ya + 1 : 0) * NW;
         // all ones on accepting lanes: u < threshold, or dE <= 0
-        const uint32_t sel = lt_mask(u, e.y) | e.z;
+        const uint32_t sel = accept_sel(u, e.y, e.z);
         if constexpr (G::has_a) row_flip_static<NW, G::BO, 6u>(ra, sel);   // X_left | Z_up
         if constexpr (G::has_b) row_flip_static<NW, G::BO, 9u>(rb, sel);   // Z_down | X_right
         acc += (int32_t)(e.x & sel);
@@ -1003,7 +1014,7 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
     constexpr int NB = RotSchedule<D>::MP / 4;
     using Blocks = std::make_integer_sequence<int, NB>;
     const int lane = threadIdx.x;
-    const int nranks = (int)uni(pl->nranks);
+    const int nranks = (int)uni(pl->nranks), kneg = (int)uni(pl->kneg);
     int32_t W[4];
     W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
     // a task's 64 chains belong to one syndrome
@@ -1057,7 +1068,9 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
         if (keep) t_stop = min(t_end, t_begin + ((t - t_begin) / kServeCheckpointEvery + 1) * kServeCheckpointEvery);
         for (; t < t_stop; ++t) {
             wave_lds_fence();
-            for (int i = lane; i < nranks; i += kWave) et_s[i].y = pl->thr[(size_t)t * nranks + i];
+            // this sweep's thresholds; 0 for the ranks with dE <= 0, whose
+            // moves are always accepted through their mask
+            for (int i = lane; i < nranks; i += kWave) et_s[i].y = i < kneg ? 0u : pl->thr[(size_t)t * nranks + i];
             wave_lds_fence();
             const uint32_t c2 = 4u * (uint32_t)t;
             int32_t acc = 0;

@@ -48,7 +48,7 @@ __device__ __forceinline__ void planar_apply(uint32_t (&r)[PlanarRows<D>::N], ui
     using G = PlanarGen<D, K, B, W>;
     constexpr int NW = PlanarRows<D>::NW;
     if constexpr (G::real) {
-        const uint32_t sel = lt_mask(u, e.y) | e.z;
+        const uint32_t sel = accept_sel(u, e.y, e.z);
         row_flip_static<NW, G::BO, 6u>(r + G::Y * NW, sel);         // X top-left | Z top-right
         row_flip_static<NW, G::BO, 9u>(r + (G::Y + 1) * NW, sel);   // Z bottom-left | X bottom-right
         acc += (int32_t)(e.x & sel);
@@ -104,7 +104,7 @@ __device__ __forceinline__ void planar_static_core(const PlanDev *pl, const Chai
     constexpr int NB = PlanarSchedule<D>::MP / 4;
     using Blocks = std::make_integer_sequence<int, NB>;
     const int lane = threadIdx.x;
-    const int nranks = (int)uni(pl->nranks), n_sweeps = (int)uni(pl->n_sweeps);
+    const int nranks = (int)uni(pl->nranks), n_sweeps = (int)uni(pl->n_sweeps), kneg = (int)uni(pl->kneg);
     int32_t W[4];
     W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
     const uint32_t uid = J.uid, cc = J.cc;
@@ -145,7 +145,8 @@ __device__ __forceinline__ void planar_static_core(const PlanDev *pl, const Chai
     if (keep) keep_min();
     for (int t = 0; t < n_sweeps; ++t) {
         wave_lds_fence();
-        for (int i = lane; i < nranks; i += kWave) et_s[i].y = pl->thr[(size_t)t * nranks + i];
+        // this sweep's thresholds; 0 for the ranks with dE <= 0 (see accept_sel)
+        for (int i = lane; i < nranks; i += kWave) et_s[i].y = i < kneg ? 0u : pl->thr[(size_t)t * nranks + i];
         wave_lds_fence();
         const uint32_t c2 = 4u * (uint32_t)t;
         int32_t acc = 0;
