@@ -5,7 +5,44 @@ weight is added once every generator touching it has been fixed, and a
 generator leaves the frontier once no unfinished qubit depends on it.  Exact
 for any lattice; fast while the frontier stays small (about d + 2 bits on
 the rotated lattice in row-major order)."""
+import ctypes as C
+import os
+import subprocess
+
 import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DP_SRC = os.path.join(HERE, "_exact_dp.c")
+DP_LIB = os.path.join(HERE, "_exact_dp.so")
+_dp = None
+
+
+def build_dp(force=False):
+    """Compile the C form of the frontier program (tests/_exact_dp.c)."""
+    if force or not os.path.exists(DP_LIB) or os.path.getmtime(DP_LIB) < os.path.getmtime(DP_SRC):
+        tmp = DP_LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, DP_SRC])
+        os.replace(tmp, DP_LIB)
+    return DP_LIB
+
+
+def coset_minimum_c(fq, fm, c0, w):
+    """The frontier program of coset_minimum in C (tests/_exact_dp.c)."""
+    global _dp
+    if _dp is None:
+        build_dp()
+        L = C.CDLL(DP_LIB)
+        L.dp_coset_minimum.restype = C.c_int64
+        L.dp_coset_minimum.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        _dp = L
+    fq = np.ascontiguousarray(fq, np.int32)
+    fm = np.ascontiguousarray(fm, np.uint8)
+    c0 = np.ascontiguousarray(c0, np.uint8)
+    w = np.ascontiguousarray(w, np.int32)
+    r = _dp.dp_coset_minimum(len(c0), len(fq), fq.ctypes.data, fm.ctypes.data, c0.ctypes.data, w.ctypes.data)
+    if r < 0:
+        raise RuntimeError(f"dp_coset_minimum failed ({r})")
+    return int(r)
 
 
 def coset_minimum(fq, fm, c0, w):

@@ -112,10 +112,35 @@ def oracle_syndromes(wl, seeds, outs, meta, picks):
 def test_d11_full_launch():
     """The headline launch: four p groups of 2048 syndromes (d = 11, 32
     replicas, 2000 sweeps) captured in one graph; the oracle decodes the
-    first 200 syndromes of every p (800 syndromes, 102400 chains)."""
+    first 200 syndromes of every p (800 syndromes, 102400 chains).  Against
+    the mathematics directly (Eqs. (18)-(21)): on those syndromes every E_P
+    bounds the exact minimum of its coset (frontier program,
+    tests/_exact_dp.c) from above, and the syndromes decoded to the exact
+    least minimum clear the binomial bar of the rate calibrated at this
+    distance (tests/golden/hit_rate_calibration_d11.py)."""
+    import os
+
+    from tests import _exact, _hitrate
     wl, seeds, outs, meta = build_launch("d11_bias100", 2048, graph=True)
     check_properties(wl, outs, meta)
-    oracle_syndromes(wl, seeds, outs, meta, [(g, i) for g in range(len(outs)) for i in range(200)])
+    n = 200
+    oracle_syndromes(wl, seeds, outs, meta, [(g, i) for g in range(len(outs)) for i in range(n)])
+    cal = _hitrate.read_calibration(os.path.join(os.path.dirname(__file__), "golden", "hit_rates_d11.txt"))
+    for gi, (o, m) in enumerate(zip(outs, meta)):
+        refs0 = o.refs[:n, 0].cpu().numpy()
+        e_cls = o.e_cls[:n].cpu().numpy().astype(np.int64)
+        e_best = o.e_best[:n].cpu().numpy()
+        w = O.weights(m["p"], O.noise(m["p"], m["eta"], m["conv"]))[0]
+        lat = m["olat"]
+
+        def exact(i):
+            return [_exact.coset_minimum_c(lat.fq, lat.fm, refs0[i] ^ lat.logical(P), w) for P in range(4)]
+
+        ex = np.array(list(pool().map(exact, range(n))), np.int64)
+        assert (e_cls >= ex).all(), f"p={m['p']}: E_P below an exact coset minimum"
+        hits = int((e_best == ex.min(axis=1)).sum())
+        print(f"[fullsize] d11 p={m['p']}: {hits}/{n} syndromes at the exact least coset minimum", flush=True)
+        assert hits >= _hitrate.bar(*cal[f"rotated_d11_p{m['p']:.2f}"], n)
 
 
 def test_mixed_distances_full_launch():

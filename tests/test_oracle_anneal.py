@@ -574,3 +574,38 @@ def test_selection_by_chain_equals_decode(layout, d, n_rep, mode):
     assert list(e_cls) == [9, 4, big, 4] and ps == 1 and bc == 1
     with pytest.raises(ValueError):
         O.reduce(np.array([1]), np.array([4]))
+
+
+@pytest.mark.parametrize("layout,d", [(O.ROTATED, 3), (O.PLANAR, 3), (O.ROTATED, 5), (O.ROTATED, 7), (O.PLANAR, 5)])
+def test_frontier_program_in_c(layout, d):
+    """The C form of the frontier program (used at d = 11) equals the Python
+    one, and enumeration of the stabilizer group where that is feasible."""
+    L = O.Lattice(layout, d)
+    rng = np.random.default_rng(70 + d + 10 * layout)
+    group = _gf2.group_elements(_gf2.generator_matrix(L.fq, L.fm, L.nq)) if L.nstab <= 16 else None
+    for k in range(3):
+        p, eta = float(rng.uniform(0.05, 0.3)), float(10 ** rng.uniform(0, 3))
+        w, _ = O.weights(p, O.noise(p, eta))
+        c0 = rng.integers(0, 4, L.nq).astype(np.uint8)
+        got = _exact.coset_minimum_c(L.fq, L.fm, c0, w)
+        assert got == _exact.coset_minimum(L.fq, L.fm, c0, w)
+        if group is not None:
+            assert got == _gf2.coset_minima(group, [c0], w)[0]
+
+
+def test_decoder_against_exact_minima_d11():
+    """At the benchmark distance (rotated d = 11, eta = 100, 32 replicas, 2000
+    sweeps of the geometric schedule 0.05 -> 10): every E_P bounds its coset's
+    exact minimum from above (Eqs. (18)-(21)); on six syndromes at p = 0.25,
+    the hardest noise of the workload."""
+    L = O.Lattice(O.ROTATED, 11)
+    p, eta = 0.25, 100.0
+    w, wg = O.weights(p, O.noise(p, eta))
+    beta = O.schedule(O.SCHED_GEOMETRIC, 0.05, 10.0, 2000)
+    rng = np.random.default_rng(111)
+    for uid in range(6):
+        _, syn = random_problem(L, p, eta, rng)
+        out = L.decode(w, wg, syn, uid, 32, beta, 5, 6)
+        exact = [_exact.coset_minimum_c(L.fq, L.fm, out["refs"][0] ^ L.logical(P), w) for P in range(4)]
+        assert all(out["e_cls"][P] >= exact[P] for P in range(4))
+        assert out["e_best"] >= min(exact)
