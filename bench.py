@@ -257,7 +257,9 @@ def run_batch(args, name, B, steps, warm, tune=True, order="colour", ladder=""):
     for k in range(steps + warm):
         row_s, row_u, row_e = [], [], []
         for gi, ((d, p, eta), plan) in enumerate(zip(specs, plans)):
-            err = inputs.sample_errors(B, plan.nq, inputs.channel(p, eta, conv), seeds["sample"], stream=k * 64 + gi)
+            # errors keyed by the sample seed and each syndrome's uid
+            err = inputs.sample_errors(B, plan.nq, inputs.channel(p, eta, conv), seeds["sample"],
+                                       uid0=(k * ng + gi) * B)
             row_s.append(D.syndrome(plan, torch.from_numpy(err).to(dev)))
             row_u.append(torch.from_numpy(inputs.sample_uids(B, (k * ng + gi) * B).view(np.int32)).to(dev))
             row_e.append(err)
@@ -742,7 +744,7 @@ def serve_setup(args):
     reqs = []
     for i in range(n):
         d, eta = specs[pick[i]]
-        err = inputs.sample_errors(1, d * d, inputs.channel(p, eta), seeds["sample"], stream=100000 + i)[0]
+        err = inputs.sample_errors(1, d * d, inputs.channel(p, eta), seeds["sample"], uid0=7_000_000 + i)[0]
         reqs.append((int(pick[i]), err))
     syns = [None] * n
     for k in range(len(specs)):   # one syndrome launch per (d, eta)

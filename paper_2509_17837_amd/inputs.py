@@ -11,6 +11,7 @@ import numpy as np
 
 # Pauli codes: I=0, Z=1, X=2, Y=3
 CODE_X, CODE_Y, CODE_Z = 2, 3, 1
+CODE_I = 0
 
 
 def channel(p: float, eta: float, convention: int = 0):
@@ -21,16 +22,45 @@ def channel(p: float, eta: float, convention: int = 0):
     return (p / (eta + 2), p * eta / (eta + 2), p / (eta + 2))
 
 
-def sample_errors(n: int, nq: int, pxyz, seed: int, stream: int = 0) -> np.ndarray:
-    """n i.i.d. error configurations [n][nq] (uint8 Pauli codes), reproducible
-    from (seed, stream)."""
-    rng = np.random.default_rng([int(seed), int(stream)])
-    u = rng.random((n, nq))
-    px, py, pz = pxyz
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+    easy as 1, 2, 3", SC'11) of counters ctr = (c0, c1, c2, c3) under key
+    (k0, k1): uint32 arrays of one shape (or scalars) -> four uint32 arrays.
+    The input sampler's own writing of the published generator (ten rounds of
+    two 32 x 32 -> 64 multiplies by 0xD2511F53 and 0xCD9E8D57, the key bumped
+    by 0x9E3779B9 and 0xBB67AE85)."""
+    m32 = np.uint64(0xFFFFFFFF)
+    c0, c1, c2, c3 = (np.asarray(c, np.uint64) & m32 for c in ctr)
+    k0, k1 = (np.uint64(int(k) & 0xFFFFFFFF) for k in key)
+    for _ in range(10):
+        p0 = np.uint64(0xD2511F53) * c0
+        p1 = np.uint64(0xCD9E8D57) * c2
+        c0, c1, c2, c3 = (p1 >> np.uint64(32)) ^ c1 ^ k0, p1 & m32, (p0 >> np.uint64(32)) ^ c3 ^ k1, p0 & m32
+        k0 = (k0 + np.uint64(0x9E3779B9)) & m32
+        k1 = (k1 + np.uint64(0xBB67AE85)) & m32
+    return tuple(c.astype(np.uint32) for c in (c0, c1, c2, c3))
+
+
+def sample_errors(n: int, nq: int, pxyz, seed: int, stream: int = 0, uid0: int = 0) -> np.ndarray:
+    """n i.i.d. error configurations [n][nq] (uint8 Pauli codes).  Qubit q of
+    sample i draws u = word 0 of Philox4x32-10 with key (seed, stream) and
+    counter (uid0 + i, q, 0x200, 0); with c1 = floor(2^32 p_x),
+    c2 = floor(2^32 (p_x + p_y)), c3 = floor(2^32 (p_x + p_y + p_z)) the code
+    is X if u < c1, else Y if u < c2, else Z if u < c3, else I."""
+    px, py, pz = (float(v) for v in pxyz)
+    c1, c2, c3 = (min(int(np.floor(np.ldexp(v, 32))), 1 << 32) for v in (px, px + py, px + py + pz))
     out = np.zeros((n, nq), np.uint8)
-    out[u < px + py + pz] = CODE_Z
-    out[u < px + py] = CODE_Y
-    out[u < px] = CODE_X
+    q = np.arange(nq, dtype=np.uint64)
+    rows = max(1, (1 << 20) // max(nq, 1))   # about 10^6 draws per chunk
+    for a in range(0, n, rows):
+        b = min(n, a + rows)
+        i = (np.arange(a, b, dtype=np.uint64) + np.uint64(uid0))[:, None]
+        u = philox4x32_10((np.broadcast_to(i, (b - a, nq)), np.broadcast_to(q, (b - a, nq)), 0x200, 0),
+                          (seed, stream))[0].astype(np.int64)
+        blk = out[a:b]
+        blk[u < c3] = CODE_Z
+        blk[u < c2] = CODE_Y
+        blk[u < c1] = CODE_X
     return out
 
 
