@@ -387,8 +387,11 @@ int xzzx_probe_lds(int bytes_per_read, int waves_per_simd, int iters, void *stre
  * Admission: a request is admitted when a device slot is free (max_slots
  * slots of max_rep replicas on at most max_qubits qubits are allocated at
  * creation: the HBM budget) and the LDS its tasks need, summed over resident
- * requests, stays within lds_budget_bytes (0 = the device's total LDS), so
- * every resident task of a slice runs concurrently.
+ * requests, stays within lds_budget_bytes (0 = four times the device's total
+ * LDS).  With a budget above the device's LDS a slice may hold more tasks
+ * than run at once; the device starts queued tasks as earlier ones end, so
+ * short tasks (small lattices) do not leave their waves idle.  A budget equal
+ * to the device's LDS keeps every task of a slice running concurrently.
  *
  * Lanes per chain: each slice picks the largest power of two up to
  * max_lanes_per_chain for which the slice's wavefronts stay within max_waves
@@ -408,7 +411,7 @@ typedef struct {
                                  smaller lattices advance proportionally more */
     int max_pending;          /* queued requests before submit returns EAGAIN */
     int greedy_mode;          /* XZZX_GREEDY_* */
-    int64_t lds_budget_bytes; /* 0: the device's total LDS */
+    int64_t lds_budget_bytes; /* 0: four times the device's total LDS */
     uint64_t greedy_seed;
     uint64_t anneal_seed;
     int max_lanes_per_chain;  /* 0: 64; 1: always the plan's own kernel; else a power of two <= 64 */

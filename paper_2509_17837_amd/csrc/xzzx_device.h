@@ -929,8 +929,16 @@ __device__ __forceinline__ void static_apply(uint32_t (&r)[StaticRows<D>::N], ui
     constexpr int NW = StaticRows<D>::NW;
     if constexpr (G::real) {
         uint32_t *ra = r + (G::has_a ? G::ya : 0) * NW, *rb = r + (G::has_b ? G::ya + 1 : 0) * NW;
-        // all ones on accepting lanes: u < threshold, or dE <= 0
-        const uint32_t sel = accept_sel(u, e.y, e.z);
+        // all ones on accepting lanes: u < threshold, or dE <= 0 (mask all
+        // ones).  Up to d = 15 (eight wavefronts per SIMD) two instructions
+        // through the carry, the table giving those ranks threshold 0; the
+        // larger lattices, at four or five wavefronts, keep the
+        // sign-extension form: the carry form's compare and borrow share one
+        // condition register, which serialises the moves of a block, and
+        // d = 31 ran 21 % slower with it
+        uint32_t sel;
+        if constexpr (D <= 15) sel = accept_sel(u, e.y, e.z);
+        else sel = lt_mask(u, e.y) | e.z;
         if constexpr (G::has_a) row_flip_static<NW, G::BO, 6u>(ra, sel);   // X_left | Z_up
         if constexpr (G::has_b) row_flip_static<NW, G::BO, 9u>(rb, sel);   // Z_down | X_right
         acc += (int32_t)(e.x & sel);
@@ -1068,9 +1076,13 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
         if (keep) t_stop = min(t_end, t_begin + ((t - t_begin) / kServeCheckpointEvery + 1) * kServeCheckpointEvery);
         for (; t < t_stop; ++t) {
             wave_lds_fence();
-            // this sweep's thresholds; 0 for the ranks with dE <= 0, whose
-            // moves are always accepted through their mask
-            for (int i = lane; i < nranks; i += kWave) et_s[i].y = i < kneg ? 0u : pl->thr[(size_t)t * nranks + i];
+            // this sweep's thresholds (0 for the ranks with dE <= 0 where the
+            // acceptance goes through the carry: see static_apply)
+            if constexpr (D <= 15) {
+                for (int i = lane; i < nranks; i += kWave) et_s[i].y = i < kneg ? 0u : pl->thr[(size_t)t * nranks + i];
+            } else {
+                for (int i = lane; i < nranks; i += kWave) et_s[i].y = pl->thr[(size_t)t * nranks + i];
+            }
             wave_lds_fence();
             const uint32_t c2 = 4u * (uint32_t)t;
             int32_t acc = 0;

@@ -14,6 +14,10 @@
 //      device and copied to pinned host memory in one transfer);
 //   4. wait for the slice, then publish finished results with their latency.
 // Requests that arrive while a slice runs join at the next slice boundary.
+// Admission may hold more tasks than the device runs at once (the default
+// LDS budget is four devices' worth): the hardware dispatcher then starts
+// queued tasks as earlier ones end, so a slice's short tasks do not leave
+// their waves idle until the slice's longest task is done.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -495,7 +499,10 @@ int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out)
     if (!rc && hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, S->device) != hipSuccess)
         lds_cu = 160 * 1024;
     if (lds_cu <= 0) lds_cu = 160 * 1024;
-    S->lds_budget = cfg->lds_budget_bytes ? (size_t)cfg->lds_budget_bytes : (size_t)cus * (size_t)lds_cu;
+    // default: four times the device's LDS, so that under load a slice holds
+    // more tasks than the CUs run at once and the waves whose short tasks end
+    // early (small lattices) take queued ones instead of idling
+    S->lds_budget = cfg->lds_budget_bytes ? (size_t)cfg->lds_budget_bytes : 4 * (size_t)cus * (size_t)lds_cu;
     S->wave_budget = cfg->max_waves ? cfg->max_waves : 32 * (int64_t)cus;
     if (!S->cfg.max_lanes_per_chain) S->cfg.max_lanes_per_chain = kWave;
     const size_t nq = (size_t)cfg->max_qubits, R = (size_t)cfg->max_rep;
