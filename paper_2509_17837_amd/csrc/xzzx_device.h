@@ -1014,26 +1014,13 @@ __device__ __forceinline__ void static_unpack(const uint32_t (&r)[StaticRows<D>:
                 dst[y * D + x] = (uint8_t)((r[y * NW + w] >> (2 * (x - 16 * w))) & 3u);
 }
 
+// The chain's starting state packed into the specialised kernel's rows (the
+// logical operators of its coset applied as asked), and its energy.
 template <int D>
-__device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
-                                 uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s, int cp_interval)
+__device__ __forceinline__ int32_t static_load(const PlanDev *pl, const ChainJob &J, bool use_x, bool use_z,
+                                               const int32_t (&W)[4], uint32_t (&r)[StaticRows<D>::N])
 {
     constexpr int NW = StaticRows<D>::NW;
-    constexpr int NB = RotSchedule<D>::MP / 4;
-    using Blocks = std::make_integer_sequence<int, NB>;
-    const int lane = threadIdx.x;
-    const int nranks = (int)uni(pl->nranks), kneg = (int)uni(pl->kneg);
-    int32_t W[4];
-    W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
-    // a task's 64 chains belong to one syndrome
-    const uint32_t uid = uni(J.uid), cc = J.cc;
-    const uint32_t k0 = uni(seed_lo), k1 = uni(seed_hi);
-    const bool use_x = !J.resume && (J.lp == 1 || J.lp == 2), use_z = !J.resume && (J.lp == 2 || J.lp == 3);
-    // lane 0 is always active and a task's chains are consecutive: chain of lane l = ci0 + l
-    const int64_t ci0 = (int64_t)(((uint64_t)uni((uint32_t)((uint64_t)J.ci >> 32)) << 32) | uni((uint32_t)J.ci));
-    const int cp_every = J.cp_out ? cp_interval : 0;
-
-    uint32_t r[StaticRows<D>::N];
     int32_t E = 0;
 #pragma unroll
     for (int y = 0; y < D; ++y) {
@@ -1056,6 +1043,30 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
             r[y * NW + w] = word;
         }
     }
+    return E;
+}
+
+template <int D>
+__device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJob &J, int t_begin, int t_end, uint32_t seed_lo,
+                                 uint32_t seed_hi, const uint16_t *lut_s, uint4 *et_s, int cp_interval)
+{
+    constexpr int NW = StaticRows<D>::NW;
+    constexpr int NB = RotSchedule<D>::MP / 4;
+    using Blocks = std::make_integer_sequence<int, NB>;
+    const int lane = threadIdx.x;
+    const int nranks = (int)uni(pl->nranks), kneg = (int)uni(pl->kneg);
+    int32_t W[4];
+    W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
+    // a task's 64 chains belong to one syndrome
+    const uint32_t uid = uni(J.uid), cc = J.cc;
+    const uint32_t k0 = uni(seed_lo), k1 = uni(seed_hi);
+    const bool use_x = !J.resume && (J.lp == 1 || J.lp == 2), use_z = !J.resume && (J.lp == 2 || J.lp == 3);
+    // lane 0 is always active and a task's chains are consecutive: chain of lane l = ci0 + l
+    const int64_t ci0 = (int64_t)(((uint64_t)uni((uint32_t)((uint64_t)J.ci >> 32)) << 32) | uni((uint32_t)J.ci));
+    const int cp_every = J.cp_out ? cp_interval : 0;
+
+    uint32_t r[StaticRows<D>::N];
+    int32_t E = static_load<D>(pl, J, use_x, use_z, W, r);
     int32_t Emin = E, stop = 0;
     if (J.resume && J.active) {
         E = J.efin[J.ci];
@@ -1123,6 +1134,105 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
         J.efin[J.ci] = E;
         if (keep) commit_kept_state(J, sub, sub != t_begin, stop);
         if (J.states) static_unpack<D>(r, J.states + (size_t)J.ci * (D * D));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Replica exchange (ladders of K fixed inverse temperatures; the paper names
+// replica exchange as future work, Sec. VII).  Shared by the generic ladder
+// kernel and the ladder kernels specialised to d.
+// ---------------------------------------------------------------------------
+// The exchange rule's threshold T(n) = floor(prod over the set bits i of n
+// of R_i / 2^32), the product in 64-bit fixed point from 2^64 - 1.
+__device__ __forceinline__ uint32_t swap_threshold(const uint64_t *R, uint32_t n)
+{
+    uint64_t p = ~0ull;
+    for (int i = 0; i < 32; ++i)
+        if ((n >> i) & 1u) p = __umul64hi(p, R[i]);
+    return (uint32_t)(p >> 32);
+}
+
+// Tables of the ladder kernels specialised to d: the (shape, pattern) ->
+// entry offset table of the annealing kernels, and one 16-byte entry
+// (dE, threshold, always-accept mask) per (level, rank), the levels' tables
+// one after another; ranks with dE <= 0 take threshold 0 (see accept_sel).
+__device__ inline void load_ladder_tables(const PlanDev *pl, uint16_t *lut_s, uint4 *et_s)
+{
+    const int lane = threadIdx.x;
+    const int nranks = pl->nranks, kneg = pl->kneg, K = pl->ladder_k;
+    for (int i = lane; i < 256 * 6; i += kWave) lut_s[i] = (uint16_t)(16u * pl->lut[i]);
+    for (int i = lane; i < K * nranks; i += kWave) {
+        const int rk = i % nranks;
+        const int32_t de = pl->dE[rk];
+        et_s[i] = make_uint4((uint32_t)de, rk < kneg ? 0u : pl->ladder_thr[i], de <= 0 ? 0xFFFFFFFFu : 0u, 0u);
+    }
+    wave_lds_fence();
+}
+
+// Exchanges of adjacent levels after sweep t: pairs (k, k + 1) for k = t mod
+// 2, t mod 2 + 2, ...; the pair's uniform is word p mod 4 of the Philox block
+// (uid, 2^31 | ladder, t, p / 4), p = (k - t mod 2) / 2, and the pair swaps
+// when the higher level's energy is not below the lower one's or when the
+// uniform falls below T(E_low - E_high).  A lane's chain keeps its state and
+// takes its partner's level.  The chains of one ladder and coset P hold the
+// slots base + 4 level + P of the ladder's block of 4K lanes, a permutation
+// of the block, so one forward permute tells every slot the lane holding it.
+__device__ __forceinline__ int ladder_exchange(int level, int32_t E, int K, uint32_t P, uint32_t uid,
+                                               uint32_t ladder_id, int t, uint32_t k0, uint32_t k1, const uint64_t *R)
+{
+    const int lane = threadIdx.x;
+    const int base = lane & ~(4 * K - 1);
+    const int holder = __builtin_amdgcn_ds_permute((base + 4 * level + (int)P) << 2, lane);
+    const int par = t & 1;
+    const bool low = ((level - par) & 1) == 0;
+    const int plevel = low ? level + 1 : level - 1;
+    const bool paired = plevel >= 0 && plevel < K;
+    const int partner = __builtin_amdgcn_ds_bpermute((base + 4 * (paired ? plevel : level) + (int)P) << 2, holder);
+    const int32_t ep = __builtin_amdgcn_ds_bpermute(partner << 2, E);
+    if (paired) {
+        const int32_t e_lo = low ? E : ep, e_hi = low ? ep : E;
+        const uint32_t p = (uint32_t)((low ? level : plevel) - par) >> 1;
+        const uint4 rr = philox4x32_10(make_uint4(uid, 0x80000000u | ladder_id, (uint32_t)t, p >> 2), k0, k1);
+        const uint32_t u = (p & 3u) == 0 ? rr.x : (p & 3u) == 1 ? rr.y : (p & 3u) == 2 ? rr.z : rr.w;
+        if (e_hi >= e_lo || u < swap_threshold(R, (uint32_t)(e_lo - e_hi))) return plevel;
+    }
+    return level;
+}
+
+// Task loop of the ladder kernels specialised to d (MODE 0: persistent
+// wavefronts on the atomic task queue; 2: one task per workgroup), tasks of
+// 64 consecutive chains; dynamic LDS: the offset table (3 KiB), then K
+// level tables.  core(G, J, lut_s, et_s) runs one lane's chain.
+constexpr uint32_t kLadderLutBytes = 2 * 256 * 6;
+
+template <int MODE, typename Core>
+__device__ __forceinline__ void ladder_static_body(const AnnealArgs &A, Core core)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint16_t *lut_s = reinterpret_cast<uint16_t *>(smem);
+    uint4 *et_s = reinterpret_cast<uint4 *>(smem + kLadderLutBytes);
+    const PlanDev *loaded = nullptr;
+    for (int iter = 0;; ++iter) {
+        uint32_t task = 0;
+        if (MODE == 2) {
+            if (iter > 0) break;
+            task = blockIdx.x;
+        } else {
+            if (threadIdx.x == 0) task = atomicAdd(A.counter, 1u);
+            task = __builtin_amdgcn_readfirstlane(__shfl(task, 0, kWave));
+        }
+        if (task >= A.n_tasks) break;
+        int gi = 0;
+        while (gi + 1 < A.n_groups && (int64_t)task >= A.g[gi + 1].task_begin) ++gi;
+        const GroupArgs &G = A.g[gi];
+        const int64_t unit0 = ((int64_t)task - G.task_begin) << 6;
+        if (G.plan != loaded) {
+            wave_lds_fence();
+            load_ladder_tables(G.plan, lut_s, et_s);
+            loaded = G.plan;
+        }
+        const ChainJob J = batch_job(G, unit0 + threadIdx.x, false);
+        core(G, J, lut_s, et_s);
     }
 }
 
@@ -1419,8 +1529,17 @@ typedef void (*AnnealKernel)(AnnealArgs);
 // padded to a multiple of four)
 AnnealKernel planar_rows_kernel(int d, bool plain);
 int planar_state_words(int d);
-// replica-exchange kernel (ladders of fixed inverse temperatures)
+// replica-exchange kernels (ladders of fixed inverse temperatures): the
+// generic one (one chain per lane, state in LDS), and the packed-row ones
+// specialised to the rotated lattice at odd d <= kLadderRowsMaxD (a task's
+// chains inside one syndrome) and to the planar lattice at odd d <= 15 (NULL
+// otherwise); the specialised ones keep each chain's rows at its first E_min
+// (ladder_rows_state_words(d) words, planar_state_words(d) on the planar
+// lattice)
 AnnealKernel ladder_kernel(bool plain);
+AnnealKernel ladder_rows_kernel(int d, bool plain);
+AnnealKernel ladder_planar_kernel(int d, bool plain);
+int ladder_rows_state_words(int d);
 typedef void (*ServeKernel)(const ServeTask *, uint32_t, uint32_t);
 
 // The specialised kernels live in several translation units (compiled in

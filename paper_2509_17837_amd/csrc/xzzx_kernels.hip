@@ -446,6 +446,23 @@ __global__ void k_rows_recovery(const uint32_t *__restrict__ snap, int words,
     const uint32_t word = snap[ci * words + (int64_t)((p >> 8) * nw + ((p & 0xFFu) >> 4))];
     recovery[idx] = (uint8_t)((word >> (2 * (p & 15u))) & 3u);
 }
+// Rotated ladder kernel specialised to d: the same from its rows,
+// chain-major with `words` words per chain (word y * nw + x / 16 holds the
+// qubit at row y, column x), one thread per (syndrome, qubit).
+__global__ void k_static_recovery(const uint32_t *__restrict__ snap, int words,
+                                  const int32_t *__restrict__ best_chain, int n_rep, int d, int64_t n_syn, int nw,
+                                  uint8_t *__restrict__ recovery)
+{
+    const int nq = d * d;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_syn * nq) return;
+    const int64_t s = idx / nq;
+    const int q = (int)(idx - s * nq);
+    const int y = q / d, x = q - y * d;
+    const int64_t ci = s * 4 * n_rep + best_chain[s];
+    const uint32_t word = snap[ci * words + (int64_t)(y * nw + (x >> 4))];
+    recovery[idx] = (uint8_t)((word >> (2 * (x & 15))) & 3u);
+}
 __global__ __launch_bounds__(kWave) void k_anneal_rows(AnnealArgs A) { batch_kernel_body<0, true, 0, false>(A); }
 __global__ __launch_bounds__(kWave) void k_anneal_rows_plain(AnnealArgs A) { batch_kernel_body<2, true, 0, false>(A); }
 
@@ -707,12 +724,35 @@ struct GroupWs {
     uint32_t *min_snap;    // random-site and planar specialised groups: each chain's state at its first E_min
 };
 
-// Words per chain of the state kept at E_min: random-site chains (packed, the
-// position nq scratch) and the planar kernel specialised to d (its rows);
-// 0 for other groups.  A plan's kernel must not change between the stages of
-// one decode.
-static int64_t min_snap_words(const Plan &P)
+// Replica exchange on the packed-row kernels specialised to d: the distance
+// when the group's ladders run there (rotated: d <= kLadderRowsMaxD and every
+// 64-chain task inside one syndrome; planar: d <= 15), else 0.  Depends on
+// the plan and n_rep only, so every stage of a decode agrees.
+static int ladder_rows_d(const xzzx_group &g)
 {
+    const Plan &P = g.plan->P;
+    if (!P.ladder_k || !P.use_rows || P.order != XZZX_ORDER_COLOUR) return 0;
+    if (P.static_d && P.static_d <= kLadderRowsMaxD && (4 * g.n_rep) % kWave == 0) return P.static_d;
+    return 0;
+}
+
+static int ladder_planar_d(const xzzx_group &g)
+{
+    const Plan &P = g.plan->P;
+    if (!P.ladder_k || !P.use_rows || P.order != XZZX_ORDER_COLOUR) return 0;
+    return P.planar_d;
+}
+
+// Words per chain of the state kept at E_min: random-site chains and the
+// generic ladder kernel (packed, the position nq scratch), the planar kernels
+// specialised to d and the rotated ladder kernels specialised to d (their
+// rows); 0 for other groups.  A plan's kernel must not change between the
+// stages of one decode.
+static int64_t min_snap_words(const xzzx_group &g)
+{
+    const Plan &P = g.plan->P;
+    if (ladder_rows_d(g)) return ladder_rows_state_words(ladder_rows_d(g));
+    if (ladder_planar_d(g)) return planar_state_words(ladder_planar_d(g));
     if (P.order == XZZX_ORDER_RANDOM_SITE || P.ladder_k) return P.lat.nq / 16 + 1;
     if (P.use_rows && P.planar_d) return planar_state_words(P.planar_d);
     return 0;
@@ -723,7 +763,7 @@ static int64_t min_snap_words(const Plan &P)
 static bool uses_static(const xzzx_group &g, int64_t unit_offset)
 {
     const Plan &P = g.plan->P;
-    return P.order == XZZX_ORDER_COLOUR && P.use_rows && P.static_d && (4 * g.n_rep) % kWave == 0 &&
+    return P.order == XZZX_ORDER_COLOUR && !P.ladder_k && P.use_rows && P.static_d && (4 * g.n_rep) % kWave == 0 &&
            unit_offset % kWave == 0;
 }
 
@@ -756,7 +796,7 @@ static size_t group_ws_bytes(const xzzx_group &g, bool decode)
     if (!g.d_chain_e) b += align256(nc * 4);
     if (!g.d_best_chain) b += align256(ns * 4);
     b += align256((size_t)checkpoints_of(g) * P.lat.d * P.static_words * nc * 4);
-    b += align256((size_t)min_snap_words(P) * nc * 4);
+    b += align256((size_t)min_snap_words(g) * nc * 4);
     return b;
 }
 
@@ -775,7 +815,7 @@ static GroupWs carve_group(const xzzx_group &g, bool decode, uint8_t *&p)
     w.best_chain = g.d_best_chain ? g.d_best_chain : reinterpret_cast<int32_t *>(take(ns * 4));
     const int ncp = checkpoints_of(g);
     w.cp_rows = ncp ? reinterpret_cast<uint32_t *>(take((size_t)ncp * P.lat.d * P.static_words * nc * 4)) : nullptr;
-    w.min_snap = min_snap_words(P) ? reinterpret_cast<uint32_t *>(take((size_t)min_snap_words(P) * nc * 4)) : nullptr;
+    w.min_snap = min_snap_words(g) ? reinterpret_cast<uint32_t *>(take((size_t)min_snap_words(g) * nc * 4)) : nullptr;
     return w;
 }
 
@@ -885,7 +925,9 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         G.task_begin = (int64_t)tasks;
         const int C = kWave / lanes;
         tasks += (uint64_t)((units + C - 1) / C);
-        lds = std::max(lds, (static_d || planar_d) ? (size_t)0
+        lds = std::max(lds, (ladder && (static_d || planar_d))
+                                ? kLadderLutBytes + 16 * (size_t)P.ladder_k * P.nranks()
+                            : (static_d || planar_d) ? (size_t)0
                             : ladder ? P.lds_bytes_ladder()
                             : site   ? P.lds_bytes_site()
                             : rows   ? P.lds_bytes_rows()
@@ -897,7 +939,11 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
     A.n_tasks = (uint32_t)tasks;
     if (lds > 65536) { set_error("LDS demand above 64 KiB"); return XZZX_ERANGE; }
     if (mode == AnnealMode::Plain) {
-        if (ladder)
+        if (ladder && static_d)
+            hipLaunchKernelGGL(ladder_rows_kernel(static_d, true), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
+        else if (ladder && planar_d)
+            hipLaunchKernelGGL(ladder_planar_kernel(planar_d, true), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
+        else if (ladder)
             hipLaunchKernelGGL(ladder_kernel(true), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         else if (site)
             hipLaunchKernelGGL(k_anneal_site_plain, dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
@@ -911,7 +957,9 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
             hipLaunchKernelGGL(bytes_kernel(2, lg), dim3((unsigned)tasks), dim3(kWave), lds, stream, A);
         return check_hip(hipGetLastError(), "plain anneal launch");
     }
-    const AnnealKernel kern = ladder     ? ladder_kernel(false)
+    const AnnealKernel kern = (ladder && static_d) ? ladder_rows_kernel(static_d, false)
+                              : (ladder && planar_d) ? ladder_planar_kernel(planar_d, false)
+                              : ladder     ? ladder_kernel(false)
                               : site     ? k_anneal_site
                               : planar_d ? planar_rows_kernel(planar_d, false)
                               : static_d ? static_rows_kernel(static_d, false)
@@ -1031,8 +1079,10 @@ static int fork_join(hipStream_t stream, int n, F launch, bool serial = false)
 // wavefronts.  Each launch has its own queue counter: d_counters[0] packed
 // rows, [1..7] byte states by lanes per chain, [16..30] the kernels
 // specialised to d = 3, 5, ..., 31, [40] random-site chains, [41..47] the
-// planar kernels specialised to d = 3, 5, ..., 15, [48] ladders; a replay (with
-// its own d_counters base) uses [0] and [2].
+// planar kernels specialised to d = 3, 5, ..., 15, [48] ladders on the generic
+// kernel, [49..55] and [56..62] ladders on the rotated and planar kernels
+// specialised to d = 3, 5, ..., 15; a replay (with its own d_counters base)
+// uses [0] and [2].
 static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
                          uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
                          hipStream_t stream, bool serial = false)
@@ -1045,12 +1095,18 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
     std::vector<int> planar_sel[kPlanarStaticMaxD + 1];   // planar kernels specialised to d
     std::vector<int> gather_sel;  // replay: recoveries gathered from the states kept at E_min
     std::vector<int> ladder_sel;  // replica exchange: one chain per lane
+    std::vector<int> ladder_rows_sel[kLadderRowsMaxD + 1];      // ... on the rotated kernels specialised to d
+    std::vector<int> ladder_planar_sel[kPlanarStaticMaxD + 1];  // ... on the planar kernels specialised to d
     int64_t total_syn = 0;
     for (int i = 0; i < n_groups; ++i) {
         if (groups[i].n_syn <= 0) continue;
         const Plan &P = groups[i].plan->P;
-        if (P.order == XZZX_ORDER_RANDOM_SITE || P.ladder_k || (mode == AnnealMode::Replay && min_snap_words(P))) {
-            (mode == AnnealMode::Replay ? gather_sel : P.ladder_k ? ladder_sel : site_sel).push_back(i);
+        if (P.order == XZZX_ORDER_RANDOM_SITE || P.ladder_k ||
+            (mode == AnnealMode::Replay && min_snap_words(groups[i]))) {
+            if (mode == AnnealMode::Replay) gather_sel.push_back(i);
+            else if (ladder_rows_d(groups[i])) ladder_rows_sel[ladder_rows_d(groups[i])].push_back(i);
+            else if (ladder_planar_d(groups[i])) ladder_planar_sel[ladder_planar_d(groups[i])].push_back(i);
+            else (P.ladder_k ? ladder_sel : site_sel).push_back(i);
             continue;
         }
         total_syn += groups[i].n_syn;
@@ -1084,11 +1140,15 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
             const int64_t n = g.n_syn * (int64_t)P.lat.nq, nc = g.n_syn * 4 * (int64_t)g.n_rep;
             if ((n + 255) / 256 * 256 > kMaxLaunchItems) { set_error("too many recovery bytes in one group"); return XZZX_ERANGE; }
             const dim3 grid((unsigned)((n + 255) / 256));
-            if (P.order == XZZX_ORDER_RANDOM_SITE || P.ladder_k)
+            if (const int ld = ladder_rows_d(g))
+                hipLaunchKernelGGL(k_static_recovery, grid, dim3(256), 0, stream, ws[i].min_snap,
+                                   (int)min_snap_words(g), ws[i].best_chain, g.n_rep, ld, g.n_syn,
+                                   2 * (ld + 1) <= 32 ? 1 : 2, g.d_recovery);
+            else if (P.order == XZZX_ORDER_RANDOM_SITE || (P.ladder_k && !ladder_planar_d(g)))
                 hipLaunchKernelGGL(k_site_recovery, grid, dim3(256), 0, stream, ws[i].min_snap, nc, ws[i].best_chain,
                                    g.n_rep, P.lat.nq, g.n_syn, g.d_recovery);
             else
-                hipLaunchKernelGGL(k_rows_recovery, grid, dim3(256), 0, stream, ws[i].min_snap, (int)min_snap_words(P),
+                hipLaunchKernelGGL(k_rows_recovery, grid, dim3(256), 0, stream, ws[i].min_snap, (int)min_snap_words(g),
                                    ws[i].best_chain, g.n_rep, P.lat.nq, g.n_syn, P.ddev, P.row_words, g.d_recovery);
             rc = check_hip(hipGetLastError(), "recovery gather launch");
         }
@@ -1114,6 +1174,12 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
     for (int d = 3; d <= kPlanarStaticMaxD; d += 2)
         if (!planar_sel[d].empty())
             sets.push_back({&planar_sel[d], true, 1, d_counters + 41 + (d - 3) / 2, 0, false, d, false});
+    for (int d = 3; d <= kLadderRowsMaxD; d += 2)
+        if (!ladder_rows_sel[d].empty())
+            sets.push_back({&ladder_rows_sel[d], true, 1, d_counters + 49 + (d - 3) / 2, d, false, 0, true});
+    for (int d = 3; d <= kPlanarStaticMaxD; d += 2)
+        if (!ladder_planar_sel[d].empty())
+            sets.push_back({&ladder_planar_sel[d], true, 1, d_counters + 56 + (d - 3) / 2, 0, false, d, true});
     for (int d = kStaticMinD; d <= kStaticMaxD; d += 2)
         if (!static_sel[d].empty())
             sets.push_back({&static_sel[d], true, 1, d_counters + 16 + (d - kStaticMinD) / 2, d, false, 0, false});

@@ -29,16 +29,6 @@ __device__ __forceinline__ LadderLds ladder_layout(int M, int ntypes, int nranks
     return o;
 }
 
-// The exchange rule's threshold T(n) = floor(prod over the set bits i of n
-// of R_i / 2^32), the product in 64-bit fixed point from 2^64 - 1.
-__device__ __forceinline__ uint32_t swap_threshold(const uint64_t *R, uint32_t n)
-{
-    uint64_t p = ~0ull;
-    for (int i = 0; i < 32; ++i)
-        if ((n >> i) & 1u) p = __umul64hi(p, R[i]);
-    return (uint32_t)(p >> 32);
-}
-
 // snap: each chain's packed state at its first E_min (word w of chain ci at
 // snap[w * snap_stride + ci]), from which the recovery is gathered
 __device__ inline void ladder_core(const PlanDev *pl, const ChainJob &J, uint32_t seed_lo, uint32_t seed_hi,

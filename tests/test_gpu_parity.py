@@ -199,13 +199,20 @@ def test_random_site_plain_graph_and_mixed():
 
 @pytest.mark.parametrize("layout,d,n_syn,R,K,sweeps", [(0, 3, 40, 4, 4, 30), (0, 11, 9, 8, 2, 20),
                                                        (0, 11, 5, 16, 16, 10), (1, 9, 7, 10, 1, 25),
-                                                       (1, 7, 6, 8, 8, 15), (0, 21, 2, 4, 4, 6), (0, 5, 3, 2, 2, 0)])
+                                                       (1, 7, 6, 8, 8, 15), (0, 21, 2, 4, 4, 6), (0, 5, 3, 2, 2, 0),
+                                                       (0, 3, 9, 16, 4, 30), (0, 7, 5, 16, 1, 20),
+                                                       (0, 13, 4, 32, 8, 12), (0, 15, 3, 16, 2, 8),
+                                                       (0, 9, 3, 16, 4, 0), (1, 3, 11, 4, 2, 30),
+                                                       (1, 15, 3, 8, 4, 6), (1, 11, 5, 12, 4, 10)])
 def test_replica_exchange_ladders(layout, d, n_syn, R, K, sweeps):
     """Replica exchange: ladders of K levels from beta 0.4 to 1.6 (replicas
     of a ladder share one greedy reference); every chain (E, E_min, stop,
     final state), the coset minima and the recovery (the best chain's state
     kept at its first E_min) equal the oracle's ladders, for ladders of one
-    to sixteen levels, both layouts, ragged tails and zero sweeps."""
+    to sixteen levels, both layouts, ragged tails and zero sweeps.  Rotated
+    d <= 15 with 4R a multiple of 64 and every planar d <= 15 run on the
+    packed-row kernels specialised to d, the rest on the generic ladder
+    kernel."""
     prob = Problem(layout, d, 0.15, 5.0, n_syn, R, sweeps, seed=1200 + d + K, conv=1 if layout else 0)
     plan = gpu_plan(prob)
     plan.set_ladder(K, 0.4, 1.6)
@@ -218,22 +225,29 @@ def test_replica_exchange_plain_graph_and_errors():
     """Ladders in the plain form, in a captured hipGraph beside an annealing
     group, and their argument checks."""
     pl_ = Problem(0, 9, 0.2, 10.0, 5, 8, 12, seed=88)
+    pr = Problem(0, 9, 0.2, 10.0, 3, 16, 12, seed=88)     # the rotated kernel specialised to d = 9
+    pp = Problem(1, 5, 0.2, 10.0, 3, 6, 12, seed=88, conv=1)   # the planar kernel specialised to d = 5
     pa = Problem(0, 11, 0.2, 10.0, 4, 16, 12, seed=88)
-    ref_l = pl_.oracle_decode(order=O.ORDER_LADDER, ladder=(4, 0.3, 2.0))
+    ladders = [pl_, pr, pp]
+    refs = [p_.oracle_decode(order=O.ORDER_LADDER, ladder=(2 if p_ is pp else 4, 0.3, 2.0)) for p_ in ladders]
     ref_a = pa.oracle_decode()
-    plan_l = gpu_plan(pl_)
-    plan_l.set_ladder(4, 0.3, 2.0)
-    compare_decode(pl_, run_decode(pl_, plan_l, flags=X.FLAG_PLAIN), ref_l)
+    plans = []
+    for p_, ref in zip(ladders, refs):
+        plan = gpu_plan(p_)
+        plan.set_ladder(2 if p_ is pp else 4, 0.3, 2.0)
+        compare_decode(p_, run_decode(p_, plan, flags=X.FLAG_PLAIN), ref)
+        plans.append(plan)
+    plan_l = plans[0]
     plan_a = gpu_plan(pa)
-    gl_, ol_ = D.make_group(plan_l, pl_.n_rep, to_dev(pl_.uid.view(np.int32)), syn=to_dev(pl_.syn), want_chains=True)
-    ga_, oa_ = D.make_group(plan_a, pa.n_rep, to_dev(pa.uid.view(np.int32)), syn=to_dev(pa.syn), want_chains=True)
-    G = D.Graph([gl_, ga_], pl_.greedy_seed, pl_.anneal_seed)
+    made = [D.make_group(plan, p_.n_rep, to_dev(p_.uid.view(np.int32)), syn=to_dev(p_.syn), want_chains=True)
+            for plan, p_ in zip(plans + [plan_a], ladders + [pa])]
+    G = D.Graph([g for g, _ in made], pl_.greedy_seed, pl_.anneal_seed)
     for _ in range(3):
         G.launch()
         G.stream.synchronize()
         torch.cuda.synchronize()
-        compare_decode(pl_, ol_, ref_l)
-        compare_decode(pa, oa_, ref_a)
+        for (_, o), p_, ref in zip(made, ladders + [pa], refs + [ref_a]):
+            compare_decode(p_, o, ref)
     with pytest.raises(X.XzzxError):
         plan_l.set_ladder(3, 0.3, 2.0)
     with pytest.raises(X.XzzxError):
