@@ -116,7 +116,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=20000, help="most requests per arrival rate (--serve)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="arrival window per rate (--serve): min(--requests, rate x this) requests")
-    ap.add_argument("--slice", type=int, default=400,
+    ap.add_argument("--slice", type=int, default=250,
                     help="sweeps per serving slice of the costliest resident request (--serve)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="most lanes per chain the server may use (--serve; 0: library default, 1: plan kernels)")

@@ -375,7 +375,8 @@ int xzzx_probe_lds(int bytes_per_read, int waves_per_simd, int iters, void *stre
  * thread owns a HIP stream on the device current at creation and runs time
  * slices: at each slice boundary it admits queued requests (greedy references
  * computed on the device), advances every resident request by
- * sweeps_per_slice sweeps in one launch per kernel family (requests of
+ * sweeps_per_slice sweeps (more with many requests resident: see the
+ * field) in one launch per kernel family (requests of
  * different distance and noise mix freely; a request advances a number of
  * sweeps inversely proportional to the sequential work of one of its sweeps,
  * so the tasks of a slice carry equal work), and finishes requests whose
@@ -397,18 +398,20 @@ int xzzx_probe_lds(int bytes_per_read, int waves_per_simd, int iters, void *stre
  * max_lanes_per_chain for which the slice's wavefronts stay within max_waves
  * and its LDS within the budget; a request then runs on the byte-state kernel
  * with that many lanes per chain, or fewer where fewer already give each lane
- * at most one block of four generators of a colour class, which cuts its
- * latency when the device is lightly loaded.  When even two lanes do
- * not fit, every request runs on its plan's own kernel choice.  Results do
- * not depend on this choice. */
+ * one generator of a colour class (or, when the class has more generators
+ * than that many lanes, at most one block of four), which cuts its latency
+ * when the device is lightly loaded.  When even two lanes do not fit, every
+ * request runs on its plan's own kernel choice.  Results do not depend on
+ * this choice. */
 typedef struct xzzx_server xzzx_server;
 
 typedef struct {
     int max_slots;            /* resident requests (device slots) */
     int max_rep;              /* largest n_rep of a request */
     int max_qubits;           /* largest lattice (qubits) of a request */
-    int sweeps_per_slice;     /* sweeps per slice of the largest resident lattice (>= 1);
-                                 smaller lattices advance proportionally more */
+    int sweeps_per_slice;     /* sweeps per slice of the largest resident lattice (>= 1) with up
+                                 to 63 requests resident, one more sweeps_per_slice per further
+                                 64; smaller lattices advance proportionally more */
     int max_pending;          /* queued requests before submit returns EAGAIN */
     int greedy_mode;          /* XZZX_GREEDY_* */
     int64_t lds_budget_bytes; /* 0: four times the device's total LDS */

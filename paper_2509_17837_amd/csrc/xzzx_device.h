@@ -267,6 +267,9 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
     const int gl = lane & ((1 << LOGG) - 1);
     const int nq = pl->nq, M = pl->M, nblk = pl->nblk, nranks = pl->nranks;
     const uint32_t kneg = (uint32_t)pl->kneg;
+    // a chain with at least as many lanes as a class has moves runs one move
+    // per lane, else whole Philox blocks per lane (same draws, same chain)
+    const bool per_move = LOGG >= 2 && M <= (1 << LOGG);
     int32_t W[4];
     W[0] = pl->W[0]; W[1] = pl->W[1]; W[2] = pl->W[2]; W[3] = pl->W[3];
     const LdsLayout lo = lds_layout(M, pl->ntypes, nranks);
@@ -358,6 +361,32 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
         for (int k = 0; k < 4; ++k) {
             const uint2 *dk = desc_s + k * M;
             int32_t acc_de = 0;
+            if (per_move) {
+                // one move per lane: lane gl takes move gl of the class, with
+                // word gl mod 4 of the class's Philox block gl / 4 (the four
+                // lanes of a block each draw it, side by side).  The moves of
+                // a class touch disjoint qubits, so each lane's loads and
+                // stores are independent of the others'; this halves the
+                // sequential LDS work of a phase against whole blocks per lane.
+                const uint4 rnd = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)gl >> 2),
+                                                seed_lo, seed_hi);
+                const uint32_t sw = (uint32_t)gl & 3u;
+                const uint32_t u = sw == 0 ? rnd.x : sw == 1 ? rnd.y : sw == 2 ? rnd.z : rnd.w;
+                const uint2 d = dk[min(gl, M - 1)];
+                const uint32_t a0 = ((d.x & 0xFFFFu) << LOGC) + c, a1 = ((d.x >> 16) << LOGC) + c;
+                const uint32_t a2 = ((d.y & 0xFFFFu) << LOGC) + c, a3 = (((d.y >> 16) & 0x7FFu) << LOGC) + c;
+                const uint32_t c0 = st[a0], c1 = st[a1], c2 = st[a2], c3 = st[a3];
+                const uint32_t pat = c0 | (c1 << 2) | (c2 << 4) | (c3 << 6);
+                const uint32_t rank = lut_s[((d.y >> 27) << 8) | pat];
+                const int2 et = et_s[rank];
+                if (gl < M && (rank < kneg || u < (uint32_t)et.y)) {
+                    st[a0] = (uint8_t)(c0 ^ 2u);
+                    st[a1] = (uint8_t)(c1 ^ 1u);
+                    st[a2] = (uint8_t)(c2 ^ 1u);
+                    st[a3] = (uint8_t)(c3 ^ 2u);
+                    acc_de = et.x;
+                }
+            } else
             for (int b = gl; b < nblk; b += (1 << LOGG)) {
                 const uint4 rnd = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)b),
                                                 seed_lo, seed_hi);

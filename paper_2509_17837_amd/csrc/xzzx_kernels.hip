@@ -93,6 +93,7 @@ struct GreedyArgs {
     uint32_t seed_lo, seed_hi;
     int max_nodes;
     int rep_div;               // ladders: replica r draws the keys of replica r / rep_div (0 or 1: itself)
+    int cache_entries;         // LDS words per colour for the pair weights (0: none)
     int64_t block0;            // (syndrome, replica) pair of workgroup 0 of this launch
 };
 
@@ -193,6 +194,9 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
     // share one set)
     constexpr int kSets = SPLIT ? 2 : 1;
     int16_t *cands = reinterpret_cast<int16_t *>(reinterpret_cast<int32_t *>(smem + 4 * nwords) + kSets * 4 * stride);
+    // pair-weight cache after the free flags, 16-byte aligned
+    const uint32_t cache_off =
+        ((uint32_t)(4 * nwords + kSets * 4 * 4 * stride + 2 * kWave * kGreedyTies + kSets * stride) + 15u) & ~15u;
     __shared__ int s_count[2];
 
     for (int i = lane; i < nwords; i += kWave) cfgw[i] = 0;
@@ -231,6 +235,33 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
             __syncthreads();
             int nfree = na;
             const bool randomized = A.mode == XZZX_GREEDY_RANDOM;
+            // a pair (i, j) weighs the interior distance or the two boundary
+            // distances, whichever is less; a pair with the virtual node (an
+            // odd count) weighs the real defect's boundary distance
+            auto weight_of_pair = [&](int i, int j, int32_t dj) -> uint32_t {
+                return i == nd ? (uint32_t)dbD[j] : j == nd ? (uint32_t)dbD[i] : (uint32_t)min(dj, dbD[i] + dbD[j]);
+            };
+            // every pair weight in LDS when the defects fit the cache (rows of
+            // an odd stride: the lanes' reads of one column fall in distinct
+            // banks), so the rounds after the first scan LDS, not the table in
+            // L2; the weights are the same either way
+            uint32_t *wc = reinterpret_cast<uint32_t *>(smem + cache_off) + set * A.cache_entries;
+            const int rs = na | 1;
+            const bool cached = (int64_t)na * rs <= (int64_t)A.cache_entries;
+            if (cached) {
+                for (int i = hl; i < na; i += kHalf) {
+                    const int32_t *drow = dint + (size_t)(i == nd ? 0 : D[i]) * n;
+                    for (int j0 = 0; j0 < na; j0 += kGreedyBatch) {
+                        int32_t dv[kGreedyBatch];
+#pragma unroll
+                        for (int k = 0; k < kGreedyBatch; ++k) dv[k] = drow[j0 + k < nd ? D[j0 + k] : 0];
+#pragma unroll
+                        for (int k = 0; k < kGreedyBatch; ++k)
+                            if (j0 + k < na) wc[i * rs + j0 + k] = weight_of_pair(i, j0 + k, dv[k]);
+                    }
+                }
+            }
+            __syncthreads();
             // every round matches at least the least free pair, so na/2 rounds
             // suffice (rounds continue while either half has work).  Free
             // defects only leave, so a defect whose least partner is still free
@@ -246,19 +277,19 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
                     // wavefront draw one for nearly every partner.  The interior
                     // distances of a batch of partners are loaded before any is used.
                     const bool iv = i == nd;   // the virtual boundary node
-                    const int32_t dbi = iv ? 0 : dbD[i];
                     const int32_t *drow = dint + (size_t)(iv ? 0 : D[i]) * n;
+                    const uint32_t *wrow = wc + i * rs;
                     int16_t *cand = cands + lane * kGreedyTies;
                     auto weight = [&](int j, int32_t dj) -> uint32_t {
-                        // a pair with the virtual node weighs the real defect's boundary distance
-                        return iv ? (uint32_t)dbD[j] : j == nd ? (uint32_t)dbi : (uint32_t)min(dj, dbi + dbD[j]);
+                        return cached ? wrow[j] : weight_of_pair(i, j, dj);
                     };
                     uint32_t bw = 0xFFFFFFFFu;
                     int nt = 0;   // partners at weight bw
                     for (int j0 = 0; j0 < na; j0 += kGreedyBatch) {
                         int32_t dv[kGreedyBatch];
 #pragma unroll
-                        for (int k = 0; k < kGreedyBatch; ++k) dv[k] = drow[j0 + k < nd ? D[j0 + k] : 0];
+                        for (int k = 0; k < kGreedyBatch; ++k)
+                            dv[k] = cached ? 0 : drow[j0 + k < nd ? D[j0 + k] : 0];
 #pragma unroll
                         for (int k = 0; k < kGreedyBatch; ++k) {
                             const int j = j0 + k;
@@ -287,7 +318,7 @@ __global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
                             // more ties than the list holds: scan again
                             for (int j = bj + 1; j < na; ++j) {
                                 if (j == i || !freef[j]) continue;
-                                const int32_t dj = (!iv && j < nd) ? drow[D[j]] : 0;
+                                const int32_t dj = (!cached && !iv && j < nd) ? drow[D[j]] : 0;
                                 if (weight(j, dj) != bw) continue;
                                 const uint32_t id = pair_id(j), key = pair_key(id);
                                 if (key < bk) { bk = key; bid = id; bj = j; }
@@ -666,15 +697,25 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // the whole wavefront per colour on larger lattices.
 static bool greedy_split(const Plan &P) { return std::max(P.hdev.ncol[0], P.hdev.ncol[1]) <= 128; }
 
-static int greedy_lds(const Plan &P, int *max_nodes)
+// LDS of a greedy workgroup: the configuration, per colour set D, best,
+// pairs, dbD and the free flags (one set per colour when the halves of the
+// wavefront match the colours at once, else one), the tie lists, and, with
+// `cache` (launches of few wavefronts, where latency matters more than
+// occupancy), the pair-weight cache of each set: 16 KiB per colour when the
+// colours run side by side (up to 63 defects), 48 KiB otherwise (up to 109).
+static int greedy_lds(const Plan &P, bool cache, GreedyArgs *A)
 {
     const int mn = std::max(P.hdev.ncol[0], P.hdev.ncol[1]);
-    *max_nodes = mn;
-    // D, best, pairs, dbD and the free flags: one set per colour when the
-    // halves of the wavefront match the colours at once, else one
+    A->max_nodes = mn;
     const int sets = greedy_split(P) ? 2 : 1;
-    return 4 * ((P.lat.nq + 3) / 4) + sets * 4 * 4 * (mn + 1) + 2 * kWave * kGreedyTies + sets * (mn + 1) + 16;
+    const int base = 4 * ((P.lat.nq + 3) / 4) + sets * 4 * 4 * (mn + 1) + 2 * kWave * kGreedyTies + sets * (mn + 1);
+    A->cache_entries = cache ? (sets == 2 ? 4096 : 12288) : 0;
+    return ((base + 15) & ~15) + sets * 4 * A->cache_entries + 16;
 }
+
+// launches of at most this many (syndrome, replica) wavefronts cache the pair
+// weights in LDS
+constexpr int64_t kGreedyCacheWaves = 2048;
 
 static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_uid, int64_t n_syn,
                          int n_rep, uint64_t seed, int mode, uint8_t *d_refs, uint8_t *d_qraw,
@@ -694,10 +735,10 @@ static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_
     A.syn_stride = P.lat.nstab;
     A.seed_lo = (uint32_t)seed;
     A.seed_hi = (uint32_t)(seed >> 32);
-    const int lds = greedy_lds(P, &A.max_nodes);
     // one launch addresses fewer than 2^32 work-items: the (syndrome, replica)
     // pairs go in chunks of at most that many wavefronts
     const int64_t blocks = n_syn * n_rep;
+    const int lds = greedy_lds(P, blocks <= kGreedyCacheWaves, &A);
     for (int64_t b0 = 0; b0 < blocks; b0 += kMaxLaunchWaves) {
         A.block0 = b0;
         const int64_t nb = std::min<int64_t>(kMaxLaunchWaves, blocks - b0);
@@ -1354,7 +1395,7 @@ int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const 
     A.mode = mode;
     A.seed_lo = (uint32_t)seed;
     A.seed_hi = (uint32_t)(seed >> 32);
-    const int lds = greedy_lds(P, &A.max_nodes);
+    const int lds = greedy_lds(P, true, &A);
     hipLaunchKernelGGL(greedy_split(P) ? k_greedy<true> : k_greedy<false>, dim3((unsigned)(n * n_rep)), dim3(kWave),
                        lds, stream, A);
     return check_hip(hipGetLastError(), "serving greedy launch");

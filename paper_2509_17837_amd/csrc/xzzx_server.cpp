@@ -127,6 +127,9 @@ size_t task_lds(const Plan &P, int *chains_per_task)
     return P.lds_bytes_anneal(P.lanes);
 }
 
+// resident requests per additional sweeps_per_slice of a slice
+constexpr int64_t kSliceGrowth = 64;
+
 // Philox blocks (four generators each) of a colour class: the byte-state
 // kernel gives each lane of a chain whole blocks
 int class_blocks(const Plan &P)
@@ -134,25 +137,35 @@ int class_blocks(const Plan &P)
     return (std::max(1, P.lat.nstab / 4) + 3) / 4;
 }
 
-// lanes per chain for a request when the slice offers g: the least power of
-// two that gives every lane at most one block, capped at g (more lanes would
-// sit idle)
+// lanes per chain for a request when the slice offers g: where g lanes can
+// take every generator of a colour class, the least power of two that gives
+// each lane one generator (the byte-state kernel's one-move-per-lane form);
+// else the least power of two that gives every lane at most one block,
+// capped at g (more lanes would sit idle)
 int lanes_for(const Plan &P, int g)
 {
-    const int nblk = class_blocks(P);
+    const int M = std::max(1, P.lat.per_class);
     int c = 1;
+    if (M <= g && g >= 4) {
+        while (c < M) c *= 2;
+        return std::max(c, 4);
+    }
+    const int nblk = class_blocks(P);
     while (c < nblk && 2 * c <= g) c *= 2;
     return c;
 }
 
 // sequential work of one sweep of one chain: attempts on the packed-row
-// kernels (g = 1); blocks per lane on the byte-state kernel, whose sweep
-// latency is set by the blocks each lane runs in turn
+// kernels (g = 1); on the byte-state kernel, in units of half a block per
+// lane: one generator per lane measured half the phase latency of one block
+// per lane (0.47 and 0.92 us at 64 lanes), and each further block per lane
+// adds about one block's latency
 int64_t sweep_cost(const Plan &P, int g)
 {
     if (g == 1) return P.lat.nstab;
     const int gr = lanes_for(P, g);
-    return (class_blocks(P) + gr - 1) / gr;
+    if (std::max(1, P.lat.per_class) <= gr && gr >= 4) return 1;
+    return 2 * ((class_blocks(P) + gr - 1) / gr);
 }
 
 size_t request_lds(const Plan &P, int n_rep)
@@ -277,10 +290,16 @@ int xzzx_server::slice()
     // the costliest resident request
     int64_t ref_cost = 1;
     for (int s : resident) ref_cost = std::max(ref_cost, sweep_cost(*slots[s].plan, G));
+    // short slices at light load let arrivals join soon after they come;
+    // with more requests resident the slices lengthen (one more
+    // sweeps_per_slice per kSliceGrowth requests), so the fixed costs of a
+    // slice (admission, host scheduling, the wait for its longest task) stay
+    // small against its work
+    const int64_t slice_sweeps = (int64_t)cfg.sweeps_per_slice * (1 + (int64_t)resident.size() / kSliceGrowth);
     for (int s : resident) {
         Slot &sl = slots[s];
         const Plan &P = *sl.plan;
-        const int64_t share = std::max<int64_t>(1, (int64_t)cfg.sweeps_per_slice * ref_cost / sweep_cost(P, G));
+        const int64_t share = std::max<int64_t>(1, slice_sweeps * ref_cost / sweep_cost(P, G));
         const int t0 = sl.t, t1 = (int)std::min<int64_t>(P.n_sweeps, t0 + share);
         // a fresh request always gets a first task (it initialises E, E_min
         // and the stored state even for an empty schedule)
