@@ -1176,8 +1176,10 @@ __device__ __forceinline__ void rows_static_core(const PlanDev *pl, const ChainJ
 __device__ __forceinline__ uint32_t swap_threshold(const uint64_t *R, uint32_t n)
 {
     uint64_t p = ~0ull;
-    for (int i = 0; i < 32; ++i)
-        if ((n >> i) & 1u) p = __umul64hi(p, R[i]);
+    // bits in ascending order, up to the highest set one
+    int i = 0;
+    for (uint32_t m = n; m != 0u; m >>= 1, ++i)
+        if (m & 1u) p = __umul64hi(p, R[i]);
     return (uint32_t)(p >> 32);
 }
 
