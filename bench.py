@@ -777,14 +777,22 @@ def serve_rate(args, S, rate, seconds, keep=()):
                    max_lanes_per_chain=args.lanes, max_waves=args.waves)
     t0 = time.perf_counter()
     tickets = []
-    for i, (k, _) in enumerate(S["reqs"][:n_rate]):
-        while True:
-            now = time.perf_counter() - t0
-            if now >= arr[i]:
-                break
+    i = 0
+    # every request whose arrival time has passed goes in one submission, so
+    # the Python loop keeps up with the offered rate
+    while i < n_rate:
+        now = time.perf_counter() - t0
+        if now < arr[i]:
             if arr[i] - now > 2e-4:
                 time.sleep((arr[i] - now) * 0.5)
-        tickets.append(srv.submit(S["plans"][k], S["syns"][i], 7_000_000 + i, S["R"]))
+            continue
+        j = i + 1
+        while j < n_rate and arr[j] <= now:
+            j += 1
+        ks = [S["reqs"][m][0] for m in range(i, j)]
+        tickets += srv.submit_many([S["plans"][k] for k in ks], S["syns"][i:j], range(7_000_000 + i, 7_000_000 + j),
+                                   S["R"])
+        i = j
     srv.drain()
     wall = time.perf_counter() - t0
     st = srv.stats()

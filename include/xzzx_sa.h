@@ -452,6 +452,13 @@ int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out);
  * are queued, EINVAL if it does not fit the server's slots. */
 int xzzx_server_submit(xzzx_server *srv, const xzzx_request *req, uint64_t *ticket);
 
+/* Queue reqs[0..n-1] in order, as n calls of xzzx_server_submit would, with
+ * one lock and one wake-up of the scheduler (callers feeding many requests
+ * at once); tickets[i] (n entries, caller-owned) identifies request i.
+ * Stops at the first request that fails (EINVAL as above; EAGAIN when the
+ * queue fills) and returns its status; *n_done requests were queued. */
+int xzzx_server_submit_many(xzzx_server *srv, const xzzx_request *reqs, int n, uint64_t *tickets, int *n_done);
+
 /* XZZX_OK and the result (released by this call) if done; ENOTREADY while
  * queued or resident; EINVAL for an unknown or already collected ticket. */
 int xzzx_server_poll(xzzx_server *srv, uint64_t ticket, xzzx_result *out);

@@ -160,6 +160,7 @@ def lib():
         "xzzx_probe_lds": (I, [I, I, I, V, P(D)]),
         "xzzx_server_create": (I, [P(ServerCfg), P(V)]),
         "xzzx_server_submit": (I, [V, P(Request), P(U64)]),
+        "xzzx_server_submit_many": (I, [V, P(Request), I, P(U64), P(C.c_int)]),
         "xzzx_server_poll": (I, [V, U64, P(Result)]),
         "xzzx_server_drain": (I, [V]),
         "xzzx_server_stats": (I, [V, P(ServeStats)]),

@@ -714,7 +714,9 @@ static int greedy_lds(const Plan &P, bool cache, GreedyArgs *A)
 }
 
 // launches of at most this many (syndrome, replica) wavefronts cache the pair
-// weights in LDS
+// weights in LDS (larger ones keep the occupancy instead: a serving slice
+// admitting thousands of requests ran its greedy launches 20 % slower with
+// the cache)
 constexpr int64_t kGreedyCacheWaves = 2048;
 
 static int launch_greedy(const Plan &P, const uint8_t *d_syn, const uint32_t *d_uid, int64_t n_syn,
@@ -1395,7 +1397,7 @@ int serve_greedy(const Plan &P, const uint8_t *d_syn, int64_t syn_stride, const 
     A.mode = mode;
     A.seed_lo = (uint32_t)seed;
     A.seed_hi = (uint32_t)(seed >> 32);
-    const int lds = greedy_lds(P, true, &A);
+    const int lds = greedy_lds(P, (int64_t)n * n_rep <= kGreedyCacheWaves, &A);
     hipLaunchKernelGGL(greedy_split(P) ? k_greedy<true> : k_greedy<false>, dim3((unsigned)(n * n_rep)), dim3(kWave),
                        lds, stream, A);
     return check_hip(hipGetLastError(), "serving greedy launch");

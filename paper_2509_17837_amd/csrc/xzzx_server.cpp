@@ -570,9 +570,10 @@ int xzzx_server_create(const xzzx_server_cfg *cfg, xzzx_server **out)
     return XZZX_OK;
 }
 
-int xzzx_server_submit(xzzx_server *srv, const xzzx_request *req, uint64_t *ticket)
+// a request the server can hold, or the error it gets
+static int check_request(const xzzx_server *srv, const xzzx_request *req)
 {
-    if (!srv || !req || !ticket || !req->plan || !req->syndrome) { set_error("NULL argument"); return XZZX_EINVAL; }
+    if (!req || !req->plan || !req->syndrome) { set_error("NULL argument"); return XZZX_EINVAL; }
     const Plan &P = req->plan->P;
     if (P.order != XZZX_ORDER_COLOUR || P.ladder_k) {
         set_error("the serving loop runs annealing plans with colour sweeps only");
@@ -583,26 +584,61 @@ int xzzx_server_submit(xzzx_server *srv, const xzzx_request *req, uint64_t *tick
         return XZZX_EINVAL;
     }
     if (request_lds(P, req->n_rep) > srv->lds_budget) { set_error("request needs more LDS than the budget"); return XZZX_EINVAL; }
-    Pending p;
-    p.plan = req->plan;
-    p.syn.assign(req->syndrome, req->syndrome + P.lat.nstab);
-    p.uid = req->uid;
-    p.n_rep = req->n_rep;
-    p.submit = Clock::now();
+    return XZZX_OK;
+}
+
+// queue requests [0, n) in order under one lock; *n_done of them queued
+static int submit_requests(xzzx_server *srv, const xzzx_request *reqs, int n, uint64_t *tickets, int *n_done)
+{
+    *n_done = 0;
+    std::vector<Pending> batch((size_t)n);
+    const auto now = Clock::now();
+    int rc = XZZX_OK, ok = 0;
+    for (; ok < n; ++ok) {
+        rc = check_request(srv, &reqs[ok]);
+        if (rc) break;
+        Pending &p = batch[(size_t)ok];
+        p.plan = reqs[ok].plan;
+        p.syn.assign(reqs[ok].syndrome, reqs[ok].syndrome + reqs[ok].plan->P.lat.nstab);
+        p.uid = reqs[ok].uid;
+        p.n_rep = reqs[ok].n_rep;
+        p.submit = now;
+    }
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->error) { set_error(srv->error_msg); return srv->error; }
-    if ((int)srv->pending.size() >= srv->cfg.max_pending) {
-        ++srv->rejected;
-        set_error("server queue full");
-        return XZZX_EAGAIN;
+    for (int i = 0; i < ok; ++i) {
+        if ((int)srv->pending.size() >= srv->cfg.max_pending) {
+            ++srv->rejected;
+            set_error("server queue full");
+            rc = XZZX_EAGAIN;
+            break;
+        }
+        Pending &p = batch[(size_t)i];
+        p.ticket = srv->next_ticket++;
+        tickets[i] = p.ticket;
+        srv->where[p.ticket] = 0;
+        srv->pending.push_back(std::move(p));
+        ++srv->submitted;
+        ++*n_done;
     }
-    p.ticket = srv->next_ticket++;
-    *ticket = p.ticket;
-    srv->where[p.ticket] = 0;
-    srv->pending.push_back(std::move(p));
-    ++srv->submitted;
-    srv->cv_work.notify_one();
-    return XZZX_OK;
+    if (*n_done) srv->cv_work.notify_one();
+    return rc;
+}
+
+int xzzx_server_submit(xzzx_server *srv, const xzzx_request *req, uint64_t *ticket)
+{
+    if (!srv || !req || !ticket) { set_error("NULL argument"); return XZZX_EINVAL; }
+    int done = 0;
+    return submit_requests(srv, req, 1, ticket, &done);
+}
+
+int xzzx_server_submit_many(xzzx_server *srv, const xzzx_request *reqs, int n, uint64_t *tickets, int *n_done)
+{
+    if (!srv || !n_done) { set_error("NULL argument"); return XZZX_EINVAL; }
+    *n_done = 0;
+    if (n < 0 || (n > 0 && (!reqs || !tickets))) { set_error("bad request array"); return XZZX_EINVAL; }
+    if (n == 0) return XZZX_OK;
+    return submit_requests(srv, reqs, n, tickets, n_done);
 }
 
 int xzzx_server_poll(xzzx_server *srv, uint64_t ticket, xzzx_result *out)

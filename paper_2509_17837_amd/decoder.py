@@ -375,6 +375,23 @@ class Server:
         self._plans[t.value] = plan
         return t.value
 
+    def submit_many(self, plans, syndromes, uids, n_rep: int):
+        """Queue len(plans) requests in one call (xzzx_server_submit_many);
+        returns their tickets in order."""
+        n = len(plans)
+        if n == 0:
+            return []
+        syns = [np.ascontiguousarray(s, np.uint8) for s in syndromes]
+        reqs = (X.Request * n)(*[X.Request(pl.h, sy.ctypes.data_as(C.c_void_p), int(u) & 0xFFFFFFFF, n_rep)
+                                 for pl, sy, u in zip(plans, syns, uids)])
+        tickets = (C.c_uint64 * n)()
+        done = C.c_int(0)
+        rc = lib().xzzx_server_submit_many(self.h, reqs, n, tickets, C.byref(done))
+        for i in range(done.value):
+            self._plans[tickets[i]] = plans[i]
+        X.check("xzzx_server_submit_many", rc)
+        return [tickets[i] for i in range(n)]
+
     def try_submit(self, plan, syndrome, uid, n_rep):
         """Like submit, but returns None when the queue is full (EAGAIN)."""
         syn = np.ascontiguousarray(syndrome, np.uint8)

@@ -129,6 +129,44 @@ def test_admission_limits():
     assert st["p99_latency_s"] >= st["p50_latency_s"] > 0
 
 
+def test_submit_many():
+    """Requests queued in one call (xzzx_server_submit_many) are served like
+    single submissions; a request that does not fit stops the batch there
+    (EINVAL, the requests before it queued), and a full queue stops it with
+    EAGAIN."""
+    R = 4
+    a = Spec(7, 0.15, 10.0, 60, 6, 21, 900)
+    b = Spec(11, 0.2, 100.0, 60, 5, 22, 950)
+    srv = D.Server(max_slots=4, max_rep=R, max_qubits=121, sweeps_per_slice=20, greedy_seed=GS, anneal_seed=AS)
+    plans = [a.plan] * len(a.uid) + [b.plan] * len(b.uid)
+    syns = list(a.syn) + list(b.syn)
+    uids = list(a.uid) + list(b.uid)
+    tickets = srv.submit_many(plans, syns, uids, R)
+    assert len(set(tickets)) == len(plans)
+    srv.drain()
+    res = [srv.poll(t) for t in tickets]
+    oa, ob = a.batch(R), b.batch(R)
+    for i in range(len(a.uid)):
+        assert same(res[i], oa, i)
+    for i in range(len(b.uid)):
+        assert same(res[len(a.uid) + i], ob, i)
+    # a 13 x 13 lattice does not fit max_qubits = 121: the batch stops there
+    big = Spec(13, 0.15, 10.0, 10, 1, 23, 990)
+    with pytest.raises(X.XzzxError) as e:
+        srv.submit_many([a.plan, big.plan, a.plan], [a.syn[0], big.syn[0], a.syn[1]], [1, 2, 3], R)
+    assert e.value.rc == X.XZZX_EINVAL
+    srv.drain()
+    assert srv.stats()["submitted"] == len(plans) + 1
+    srv.close()
+    small = D.Server(max_slots=1, max_rep=R, max_qubits=49, sweeps_per_slice=20, max_pending=2,
+                     greedy_seed=GS, anneal_seed=AS)
+    with pytest.raises(X.XzzxError) as e:
+        small.submit_many([a.plan] * 6, list(a.syn), list(a.uid), R)
+    assert e.value.rc == X.XZZX_EAGAIN
+    small.drain()
+    small.close()
+
+
 def test_byte_kernel_and_empty_schedule():
     """Requests on the byte-state kernel (planar-free path via set_kernel) and
     with an empty schedule are served like the batch decoder serves them."""
