@@ -343,6 +343,10 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
     int32_t meta = J.cp_meta0;
     int sb = kept_scratch(meta);
     int sub = t_begin;
+    // one-move-per-lane form: the Philox block of the coming phase
+    uint4 rnd_pm = make_uint4(0u, 0u, 0u, 0u);
+    if (per_move)
+        rnd_pm = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t_begin, (uint32_t)gl >> 2), seed_lo, seed_hi);
 
     for (int t = t_begin; t < t_end && 4 * t < last_phase; ++t) {
         if (keep && t > sub && (t - t_begin) % kServeCheckpointEvery == 0) {
@@ -368,8 +372,11 @@ __device__ inline void bytes_core(const PlanDev *pl, const ChainJob &J, int t_be
                 // a class touch disjoint qubits, so each lane's loads and
                 // stores are independent of the others'; this halves the
                 // sequential LDS work of a phase against whole blocks per lane.
-                const uint4 rnd = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t + (uint32_t)k, (uint32_t)gl >> 2),
-                                                seed_lo, seed_hi);
+                // The block of the next phase (counter 4t + k + 1) is drawn
+                // here, so its multiplies overlap this phase's LDS round trips.
+                const uint4 rnd = rnd_pm;
+                rnd_pm = philox4x32_10(make_uint4(uid, cc, 4u * (uint32_t)t + (uint32_t)k + 1u, (uint32_t)gl >> 2),
+                                       seed_lo, seed_hi);
                 const uint32_t sw = (uint32_t)gl & 3u;
                 const uint32_t u = sw == 0 ? rnd.x : sw == 1 ? rnd.y : sw == 2 ? rnd.z : rnd.w;
                 const uint2 d = dk[min(gl, M - 1)];
