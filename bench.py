@@ -122,6 +122,8 @@ def parse():
                     help="most lanes per chain the server may use (--serve; 0: library default, 1: plan kernels)")
     ap.add_argument("--waves", type=int, default=0, help="wave budget per serving slice (--serve; 0: default)")
     ap.add_argument("--slots", type=int, default=32768, help="resident requests at most (--serve)")
+    ap.add_argument("--lds-budget", type=int, default=0,
+                    help="LDS bytes the resident requests' tasks may take (--serve; 0: library default)")
     ap.add_argument("--by-distance", action="store_true",
                     help="annealing rate of the default kernel for each odd d in --distances")
     ap.add_argument("--distances", default="11,13,15,17,21,25,29,31")
@@ -774,7 +776,7 @@ def serve_rate(args, S, rate, seconds, keep=()):
     arr = inputs.poisson_arrivals(rate, n_rate, S["seeds"]["sample"] + int(rate))
     srv = D.Server(max_slots=args.slots, max_rep=S["R"], max_qubits=max(d * d for d in S["wl"]["d"]),
                    sweeps_per_slice=args.slice, greedy_seed=S["seeds"]["greedy"], anneal_seed=S["seeds"]["anneal"],
-                   max_lanes_per_chain=args.lanes, max_waves=args.waves)
+                   max_lanes_per_chain=args.lanes, max_waves=args.waves, lds_budget_bytes=args.lds_budget)
     t0 = time.perf_counter()
     tickets = []
     i = 0
