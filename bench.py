@@ -327,7 +327,7 @@ def run_batch(args, name, B, steps, warm, tune=True, order="colour", ladder=""):
         kernel_name = "k_anneal_site"
     elif kinds == {X.KERNEL_LADDER} and layout == X.PLANAR and len(set(wl["d"])) == 1 and wl["d"][0] <= 15:
         kernel_name = f"k_anneal_ladder_planar_d{wl['d'][0]}"   # ladders on planar packed rows specialised to d
-    elif kinds == {X.KERNEL_LADDER} and len(set(wl["d"])) == 1 and wl["d"][0] <= 15 and (4 * R) % 64 == 0:
+    elif kinds == {X.KERNEL_LADDER} and len(set(wl["d"])) == 1 and wl["d"][0] <= 31 and (4 * R) % 64 == 0:
         kernel_name = f"k_anneal_ladder_rows_d{wl['d'][0]}"     # ladders on packed rows specialised to d
     elif kinds == {X.KERNEL_LADDER}:
         kernel_name = "k_anneal_ladder"

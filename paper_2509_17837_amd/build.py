@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxzzx_sa.so")
-SOURCES = ["xzzx_planar.hip", "xzzx_ladder_planar.hip", "xzzx_ladder_rows.hip", "xzzx_ladder.hip", "xzzx_serve_29.hip", "xzzx_serve_31.hip", "xzzx_serve_25.hip", "xzzx_serve_21.hip", "xzzx_serve_15.hip", "xzzx_serve_9.hip",
+SOURCES = ["xzzx_planar.hip", "xzzx_ladder_planar.hip", "xzzx_ladder_rows_c.hip", "xzzx_ladder_rows_b.hip", "xzzx_ladder_rows.hip", "xzzx_ladder.hip", "xzzx_serve_29.hip", "xzzx_serve_31.hip", "xzzx_serve_25.hip", "xzzx_serve_21.hip", "xzzx_serve_15.hip", "xzzx_serve_9.hip",
            "xzzx_static_h.hip", "xzzx_static_g.hip", "xzzx_static_f.hip", "xzzx_static_e.hip", "xzzx_static_d.hip",
            "xzzx_static_c.hip", "xzzx_static_b.hip", "xzzx_static_a.hip",
            "xzzx_kernels.hip", "xzzx_probe.hip", "xzzx_host.cpp", "xzzx_server.cpp", "xzzx_tune.cpp"]   # longest first

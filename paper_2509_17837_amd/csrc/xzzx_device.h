@@ -1576,6 +1576,7 @@ int planar_state_words(int d);
 // lattice)
 AnnealKernel ladder_kernel(bool plain);
 AnnealKernel ladder_rows_kernel(int d, bool plain);
+AnnealKernel ladder_rows_kernel_large(int d, bool plain);   // d = 17 .. 31 (NULL otherwise)
 AnnealKernel ladder_planar_kernel(int d, bool plain);
 int ladder_rows_state_words(int d);
 typedef void (*ServeKernel)(const ServeTask *, uint32_t, uint32_t);

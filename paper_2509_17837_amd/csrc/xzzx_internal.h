@@ -167,9 +167,8 @@ constexpr int kStaticRanks = 128;
 // lookup of six shapes and the 16-byte move-energy entries
 constexpr size_t kStaticLdsBytes = 2 * 256 * 6 + 16 * kStaticRanks;
 // Rotated distances whose replica-exchange ladders run on a packed-row
-// kernel specialised to d (one word per row); larger ones use the generic
-// ladder kernel.
-constexpr int kLadderRowsMaxD = 15;
+// kernel specialised to d (every distance with such an annealing kernel).
+constexpr int kLadderRowsMaxD = 31;
 // The specialised kernel's state checkpoints (the replay of a syndrome's
 // best chain starts from the last one before its E_min phase): every
 // kCheckpointEvery sweeps, or sparser so that a chain keeps at most

@@ -1123,9 +1123,9 @@ static int fork_join(hipStream_t stream, int n, F launch, bool serial = false)
 // rows, [1..7] byte states by lanes per chain, [16..30] the kernels
 // specialised to d = 3, 5, ..., 31, [40] random-site chains, [41..47] the
 // planar kernels specialised to d = 3, 5, ..., 15, [48] ladders on the generic
-// kernel, [49..55] and [56..62] ladders on the rotated and planar kernels
-// specialised to d = 3, 5, ..., 15; a replay (with its own d_counters base)
-// uses [0] and [2].
+// kernel, [49..55] and [31..38] ladders on the rotated kernels specialised to
+// d = 3, ..., 15 and d = 17, ..., 31, [56..62] on the planar ones
+// (d = 3, ..., 15); a replay (with its own d_counters base) uses [0] and [2].
 static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_groups, AnnealMode mode,
                          uint64_t seed, int64_t unit_offset, int64_t units_override, uint32_t *d_counters,
                          hipStream_t stream, bool serial = false)
@@ -1219,7 +1219,8 @@ static int launch_anneal(const xzzx_group *groups, const GroupWs *ws, int n_grou
             sets.push_back({&planar_sel[d], true, 1, d_counters + 41 + (d - 3) / 2, 0, false, d, false});
     for (int d = 3; d <= kLadderRowsMaxD; d += 2)
         if (!ladder_rows_sel[d].empty())
-            sets.push_back({&ladder_rows_sel[d], true, 1, d_counters + 49 + (d - 3) / 2, d, false, 0, true});
+            sets.push_back({&ladder_rows_sel[d], true, 1, d_counters + (d <= 15 ? 49 + (d - 3) / 2 : 31 + (d - 17) / 2),
+                            d, false, 0, true});
     for (int d = 3; d <= kPlanarStaticMaxD; d += 2)
         if (!ladder_planar_sel[d].empty())
             sets.push_back({&ladder_planar_sel[d], true, 1, d_counters + 56 + (d - 3) / 2, 0, false, d, true});

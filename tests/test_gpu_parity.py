@@ -203,16 +203,18 @@ def test_random_site_plain_graph_and_mixed():
                                                        (0, 3, 9, 16, 4, 30), (0, 7, 5, 16, 1, 20),
                                                        (0, 13, 4, 32, 8, 12), (0, 15, 3, 16, 2, 8),
                                                        (0, 9, 3, 16, 4, 0), (1, 3, 11, 4, 2, 30),
-                                                       (1, 15, 3, 8, 4, 6), (1, 11, 5, 12, 4, 10)])
+                                                       (1, 15, 3, 8, 4, 6), (1, 11, 5, 12, 4, 10),
+                                                       (0, 17, 2, 16, 4, 6), (0, 23, 2, 16, 2, 4),
+                                                       (0, 31, 1, 16, 16, 3)])
 def test_replica_exchange_ladders(layout, d, n_syn, R, K, sweeps):
     """Replica exchange: ladders of K levels from beta 0.4 to 1.6 (replicas
     of a ladder share one greedy reference); every chain (E, E_min, stop,
     final state), the coset minima and the recovery (the best chain's state
     kept at its first E_min) equal the oracle's ladders, for ladders of one
     to sixteen levels, both layouts, ragged tails and zero sweeps.  Rotated
-    d <= 15 with 4R a multiple of 64 and every planar d <= 15 run on the
-    packed-row kernels specialised to d, the rest on the generic ladder
-    kernel."""
+    lattices with 4R a multiple of 64 (d <= 31) and every planar d <= 15 run
+    on the packed-row kernels specialised to d, the rest on the generic
+    ladder kernel."""
     prob = Problem(layout, d, 0.15, 5.0, n_syn, R, sweeps, seed=1200 + d + K, conv=1 if layout else 0)
     plan = gpu_plan(prob)
     plan.set_ladder(K, 0.4, 1.6)
