@@ -1239,16 +1239,14 @@ __device__ __forceinline__ int ladder_exchange(int level, int32_t E, int K, uint
 
 // Task loop of the ladder kernels specialised to d (MODE 0: persistent
 // wavefronts on the atomic task queue; 2: one task per workgroup), tasks of
-// 64 consecutive chains; dynamic LDS: the offset table (3 KiB), then K
-// level tables.  core(G, J, lut_s, et_s) runs one lane's chain.
-constexpr uint32_t kLadderLutBytes = 2 * 256 * 6;
-
+// 64 consecutive chains.  The offset table is static LDS, so its address
+// folds into each lookup's instruction; the K level tables are dynamic LDS
+// (16 K n_ranks bytes).  core(G, J, lut_s, et_s) runs one lane's chain.
 template <int MODE, typename Core>
 __device__ __forceinline__ void ladder_static_body(const AnnealArgs &A, Core core)
 {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint16_t *lut_s = reinterpret_cast<uint16_t *>(smem);
-    uint4 *et_s = reinterpret_cast<uint4 *>(smem + kLadderLutBytes);
+    __shared__ uint16_t lut_s[256 * 6];
+    extern __shared__ __align__(16) uint4 et_s[];
     const PlanDev *loaded = nullptr;
     for (int iter = 0;; ++iter) {
         uint32_t task = 0;

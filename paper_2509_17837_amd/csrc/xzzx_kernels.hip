@@ -969,7 +969,7 @@ static int launch_set(const xzzx_group *groups, const GroupWs *ws, const std::ve
         const int C = kWave / lanes;
         tasks += (uint64_t)((units + C - 1) / C);
         lds = std::max(lds, (ladder && (static_d || planar_d))
-                                ? kLadderLutBytes + 16 * (size_t)P.ladder_k * P.nranks()
+                                ? 16 * (size_t)P.ladder_k * P.nranks()
                             : (static_d || planar_d) ? (size_t)0
                             : ladder ? P.lds_bytes_ladder()
                             : site   ? P.lds_bytes_site()
