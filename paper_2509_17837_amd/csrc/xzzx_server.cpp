@@ -263,7 +263,11 @@ int xzzx_server::slice()
 
     // ---- 2. one slice of sweeps for every resident request -----------------
     ServeTask *h_tasks = reinterpret_cast<ServeTask *>(h_stage + st_tasks);
-    std::vector<ServeTask> rows_t, bytes_t, static_t[kStaticMaxD + 1];
+    // (sequential work of the task, task): each family's tasks are staged
+    // longest first, so the slice's long tasks start early and short ones
+    // fill the device around them
+    using CostTask = std::pair<int64_t, ServeTask>;
+    std::vector<CostTask> rows_t, bytes_t, static_t[kStaticMaxD + 1];
     size_t lds_rows = 0, lds_bytes = 0;
     std::vector<int> finished;
     // lanes per chain for this slice: at light load every chain spreads over
@@ -333,9 +337,10 @@ int xzzx_server::slice()
                 while ((1 << lg) < gr) ++lg;
                 T.log_lanes = rows ? 0 : lg;
                 T.row_words = rows ? P.row_words : 0;
-                if (rows && P.static_d) static_t[serve_class_max(P.static_d)].push_back(T);
-                else if (rows) { rows_t.push_back(T); lds_rows = std::max(lds_rows, lds); }
-                else { bytes_t.push_back(T); lds_bytes = std::max(lds_bytes, lds); }
+                const int64_t cost = (int64_t)(t1 - t0) * sweep_cost(P, G);
+                if (rows && P.static_d) static_t[serve_class_max(P.static_d)].emplace_back(cost, T);
+                else if (rows) { rows_t.emplace_back(cost, T); lds_rows = std::max(lds_rows, lds); }
+                else { bytes_t.emplace_back(cost, T); lds_bytes = std::max(lds_bytes, lds); }
             }
             sl.t = t1;
         }
@@ -346,8 +351,9 @@ int xzzx_server::slice()
     // (largest lattices first)
     std::vector<ServeLaunch> launches;
     size_t nt = 0;
-    auto add = [&](const std::vector<ServeTask> &v, int kind, int d, size_t lds) {
+    auto add = [&](std::vector<CostTask> &v, int kind, int d, size_t lds) {
         if (v.empty()) return;
+        std::stable_sort(v.begin(), v.end(), [](const CostTask &a, const CostTask &b) { return a.first > b.first; });
         ServeLaunch L{};
         L.tasks = reinterpret_cast<const ServeTask *>(d_stage + st_tasks) + nt;
         L.n = (int32_t)v.size();
@@ -364,11 +370,10 @@ int xzzx_server::slice()
     if (nt > max_tasks) { set_error("serving task buffer overflow"); return XZZX_ERANGE; }
     if (nt) {
         size_t at = 0;
-        for (const auto *v : {&rows_t, &bytes_t}) { std::copy(v->begin(), v->end(), h_tasks + at); at += v->size(); }
-        for (int c : kClasses) {
-            std::copy(static_t[c].begin(), static_t[c].end(), h_tasks + at);
-            at += static_t[c].size();
-        }
+        for (const auto *v : {&rows_t, &bytes_t})
+            for (const CostTask &ct : *v) h_tasks[at++] = ct.second;
+        for (int c : kClasses)
+            for (const CostTask &ct : static_t[c]) h_tasks[at++] = ct.second;
         rc = check(hipMemcpyAsync(d_stage + st_tasks, h_tasks, nt * sizeof(ServeTask), hipMemcpyHostToDevice, stream),
                    "stage tasks");
         if (rc) return rc;
