@@ -157,9 +157,9 @@ int lanes_for(const Plan &P, int g)
 
 // sequential work of one sweep of one chain: attempts on the packed-row
 // kernels (g = 1); on the byte-state kernel, in units of half a block per
-// lane: one generator per lane measured half the phase latency of one block
-// per lane (0.47 and 0.92 us at 64 lanes), and each further block per lane
-// adds about one block's latency
+// lane: one generator per lane measured about half the phase latency of one
+// block per lane (0.43-0.47 and 0.92 us at 64 lanes), and each further block
+// per lane adds about one block's latency
 int64_t sweep_cost(const Plan &P, int g)
 {
     if (g == 1) return P.lat.nstab;
