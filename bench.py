@@ -50,23 +50,34 @@ LDS_PEAK_BYTES = 256 * 256 * 2.4e9
 
 
 def kernel_source_sha256(kernel=""):
-    """Digest of the sources a kernel is built from, in name order.  The
-    annealing kernels specialised to a distance (k_anneal_rows_d<D>) come
-    from the headers and the xzzx_static_*.hip units alone, the planar ones
-    (k_anneal_planar_d<D>) from the headers and xzzx_planar.hip; any other
-    kernel is digested with every device source."""
+    """Digest of the sources a kernel is built from, in name order: its
+    translation units and every header they include, transitively.  The
+    annealing kernels specialised to a distance come from the xzzx_static_*
+    units (k_anneal_rows_d<D>), xzzx_planar.hip (k_anneal_planar_d<D>),
+    xzzx_ladder_rows*.hip (k_anneal_ladder_rows_d<D>) and
+    xzzx_ladder_planar.hip (k_anneal_ladder_planar_d<D>); any other kernel
+    is digested with every device source."""
     import glob
     import hashlib
+    import re
 
     csrc = os.path.join(ROOT, "paper_2509_17837_amd", "csrc")
-    inc = os.path.join(ROOT, "include")
-    files = glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(inc, "*.h"))
-    if kernel.startswith("k_anneal_rows_d"):
-        files += glob.glob(os.path.join(csrc, "xzzx_static_*.hip"))
-    elif kernel.startswith("k_anneal_planar_d"):
-        files += [os.path.join(csrc, "xzzx_planar.hip")]
-    else:
-        files += glob.glob(os.path.join(csrc, "*.hip"))
+    units = {
+        "k_anneal_rows_d": "xzzx_static_*.hip",
+        "k_anneal_planar_d": "xzzx_planar.hip",
+        "k_anneal_ladder_rows_d": "xzzx_ladder_rows*.hip",
+        "k_anneal_ladder_planar_d": "xzzx_ladder_planar.hip",
+    }
+    pattern = next((g for k, g in units.items() if kernel.startswith(k)), "*.hip")
+    todo = glob.glob(os.path.join(csrc, pattern))
+    files = set()
+    while todo:
+        f = os.path.realpath(todo.pop())
+        if f in files:
+            continue
+        files.add(f)
+        for inc in re.findall(r'^#include "([^"]+)"', open(f).read(), re.M):
+            todo.append(os.path.join(os.path.dirname(f), inc))
     h = hashlib.sha256()
     for f in sorted(files, key=os.path.basename):
         h.update(os.path.basename(f).encode())

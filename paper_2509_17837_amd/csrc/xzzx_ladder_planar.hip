@@ -17,13 +17,12 @@ __device__ __forceinline__ void ladder_planar_core(const PlanDev *pl, const Chai
                                                    uint32_t *snap)
 {
     using PR = PlanarRows<D>;
-    constexpr int NB = PlanarSchedule<D>::MP / 4;
-    using Blocks = std::make_integer_sequence<int, NB>;
     const int nranks = (int)uni(pl->nranks), n_sweeps = (int)uni(pl->n_sweeps), K = (int)uni(pl->ladder_k);
     int32_t W[4];
     W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
     const uint32_t uid = J.uid, cc = J.cc;
     const uint32_t k0 = uni(seed_lo), k1 = uni(seed_hi);
+    const PlanarLaneKey lk = planar_lane_key(uid, k1);
     // ladder position: replica r = bK + j starts at level j; coset P
     const uint32_t rep = cc >> 2, P = cc & 3u;
     const uint32_t ladder_id = 4u * (rep / (uint32_t)K) + P;
@@ -39,19 +38,19 @@ __device__ __forceinline__ void ladder_planar_core(const PlanDev *pl, const Chai
         const uint4 *et_l = et_s + level * nranks;
         const uint32_t c2 = 4u * (uint32_t)t;
         int32_t acc = 0;
-        planar_class<D, 0>(r, uid, cc, c2, k0, k1, lut_s, et_l, acc, Blocks{});
+        planar_class<D, 0, planar_ladder_pipelined(D)>(r, lk, cc, c2, k0, k1, lut_s, et_l, acc);
         E += acc;
         if (E < Emin) { Emin = E; stop = 4 * t + 1; if (keep) store_rows(keep, r); }
         acc = 0;
-        planar_class<D, 1>(r, uid, cc, c2 + 1u, k0, k1, lut_s, et_l, acc, Blocks{});
+        planar_class<D, 1, planar_ladder_pipelined(D)>(r, lk, cc, c2 + 1u, k0, k1, lut_s, et_l, acc);
         E += acc;
         if (E < Emin) { Emin = E; stop = 4 * t + 2; if (keep) store_rows(keep, r); }
         acc = 0;
-        planar_class<D, 2>(r, uid, cc, c2 + 2u, k0, k1, lut_s, et_l, acc, Blocks{});
+        planar_class<D, 2, planar_ladder_pipelined(D)>(r, lk, cc, c2 + 2u, k0, k1, lut_s, et_l, acc);
         E += acc;
         if (E < Emin) { Emin = E; stop = 4 * t + 3; if (keep) store_rows(keep, r); }
         acc = 0;
-        planar_class<D, 3>(r, uid, cc, c2 + 3u, k0, k1, lut_s, et_l, acc, Blocks{});
+        planar_class<D, 3, planar_ladder_pipelined(D)>(r, lk, cc, c2 + 3u, k0, k1, lut_s, et_l, acc);
         E += acc;
         if (E < Emin) { Emin = E; stop = 4 * t + 4; if (keep) store_rows(keep, r); }
         if (K > 1) level = ladder_exchange(level, E, K, P, uid, ladder_id, t, k0, k1, pl->ladder_pow);

@@ -14,14 +14,13 @@ __device__ __forceinline__ void planar_static_core(const PlanDev *pl, const Chai
                                                    uint32_t *snap)
 {
     using PR = PlanarRows<D>;
-    constexpr int NB = PlanarSchedule<D>::MP / 4;
-    using Blocks = std::make_integer_sequence<int, NB>;
     const int lane = threadIdx.x;
     const int nranks = (int)uni(pl->nranks), n_sweeps = (int)uni(pl->n_sweeps), kneg = (int)uni(pl->kneg);
     int32_t W[4];
     W[0] = 0; W[1] = (int32_t)uni(pl->W[1]); W[2] = (int32_t)uni(pl->W[2]); W[3] = (int32_t)uni(pl->W[3]);
     const uint32_t uid = J.uid, cc = J.cc;
     const uint32_t k0 = uni(seed_lo), k1 = uni(seed_hi);
+    const PlanarLaneKey lk = planar_lane_key(uid, k1);
     const bool use_x = J.lp == 1 || J.lp == 2, use_z = J.lp == 2 || J.lp == 3;
 
     uint32_t r[PR::N];
@@ -38,19 +37,19 @@ __device__ __forceinline__ void planar_static_core(const PlanDev *pl, const Chai
         wave_lds_fence();
         const uint32_t c2 = 4u * (uint32_t)t;
         int32_t acc = 0;
-        planar_class<D, 0>(r, uid, cc, c2, k0, k1, lut_s, et_s, acc, Blocks{});
+        planar_class<D, 0, planar_pipelined(D)>(r, lk, cc, c2, k0, k1, lut_s, et_s, acc);
         E += acc;
         if (E < Emin) { Emin = E; stop = 4 * t + 1; if (keep) keep_min(); }
         acc = 0;
-        planar_class<D, 1>(r, uid, cc, c2 + 1u, k0, k1, lut_s, et_s, acc, Blocks{});
+        planar_class<D, 1, planar_pipelined(D)>(r, lk, cc, c2 + 1u, k0, k1, lut_s, et_s, acc);
         E += acc;
         if (E < Emin) { Emin = E; stop = 4 * t + 2; if (keep) keep_min(); }
         acc = 0;
-        planar_class<D, 2>(r, uid, cc, c2 + 2u, k0, k1, lut_s, et_s, acc, Blocks{});
+        planar_class<D, 2, planar_pipelined(D)>(r, lk, cc, c2 + 2u, k0, k1, lut_s, et_s, acc);
         E += acc;
         if (E < Emin) { Emin = E; stop = 4 * t + 3; if (keep) keep_min(); }
         acc = 0;
-        planar_class<D, 3>(r, uid, cc, c2 + 3u, k0, k1, lut_s, et_s, acc, Blocks{});
+        planar_class<D, 3, planar_pipelined(D)>(r, lk, cc, c2 + 3u, k0, k1, lut_s, et_s, acc);
         E += acc;
         if (E < Emin) { Emin = E; stop = 4 * t + 4; if (keep) keep_min(); }
     }
