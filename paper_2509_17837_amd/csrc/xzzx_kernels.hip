@@ -172,9 +172,11 @@ __device__ void walk_boundary(const PlanDev *pl, int g, int u, uint32_t *cfgw)
 // half of the wavefront (32 lanes) runs one, and both XOR their paths into the
 // shared configuration -- twice the lanes at work where a colour has no more
 // than a few dozen defects.  Otherwise the whole wavefront runs the colours one
-// after the other.
+// after the other.  The kernel waits on memory most of the time, so the split
+// form is held to eight wavefronts per SIMD (64 VGPRs; at its natural 68 it
+// ran seven, and the d = 11 and planar d = 9 greedy stages took 4-5 % longer).
 template <bool SPLIT>
-__global__ __launch_bounds__(kWave) void k_greedy(GreedyArgs A)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(SPLIT ? 8 : 1, 8))) void k_greedy(GreedyArgs A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const PlanDev *pl = A.plan;
