@@ -205,7 +205,8 @@ def test_random_site_plain_graph_and_mixed():
                                                        (0, 9, 3, 16, 4, 0), (1, 3, 11, 4, 2, 30),
                                                        (1, 15, 3, 8, 4, 6), (1, 11, 5, 12, 4, 10),
                                                        (0, 17, 2, 16, 4, 6), (0, 23, 2, 16, 2, 4),
-                                                       (0, 31, 1, 16, 16, 3)])
+                                                       (0, 31, 1, 16, 16, 3), (1, 13, 3, 8, 2, 6),
+                                                       (1, 5, 6, 4, 2, 20)])
 def test_replica_exchange_ladders(layout, d, n_syn, R, K, sweeps):
     """Replica exchange: ladders of K levels from beta 0.4 to 1.6 (replicas
     of a ladder share one greedy reference); every chain (E, E_min, stop,
