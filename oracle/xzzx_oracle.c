@@ -21,9 +21,10 @@
  * Pinning status: every function below is pinned by a CPU test (closed forms,
  * brute force, invariants, published known-answer vectors), except the exact
  * tie order of the randomized greedy matching, which the paper leaves free
- * ("pick uniformly at random", Alg. 6) -- only its distributional properties
- * and its matching weight are pinned; the byte-exact order is this oracle's
- * definition (parity unpinned by the paper).
+ * (Alg. 6 leaves the choice among equal pairs to chance) -- only its
+ * distributional properties and its matching weight are pinned; the
+ * byte-exact order is this oracle's definition (parity unpinned by the
+ * paper).
  */
 #include <math.h>
 #include <stdint.h>
@@ -451,7 +452,7 @@ int or_symp(const or_lat *L, const uint8_t *a, const uint8_t *b)
     return s;
 }
 
-/* Logical class of a*b (Alg. 7, "via commutation with L_X and L_Z"):
+/* Logical class of a*b (Alg. 7: found from commutation with L_X and L_Z):
  * a*b must have a trivial syndrome.  Returns 0=I, 1=X, 2=Y, 3=Z, or -1 if the
  * product is not syndrome-free.  [a*b] = [L_X] anticommutes with L_Z only,
  * [L_Z] with L_X only, [L_Y] with both. */
@@ -835,7 +836,7 @@ int or_greedy_pairs(or_lat *L, const int32_t wg[2], const uint8_t *syn, uint32_t
 /* so their moves commute.  The draw for generator (k, m) -- rank m in class  */
 /* k -- in sweep t of chain c of syndrome uid is word (m mod 4) of           */
 /* Philox(seed; uid, c, 4t + k, m div 4).  E_min is updated after each class  */
-/* (the parallel counterpart of "after every step" in Alg. 2), strictly, so   */
+/* (the parallel counterpart of the per-step update of Alg. 2), strictly, so  */
 /* the snapshot is the first configuration attaining it; stop = 4t + k + 1    */
 /* records that phase (0 = the initial configuration).                         */
 /* ------------------------------------------------------------------------- */

@@ -62,7 +62,7 @@ __global__ void k_syndrome(const PlanDev *__restrict__ pl, const uint8_t *__rest
 // Greedy matching (Algs. 5-6) -- one wavefront per (syndrome, replica), one
 // colour per half wavefront or the colours in turn (see k_greedy).
 //
-// The sequential rule "take the free pair of least (weight, key, pair id)"
+// The sequential rule -- take the free pair of least (weight, key, pair id) --
 // is evaluated as repeated mutual-best elimination: every free defect finds
 // its least free partner, and pairs that are each other's least are matched.
 // Under a strict total order the pair taken first by the sequential scan is
