@@ -78,7 +78,7 @@ enum {
 };
 
 enum { XZZX_ROTATED = 0, XZZX_PLANAR = 1 };
-enum { XZZX_BIAS_BASELINE = 0, XZZX_BIAS_PAPER = 1 };
+enum { XZZX_BIAS_RATIO = 0, XZZX_BIAS_PAPER = 1 };
 enum { XZZX_SCHED_LINEAR = 0, XZZX_SCHED_GEOMETRIC = 1, XZZX_SCHED_PAPER_LOG = 2 };
 enum { XZZX_GREEDY_RANDOM = 0, XZZX_GREEDY_SAME = 1, XZZX_GREEDY_BOUNDARY = 2 };
 
@@ -133,7 +133,8 @@ int xzzx_lattice_logicals(const xzzx_lattice *lat, uint8_t *lx, uint8_t *lz);
 
 /* ---- noise, weights, schedules (Eqs. (5)-(12), (23)-(24)) ----------------- */
 
-/* convention XZZX_BIAS_BASELINE: p_Y = p eta/(eta+1), p_X = p_Z = p/(2(eta+1));
+/* convention XZZX_BIAS_RATIO (eta = p_Y / (p_X + p_Z)): p_Y = p eta/(eta+1),
+ * p_X = p_Z = p/(2(eta+1));
  * XZZX_BIAS_PAPER: p_x:p_y:p_z = 1:eta:1 (Sec. V.A).  pxyz = (p_X, p_Y, p_Z).
  * EINVAL unless 0 < p < 1/2 and eta > 0. */
 int xzzx_noise(double p, double eta, int convention, double pxyz[3]);

@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "xzzx_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 ROTATED, PLANAR = 0, 1
-CONV_BASELINE, CONV_PAPER = 0, 1
+CONV_RATIO, CONV_PAPER = 0, 1
 SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
 ORDER_COLOUR, ORDER_RANDOM_SITE, ORDER_LADDER = 0, 1, 2   # colour sweeps; random-site steps (Alg. 3); replica exchange
@@ -109,7 +109,7 @@ def philox(ctr, key):
     return out
 
 
-def noise(p, eta, conv=CONV_BASELINE):
+def noise(p, eta, conv=CONV_RATIO):
     out = np.zeros(3, np.float64)
     rc = lib().or_noise(p, eta, conv, out)
     if rc:

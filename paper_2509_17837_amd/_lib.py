@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libxzzx_sa.so")
 
 XZZX_OK, XZZX_EINVAL, XZZX_ENOMEM, XZZX_EDEVICE, XZZX_ERANGE, XZZX_EAGAIN, XZZX_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
 ROTATED, PLANAR = 0, 1
-BIAS_BASELINE, BIAS_PAPER = 0, 1
+BIAS_RATIO, BIAS_PAPER = 0, 1
 SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_PAPER_LOG = 0, 1, 2
 GREEDY_RANDOM, GREEDY_SAME, GREEDY_BOUNDARY = 0, 1, 2
 FLAG_PLAIN = 1

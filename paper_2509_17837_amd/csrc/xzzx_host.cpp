@@ -748,7 +748,7 @@ int xzzx_noise(double p, double eta, int convention, double pxyz[3])
         return XZZX_EINVAL;
     }
     double px, py;
-    if (convention == XZZX_BIAS_BASELINE) {
+    if (convention == XZZX_BIAS_RATIO) {
         px = p / (2.0 * (eta + 1.0));
         py = p * eta / (eta + 1.0);
     } else if (convention == XZZX_BIAS_PAPER) {

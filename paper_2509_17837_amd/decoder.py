@@ -57,7 +57,7 @@ def _dev(t, dtype, name):
 # ---------------------------------------------------------------------------
 # host-side model calls
 # ---------------------------------------------------------------------------
-def noise(p, eta, convention=X.BIAS_BASELINE):
+def noise(p, eta, convention=X.BIAS_RATIO):
     out = np.zeros(3, np.float64)
     call("xzzx_noise", p, eta, convention, _np_p(out))
     return out

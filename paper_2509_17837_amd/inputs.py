@@ -91,7 +91,7 @@ WORKLOADS = {
 WORKLOAD_INDEX = {name: k for k, name in enumerate(WORKLOADS)}
 SCHEDULE_KIND = {"linear": 0, "geometric": 1, "paper_log": 2}
 LAYOUT_KIND = {"rotated": 0, "planar": 1}
-CONVENTION_KIND = {"baseline": 0, "paper": 1}
+CONVENTION_KIND = {"ratio": 0, "paper": 1}
 
 
 def layout_of(wl) -> int:
@@ -99,7 +99,7 @@ def layout_of(wl) -> int:
 
 
 def convention_of(wl) -> int:
-    return CONVENTION_KIND[wl.get("convention", "baseline")]
+    return CONVENTION_KIND[wl.get("convention", "ratio")]
 
 
 def seeds(name: str):

@@ -71,8 +71,8 @@ def test_philox_matches_rocrand():
 
 
 def test_noise_conventions():
-    # BASELINE form: p_Y = p eta/(eta+1), p_X = p_Z = p/(2(eta+1))
-    px, py, pz = O.noise(0.15, 10.0, O.CONV_BASELINE)
+    # ratio form (eta = p_Y/(p_X + p_Z)): p_Y = p eta/(eta+1), p_X = p_Z = p/(2(eta+1))
+    px, py, pz = O.noise(0.15, 10.0, O.CONV_RATIO)
     assert math.isclose(px + py + pz, 0.15, rel_tol=1e-15)
     assert px == pz and math.isclose(py / px, 20.0, rel_tol=1e-14)
     # Sec. V.A: p_x:p_y:p_z = 1:eta:1; eta=1 is depolarizing p/3 each
@@ -86,7 +86,7 @@ def test_noise_conventions():
 
 
 # Expected integer weights of the measured workloads: round(2^16 * -ln(p_P/(1-p)))
-# with the BASELINE noise form (values tabulated with the workload definitions).
+# with the ratio noise form (values tabulated with the workload definitions).
 WEIGHT_TABLE = [
     # p, eta, W_X(=W_Z), W_Y, W~
     (0.15, 10.0, 316253, 119925, 116728),
