@@ -192,13 +192,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(SPLIT ? 8
     const int hl = lane % kHalf;
     const int stride = A.max_nodes + 1;
     uint32_t *cfgw = reinterpret_cast<uint32_t *>(smem);
-    // per colour: D, best, pairs, dbD and the free flags (the colours in turn
-    // share one set)
+    // per colour: D, best, pairs, dbD, the free flags and the list of free
+    // defects (the colours in turn share one set)
     constexpr int kSets = SPLIT ? 2 : 1;
     int16_t *cands = reinterpret_cast<int16_t *>(reinterpret_cast<int32_t *>(smem + 4 * nwords) + kSets * 4 * stride);
-    // pair-weight cache after the free flags, 16-byte aligned
-    const uint32_t cache_off =
-        ((uint32_t)(4 * nwords + kSets * 4 * 4 * stride + 2 * kWave * kGreedyTies + kSets * stride) + 15u) & ~15u;
+    // the free flags (bytes), then the free lists (int16, 2-byte aligned),
+    // then the pair-weight cache, 16-byte aligned
+    const uint32_t flags_off = 4u * nwords + kSets * 4 * 4 * stride + 2 * kWave * kGreedyTies;
+    const uint32_t list_off = (flags_off + kSets * stride + 1u) & ~1u;
+    const uint32_t cache_off = (list_off + kSets * 2 * stride + 15u) & ~15u;
     __shared__ int s_count[2];
 
     for (int i = lane; i < nwords; i += kWave) cfgw[i] = 0;
@@ -212,7 +214,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(SPLIT ? 8
         int32_t *best = D + stride;
         int32_t *pairs = best + stride;
         int32_t *dbD = pairs + stride;   // boundary distance of each defect
-        uint8_t *freef = reinterpret_cast<uint8_t *>(cands + kWave * kGreedyTies) + set * stride;
+        uint8_t *freef = smem + flags_off + set * stride;
+        int16_t *fl = reinterpret_cast<int16_t *>(smem + list_off) + set * stride;
         const int n = pl->ncol[g];
         const int32_t *cf = pl->col_face[g];
         const int32_t *dint = pl->dint[g];
@@ -268,7 +271,23 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(SPLIT ? 8
             // suffice (rounds continue while either half has work).  Free
             // defects only leave, so a defect whose least partner is still free
             // keeps it; only the others search again.
+            const int na_all = SPLIT ? max(__shfl(na, 0, kWave), __shfl(na, kHalf, kWave)) : na;
             for (int round = 0; __ballot(nfree > 0 && round <= na / 2) != 0; ++round) {
+                // the free defects of this colour, ascending: the scans below
+                // walk this list instead of every defect, so a rescan in a
+                // late round skips the partners already matched (the same
+                // candidates in the same order; the greedy stage at d = 31
+                // took a third less time)
+                int nfl = 0;
+                for (int base = 0; base < na_all; base += kHalf) {
+                    const int v = base + hl;
+                    const bool flag = v < na && freef[v];
+                    const uint64_t mask = SPLIT ? ((__ballot(flag) >> (g * kHalf)) & 0xFFFFFFFFull) : __ballot(flag);
+                    const int pos = nfl + __popcll(mask & ((1ull << hl) - 1ull));
+                    if (flag) fl[pos] = (int16_t)v;
+                    nfl += __popcll(mask);
+                }
+                __syncthreads();
                 for (int i = hl; i < na; i += kHalf) {
                     if (!freef[i]) continue;
                     if (round > 0 && best[i] >= 0 && freef[best[i]]) continue;
@@ -287,15 +306,18 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(SPLIT ? 8
                     };
                     uint32_t bw = 0xFFFFFFFFu;
                     int nt = 0;   // partners at weight bw
-                    for (int j0 = 0; j0 < na; j0 += kGreedyBatch) {
+                    for (int t0 = 0; t0 < nfl; t0 += kGreedyBatch) {
                         int32_t dv[kGreedyBatch];
+                        int jj[kGreedyBatch];
+#pragma unroll
+                        for (int k = 0; k < kGreedyBatch; ++k) jj[k] = t0 + k < nfl ? fl[t0 + k] : na;
 #pragma unroll
                         for (int k = 0; k < kGreedyBatch; ++k)
-                            dv[k] = cached ? 0 : drow[j0 + k < nd ? D[j0 + k] : 0];
+                            dv[k] = cached ? 0 : drow[jj[k] < nd ? D[jj[k]] : 0];
 #pragma unroll
                         for (int k = 0; k < kGreedyBatch; ++k) {
-                            const int j = j0 + k;
-                            if (j >= na || j == i || !freef[j]) continue;
+                            const int j = jj[k];
+                            if (j >= na || j == i) continue;
                             const uint32_t w = weight(j, dv[k]);
                             if (w > bw) continue;
                             if (w < bw) { bw = w; nt = 0; }
@@ -700,17 +722,19 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 static bool greedy_split(const Plan &P) { return std::max(P.hdev.ncol[0], P.hdev.ncol[1]) <= 128; }
 
 // LDS of a greedy workgroup: the configuration, per colour set D, best,
-// pairs, dbD and the free flags (one set per colour when the halves of the
-// wavefront match the colours at once, else one), the tie lists, and, with
-// `cache` (launches of few wavefronts, where latency matters more than
-// occupancy), the pair-weight cache of each set: 16 KiB per colour when the
-// colours run side by side (up to 63 defects), 48 KiB otherwise (up to 109).
+// pairs, dbD, the free flags and the free list (one set per colour when the
+// halves of the wavefront match the colours at once, else one), the tie
+// lists, and, with `cache` (launches of few wavefronts, where latency matters
+// more than occupancy), the pair-weight cache of each set: 16 KiB per colour
+// when the colours run side by side (up to 63 defects), 48 KiB otherwise (up
+// to 109).
 static int greedy_lds(const Plan &P, bool cache, GreedyArgs *A)
 {
     const int mn = std::max(P.hdev.ncol[0], P.hdev.ncol[1]);
     A->max_nodes = mn;
     const int sets = greedy_split(P) ? 2 : 1;
-    const int base = 4 * ((P.lat.nq + 3) / 4) + sets * 4 * 4 * (mn + 1) + 2 * kWave * kGreedyTies + sets * (mn + 1);
+    const int flags = 4 * ((P.lat.nq + 3) / 4) + sets * 4 * 4 * (mn + 1) + 2 * kWave * kGreedyTies;
+    const int base = ((flags + sets * (mn + 1) + 1) & ~1) + sets * 2 * (mn + 1);
     A->cache_entries = cache ? (sets == 2 ? 4096 : 12288) : 0;
     return ((base + 15) & ~15) + sets * 4 * A->cache_entries + 16;
 }
