@@ -273,11 +273,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(SPLIT ? 8
             // keeps it; only the others search again.
             const int na_all = SPLIT ? max(__shfl(na, 0, kWave), __shfl(na, kHalf, kWave)) : na;
             for (int round = 0; __ballot(nfree > 0 && round <= na / 2) != 0; ++round) {
-                // the free defects of this colour, ascending: the scans below
-                // walk this list instead of every defect, so a rescan in a
-                // late round skips the partners already matched (the same
-                // candidates in the same order; the greedy stage at d = 31
-                // took a third less time)
+                // the free defects of this colour, ascending: the defects and
+                // the partners the round scans come from this list, so a late
+                // round skips the ones already matched (the same candidates in
+                // the same order; the greedy stage at d = 31 took a third less
+                // time)
                 int nfl = 0;
                 for (int base = 0; base < na_all; base += kHalf) {
                     const int v = base + hl;
@@ -288,8 +288,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(SPLIT ? 8
                     nfl += __popcll(mask);
                 }
                 __syncthreads();
-                for (int i = hl; i < na; i += kHalf) {
-                    if (!freef[i]) continue;
+                for (int t = hl; t < nfl; t += kHalf) {
+                    const int i = fl[t];
                     if (round > 0 && best[i] >= 0 && freef[best[i]]) continue;
                     // least (w, key, id) over free partners j, in two passes: the
                     // least weight and the partners at it (in ascending j, so
@@ -352,8 +352,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(SPLIT ? 8
                     best[i] = bj;
                 }
                 __syncthreads();
-                for (int i = hl; i < na; i += kHalf) {
-                    if (!freef[i]) continue;
+                for (int t = hl; t < nfl; t += kHalf) {
+                    const int i = fl[t];
                     const int j = best[i];
                     if (j > i && best[j] == i) {
                         const int p = atomicAdd(&s_count[g], 1);
