@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(SPLIT ? 8
                 // the free defects of this colour, ascending: the defects and
                 // the partners the round scans come from this list, so a late
                 // round skips the ones already matched (the same candidates in
-                // the same order; the greedy stage at d = 31 took a third less
+                // the same order; the greedy stage at d = 31 took half the
                 // time)
                 int nfl = 0;
                 for (int base = 0; base < na_all; base += kHalf) {
